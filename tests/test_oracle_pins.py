@@ -1,0 +1,320 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle:
+published generator outputs, the paper's worked examples (Figs. 6, 7, 10),
+independent algorithms (nested loops, hash join, Python's stable sort,
+numpy), closed forms and invariants."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from conftest import GOLDEN
+
+U64 = (1 << 64) - 1
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _tup(rows):
+    return np.array(rows, dtype=np.uint64).reshape(-1, 2)
+
+
+# ---------------------------------------------------------------- hashing
+
+def test_splitmix64_published_outputs():
+    g = _golden("splitmix64_seed0.json")
+    got = [oracle.splitmix_at(g["seed"], i) for i in range(len(g["outputs_hex"]))]
+    assert got == [int(h, 16) for h in g["outputs_hex"]]
+    # the generator module carries its own SplitMix64; it must agree too
+    assert [workloads.splitmix_at(0, i) for i in range(4)] == got
+
+
+def test_pair_hash_vectors():
+    g = _golden("pair_hash.json")
+    assert oracle.mix64(0x9E3779B97F4A7C15) == int(g["mix_of_gamma_hex"], 16)
+    for v in g["vectors"]:
+        assert oracle.pair_hash(int(v["k"]), int(v["rp"]), int(v["sp"])) == int(v["H_hex"], 16)
+
+
+def test_pair_hash_not_symmetric_in_payloads():
+    # a transposed operand (rp <-> sp) must change the checksum term
+    assert oracle.pair_hash(7, 1, 2) != oracle.pair_hash(7, 2, 1)
+
+
+def test_example_join():
+    g = _golden("pair_hash.json")["example_join"]
+    R, S = _tup(g["R"]), _tup(g["S"])
+    for fn in (oracle.join, oracle.join_nested):
+        r = fn(R, S, pairs=True)
+        assert r.count == g["count"]
+        assert r.checksum == int(g["checksum_hex"], 16)
+        assert r.pairs.tolist() == g["pairs"]
+        assert r.maxsum == g["max_payload_sum"] and r.nonempty
+
+
+# ------------------------------------------------ the join, by definition
+
+def _rand_rel(rng, n, domain):
+    k = rng.integers(0, domain, size=n, dtype=np.uint64) if domain else rng.integers(0, U64, size=n, dtype=np.uint64,
+                                                                                      endpoint=True)
+    p = rng.integers(0, U64, size=n, dtype=np.uint64, endpoint=True)
+    return np.stack([k, p], axis=1)
+
+
+CASES = [(0, 0, 4), (0, 10, 4), (10, 0, 4), (1, 1, 1), (50, 70, 8), (200, 300, 40), (333, 1000, 1000),
+         (100, 100, 0), (64, 64, 1), (1000, 50, 3)]
+
+
+@pytest.mark.parametrize("nR,nS,domain", CASES)
+def test_join_matches_nested_loops(nR, nS, domain):
+    rng = np.random.default_rng(nR * 7919 + nS * 31 + domain)
+    R, S = _rand_rel(rng, nR, domain), _rand_rel(rng, nS, domain)
+    a = oracle.join(R, S, pairs=True, cap=max(1, nR * nS))
+    b = oracle.join_nested(R, S, pairs=True)
+    assert (a.count, a.checksum, a.maxsum, a.nonempty) == (b.count, b.checksum, b.maxsum, b.nonempty)
+    assert np.array_equal(a.pairs, b.pairs)
+
+
+def test_join_extreme_keys_and_payloads():
+    R = _tup([(0, U64), (U64, 1), (U64, U64), (5, 0)])
+    S = _tup([(U64, U64), (0, 1), (0, 2), (6, 0), (U64, 0)])
+    a = oracle.join(R, S, pairs=True)
+    b = oracle.join_nested(R, S, pairs=True)
+    assert a.count == 6
+    assert (a.count, a.checksum, a.maxsum, a.nonempty) == (b.count, b.checksum, b.maxsum, b.nonempty)
+    assert np.array_equal(a.pairs, b.pairs)
+    # wrapping payload sums: U64+1 -> 0, U64+2 -> 1, 1+U64 -> 0, 1+0, U64+U64 -> U64-1, U64+0 = U64
+    assert a.maxsum == U64
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_join_matches_hash_join_and_invariant(seed):
+    rng = np.random.default_rng(seed)
+    R = _rand_rel(rng, 30000, 20000)
+    S = _rand_rel(rng, 90000, 25000)
+    a = oracle.join(R, S)
+    h, inv = oracle.join_hash(R, S)
+    assert (a.count, a.checksum, a.maxsum) == (h.count, h.checksum, h.maxsum)
+    assert inv == a.count
+    # invariant computed a third way: key multiplicities with numpy
+    kr, cr = np.unique(R[:, 0], return_counts=True)
+    ks, cs = np.unique(S[:, 0], return_counts=True)
+    common, ir, is_ = np.intersect1d(kr, ks, return_indices=True)
+    assert int(np.sum(cr[ir].astype(np.int64) * cs[is_].astype(np.int64))) == a.count
+
+
+def test_fk_closed_form_equals_join():
+    w = workloads.make("fk_small", scale_shift=4)
+    fk = oracle.fk_closed_form(w.R, w.S, w.partner)
+    a = oracle.join(w.R, w.S)
+    assert fk.count == len(w.S) == a.count
+    assert fk.checksum == a.checksum and fk.maxsum == a.maxsum
+
+
+def test_fk_closed_form_detects_broken_partner():
+    w = workloads.make("fk_small", scale_shift=8)
+    p = w.partner.copy()
+    p[3] = (p[3] + 1) % len(w.R)
+    with pytest.raises(RuntimeError):
+        oracle.fk_closed_form(w.R, w.S, p)
+
+
+def test_lognormal_generator_count_pins_oracle():
+    w = workloads.make("lognormal", scale_shift=12)   # |R| = 2^16, |S| = 2^18
+    a = oracle.join(w.R, w.S)
+    h, inv = oracle.join_hash(w.R, w.S)
+    assert a.count == w.expected_count == inv == h.count
+    assert a.checksum == h.checksum
+
+
+# ---------------------------------------------------------- phase 1 sort
+
+def test_stable_sort_matches_python_sorted():
+    rng = np.random.default_rng(5)
+    T = _rand_rel(rng, 5000, 300)
+    ref = sorted(T.tolist(), key=lambda t: t[0])      # Python's sort is stable
+    assert oracle.sort_by_key(T).tolist() == ref
+
+
+@pytest.mark.parametrize("run_len", [1, 7, 64, 1000, 5000])
+def test_sort_runs(run_len):
+    rng = np.random.default_rng(run_len)
+    S = _rand_rel(rng, 3001, 500)
+    out = oracle.sort_runs(S, run_len)
+    for a in range(0, len(S), run_len):
+        ref = sorted(S[a:a + run_len].tolist(), key=lambda t: t[0])
+        assert out[a:a + run_len].tolist() == ref
+
+
+# --------------------------------------------- phase 2: Figs. 6 and 10
+
+def _fig_partition(g):
+    shift = 64 - g["key_bits"]
+    C = np.concatenate([_tup([(k, 100 * i + j) for j, k in enumerate(ch)]) for i, ch in enumerate(g["chunks"])])
+    chunk_len = len(g["chunks"][0])
+    assert all(len(ch) == chunk_len for ch in g["chunks"][:-1])
+    P = max(g["sp"]) + 1
+    return oracle.radix_partition(C, chunk_len, g["B"], shift, g["sp"], P), C, P
+
+
+def test_fig6_histograms_and_prefix_sums():
+    g = _golden("fig6_partition.json")
+    (hist, ps, base, out), C, P = _fig_partition(g)
+    assert hist[0].tolist() == g["h1"]
+    assert ps[0].tolist() == g["ps1"]
+    assert ps[1].tolist() == g["ps2"]
+
+
+def test_fig10_histograms_prefix_sums_and_sizes():
+    g = _golden("fig10_partition.json")
+    (hist, ps, base, out), C, P = _fig_partition(g)
+    assert hist.tolist() == g["h"]
+    assert ps[0].tolist() == g["ps1"] and ps[1].tolist() == g["ps2"]
+    assert np.diff(base).tolist() == g["partition_sizes"]
+    # the 2-bit radix histograms of the chunks, by direct counting
+    for i, ch in enumerate(g["chunks"]):
+        assert [sum(1 for k in ch if k >> 3 == d) for d in range(4)] == g["radix_hist"][i]
+
+
+def test_fig10_cost_split_with_correlated_s():
+    g = _golden("fig10_partition.json")
+    h = np.array(g["cluster_totals"], np.uint64)
+    s = 4 * h                                        # S correlated with R (multiplicity 4)
+    opt, first = oracle.cost_splitters_dp(h, s, P=2, T=2)
+    assert first.tolist() == g["cost_split_first_buckets"]
+
+
+def test_cost_dp_brute_force_small():
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        nb, P = int(rng.integers(1, 7)), int(rng.integers(1, 4))
+        h = rng.integers(0, 50, nb).astype(np.uint64)
+        s = rng.integers(0, 200, nb).astype(np.uint64)
+        opt, first = oracle.cost_splitters_dp(h, s, P, 4)
+        # brute force over all non-decreasing cut vectors
+        import itertools
+        best = None
+        for cuts in itertools.combinations_with_replacement(range(nb + 1), P - 1):
+            bounds = [0, *cuts, nb]
+            worst = max(oracle.split_cost(int(h[a:b].sum()), 4, int(s[a:b].sum())) for a, b in zip(bounds, bounds[1:]))
+            best = worst if best is None else min(best, worst)
+        assert opt == pytest.approx(best)
+
+
+@pytest.mark.parametrize("B,chunk_len", [(1, 5), (3, 17), (6, 100), (8, 1000)])
+def test_radix_partition_prefix_sums_and_scatter(B, chunk_len):
+    rng = np.random.default_rng(B)
+    C = _rand_rel(rng, 2500, 0)
+    P = 5
+    sp = np.sort(rng.integers(0, P, 1 << B)).astype(np.uint32)  # non-decreasing map
+    hist, ps, base, out = oracle.radix_partition(C, chunk_len, B, 0, sp, P)
+    dig = (C[:, 0] >> np.uint64(64 - B)).astype(np.int64)
+    part = sp[dig]
+    nchunk = (len(C) + chunk_len - 1) // chunk_len
+    for i in range(nchunk):
+        sl = part[i * chunk_len:(i + 1) * chunk_len]
+        assert hist[i].tolist() == [int(np.sum(sl == j)) for j in range(P)]
+    # ps_i[j] = sum_{k<i} h_k[j]: running sums written out by hand
+    run = [0] * P
+    for i in range(nchunk):
+        assert ps[i].tolist() == run
+        run = [run[j] + int(hist[i][j]) for j in range(P)]
+    # partition j holds its tuples in chunk order, input order within a chunk
+    for j in range(P):
+        want = C[part == j].tolist()
+        assert out[int(base[j]):int(base[j + 1])].tolist() == want
+
+
+# ------------------------------------------- splitters and bucket function
+
+def test_sample_splitters_against_numpy():
+    rng = np.random.default_rng(3)
+    T = _rand_rel(rng, 10007, 0)
+    nb, os_, seed = 16, 8, 0xABC
+    spl = oracle.sample_splitters(T, nb, os_, seed)
+    m = nb * os_
+    pos = [(workloads.splitmix_at(seed, t) * len(T)) >> 64 for t in range(m)]
+    smp = np.sort(T[pos, 0])
+    assert spl.tolist() == [int(smp[b * os_]) for b in range(1, nb)]
+
+
+def test_bucket_of_monotone_and_isolates_frequent_keys():
+    spl = np.array([10, 20, 20, 20, 30, 40, 40], np.uint64)
+    nb = len(spl) + 1
+    keys = list(range(0, 50))
+    b = [oracle.bucket_of(spl, nb, k) for k in keys]
+    assert b == sorted(b)                                       # non-decreasing
+    assert [k for k in keys if b[keys.index(k)] == b[20]] == [20]   # 20 alone
+    assert [k for k in keys if b[keys.index(k)] == b[40]] == [40]   # 40 alone
+    assert b[9] == 0 and b[10] == 1 and b[19] == 1 and b[21] == 4 and b[49] == 7
+
+
+def test_bucket_partition_is_stable_partition():
+    rng = np.random.default_rng(9)
+    T = _rand_rel(rng, 3000, 100)
+    spl = np.array(sorted(rng.integers(0, 100, 15).tolist()), np.uint64)
+    out, bstart = oracle.bucket_partition(T, spl, 16)
+    b = np.array([oracle.bucket_of(spl, 16, int(k)) for k in T[:, 0]])
+    for j in range(16):
+        assert out[int(bstart[j]):int(bstart[j + 1])].tolist() == T[b == j].tolist()
+
+
+# ------------------------------------------------------ phase 4 search
+
+def test_lower_bound_and_interpolation_agree():
+    rng = np.random.default_rng(4)
+    for trial in range(200):
+        n = int(rng.integers(0, 300))
+        dom = int(rng.choice([2, 10, 1000, 1 << 40, 0]))
+        run = oracle.sort_by_key(_rand_rel(rng, n, dom))
+        probes = [0, U64, 1, U64 - 1] + ([int(run[rng.integers(0, n), 0])] if n else [])
+        probes += [int(x) for x in rng.integers(0, U64, 5, dtype=np.uint64, endpoint=True)]
+        for key in probes:
+            want = int(np.searchsorted(run[:, 0], np.uint64(key), side="left"))
+            assert oracle.lower_bound(run, key) == want
+            assert oracle.interp_search(run, key)[0] == want
+
+
+def test_interpolation_two_steps_on_arithmetic_run():
+    # Fig. 7: on evenly spaced keys the rule of proportion lands at once; two
+    # narrowing steps find the start (plus the two end-point reads).
+    n, a, d = 1 << 16, 1000, 7
+    run = _tup([(a + i * d, i) for i in range(n)])
+    for t in [17, 123, 40000, n - 2]:   # beyond the 16-wide bisection tail
+        pos, probes = oracle.interp_search(run, a + t * d)
+        assert pos == t
+        assert probes == 4
+
+
+def test_equi_height_bounds():
+    run = _tup([(10 * i, 0) for i in range(1000)])
+    assert oracle.equi_height(run, 4).tolist() == [2000, 4000, 6000, 8000]
+
+
+# ------------------------------------------------- the whole P-MPSM on CPU
+
+@pytest.mark.parametrize("T,B,domain", [(1, 1, 1000), (4, 2, 1000), (7, 5, 64), (32, 10, 0), (3, 8, 1)])
+def test_pmpsm_join_equals_definition(T, B, domain):
+    rng = np.random.default_rng(T * 100 + B)
+    R, S = _rand_rel(rng, 2000, domain), _rand_rel(rng, 5000, domain)
+    # shift so that the B leading bits discriminate the key domain (Section 3.2.1)
+    shift = 0 if domain in (0, 1) else 64 - int(domain - 1).bit_length()
+    a = oracle.pmpsm_join(R, S, T, B, shift)
+    b = oracle.join(R, S)
+    assert (a.count, a.checksum, a.maxsum) == (b.count, b.checksum, b.maxsum)
+
+
+def test_pmpsm_join_with_skewed_splitter_vector():
+    rng = np.random.default_rng(77)
+    R = _rand_rel(rng, 3000, 1 << 20)
+    S = _rand_rel(rng, 9000, 1 << 20)
+    B, T = 6, 5
+    sp = np.sort(rng.integers(0, T, 1 << B)).astype(np.uint32)
+    a = oracle.pmpsm_join(R, S, T, B, 44, sp)
+    b = oracle.join(R, S)
+    assert (a.count, a.checksum) == (b.count, b.checksum)
