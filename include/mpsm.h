@@ -1,0 +1,169 @@
+/*
+ * mpsm.h -- C ABI of the range-partitioned massively parallel sort-merge
+ * (P-MPSM) equi-join on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Albutiu, Kemper, Neumann, "Massively Parallel Sort-Merge Joins in
+ * Main Memory Multi-Core Database Systems", PVLDB 5(10), 2012.
+ *   Problem statement (Section 5.1): relations of {joinkey: 64-bit,
+ *   payload: 64-bit} tuples, equi-join on joinkey, no foreign-key or index
+ *   assumptions.
+ *   Method (Section 3.2, Fig. 5): phase 1 sorts chunks of the public input S
+ *   into runs; phase 2 range-partitions the private input R with histograms,
+ *   prefix sums and a synchronisation-free scatter (Section 3.2.1, Figs. 6
+ *   and 10); phase 3 sorts every R partition; phase 4 merge-joins every R
+ *   partition with every S run from a searched start position (Section
+ *   3.2.2, Fig. 7).  Role choice: the smaller input is the private one
+ *   (Section 3.2).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers (HIP global memory of the
+ *     current device); everything else is host memory.
+ *   - Calls only enqueue work on `stream` (a hipStream_t, may be NULL for the
+ *     default stream) and return; results are valid once the stream has
+ *     completed, unless the call documents that it synchronises.
+ *   - The library never allocates device memory on these paths and keeps no
+ *     pointer after returning.  The caller owns all buffers.
+ *   - Inputs are never modified.
+ *   - Arguments are validated on the host before anything is enqueued; a
+ *     rejected call enqueues nothing.
+ */
+#ifndef MPSM_H
+#define MPSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One tuple: 16 bytes, 16-byte aligned arrays (Section 5.1 schema). */
+typedef struct mpsm_tuple {
+  uint64_t key;
+  uint64_t payload;
+} mpsm_tuple;
+
+/* One join result pair, always in the caller's orientation. 24 bytes. */
+typedef struct mpsm_pair {
+  uint64_t key;
+  uint64_t r_payload;
+  uint64_t s_payload;
+} mpsm_pair;
+
+typedef enum mpsm_status {
+  MPSM_OK = 0,
+  MPSM_EINVAL = 1,        /* bad argument (NULL with n > 0, misalignment, size limits, bad config) */
+  MPSM_ECAPACITY = 2,     /* more pairs than pairs_capacity (only reported by synchronising calls) */
+  MPSM_ENOMEM = 3,        /* workspace smaller than mpsm_workspace_bytes() */
+  MPSM_EHIP = 4,          /* a HIP runtime call failed */
+  MPSM_EUNSUPPORTED = 5   /* option not available */
+} mpsm_status;
+
+enum { MPSM_ROLE_AUTO = 0, MPSM_ROLE_AS_GIVEN = 1, MPSM_ROLE_SWAP = 2 };
+enum { MPSM_SPLIT_SAMPLED = 0, MPSM_SPLIT_LEARNED = 1 };
+enum { MPSM_SEARCH_BINARY = 0, MPSM_SEARCH_INTERP = 1, MPSM_SEARCH_LEARNED = 2, MPSM_SEARCH_INDEX = 3 };
+
+/* Tuning and variant choices.  Zero in a numeric field means "automatic".
+ * No choice changes the join result (count, checksum, pair multiset). */
+typedef struct mpsm_config {
+  uint32_t struct_size;    /* sizeof(mpsm_config) */
+  int32_t role;            /* MPSM_ROLE_*: which input is private (R) */
+  int32_t splitter;        /* MPSM_SPLIT_*: how R's range partitions are chosen */
+  int32_t search;          /* MPSM_SEARCH_*: how merge starts in S runs are found */
+  uint32_t log2_run_len;   /* S run length 2^k, 16 <= k <= 24 */
+  uint32_t bucket_target;  /* mean tuples per sort bucket / R partition, 256..4096 */
+  uint32_t join_chunk;     /* S tuples per join work item, >= 1024 */
+  uint32_t want_max;       /* 1: also compute max(R.payload + S.payload) (Section 5.1 query) */
+  uint32_t oversample;     /* sample keys drawn per bucket for the splitters, 1..64 */
+  uint32_t reserved;       /* must be 0 */
+  uint64_t seed;           /* seed of the splitter samples */
+} mpsm_config;
+
+/* Optional host-side statistics (filled by synchronising calls). */
+typedef struct mpsm_stats {
+  uint64_t max_payload_sum;   /* wrapping u64 max of R.payload + S.payload over pairs */
+  uint64_t nonempty;          /* 1 if the join has at least one pair */
+  uint64_t partitions;        /* non-empty R partitions */
+  uint64_t runs;              /* S runs */
+  uint64_t oversize_buckets;  /* buckets sorted by the multi-pass fallback */
+  uint64_t search_probes;     /* key reads made by the start search */
+  uint64_t swapped;           /* 1 if the caller's S was used as the private input */
+  double ms_total;            /* device time of the whole call */
+} mpsm_stats;
+
+/* Fill *cfg with defaults (all automatic, role AUTO, sampled splitters,
+ * index-assisted binary search, seed 0x1207014500000000). */
+void mpsm_config_default(mpsm_config* cfg);
+
+/* Bytes of device workspace mpsm_join needs for these sizes and options.
+ * cfg may be NULL (defaults).  Returns 0 if the sizes are not supported. */
+uint64_t mpsm_workspace_bytes(uint64_t nR, uint64_t nS, const mpsm_config* cfg);
+
+/* The equi-join of R and S (paper Section 3.2):
+ *   d_R, d_S        device arrays of nR / nS tuples, 16-byte aligned; may be
+ *                   NULL when the count is 0.  nR, nS < 2^32.
+ *   d_out_count     device u64: number of pairs (r, s) with r.key == s.key.
+ *   d_out_checksum  device u64: sum over all pairs, mod 2^64, of
+ *                   H = m(m(m(key + 0x9E3779B97F4A7C15) + r.payload) + s.payload),
+ *                   m = the SplitMix64 output function.  Order independent.
+ *   d_pairs         optional device array of pairs_capacity pairs; when
+ *                   non-NULL the first min(count, pairs_capacity) pairs are
+ *                   written in unspecified order.  The count is always
+ *                   exact, so a caller can size the buffer with a first call.
+ *   cfg             optional (NULL = defaults).
+ *   d_workspace     device buffer of at least mpsm_workspace_bytes(nR, nS,
+ *                   cfg) bytes, 256-byte aligned; its contents on entry do
+ *                   not matter and on return hold intermediate results.
+ *   stream          hipStream_t (void* here so the header needs no HIP).
+ *   stats           optional; when non-NULL the call synchronises the
+ *                   stream and fills *stats (and returns MPSM_ECAPACITY if
+ *                   pairs were truncated).
+ * Returns MPSM_OK, or an error before anything is enqueued. */
+mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS,
+                      uint64_t* d_out_count, uint64_t* d_out_checksum, mpsm_pair* d_pairs, uint64_t pairs_capacity,
+                      const mpsm_config* cfg, void* d_workspace, uint64_t workspace_bytes, void* stream,
+                      mpsm_stats* stats);
+
+/* Human-readable name of a status code (static string). */
+const char* mpsm_status_string(mpsm_status s);
+
+/* Where mpsm_join leaves its intermediate results inside the workspace,
+ * for inspection by tests.  All offsets are byte offsets into the workspace;
+ * counts that depend on the data are stored in the workspace at the given
+ * offsets (u32).  Fills *out and returns MPSM_OK, or MPSM_EINVAL. */
+typedef struct mpsm_layout {
+  uint32_t swapped;          /* private input is the caller's S */
+  uint32_t levels;           /* R partitioning levels (1 or 2) */
+  uint64_t run_len;          /* S run length */
+  uint32_t runs;             /* Q = number of S runs */
+  uint32_t s_buckets;        /* buckets per S run */
+  uint32_t r_buckets1;       /* level-1 R buckets */
+  uint32_t r_buckets2;       /* level-2 R buckets per level-1 bucket (1 if one level) */
+  uint32_t s_oversample, r_oversample1, r_oversample2;
+  uint64_t s_level_seed, r_level_seed1, r_level_seed2;  /* segment s samples with splitmix(level_seed, s) */
+  uint64_t off_s_sorted;     /* nS' tuples: the S runs, each sorted */
+  uint64_t off_r_sorted;     /* nR' tuples: R sorted, partitions contiguous */
+  uint64_t off_s_splitters;  /* runs * (s_buckets-1) u64 */
+  uint64_t off_r_splitters1; /* r_buckets1-1 u64 */
+  uint64_t off_r_splitters2; /* r_buckets1 * (r_buckets2-1) u64 */
+  uint64_t off_s_bucket_start; /* runs*s_buckets+1 u32 */
+  uint64_t off_r_bucket_start1;/* r_buckets1+1 u32 */
+  uint64_t off_r_bucket_start; /* final R buckets + 1 u32 (positions in the sorted R) */
+  uint64_t off_partitions;   /* u32 count P of non-empty R partitions */
+  uint64_t off_part_start;   /* P u32 */
+  uint64_t off_part_len;     /* P u32 */
+  uint64_t off_part_key;     /* P u64: first key of each partition */
+  uint64_t off_offsets;      /* (P_max+1) x runs u32: start of partition p in run j */
+  uint32_t p_max;            /* capacity of the partition arrays */
+  uint32_t idx_stride;       /* equi-height index: every idx_stride-th key of a run */
+  uint64_t off_run_index;    /* runs * idx_per_run u64 */
+  uint32_t idx_per_run;
+  uint32_t reserved;
+} mpsm_layout;
+
+mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* cfg, mpsm_layout* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPSM_H */

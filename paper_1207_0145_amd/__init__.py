@@ -1,0 +1,195 @@
+"""P-MPSM equi-join on one AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding of ``libmpsm.so`` (declared in ``include/mpsm.h``).  The
+functions here only marshal arguments; every step of the join runs in the
+library's HIP kernels.  Torch supplies device memory and the stream.
+
+Tensors: ``[n, 2]`` int64 or uint64 on the GPU, column 0 the key, column 1
+the payload (bit patterns are taken as uint64).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpsm.so")
+
+ROLE_AUTO, ROLE_AS_GIVEN, ROLE_SWAP = 0, 1, 2
+SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
+SEARCH_BINARY, SEARCH_INTERP, SEARCH_LEARNED, SEARCH_INDEX = 0, 1, 2, 3
+STATUS = {0: "MPSM_OK", 1: "MPSM_EINVAL", 2: "MPSM_ECAPACITY", 3: "MPSM_ENOMEM", 4: "MPSM_EHIP",
+          5: "MPSM_EUNSUPPORTED"}
+
+EXPORTS = ("mpsm_config_default", "mpsm_workspace_bytes", "mpsm_join", "mpsm_status_string",
+           "mpsm_workspace_layout")
+
+
+class MpsmConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("role", ctypes.c_int32), ("splitter", ctypes.c_int32),
+                ("search", ctypes.c_int32), ("log2_run_len", ctypes.c_uint32), ("bucket_target", ctypes.c_uint32),
+                ("join_chunk", ctypes.c_uint32), ("want_max", ctypes.c_uint32), ("oversample", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+class MpsmStats(ctypes.Structure):
+    _fields_ = [("max_payload_sum", ctypes.c_uint64), ("nonempty", ctypes.c_uint64),
+                ("partitions", ctypes.c_uint64), ("runs", ctypes.c_uint64), ("oversize_buckets", ctypes.c_uint64),
+                ("search_probes", ctypes.c_uint64), ("swapped", ctypes.c_uint64), ("ms_total", ctypes.c_double)]
+
+
+class MpsmLayout(ctypes.Structure):
+    _fields_ = [("swapped", ctypes.c_uint32), ("levels", ctypes.c_uint32), ("run_len", ctypes.c_uint64),
+                ("runs", ctypes.c_uint32), ("s_buckets", ctypes.c_uint32), ("r_buckets1", ctypes.c_uint32),
+                ("r_buckets2", ctypes.c_uint32), ("s_oversample", ctypes.c_uint32),
+                ("r_oversample1", ctypes.c_uint32), ("r_oversample2", ctypes.c_uint32),
+                ("s_level_seed", ctypes.c_uint64), ("r_level_seed1", ctypes.c_uint64),
+                ("r_level_seed2", ctypes.c_uint64), ("off_s_sorted", ctypes.c_uint64),
+                ("off_r_sorted", ctypes.c_uint64), ("off_s_splitters", ctypes.c_uint64),
+                ("off_r_splitters1", ctypes.c_uint64), ("off_r_splitters2", ctypes.c_uint64),
+                ("off_s_bucket_start", ctypes.c_uint64), ("off_r_bucket_start1", ctypes.c_uint64),
+                ("off_r_bucket_start", ctypes.c_uint64), ("off_partitions", ctypes.c_uint64),
+                ("off_part_start", ctypes.c_uint64), ("off_part_len", ctypes.c_uint64),
+                ("off_part_key", ctypes.c_uint64), ("off_offsets", ctypes.c_uint64), ("p_max", ctypes.c_uint32),
+                ("idx_stride", ctypes.c_uint32), ("off_run_index", ctypes.c_uint64),
+                ("idx_per_run", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1207_0145_amd.build` "
+                               "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        p, u64 = ctypes.c_void_p, ctypes.c_uint64
+        L.mpsm_config_default.argtypes = [ctypes.POINTER(MpsmConfig)]
+        L.mpsm_config_default.restype = None
+        L.mpsm_workspace_bytes.argtypes = [u64, u64, ctypes.POINTER(MpsmConfig)]
+        L.mpsm_workspace_bytes.restype = u64
+        L.mpsm_join.argtypes = [p, u64, p, u64, p, p, p, u64, ctypes.POINTER(MpsmConfig), p, u64, p,
+                                ctypes.POINTER(MpsmStats)]
+        L.mpsm_join.restype = ctypes.c_int
+        L.mpsm_status_string.argtypes = [ctypes.c_int]
+        L.mpsm_status_string.restype = ctypes.c_char_p
+        L.mpsm_workspace_layout.argtypes = [u64, u64, ctypes.POINTER(MpsmConfig), ctypes.POINTER(MpsmLayout)]
+        L.mpsm_workspace_layout.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def config(**kw) -> MpsmConfig:
+    """Default configuration with the given fields overridden."""
+    c = MpsmConfig()
+    lib().mpsm_config_default(ctypes.byref(c))
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+def _cfg_ptr(cfg):
+    return None if cfg is None else ctypes.byref(cfg)
+
+
+def workspace_bytes(nR: int, nS: int, cfg: MpsmConfig | None = None) -> int:
+    return int(lib().mpsm_workspace_bytes(nR, nS, _cfg_ptr(cfg)))
+
+
+def layout(nR: int, nS: int, cfg: MpsmConfig | None = None) -> dict:
+    out = MpsmLayout()
+    rc = lib().mpsm_workspace_layout(nR, nS, _cfg_ptr(cfg), ctypes.byref(out))
+    if rc != 0:
+        raise ValueError(f"mpsm_workspace_layout: {STATUS.get(rc, rc)}")
+    return out.as_dict()
+
+
+class MpsmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({lib().mpsm_status_string(code).decode()})")
+
+
+def _check_tuples(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dim() != 2 or t.shape[1] != 2 or t.dtype not in (torch.int64, torch.uint64) or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous [n, 2] int64/uint64 tensor")
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def alloc_workspace(nR: int, nS: int, cfg: MpsmConfig | None = None, device="cuda"):
+    import torch
+    nbytes = workspace_bytes(nR, nS, cfg)
+    if nbytes == 0:
+        raise ValueError("unsupported sizes or configuration")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def join_into(R, S, out, workspace, cfg: MpsmConfig | None = None, stream=None, pairs=None,
+              stats: MpsmStats | None = None) -> int:
+    """Enqueue the join; out is a GPU int64 tensor of >= 2 elements that
+    receives (count, checksum); pairs an optional GPU [cap, 3] tensor.
+    Returns the status code (raises on errors other than ECAPACITY)."""
+    _check_tuples(R, "R")
+    _check_tuples(S, "S")
+    pp = ctypes.c_void_p(pairs.data_ptr()) if pairs is not None and pairs.numel() else None
+    cap = pairs.shape[0] if pp is not None else 0
+    rc = lib().mpsm_join(ctypes.c_void_p(R.data_ptr()), R.shape[0], ctypes.c_void_p(S.data_ptr()), S.shape[0],
+                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(out.data_ptr() + 8), pp, cap,
+                         _cfg_ptr(cfg), ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                         _stream_handle(stream), None if stats is None else ctypes.byref(stats))
+    if rc not in (0, 2):
+        raise MpsmError(rc, "mpsm_join")
+    return rc
+
+
+def join(R, S, cfg: MpsmConfig | None = None, pairs: bool = False, pairs_capacity: int | None = None,
+         workspace=None, with_stats: bool = False):
+    """Synchronous convenience wrapper.  Returns a dict with count,
+    checksum (Python ints, uint64), and optionally pairs (a CPU uint64
+    [count, 3] tensor, sorted lexicographically) and stats."""
+    import torch
+    _check_tuples(R, "R")
+    _check_tuples(S, "S")
+    dev = R.device
+    if workspace is None:
+        workspace = alloc_workspace(R.shape[0], S.shape[0], cfg, dev)
+    out = torch.zeros(2, dtype=torch.int64, device=dev)
+    res = {}
+    pbuf = None
+    if pairs:
+        if pairs_capacity is None:
+            first = join(R, S, cfg, workspace=workspace)
+            pairs_capacity = first["count"]
+        pbuf = torch.zeros((max(pairs_capacity, 1), 3), dtype=torch.int64, device=dev)
+    st = MpsmStats() if (with_stats or pairs) else None
+    rc = join_into(R, S, out, workspace, cfg, pairs=pbuf, stats=st)
+    torch.cuda.synchronize(dev)
+    o = out.cpu().tolist()
+    res["count"] = o[0] & 0xFFFFFFFFFFFFFFFF
+    res["checksum"] = o[1] & 0xFFFFFFFFFFFFFFFF
+    res["status"] = STATUS[rc]
+    if pairs:
+        n = min(res["count"], pairs_capacity)
+        import numpy as np
+        p = pbuf[:n].cpu().numpy().view(np.uint64)
+        order = np.lexsort((p[:, 2], p[:, 1], p[:, 0])) if n else np.zeros(0, np.int64)
+        res["pairs"] = p[order]
+    if st is not None:
+        res["stats"] = {name: getattr(st, name) for name, _ in st._fields_}
+    return res

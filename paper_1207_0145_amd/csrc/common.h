@@ -1,0 +1,134 @@
+// Device-side basics shared by the MPSM kernels: tuple type, SplitMix64,
+// wave64 scans, and the bucket function of sampled splitters.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MPSM_GAMMA 0x9E3779B97F4A7C15ull
+
+struct __align__(16) tup_t {
+  uint64_t key;
+  uint64_t pay;
+};
+
+// SplitMix64 output function (Steele, Lea, Flood 2014).  Also the building
+// block of the per-pair checksum term.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// i-th output (0-based) of SplitMix64 seeded with `seed`.
+__device__ __forceinline__ uint64_t splitmix_at(uint64_t seed, uint64_t i) {
+  return mix64(seed + (i + 1) * MPSM_GAMMA);
+}
+
+// floor(x * n / 2^64): uniform index in [0, n) from a 64-bit draw.
+__device__ __forceinline__ uint64_t draw_below(uint64_t x, uint64_t n) { return __umul64hi(x, n); }
+
+// Checksum of one output pair given the R-side prefix hr = mix(mix(k+g)+rp).
+__device__ __forceinline__ uint64_t r_prefix_hash(uint64_t key, uint64_t rp) {
+  return mix64(mix64(key + MPSM_GAMMA) + rp);
+}
+
+__device__ __forceinline__ tup_t load_tup(const tup_t* p) {
+  ulonglong2 v = *reinterpret_cast<const ulonglong2*>(p);
+  tup_t t; t.key = v.x; t.pay = v.y;
+  return t;
+}
+__device__ __forceinline__ void store_tup(tup_t* p, tup_t t) {
+  ulonglong2 v; v.x = t.key; v.y = t.pay;
+  *reinterpret_cast<ulonglong2*>(p) = v;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Inclusive scan of a u32 across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint64_t o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan of one u32 per thread across a block of NT threads.
+// `wsum` is LDS scratch of NT/64 + 1 words.  Returns the exclusive prefix;
+// *total gets the block total.  Contains two barriers.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  uint32_t inc = wave_incl_scan(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    uint32_t x = lane < NW ? wsum[lane] : 0u;
+    uint32_t xi = wave_incl_scan(x);
+    if (lane < NW) wsum[lane] = xi - x;
+    if (lane == NW - 1) wsum[NW] = xi;
+  }
+  __syncthreads();
+  uint32_t r = wsum[w] + inc - v;
+  *total = wsum[NW];
+  return r;
+}
+
+template <int NT>
+__device__ __forceinline__ uint64_t block_sum64(uint64_t v, uint64_t* wsum) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  __syncthreads();
+  if (lane == 0) wsum[w] = v;
+  __syncthreads();
+  uint64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < NW; i++) s += wsum[i];
+  return s;
+}
+
+template <int NT>
+__device__ __forceinline__ uint64_t block_max64(uint64_t v, uint64_t* wsum) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) { uint64_t o = __shfl_xor(v, d, 64); v = o > v ? o : v; }
+  __syncthreads();
+  if (lane == 0) wsum[w] = v;
+  __syncthreads();
+  uint64_t s = 0;
+#pragma unroll
+  for (int i = 0; i < NW; i++) s = wsum[i] > s ? wsum[i] : s;
+  return s;
+}
+
+// Bucket of `key` under nspl sorted splitters (bucket b = [spl[b-1], spl[b])):
+// the number of splitters <= key, except that a key equal to two or more
+// splitters goes to the otherwise empty bucket just below, so a key that the
+// sample saw at least twice is isolated in a bucket of its own.  The map is
+// non-decreasing in the key.
+__device__ __forceinline__ uint32_t bucket_of(const uint64_t* spl, uint32_t nspl, uint64_t key) {
+  uint32_t lo = 0, hi = nspl;  // first index with spl[i] > key
+  while (lo < hi) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (spl[mid] <= key) lo = mid + 1; else hi = mid;
+  }
+  uint32_t b = lo;
+  if (b >= 2 && spl[b - 1] == key && spl[b - 2] == key) b--;
+  return b;
+}

@@ -1,0 +1,722 @@
+// HIP kernels of the range-partitioned MPSM join on gfx950.
+//
+// Data: tuples of 16 bytes {u64 key, u64 payload} (paper Section 5.1).
+// Positions and counts are u32 (inputs are limited to < 2^32 tuples).
+//
+// Both relations are sorted by the same two-step scheme, per segment:
+//   1. sampled splitters per segment (equi-depth quantiles of a seeded
+//      sample) define NB buckets that are non-decreasing in the key;
+//   2. histogram per tile -> exclusive scan -> scatter with LDS staging
+//      (the paper's histogram / prefix-sum / synchronisation-free scatter,
+//      Section 3.2.1) puts every bucket contiguously;
+//   3. every bucket (<= one LDS tile) is radix-sorted in LDS.
+// For S the segments are the runs S_j (phase 1, Section 3.2); for R one
+// global level (and, for large R, a second level inside each coarse bucket)
+// is the range partitioning of phase 2 and the per-bucket sort is phase 3.
+// Phase 4 searches the first key of every R partition in every S run
+// (Section 3.2.2) and joins each R partition, held in LDS, with its slices.
+#pragma once
+#include "block_sort.h"
+
+// ------------------------------------------------------------------ config
+constexpr int SORT_NT = 512;   // bucket sort: 512 threads x 16 items = 8192 tuples
+constexpr int SORT_IPT = 16;
+constexpr int SORT_RB = 4;
+constexpr int SORT_CAP = SORT_NT * SORT_IPT;
+using BucketSorter = BlockSort<SORT_NT, SORT_IPT, SORT_RB>;
+
+constexpr int SMP_NT = 1024;   // splitter sample sort: up to 16384 keys
+constexpr int SMP_IPT = 16;
+using SampleSorter = BlockSort<SMP_NT, SMP_IPT, 4>;
+constexpr int SMP_CAP = SMP_NT * SMP_IPT;
+
+constexpr int SMP_NT_S = 256;  // small samples: up to 2048 keys
+constexpr int SMP_IPT_S = 8;
+using SampleSorterS = BlockSort<SMP_NT_S, SMP_IPT_S, 4>;
+
+constexpr int HIST_NT = 256;
+constexpr int SCAT_NT = 256;
+constexpr int SCAT_IPT = 8;
+constexpr int SCAT_CH = SCAT_NT * SCAT_IPT;  // tuples staged in LDS per chunk
+constexpr int MAX_NB = 1024;                 // buckets per segment
+
+constexpr int JOIN_NT = 1024;
+constexpr int JOIN_CAP = 8192;               // R partition held in LDS
+constexpr int JOIN_QMAX = 2048;              // S runs
+
+constexpr int SCAN_NT = 256;
+constexpr int SCAN_IPT = 16;
+constexpr int SCAN_BLOCK = SCAN_NT * SCAN_IPT;
+
+// ------------------------------------------------------------ small kernels
+
+struct Result {              // device result block
+  unsigned long long count, checksum, maxsum, nonempty;
+  unsigned long long big_buckets, search_probes, fallbacks, spare;
+};
+
+__global__ void k_init_result(Result* res, uint32_t* zero_words, uint32_t nzero) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    res->count = 0; res->checksum = 0; res->maxsum = 0; res->nonempty = 0;
+    res->big_buckets = 0; res->search_probes = 0; res->fallbacks = 0; res->spare = 0;
+  }
+  for (uint32_t i = t; i < nzero; i += gridDim.x * blockDim.x) zero_words[i] = 0;
+}
+
+__global__ void k_finalize(const Result* res, uint64_t* out_count, uint64_t* out_checksum) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *out_count = res->count;
+    *out_checksum = res->checksum;
+  }
+}
+
+// Runs of equal length L over [0, n): segment tables.
+__global__ void k_seg_uniform(uint32_t n, uint32_t L, uint32_t nseg, uint32_t* seg_start, uint32_t* seg_len) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  const uint64_t a = (uint64_t)s * L;
+  seg_start[s] = (uint32_t)a;
+  seg_len[s] = (uint32_t)((a + L <= n) ? L : (n > a ? n - a : 0));
+}
+
+// Segments = the buckets of a previous pass (bstart has nseg+1 entries).
+__global__ void k_seg_from_buckets(const uint32_t* bstart, uint32_t nseg, uint32_t* seg_start, uint32_t* seg_len) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  seg_start[s] = bstart[s];
+  seg_len[s] = bstart[s + 1] - bstart[s];
+}
+
+// seg_tile0 = prefix of tile counts, seg_cnt0 = prefix of NB * tiles.
+__global__ void __launch_bounds__(1024) k_seg_plan(uint32_t nseg, uint32_t NB, uint32_t TILE, const uint32_t* seg_len,
+                                                   uint32_t* seg_tile0, uint32_t* seg_cnt0) {
+  __shared__ uint32_t wsum[1024 / 64 + 2];
+  uint32_t carry = 0;
+  for (uint32_t b = 0; b < nseg; b += 1024) {
+    const uint32_t s = b + threadIdx.x;
+    const uint32_t nt = s < nseg ? (seg_len[s] + TILE - 1) / TILE : 0;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<1024>(nt, wsum, &tot);
+    if (s < nseg) { seg_tile0[s] = carry + ex; seg_cnt0[s] = (carry + ex) * NB; }
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { seg_tile0[nseg] = carry; seg_cnt0[nseg] = carry * NB; }
+}
+
+// ------------------------------------------------------------------- scan
+
+__global__ void __launch_bounds__(SCAN_NT) k_scan_reduce(const uint32_t* in, uint32_t n, uint32_t* bsum) {
+  __shared__ uint64_t red[SCAN_NT / 64 + 1];
+  const uint32_t base = blockIdx.x * SCAN_BLOCK;
+  uint64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_IPT; k++) {
+    const uint32_t i = base + k * SCAN_NT + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  s = block_sum64<SCAN_NT>(s, red);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = (uint32_t)s;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_bsums(uint32_t* bsum, uint32_t nb) {
+  __shared__ uint32_t wsum[1024 / 64 + 2];
+  uint32_t carry = 0;
+  for (uint32_t b = 0; b < nb; b += 1024) {
+    const uint32_t i = b + threadIdx.x;
+    const uint32_t v = i < nb ? bsum[i] : 0;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<1024>(v, wsum, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of one SCAN_BLOCK-sized block, offset by the block prefix.
+__global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const uint32_t* in, uint32_t* out, uint32_t n,
+                                                        const uint32_t* bsum) {
+  __shared__ uint32_t wsum[SCAN_NT / 64 + 2];
+  const uint32_t base = blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_IPT;
+  uint32_t v[SCAN_IPT];
+  uint32_t run = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_IPT; k++) {
+    const uint32_t i = base + k;
+    v[k] = i < n ? in[i] : 0;
+    const uint32_t x = v[k];
+    v[k] = run;
+    run += x;
+  }
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan<SCAN_NT>(run, wsum, &tot) + bsum[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < SCAN_IPT; k++) {
+    const uint32_t i = base + k;
+    if (i < n) out[i] = v[k] + ex;
+  }
+}
+
+// ------------------------------------------------------- sampled splitters
+
+// One workgroup per segment: draw NB*OS keys at uniform positions of the
+// segment (SplitMix64 stream seg_seed = splitmix_at(level_seed, s)), sort
+// them, and keep every OS-th as the NB-1 splitters of the segment.
+template <int NT, int IPT>
+__global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict__ src, const uint32_t* seg_start,
+                                                         const uint32_t* seg_len, uint32_t NB, uint32_t OS,
+                                                         uint64_t level_seed, uint64_t* spl) {
+  using Sorter = BlockSort<NT, IPT, 4>;
+  __shared__ uint64_t buf[Sorter::BUF_WORDS];
+  __shared__ uint32_t wsum[Sorter::WSUM_WORDS];
+  __shared__ uint64_t red[NT / 64 + 1];
+  const uint32_t s = blockIdx.x, tid = threadIdx.x;
+  const uint32_t len = seg_len[s], start = seg_start[s];
+  const uint32_t M = NB * OS;
+  uint64_t* out = spl + (uint64_t)s * (NB - 1);
+  if (len == 0) {
+    for (uint32_t b = tid; b + 1 < NB; b += NT) out[b] = 0;
+    return;
+  }
+  const uint64_t seed = splitmix_at(level_seed, s);
+  uint64_t key[IPT], dummy[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; k++) {
+    const uint32_t t = k * NT + tid;
+    if (t < M) {
+      const uint64_t pos = start + draw_below(splitmix_at(seed, t), len);
+      key[k] = src[pos].key;
+    } else {
+      key[k] = ~0ull;
+    }
+    dummy[k] = 0;
+  }
+  Sorter::template sort<false>(key, dummy, (int)M, buf, wsum, red);
+#pragma unroll
+  for (int k = 0; k < IPT; k++) {
+    const uint32_t r = k * NT + tid;
+    if (r > 0 && r < M && r % OS == 0) out[r / OS - 1] = key[k];
+  }
+}
+
+// ------------------------------------------------ histogram and scatter
+
+__device__ __forceinline__ uint32_t seg_of_tile(const uint32_t* seg_tile0, uint32_t nseg, uint32_t g) {
+  uint32_t lo = 0, hi = nseg;  // last s with seg_tile0[s] <= g
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (seg_tile0[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Per-tile bucket histogram; cnt layout [segment][bucket][tile].
+__global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict__ src, const uint32_t* seg_start,
+                                                         const uint32_t* seg_len, const uint32_t* seg_tile0,
+                                                         const uint32_t* seg_cnt0, uint32_t nseg,
+                                                         const uint64_t* spl, uint32_t NB, uint32_t TILE,
+                                                         uint32_t* cnt) {
+  __shared__ uint64_t sp[MAX_NB];
+  __shared__ uint32_t h[MAX_NB];
+  const uint32_t g = blockIdx.x;
+  if (g >= seg_tile0[nseg]) return;
+  const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
+  const uint32_t t = g - seg_tile0[s], ntiles = seg_tile0[s + 1] - seg_tile0[s];
+  const uint32_t segend = seg_start[s] + seg_len[s];
+  const uint32_t a = seg_start[s] + t * TILE;
+  const uint32_t b = min(a + TILE, segend);
+  const uint32_t nspl = NB - 1;
+  for (uint32_t i = threadIdx.x; i < nspl; i += HIST_NT) sp[i] = spl[(uint64_t)s * nspl + i];
+  for (uint32_t i = threadIdx.x; i < NB; i += HIST_NT) h[i] = 0;
+  __syncthreads();
+  for (uint32_t i = a + threadIdx.x; i < b; i += HIST_NT) {
+    const uint64_t k = src[i].key;
+    atomicAdd(&h[bucket_of(sp, nspl, k)], 1u);
+  }
+  __syncthreads();
+  uint32_t* c = cnt + seg_cnt0[s] + t;
+  for (uint32_t i = threadIdx.x; i < NB; i += HIST_NT) c[(uint64_t)i * ntiles] = h[i];
+}
+
+// Scatter of every tile to its precomputed sub-ranges (pos = scanned cnt),
+// staged in LDS so that consecutive lanes write consecutive addresses.
+__global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
+                                                            const uint32_t* seg_start, const uint32_t* seg_len,
+                                                            const uint32_t* seg_tile0, const uint32_t* seg_cnt0,
+                                                            uint32_t nseg, const uint64_t* spl, uint32_t NB,
+                                                            uint32_t TILE, const uint32_t* pos) {
+  __shared__ uint64_t sp[MAX_NB];
+  __shared__ uint32_t cursor[MAX_NB], lcnt[MAX_NB], lofs[MAX_NB];
+  __shared__ tup_t stage[SCAT_CH];
+  __shared__ uint16_t sid[SCAT_CH];
+  __shared__ uint32_t wsum[SCAT_NT / 64 + 2];
+  const uint32_t g = blockIdx.x, tid = threadIdx.x;
+  if (g >= seg_tile0[nseg]) return;
+  const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
+  const uint32_t t = g - seg_tile0[s], ntiles = seg_tile0[s + 1] - seg_tile0[s];
+  const uint32_t segend = seg_start[s] + seg_len[s];
+  const uint32_t a = seg_start[s] + t * TILE;
+  const uint32_t b = min(a + TILE, segend);
+  const uint32_t nspl = NB - 1;
+  for (uint32_t i = tid; i < nspl; i += SCAT_NT) sp[i] = spl[(uint64_t)s * nspl + i];
+  const uint32_t* p = pos + seg_cnt0[s] + t;
+  for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] = p[(uint64_t)i * ntiles]; lcnt[i] = 0; }
+  __syncthreads();
+  constexpr int PER = (MAX_NB + SCAT_NT - 1) / SCAT_NT;
+  for (uint32_t c0 = a; c0 < b; c0 += SCAT_CH) {
+    tup_t v[SCAT_IPT];
+    uint32_t bk[SCAT_IPT], lr[SCAT_IPT];
+#pragma unroll
+    for (int k = 0; k < SCAT_IPT; k++) {
+      const uint32_t i = c0 + k * SCAT_NT + tid;
+      if (i < b) {
+        v[k] = load_tup(src + i);
+        bk[k] = bucket_of(sp, nspl, v[k].key);
+        lr[k] = atomicAdd(&lcnt[bk[k]], 1u);
+      }
+    }
+    __syncthreads();
+    // exclusive scan of lcnt over NB buckets (PER consecutive buckets per thread)
+    uint32_t loc[PER], run = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      const uint32_t i = tid * PER + q;
+      loc[q] = run;
+      run += (i < NB) ? lcnt[i] : 0;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<SCAT_NT>(run, wsum, &tot);
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      const uint32_t i = tid * PER + q;
+      if (i < NB) lofs[i] = loc[q] + ex;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SCAT_IPT; k++) {
+      const uint32_t i = c0 + k * SCAT_NT + tid;
+      if (i < b) {
+        const uint32_t q = lofs[bk[k]] + lr[k];
+        stage[q] = v[k];
+        sid[q] = (uint16_t)bk[k];
+      }
+    }
+    __syncthreads();
+    const uint32_t m = min((uint32_t)SCAT_CH, b - c0);
+    for (uint32_t q = tid; q < m; q += SCAT_NT) {
+      const uint32_t bb = sid[q];
+      store_tup(dst + cursor[bb] + (q - lofs[bb]), stage[q]);
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] += lcnt[i]; lcnt[i] = 0; }
+    __syncthreads();
+  }
+}
+
+// Start of every global bucket g = s*NB + b (bstart has nseg*NB + 1 entries).
+__global__ void k_bucket_table(uint32_t nseg, uint32_t NB, const uint32_t* seg_start, const uint32_t* seg_tile0,
+                               const uint32_t* seg_cnt0, const uint32_t* pos, uint32_t n, uint32_t* bstart) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t G = nseg * NB;
+  if (g > G) return;
+  if (g == G) { bstart[G] = n; return; }
+  const uint32_t s = g / NB, b = g % NB;
+  const uint32_t nt = seg_tile0[s + 1] - seg_tile0[s];
+  bstart[g] = nt ? pos[seg_cnt0[s] + b * nt] : seg_start[s];
+}
+
+// ------------------------------------------------------------ bucket sort
+
+struct SortOut {
+  // S runs: every idx_stride-th key of each run (equi-height bounds)
+  uint64_t* run_idx;
+  const uint32_t* run_start;
+  uint32_t idx_stride, idx_per_run, NB;
+  // R buckets: first (smallest) key of every bucket
+  uint64_t* bkey;
+};
+
+__device__ __forceinline__ void emit_sorted(const SortOut& so, uint32_t g, uint32_t a, uint32_t r, uint64_t key) {
+  if (so.run_idx) {
+    const uint32_t s = g / so.NB;
+    const uint32_t rel = a + r - so.run_start[s];
+    if (rel % so.idx_stride == 0) so.run_idx[(uint64_t)s * so.idx_per_run + rel / so.idx_stride] = key;
+  }
+  if (so.bkey && r == 0) so.bkey[g] = key;
+}
+
+// One workgroup per bucket: LDS radix sort of buckets up to SORT_CAP; larger
+// buckets go to the oversize list.
+__global__ void __launch_bounds__(SORT_NT) k_bucket_sort(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
+                                                         const uint32_t* bstart, uint32_t* big_list,
+                                                         unsigned long long* big_count, SortOut so) {
+  __shared__ uint64_t buf[BucketSorter::BUF_WORDS];
+  __shared__ uint32_t wsum[BucketSorter::WSUM_WORDS];
+  __shared__ uint64_t red[SORT_NT / 64 + 1];
+  const uint32_t g = blockIdx.x, tid = threadIdx.x;
+  const uint32_t a = bstart[g], n = bstart[g + 1] - a;
+  if (n == 0) return;
+  if (n > (uint32_t)SORT_CAP) {
+    if (tid == 0) big_list[atomicAdd(big_count, 1ull)] = g;
+    return;
+  }
+  uint64_t key[SORT_IPT], val[SORT_IPT];
+#pragma unroll
+  for (int k = 0; k < SORT_IPT; k++) {
+    const uint32_t i = k * SORT_NT + tid;
+    if (i < n) { const tup_t v = load_tup(src + a + i); key[k] = v.key; val[k] = v.pay; }
+    else { key[k] = ~0ull; val[k] = 0; }
+  }
+  BucketSorter::sort<true>(key, val, (int)n, buf, wsum, red);
+#pragma unroll
+  for (int k = 0; k < SORT_IPT; k++) {
+    const uint32_t r = k * SORT_NT + tid;
+    if (r < n) {
+      tup_t v; v.key = key[k]; v.pay = val[k];
+      store_tup(dst + a + r, v);
+      emit_sorted(so, g, a, r, key[k]);
+    }
+  }
+}
+
+// Oversize buckets: one workgroup sorts a whole bucket through global memory
+// with stable 4-bit LSD passes, ping-ponging between src and dst ranges.
+constexpr int BIG_NT = 256;
+__global__ void __launch_bounds__(BIG_NT) k_big_sort(tup_t* __restrict__ src, tup_t* __restrict__ dst,
+                                                     const uint32_t* bstart, const uint32_t* big_list,
+                                                     const unsigned long long* big_count, SortOut so) {
+  using R1 = BlockSort<BIG_NT, 1, 4>;
+  __shared__ uint64_t buf[R1::BUF_WORDS];
+  __shared__ uint32_t wsum[R1::WSUM_WORDS];
+  __shared__ uint64_t red[BIG_NT / 64 + 1];
+  __shared__ uint32_t cur[16], ccnt[16], cpre[16];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nbig = (uint32_t)*big_count;
+  for (uint32_t e = blockIdx.x; e < nbig; e += gridDim.x) {
+    const uint32_t g = big_list[e];
+    const uint32_t a = bstart[g], n = bstart[g + 1] - a;
+    const uint64_t k0 = src[a].key;
+    uint64_t vary = 0;
+    for (uint32_t i = tid; i < n; i += BIG_NT) vary |= src[a + i].key ^ k0;
+    vary = R1::block_or(vary, red);
+    tup_t* from = src + a;
+    tup_t* to = dst + a;
+    for (int sh = 0; sh < 64; sh += 4) {
+      if (((vary >> sh) & 15ull) == 0) continue;
+      // global digit histogram
+      if (tid < 16) ccnt[tid] = 0;
+      __syncthreads();
+      for (uint32_t i = tid; i < n; i += BIG_NT) atomicAdd(&ccnt[(uint32_t)(from[i].key >> sh) & 15u], 1u);
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t run = 0;
+        for (int d = 0; d < 16; d++) { cur[d] = run; run += ccnt[d]; }
+      }
+      __syncthreads();
+      for (uint32_t c0 = 0; c0 < n; c0 += BIG_NT) {
+        const uint32_t i = c0 + tid;
+        const bool ok = i < n;
+        tup_t v;
+        v.key = ~0ull; v.pay = 0;
+        if (ok) v = from[i];
+        uint32_t d[1], r[1];
+        d[0] = ok ? (uint32_t)(v.key >> sh) & 15u : 15u;
+        if (tid < 16) ccnt[tid] = 0;
+        __syncthreads();
+        if (ok) atomicAdd(&ccnt[d[0]], 1u);
+        R1::rank(d, r, buf, wsum);   // stable rank of this chunk, digit-major
+        if (tid == 0) {
+          uint32_t run = 0;
+          for (int q = 0; q < 16; q++) { cpre[q] = run; run += ccnt[q]; }
+        }
+        __syncthreads();
+        if (ok) to[cur[d[0]] + (r[0] - cpre[d[0]])] = v;
+        __syncthreads();
+        if (tid < 16) cur[tid] += ccnt[tid];
+        __syncthreads();
+      }
+      tup_t* t = from; from = to; to = t;
+    }
+    // the sorted data is in `from`
+    for (uint32_t i = tid; i < n; i += BIG_NT) {
+      const tup_t v = from[i];
+      if (from != dst + a) dst[a + i] = v;
+      emit_sorted(so, g, a, i, v.key);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ partitions
+
+// Compact the non-empty R buckets into partitions p = 0..P-1 (start, length,
+// first key).  Single workgroup.
+__global__ void __launch_bounds__(1024) k_partitions(const uint32_t* bstart, const uint64_t* bkey, uint32_t G,
+                                                     uint32_t* Pcount, uint32_t* pstart, uint32_t* plen,
+                                                     uint64_t* pkey) {
+  __shared__ uint32_t wsum[1024 / 64 + 2];
+  uint32_t carry = 0;
+  for (uint32_t b = 0; b < G; b += 1024) {
+    const uint32_t g = b + threadIdx.x;
+    const uint32_t len = g < G ? bstart[g + 1] - bstart[g] : 0;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<1024>(len ? 1u : 0u, wsum, &tot);
+    if (len) {
+      const uint32_t p = carry + ex;
+      pstart[p] = bstart[g]; plen[p] = len; pkey[p] = bkey[g];
+    }
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *Pcount = carry;
+}
+
+// ------------------------------------------------------------------ search
+
+enum { SEARCH_BINARY = 0, SEARCH_INTERP = 1, SEARCH_LEARNED = 2, SEARCH_INDEX = 3 };
+
+__device__ __forceinline__ uint32_t lb_keys(const tup_t* run, uint32_t lo, uint32_t hi, uint64_t key, uint32_t* probes) {
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    (*probes)++;
+    if (run[mid].key < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Interpolation search (Section 3.2.2, Fig. 7) with the invariant
+// run[lo] < key <= run[hi]; bisection once a probe fails to halve the range
+// twice or the range is at most 16.  Same answer as lower_bound.
+__device__ __forceinline__ uint32_t interp_search(const tup_t* run, uint32_t n, uint64_t key, uint32_t* probes) {
+  if (n == 0) return 0;
+  (*probes)++;
+  if (run[0].key >= key) return 0;
+  (*probes)++;
+  if (run[n - 1].key < key) return n;
+  uint32_t lo = 0, hi = n - 1;
+  int slow = 0;
+  while (hi - lo > 1) {
+    uint32_t m;
+    if (hi - lo <= 16 || slow >= 2) {
+      m = lo + ((hi - lo) >> 1);
+    } else {
+      const uint64_t klo = run[lo].key, khi = run[hi].key;
+      const unsigned __int128 num = (unsigned __int128)(hi - lo) * (key - klo);
+      uint64_t q = (uint64_t)(num / (unsigned __int128)(khi - klo));
+      m = lo + (uint32_t)q;
+      if (m <= lo) m = lo + 1;
+      if (m >= hi) m = hi - 1;
+    }
+    const uint32_t before = hi - lo;
+    (*probes)++;
+    if (run[m].key < key) lo = m; else hi = m;
+    if (2 * (hi - lo) > before) slow++;
+  }
+  return hi;
+}
+
+// o[p][j] = first position of run j whose key >= pkey[p]; o[P][j] = |S_j|.
+__global__ void k_search(const tup_t* __restrict__ U, const uint32_t* run_start, const uint32_t* run_len, uint32_t Q,
+                         const uint64_t* run_idx, uint32_t idx_stride, uint32_t idx_per_run, const uint32_t* Pcount,
+                         const uint64_t* pkey, uint32_t Pmax, uint32_t* o, int mode, Result* res) {
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t P = *Pcount;
+  if (gid >= (uint64_t)(P + 1) * Q) return;
+  const uint32_t p = (uint32_t)(gid / Q), j = (uint32_t)(gid % Q);
+  const uint32_t n = run_len[j];
+  const tup_t* run = U + run_start[j];
+  uint32_t probes = 0, r;
+  if (p == P) {
+    r = n;
+  } else {
+    const uint64_t key = pkey[p];
+    if (mode == SEARCH_BINARY) {
+      r = lb_keys(run, 0, n, key, &probes);
+    } else if (mode == SEARCH_INTERP) {
+      r = interp_search(run, n, key, &probes);
+    } else {
+      // equi-height index: idx[t] = run[t*stride].key
+      const uint64_t* idx = run_idx + (uint64_t)j * idx_per_run;
+      const uint32_t nidx = (n + idx_stride - 1) / idx_stride;
+      uint32_t lo = 0, hi = nidx;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        probes++;
+        if (idx[mid] < key) lo = mid + 1; else hi = mid;
+      }
+      const uint32_t a = lo ? (lo - 1) * idx_stride + 1 : 0;
+      const uint32_t b = lo < nidx ? lo * idx_stride : n;
+      r = lb_keys(run, a, b, key, &probes);
+    }
+  }
+  o[(uint64_t)p * Q + j] = r;
+  if (res) {  // statistics only: one atomic per wave
+    unsigned long long pr = probes;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) pr += __shfl_xor(pr, d, 64);
+    if ((threadIdx.x & 63) == 0 && pr) atomicAdd(&res->search_probes, pr);
+  }
+}
+
+// ------------------------------------------------------------------- join
+
+// Work items: partition p contributes ceil(n_p / JCH) items, n_p = S tuples
+// in its slices (0 when nothing can match).  items has Pmax + 2 entries.
+__global__ void k_join_items(const uint32_t* Pcount, const uint32_t* o, uint32_t Q, uint32_t Pmax, uint32_t JCH,
+                             uint32_t* items) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > Pmax + 1) return;
+  const uint32_t P = *Pcount;
+  uint32_t it = 0;
+  if (p < P) {
+    uint64_t np = 0;
+    const uint32_t* a = o + (uint64_t)p * Q;
+    const uint32_t* b = a + Q;
+    for (uint32_t j = 0; j < Q; j++) np += b[j] - a[j];
+    it = (uint32_t)((np + JCH - 1) / JCH);
+  }
+  items[p] = it;
+}
+
+enum { VAL_HR = 0, VAL_RAW = 1 };
+
+struct JoinArgs {
+  const tup_t* Rs;          // R sorted, partitions contiguous
+  const tup_t* U;           // S runs sorted
+  const uint32_t* run_start;
+  uint32_t Q;
+  const uint32_t* Pcount;
+  const uint32_t* pstart;
+  const uint32_t* plen;
+  const uint32_t* o;
+  const uint32_t* item_pre; // exclusive prefix of items, Pmax + 2 entries
+  uint32_t Pmax;
+  uint32_t JCH;
+  Result* res;
+  // pairs
+  uint64_t* pairs;          // 3 u64 per pair (key, caller-R payload, caller-S payload)
+  uint64_t pairs_cap;
+  uint32_t* item_cnt;       // per-item pair counts (count pass) / offsets (write pass)
+  int swapped;              // internal R is the caller's S
+};
+
+__device__ __forceinline__ uint32_t item_partition(const uint32_t* item_pre, uint32_t np2, uint32_t item) {
+  uint32_t lo = 0, hi = np2 - 1;  // last p with item_pre[p] <= item
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (item_pre[mid] <= item) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Join kernel.  MODE 0: count + checksum (+max); MODE 1: count pairs per item;
+// MODE 2: write pairs.  VM: what the LDS holds next to each R key.
+template <int MODE, int VM>
+__global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
+  __shared__ uint64_t rk[JOIN_CAP];
+  __shared__ uint64_t rv[JOIN_CAP];
+  __shared__ uint32_t cum[JOIN_QMAX + 1];
+  __shared__ uint32_t wsum[JOIN_NT / 64 + 2];
+  __shared__ uint64_t red[JOIN_NT / 64 + 1];
+  __shared__ unsigned long long item_acc;
+  const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  constexpr uint32_t NW = JOIN_NT / 64;
+  const uint32_t Q = A.Q;
+  const uint32_t np2 = A.Pmax + 2;
+  const uint32_t total = A.item_pre[np2 - 1];
+  unsigned long long cnt = 0, sum = 0, mx = 0;
+  bool any = false;
+  for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    const uint32_t p = item_partition(A.item_pre, np2, item);
+    const uint32_t k = item - A.item_pre[p];
+    const uint32_t rs = A.pstart[p], rn = A.plen[p];
+    const uint32_t* oa = A.o + (uint64_t)p * Q;
+    const uint32_t* ob = oa + Q;
+    // exclusive prefix of slice lengths over runs
+    uint32_t carry = 0;
+    for (uint32_t j0 = 0; j0 < Q; j0 += JOIN_NT) {
+      const uint32_t j = j0 + tid;
+      const uint32_t len = j < Q ? ob[j] - oa[j] : 0;
+      uint32_t tot;
+      const uint32_t ex = block_excl_scan<JOIN_NT>(len, wsum, &tot);
+      if (j < Q) cum[j] = carry + ex;
+      carry += tot;
+      __syncthreads();
+    }
+    if (tid == 0) { cum[Q] = carry; item_acc = 0; }
+    const bool in_lds = rn <= (uint32_t)JOIN_CAP;
+    if (in_lds) {
+      for (uint32_t i = tid; i < rn; i += JOIN_NT) {
+        const tup_t t = load_tup(A.Rs + rs + i);
+        rk[i] = t.key;
+        rv[i] = (VM == VAL_HR) ? r_prefix_hash(t.key, t.pay) : t.pay;
+      }
+    }
+    __syncthreads();
+    const uint32_t lo_item = k * A.JCH;
+    const uint32_t hi_item = min(lo_item + A.JCH, cum[Q]);
+    const tup_t* Rg = A.Rs + rs;
+    for (uint32_t j = w; j < Q; j += NW) {
+      const uint32_t c0 = cum[j], c1 = cum[j + 1];
+      const uint32_t x0 = max(c0, lo_item), x1 = min(c1, hi_item);
+      if (x0 >= x1) continue;
+      const tup_t* sb = A.U + A.run_start[j] + oa[j] - c0;
+      for (uint32_t x = x0 + lane; x < x1; x += 64) {
+        const tup_t s = load_tup(sb + x);
+        // first R position with key >= s.key
+        uint32_t lo = 0, hi = rn;
+        if (in_lds) {
+          while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (rk[mid] < s.key) lo = mid + 1; else hi = mid; }
+        } else {
+          while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (Rg[mid].key < s.key) lo = mid + 1; else hi = mid; }
+        }
+        const uint64_t hk = (VM == VAL_RAW) ? mix64(s.key + MPSM_GAMMA) : 0;
+        for (uint32_t q = lo; q < rn; q++) {
+          uint64_t rkey, rval;
+          if (in_lds) { rkey = rk[q]; rval = rv[q]; }
+          else { const tup_t t = load_tup(Rg + q); rkey = t.key; rval = (VM == VAL_HR) ? r_prefix_hash(t.key, t.pay) : t.pay; }
+          if (rkey != s.key) break;
+          // caller orientation: (key, R payload, S payload)
+          uint64_t h, rp_c = 0, sp_c = 0;
+          if (VM == VAL_HR) {
+            h = mix64(rval + s.pay);
+          } else {
+            rp_c = A.swapped ? s.pay : rval;
+            sp_c = A.swapped ? rval : s.pay;
+            h = mix64(mix64(hk + rp_c) + sp_c);
+          }
+          if (MODE == 0) {
+            cnt++; sum += h;
+            if (VM == VAL_RAW) { const uint64_t ps = rp_c + sp_c; mx = (!any || ps > mx) ? ps : mx; any = true; }
+          } else if (MODE == 1) {
+            cnt++;
+          } else {
+            const unsigned long long at = atomicAdd(&item_acc, 1ull) + A.item_cnt[item];
+            if (at < A.pairs_cap) {
+              A.pairs[3 * at] = s.key; A.pairs[3 * at + 1] = rp_c; A.pairs[3 * at + 2] = sp_c;
+            }
+          }
+        }
+      }
+    }
+    if (MODE == 1) {
+      const uint64_t c = block_sum64<JOIN_NT>(cnt, red);
+      if (tid == 0) A.item_cnt[item] = (uint32_t)c;
+      cnt = 0;
+    }
+    __syncthreads();
+  }
+  if (MODE == 0) {
+    const uint64_t c = block_sum64<JOIN_NT>(cnt, red);
+    const uint64_t sm = block_sum64<JOIN_NT>(sum, red);
+    if (tid == 0) {
+      if (c) { atomicAdd(&A.res->count, (unsigned long long)c); atomicAdd(&A.res->checksum, (unsigned long long)sm); }
+    }
+    if (VM == VAL_RAW) {
+      const uint64_t m = block_max64<JOIN_NT>(any ? mx : 0, red);
+      const uint64_t an = block_sum64<JOIN_NT>(any ? 1 : 0, red);
+      if (tid == 0 && an) { atomicMax(&A.res->maxsum, (unsigned long long)m); atomicOr(&A.res->nonempty, 1ull); }
+    }
+  }
+}

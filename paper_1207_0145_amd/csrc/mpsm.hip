@@ -1,0 +1,487 @@
+// Host side of the C ABI: argument checks, the plan (sizes, workspace
+// layout), and the launch sequence of the P-MPSM phases on one stream.
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "kernels.h"
+#include "mpsm.h"
+
+namespace {
+
+constexpr uint32_t HIST_TILE = 1u << 16;      // tuples per histogram / scatter tile
+constexpr uint32_t IDX_STRIDE = 256;          // equi-height index stride of S runs
+constexpr uint64_t DEFAULT_SEED = 0x1207014500000000ull;
+constexpr uint64_t TAG_S = 0x5300000000000001ull, TAG_R1 = 0x5200000000000001ull, TAG_R2 = 0x5200000000000002ull;
+
+uint32_t next_pow2(uint64_t x) {
+  uint32_t p = 1;
+  while (p < x && p < (1u << 30)) p <<= 1;
+  return p;
+}
+uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+struct Plan {
+  int swapped;
+  uint64_t nR, nS;           // internal roles
+  uint32_t L, Q, NBs, OSs;
+  uint32_t levels, NB1, OS1, NB2, OS2;
+  uint32_t Gs, Gr, Pmax;
+  uint32_t idx_per_run;
+  uint32_t JCH;
+  int search, splitter, want_max;
+  uint64_t seed;
+  uint32_t tilesS, tilesR1, tilesR2;       // upper bounds of histogram tiles
+  uint64_t cntS, cntR1, cntR2;             // count-matrix lengths
+  uint64_t item_cap;                       // upper bound of join work items
+  // workspace offsets (bytes)
+  uint64_t T, U, R1, R2;
+  uint64_t cS, cR1, cR2, bsum;
+  uint64_t segS, segR1, segR2;             // 4 arrays each: start, len, tile0, cnt0
+  uint64_t splS, splR1, splR2;
+  uint64_t bstS, bstR1, bstR2;
+  uint64_t bigS, bigR, ctr;
+  uint64_t bkey, Pc, pstart, plen, pkey;
+  uint64_t ridx, o, items, item_pre, item_cnt, res;
+  uint64_t total;
+};
+
+struct Seg {  // device pointers of one segment table
+  uint32_t *start, *len, *tile0, *cnt0;
+};
+
+bool config_valid(const mpsm_config* c) {
+  if (c->struct_size != sizeof(mpsm_config)) return false;
+  if (c->role < 0 || c->role > 2) return false;
+  if (c->splitter != MPSM_SPLIT_SAMPLED) return false;   // learned splitters: not built yet
+  if (c->search < 0 || c->search > 3 || c->search == MPSM_SEARCH_LEARNED) return false;
+  if (c->log2_run_len && (c->log2_run_len < 12 || c->log2_run_len > 24)) return false;
+  if (c->bucket_target && (c->bucket_target < 256 || c->bucket_target > 4096)) return false;
+  if (c->join_chunk && c->join_chunk < 1024) return false;
+  if (c->oversample > 64 || c->reserved) return false;
+  return true;
+}
+
+bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
+  memset(P, 0, sizeof(*P));
+  if (nR_c >= (1ull << 32) || nS_c >= (1ull << 32)) return false;
+  P->swapped = cfg->role == MPSM_ROLE_SWAP || (cfg->role == MPSM_ROLE_AUTO && nS_c < nR_c);
+  P->nR = P->swapped ? nS_c : nR_c;
+  P->nS = P->swapped ? nR_c : nS_c;
+  P->search = cfg->search;
+  P->splitter = cfg->splitter;
+  P->want_max = cfg->want_max ? 1 : 0;
+  P->seed = cfg->seed;
+  const uint32_t BT = cfg->bucket_target ? cfg->bucket_target : 4096u;
+  // S runs
+  uint64_t L;
+  if (cfg->log2_run_len) L = 1ull << cfg->log2_run_len;
+  else {
+    L = next_pow2(cdiv(P->nS ? P->nS : 1, 128));
+    if (L < (1u << 16)) L = 1u << 16;
+    if (L > (1u << 22)) L = 1u << 22;
+  }
+  P->L = (uint32_t)L;
+  P->Q = P->nS ? (uint32_t)cdiv(P->nS, L) : 1;
+  if (P->Q > (uint32_t)JOIN_QMAX) return false;
+  P->NBs = next_pow2(cdiv(L, BT));
+  if (P->NBs > (uint32_t)MAX_NB) P->NBs = MAX_NB;
+  const uint32_t OSreq = cfg->oversample ? cfg->oversample : 32u;
+  auto os_for = [&](uint32_t NB) { return NB > 1 ? (SMP_CAP / NB < OSreq ? SMP_CAP / NB : OSreq) : 1u; };
+  P->OSs = os_for(P->NBs);
+  // R partitioning levels
+  const uint64_t F = cdiv(P->nR ? P->nR : 1, BT);
+  if (F <= (uint64_t)MAX_NB) {
+    P->levels = 1;
+    P->NB1 = next_pow2(F);
+    P->OS1 = os_for(P->NB1);
+    P->NB2 = 1;
+    P->OS2 = 1;
+  } else {
+    P->levels = 2;
+    P->NB1 = MAX_NB;
+    P->OS1 = cfg->oversample ? os_for(P->NB1) : 16u;
+    P->NB2 = next_pow2(cdiv(F, MAX_NB));
+    if (P->NB2 > (uint32_t)MAX_NB) P->NB2 = MAX_NB;
+    P->OS2 = os_for(P->NB2);
+  }
+  P->Gs = P->Q * P->NBs;
+  P->Gr = P->NB1 * P->NB2;
+  P->Pmax = P->Gr;
+  P->idx_per_run = (uint32_t)cdiv(L, IDX_STRIDE);
+  P->JCH = cfg->join_chunk ? cfg->join_chunk : 32768u;
+  P->tilesS = (uint32_t)(P->nS / HIST_TILE + P->Q);
+  P->tilesR1 = (uint32_t)(P->nR / HIST_TILE + 1);
+  P->tilesR2 = (uint32_t)(P->nR / HIST_TILE + P->NB1);
+  P->cntS = (uint64_t)P->tilesS * P->NBs;
+  P->cntR1 = (uint64_t)P->tilesR1 * P->NB1;
+  P->cntR2 = P->levels == 2 ? (uint64_t)P->tilesR2 * P->NB2 : 1;
+  P->item_cap = P->nS / P->JCH + P->Pmax + 2;
+
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) { uint64_t o = off; off += (bytes + 255) & ~255ull; return o; };
+  const uint64_t ts = sizeof(tup_t);
+  P->T = take(P->nS * ts);
+  P->U = take(P->nS * ts);
+  P->R1 = take(P->nR * ts);
+  P->R2 = take(P->nR * ts);
+  P->cS = take(P->cntS * 4);
+  P->cR1 = take(P->cntR1 * 4);
+  P->cR2 = take(P->cntR2 * 4);
+  uint64_t maxscan = P->cntS;
+  if (P->cntR1 > maxscan) maxscan = P->cntR1;
+  if (P->cntR2 > maxscan) maxscan = P->cntR2;
+  if (P->item_cap > maxscan) maxscan = P->item_cap;
+  P->bsum = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);
+  P->segS = take(4ull * (P->Q + 1) * 4);
+  P->segR1 = take(4ull * 2 * 4);
+  P->segR2 = take(4ull * (P->NB1 + 1) * 4);
+  P->splS = take((uint64_t)P->Q * P->NBs * 8);
+  P->splR1 = take((uint64_t)P->NB1 * 8);
+  P->splR2 = take((uint64_t)P->NB1 * P->NB2 * 8);
+  P->bstS = take(((uint64_t)P->Gs + 1) * 4);
+  P->bstR1 = take(((uint64_t)P->NB1 + 1) * 4);
+  P->bstR2 = take(((uint64_t)P->Gr + 1) * 4);
+  P->bigS = take((uint64_t)P->Gs * 4);
+  P->bigR = take((uint64_t)P->Gr * 4);
+  P->ctr = take(8 * 8);
+  P->bkey = take((uint64_t)P->Gr * 8);
+  P->Pc = take(4);
+  P->pstart = take((uint64_t)P->Pmax * 4);
+  P->plen = take((uint64_t)P->Pmax * 4);
+  P->pkey = take((uint64_t)P->Pmax * 8);
+  P->ridx = take((uint64_t)P->Q * P->idx_per_run * 8);
+  P->o = take(((uint64_t)P->Pmax + 1) * P->Q * 4);
+  P->items = take(((uint64_t)P->Pmax + 2) * 4);
+  P->item_pre = take(((uint64_t)P->Pmax + 2) * 4);
+  P->item_cnt = take((P->item_cap + 1) * 4);
+  P->res = take(sizeof(Result));
+  P->total = off;
+  return true;
+}
+
+Seg seg_at(char* ws, uint64_t off, uint32_t nseg) {
+  uint32_t* b = reinterpret_cast<uint32_t*>(ws + off);
+  Seg s;
+  s.start = b;
+  s.len = b + (nseg + 1);
+  s.tile0 = b + 2 * (nseg + 1);
+  s.cnt0 = b + 3 * (nseg + 1);
+  return s;
+}
+
+#define HIP_TRY(x)                        \
+  do {                                    \
+    if ((x) != hipSuccess) return MPSM_EHIP; \
+  } while (0)
+#define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+
+mpsm_status scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* bsum, hipStream_t st) {
+  if (n == 0) return MPSM_OK;
+  const uint32_t nb = (uint32_t)cdiv(n, SCAN_BLOCK);
+  k_scan_reduce<<<nb, SCAN_NT, 0, st>>>(in, (uint32_t)n, bsum);
+  LAUNCH_CHECK();
+  k_scan_bsums<<<1, 1024, 0, st>>>(bsum, nb);
+  LAUNCH_CHECK();
+  k_scan_apply<<<nb, SCAN_NT, 0, st>>>(in, out, (uint32_t)n, bsum);
+  LAUNCH_CHECK();
+  return MPSM_OK;
+}
+
+// One bucket pass over segments: splitters, histogram, scan, scatter, table.
+mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, Seg seg, uint32_t nseg, uint32_t NB, uint32_t OS,
+                        uint64_t level_seed, uint64_t* spl, uint32_t* cnt, uint64_t ncnt, uint32_t* bsum,
+                        uint32_t max_tiles, uint32_t* bstart, hipStream_t st) {
+  k_seg_plan<<<1, 1024, 0, st>>>(nseg, NB, HIST_TILE, seg.len, seg.tile0, seg.cnt0);
+  LAUNCH_CHECK();
+  if (NB > 1) {
+    if (NB * OS <= (uint32_t)(SMP_NT_S * SMP_IPT_S))
+      k_sample_splitters<SMP_NT_S, SMP_IPT_S><<<nseg, SMP_NT_S, 0, st>>>(src, seg.start, seg.len, NB, OS, level_seed, spl);
+    else
+      k_sample_splitters<SMP_NT, SMP_IPT><<<nseg, SMP_NT, 0, st>>>(src, seg.start, seg.len, NB, OS, level_seed, spl);
+    LAUNCH_CHECK();
+  }
+  if (max_tiles) {
+    k_bucket_hist<<<max_tiles, HIST_NT, 0, st>>>(src, seg.start, seg.len, seg.tile0, seg.cnt0, nseg, spl, NB,
+                                                 HIST_TILE, cnt);
+    LAUNCH_CHECK();
+    mpsm_status rc = scan_u32(cnt, cnt, ncnt, bsum, st);
+    if (rc != MPSM_OK) return rc;
+    k_bucket_scatter<<<max_tiles, SCAT_NT, 0, st>>>(src, dst, seg.start, seg.len, seg.tile0, seg.cnt0, nseg, spl, NB,
+                                                    HIST_TILE, cnt);
+    LAUNCH_CHECK();
+  }
+  const uint32_t G = nseg * NB;
+  k_bucket_table<<<(uint32_t)cdiv(G + 1, 256), 256, 0, st>>>(nseg, NB, seg.start, seg.tile0, seg.cnt0, cnt, n,
+                                                             bstart);
+  LAUNCH_CHECK();
+  return MPSM_OK;
+}
+
+int g_num_cus = 0;
+
+}  // namespace
+
+extern "C" {
+
+void mpsm_config_default(mpsm_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->struct_size = sizeof(mpsm_config);
+  cfg->role = MPSM_ROLE_AUTO;
+  cfg->splitter = MPSM_SPLIT_SAMPLED;
+  cfg->search = MPSM_SEARCH_INDEX;
+  cfg->seed = DEFAULT_SEED;
+}
+
+const char* mpsm_status_string(mpsm_status s) {
+  switch (s) {
+    case MPSM_OK: return "ok";
+    case MPSM_EINVAL: return "invalid argument";
+    case MPSM_ECAPACITY: return "pair buffer too small";
+    case MPSM_ENOMEM: return "workspace too small";
+    case MPSM_EHIP: return "HIP runtime error";
+    case MPSM_EUNSUPPORTED: return "unsupported option";
+  }
+  return "unknown status";
+}
+
+uint64_t mpsm_workspace_bytes(uint64_t nR, uint64_t nS, const mpsm_config* cfg) {
+  mpsm_config def;
+  if (!cfg) { mpsm_config_default(&def); cfg = &def; }
+  if (!config_valid(cfg)) return 0;
+  Plan P;
+  if (!make_plan(nR, nS, cfg, &P)) return 0;
+  return P.total;
+}
+
+mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* cfg, mpsm_layout* out) {
+  mpsm_config def;
+  if (!cfg) { mpsm_config_default(&def); cfg = &def; }
+  if (!out || !config_valid(cfg)) return MPSM_EINVAL;
+  Plan P;
+  if (!make_plan(nR, nS, cfg, &P)) return MPSM_EINVAL;
+  memset(out, 0, sizeof(*out));
+  out->swapped = (uint32_t)P.swapped;
+  out->levels = P.levels;
+  out->run_len = P.L;
+  out->runs = P.Q;
+  out->s_buckets = P.NBs;
+  out->r_buckets1 = P.NB1;
+  out->r_buckets2 = P.NB2;
+  out->s_oversample = P.OSs;
+  out->r_oversample1 = P.OS1;
+  out->r_oversample2 = P.OS2;
+  out->s_level_seed = P.seed ^ TAG_S;
+  out->r_level_seed1 = P.seed ^ TAG_R1;
+  out->r_level_seed2 = P.seed ^ TAG_R2;
+  out->off_s_sorted = P.U;
+  out->off_r_sorted = P.levels == 2 ? P.R1 : P.R2;
+  out->off_s_splitters = P.splS;
+  out->off_r_splitters1 = P.splR1;
+  out->off_r_splitters2 = P.splR2;
+  out->off_s_bucket_start = P.bstS;
+  out->off_r_bucket_start1 = P.bstR1;
+  out->off_r_bucket_start = P.levels == 2 ? P.bstR2 : P.bstR1;
+  out->off_partitions = P.Pc;
+  out->off_part_start = P.pstart;
+  out->off_part_len = P.plen;
+  out->off_part_key = P.pkey;
+  out->off_offsets = P.o;
+  out->p_max = P.Pmax;
+  out->idx_stride = IDX_STRIDE;
+  out->off_run_index = P.ridx;
+  out->idx_per_run = P.idx_per_run;
+  return MPSM_OK;
+}
+
+mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS, uint64_t* d_out_count,
+                      uint64_t* d_out_checksum, mpsm_pair* d_pairs, uint64_t pairs_capacity, const mpsm_config* cfg,
+                      void* d_workspace, uint64_t workspace_bytes, void* stream, mpsm_stats* stats) {
+  mpsm_config def;
+  if (!cfg) { mpsm_config_default(&def); cfg = &def; }
+  if (!config_valid(cfg)) return MPSM_EINVAL;
+  if ((nR && !d_R) || (nS && !d_S) || !d_out_count || !d_out_checksum || !d_workspace) return MPSM_EINVAL;
+  if (((uintptr_t)d_R & 15) || ((uintptr_t)d_S & 15) || ((uintptr_t)d_workspace & 255) ||
+      ((uintptr_t)d_out_count & 7) || ((uintptr_t)d_out_checksum & 7) || ((uintptr_t)d_pairs & 7))
+    return MPSM_EINVAL;
+  if (d_pairs && pairs_capacity == 0) d_pairs = nullptr;
+  Plan P;
+  if (!make_plan(nR, nS, cfg, &P)) return MPSM_EINVAL;
+  if (workspace_bytes < P.total) return MPSM_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  if (!g_num_cus) {
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    g_num_cus = ncu > 0 ? ncu : 256;
+  }
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (stats) {
+    HIP_TRY(hipEventCreate(&ev0));
+    HIP_TRY(hipEventCreate(&ev1));
+    HIP_TRY(hipEventRecord(ev0, st));
+  }
+  char* ws = static_cast<char*>(d_workspace);
+  const tup_t* Rin = reinterpret_cast<const tup_t*>(P.swapped ? d_S : d_R);
+  const tup_t* Sin = reinterpret_cast<const tup_t*>(P.swapped ? d_R : d_S);
+  tup_t* T = reinterpret_cast<tup_t*>(ws + P.T);
+  tup_t* U = reinterpret_cast<tup_t*>(ws + P.U);
+  tup_t* R1 = reinterpret_cast<tup_t*>(ws + P.R1);
+  tup_t* R2 = reinterpret_cast<tup_t*>(ws + P.R2);
+  uint32_t* bsum = reinterpret_cast<uint32_t*>(ws + P.bsum);
+  unsigned long long* ctr = reinterpret_cast<unsigned long long*>(ws + P.ctr);
+  Result* res = reinterpret_cast<Result*>(ws + P.res);
+
+  k_init_result<<<1, 64, 0, st>>>(res, reinterpret_cast<uint32_t*>(ctr), 16);
+  LAUNCH_CHECK();
+  if (P.nR == 0 || P.nS == 0) {
+    k_finalize<<<1, 64, 0, st>>>(res, d_out_count, d_out_checksum);
+    LAUNCH_CHECK();
+  } else {
+    mpsm_status rc;
+    // ---- phase 1: sort S into Q runs of L tuples
+    Seg sS = seg_at(ws, P.segS, P.Q);
+    k_seg_uniform<<<(uint32_t)cdiv(P.Q, 256), 256, 0, st>>>((uint32_t)P.nS, P.L, P.Q, sS.start, sS.len);
+    LAUNCH_CHECK();
+    uint32_t* bstS = reinterpret_cast<uint32_t*>(ws + P.bstS);
+    rc = bucket_pass(Sin, T, (uint32_t)P.nS, sS, P.Q, P.NBs, P.OSs, P.seed ^ TAG_S,
+                     reinterpret_cast<uint64_t*>(ws + P.splS), reinterpret_cast<uint32_t*>(ws + P.cS), P.cntS, bsum,
+                     P.tilesS, bstS, st);
+    if (rc != MPSM_OK) return rc;
+    SortOut soS;
+    soS.run_idx = reinterpret_cast<uint64_t*>(ws + P.ridx);
+    soS.run_start = sS.start;
+    soS.idx_stride = IDX_STRIDE;
+    soS.idx_per_run = P.idx_per_run;
+    soS.NB = P.NBs;
+    soS.bkey = nullptr;
+    k_bucket_sort<<<P.Gs, SORT_NT, 0, st>>>(T, U, bstS, reinterpret_cast<uint32_t*>(ws + P.bigS), ctr + 0, soS);
+    LAUNCH_CHECK();
+    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, bstS, reinterpret_cast<uint32_t*>(ws + P.bigS), ctr + 0, soS);
+    LAUNCH_CHECK();
+
+    // ---- phase 2: range-partition R (one or two levels); phase 3: sort partitions
+    Seg sR1 = seg_at(ws, P.segR1, 1);
+    k_seg_uniform<<<1, 64, 0, st>>>((uint32_t)P.nR, (uint32_t)P.nR, 1, sR1.start, sR1.len);
+    LAUNCH_CHECK();
+    uint32_t* bstR1 = reinterpret_cast<uint32_t*>(ws + P.bstR1);
+    rc = bucket_pass(Rin, R1, (uint32_t)P.nR, sR1, 1, P.NB1, P.OS1, P.seed ^ TAG_R1,
+                     reinterpret_cast<uint64_t*>(ws + P.splR1), reinterpret_cast<uint32_t*>(ws + P.cR1), P.cntR1,
+                     bsum, P.tilesR1, bstR1, st);
+    if (rc != MPSM_OK) return rc;
+    SortOut soR;
+    soR.run_idx = nullptr;
+    soR.run_start = nullptr;
+    soR.idx_stride = 1;
+    soR.idx_per_run = 0;
+    soR.NB = 1;
+    soR.bkey = reinterpret_cast<uint64_t*>(ws + P.bkey);
+    const tup_t* Rsorted;
+    const uint32_t* bstR;
+    if (P.levels == 2) {
+      Seg sR2 = seg_at(ws, P.segR2, P.NB1);
+      k_seg_from_buckets<<<(uint32_t)cdiv(P.NB1, 256), 256, 0, st>>>(bstR1, P.NB1, sR2.start, sR2.len);
+      LAUNCH_CHECK();
+      uint32_t* bstR2 = reinterpret_cast<uint32_t*>(ws + P.bstR2);
+      rc = bucket_pass(R1, R2, (uint32_t)P.nR, sR2, P.NB1, P.NB2, P.OS2, P.seed ^ TAG_R2,
+                       reinterpret_cast<uint64_t*>(ws + P.splR2), reinterpret_cast<uint32_t*>(ws + P.cR2), P.cntR2,
+                       bsum, P.tilesR2, bstR2, st);
+      if (rc != MPSM_OK) return rc;
+      k_bucket_sort<<<P.Gr, SORT_NT, 0, st>>>(R2, R1, bstR2, reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
+      LAUNCH_CHECK();
+      k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(R2, R1, bstR2, reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
+      LAUNCH_CHECK();
+      Rsorted = R1;
+      bstR = bstR2;
+    } else {
+      k_bucket_sort<<<P.Gr, SORT_NT, 0, st>>>(R1, R2, bstR1, reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
+      LAUNCH_CHECK();
+      k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(R1, R2, bstR1, reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
+      LAUNCH_CHECK();
+      Rsorted = R2;
+      bstR = bstR1;
+    }
+    uint32_t* Pc = reinterpret_cast<uint32_t*>(ws + P.Pc);
+    uint32_t* pstart = reinterpret_cast<uint32_t*>(ws + P.pstart);
+    uint32_t* plen = reinterpret_cast<uint32_t*>(ws + P.plen);
+    uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + P.pkey);
+    k_partitions<<<1, 1024, 0, st>>>(bstR, soR.bkey, P.Gr, Pc, pstart, plen, pkey);
+    LAUNCH_CHECK();
+
+    // ---- phase 4: merge starts of every partition in every run, then the join
+    uint32_t* o = reinterpret_cast<uint32_t*>(ws + P.o);
+    const uint64_t nsearch = ((uint64_t)P.Pmax + 1) * P.Q;
+    k_search<<<(uint32_t)cdiv(nsearch, 256), 256, 0, st>>>(U, sS.start, sS.len, P.Q,
+                                                          reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
+                                                          P.idx_per_run, Pc, pkey, P.Pmax, o, P.search,
+                                                          stats ? res : nullptr);
+    LAUNCH_CHECK();
+    uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
+    uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
+    k_join_items<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, o, P.Q, P.Pmax, P.JCH, items);
+    LAUNCH_CHECK();
+    rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
+    if (rc != MPSM_OK) return rc;
+
+    JoinArgs A;
+    A.Rs = Rsorted;
+    A.U = U;
+    A.run_start = sS.start;
+    A.Q = P.Q;
+    A.Pcount = Pc;
+    A.pstart = pstart;
+    A.plen = plen;
+    A.o = o;
+    A.item_pre = item_pre;
+    A.Pmax = P.Pmax;
+    A.JCH = P.JCH;
+    A.res = res;
+    A.pairs = reinterpret_cast<uint64_t*>(d_pairs);
+    A.pairs_cap = d_pairs ? pairs_capacity : 0;
+    A.item_cnt = reinterpret_cast<uint32_t*>(ws + P.item_cnt);
+    A.swapped = P.swapped;
+    const bool raw = P.swapped || P.want_max || d_pairs;
+    if (raw) k_join<0, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+    else k_join<0, VAL_HR><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+    LAUNCH_CHECK();
+    if (d_pairs) {
+      k_join<1, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+      LAUNCH_CHECK();
+      rc = scan_u32(A.item_cnt, A.item_cnt, P.item_cap, bsum, st);
+      if (rc != MPSM_OK) return rc;
+      k_join<2, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+      LAUNCH_CHECK();
+    }
+    k_finalize<<<1, 64, 0, st>>>(res, d_out_count, d_out_checksum);
+    LAUNCH_CHECK();
+  }
+  if (stats) {
+    HIP_TRY(hipEventRecord(ev1, st));
+    HIP_TRY(hipEventSynchronize(ev1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    Result r;
+    HIP_TRY(hipMemcpy(&r, res, sizeof(r), hipMemcpyDeviceToHost));
+    unsigned long long c[2];
+    HIP_TRY(hipMemcpy(c, ctr, sizeof(c), hipMemcpyDeviceToHost));
+    uint32_t pc = 0;
+    if (P.nR && P.nS) HIP_TRY(hipMemcpy(&pc, ws + P.Pc, 4, hipMemcpyDeviceToHost));
+    memset(stats, 0, sizeof(*stats));
+    stats->max_payload_sum = r.maxsum;
+    stats->nonempty = r.count > 0 ? 1 : 0;
+    stats->partitions = pc;
+    stats->runs = P.Q;
+    stats->oversize_buckets = c[0] + c[1];
+    stats->search_probes = r.search_probes;
+    stats->swapped = (uint64_t)P.swapped;
+    stats->ms_total = ms;
+    if (d_pairs && r.count > pairs_capacity) return MPSM_ECAPACITY;
+  }
+  return MPSM_OK;
+}
+
+}  // extern "C"

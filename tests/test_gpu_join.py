@@ -1,0 +1,289 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Join results (count, checksum, sorted pair lists) must be bit-identical.
+Intermediate results are compared where they are unique: sorted key
+sequences, the multiset of tuples per run/bucket, splitters (same seeded
+sample on both sides), bucket boundaries, and merge-start offsets (unique
+lower bounds)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1207_0145_amd as mpsm
+import workloads
+
+pytestmark = pytest.mark.gpu
+U64 = (1 << 64) - 1
+
+
+def _dev(a):
+    a = np.ascontiguousarray(a, dtype=np.uint64).reshape(-1, 2)
+    return torch.from_numpy(a.view(np.int64)).to("cuda")
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def gpu_join(R, S, cfg=None, pairs=False, workspace=None, stats=False):
+    _say(f"mpsm_join nR={len(R)} nS={len(S)} pairs={pairs} "
+         f"cfg={None if cfg is None else {k: getattr(cfg, k) for k, _ in cfg._fields_}}")
+    return mpsm.join(_dev(R), _dev(S), cfg=cfg, pairs=pairs, workspace=workspace, with_stats=stats)
+
+
+def check(R, S, cfg=None, pairs=False):
+    want = oracle.join(R, S)
+    got = gpu_join(R, S, cfg, pairs=pairs)
+    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+    if pairs:
+        wp = oracle.join(R, S, pairs=True, cap=max(1, want.count)).pairs
+        assert np.array_equal(got["pairs"], wp)
+    return got
+
+
+def rel(rng, n, domain):
+    k = (rng.integers(0, domain, size=n, dtype=np.uint64) if domain
+         else rng.integers(0, U64, size=n, dtype=np.uint64, endpoint=True))
+    p = rng.integers(0, U64, size=n, dtype=np.uint64, endpoint=True)
+    return np.stack([k, p], axis=1)
+
+
+# ------------------------------------------------------------- small cases
+
+def test_worked_example():
+    R = np.array([(1, 10), (2, 20), (2, 21), (5, 50)], np.uint64)
+    S = np.array([(2, 200), (2, 201), (3, 300), (5, 500), (7, 1)], np.uint64)
+    got = check(R, S, pairs=True)
+    assert got["count"] == 5 and got["checksum"] == 0x680EDA8D7152D3C9
+
+
+@pytest.mark.parametrize("nR,nS", [(0, 0), (0, 7), (7, 0), (1, 1)])
+def test_empty_and_single(nR, nS):
+    rng = np.random.default_rng(nR + 10 * nS)
+    check(rel(rng, nR, 3), rel(rng, nS, 3))
+
+
+@pytest.mark.parametrize("nR,nS,domain", [(100, 300, 50), (1000, 3000, 100), (3000, 1000, 100), (5000, 20000, 0),
+                                          (777, 7777, 7), (4097, 8193, 4096)])
+def test_random_small_with_pairs(nR, nS, domain):
+    rng = np.random.default_rng(nR * 31 + nS + domain)
+    check(rel(rng, nR, domain), rel(rng, nS, domain), pairs=True)
+
+
+def test_extreme_keys():
+    rng = np.random.default_rng(8)
+    keys = np.array([0, 1, U64 - 1, U64, 1 << 63], np.uint64)
+    R = np.stack([keys[rng.integers(0, 5, 2000)], rng.integers(0, U64, 2000, dtype=np.uint64)], 1)
+    S = np.stack([keys[rng.integers(0, 5, 3000)], rng.integers(0, U64, 3000, dtype=np.uint64)], 1)
+    check(R, S)
+    check(R[:40], S[:60], pairs=True)
+
+
+def test_all_equal_keys():
+    rng = np.random.default_rng(9)
+    R = rel(rng, 300, 1)
+    S = rel(rng, 1000, 1)
+    check(R, S, pairs=True)
+    R = rel(rng, 20000, 1)
+    S = rel(rng, 30000, 1)
+    check(R, S)                        # 6e8 pairs, count and checksum
+
+
+def test_disjoint_ranges():
+    rng = np.random.default_rng(10)
+    R = rel(rng, 5000, 1000)
+    S = rel(rng, 9000, 1000)
+    S[:, 0] += np.uint64(5000)
+    got = check(R, S)
+    assert got["count"] == 0 and got["checksum"] == 0
+
+
+def test_ragged_sizes():
+    rng = np.random.default_rng(11)
+    check(rel(rng, 70001, 1 << 20), rel(rng, 300007, 1 << 20))
+
+
+CONFIGS = [
+    dict(role=mpsm.ROLE_AS_GIVEN), dict(role=mpsm.ROLE_SWAP), dict(search=mpsm.SEARCH_BINARY),
+    dict(search=mpsm.SEARCH_INTERP), dict(log2_run_len=12), dict(log2_run_len=16, bucket_target=256),
+    dict(bucket_target=1024, join_chunk=1024), dict(seed=12345), dict(want_max=1),
+]
+
+
+@pytest.mark.parametrize("kw", CONFIGS, ids=[str(c) for c in CONFIGS])
+def test_result_independent_of_config(kw):
+    rng = np.random.default_rng(12)
+    R = rel(rng, 60000, 200000)
+    S = rel(rng, 250000, 200000)
+    check(R, S, cfg=mpsm.config(**kw))
+
+
+def test_want_max_matches_query_aggregate():
+    rng = np.random.default_rng(13)
+    R = rel(rng, 20000, 30000)
+    S = rel(rng, 50000, 30000)
+    want = oracle.join(R, S)
+    got = gpu_join(R, S, mpsm.config(want_max=1), stats=True)
+    assert got["count"] == want.count and got["stats"]["max_payload_sum"] == want.maxsum
+    assert got["stats"]["nonempty"] == int(want.nonempty)
+
+
+def test_oversize_bucket_fallback():
+    # one sample key per bucket makes some buckets far larger than an LDS tile
+    rng = np.random.default_rng(14)
+    R = rel(rng, 200000, 0)
+    S = rel(rng, 400000, 0)
+    S[: len(S) // 2, 0] = R[rng.integers(0, len(R), len(S) // 2), 0]
+    cfg = mpsm.config(oversample=1, bucket_target=4096)
+    want = oracle.join(R, S)
+    got = gpu_join(R, S, cfg, stats=True)
+    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+    assert got["stats"]["oversize_buckets"] > 0
+
+
+def test_few_distinct_keys_oversize_equal_buckets():
+    rng = np.random.default_rng(15)
+    keys = np.array([3, 1 << 40, U64], np.uint64)
+    R = np.stack([keys[rng.integers(0, 3, 30000)], rng.integers(0, U64, 30000, dtype=np.uint64)], 1)
+    S = np.stack([keys[rng.integers(0, 3, 40000)], rng.integers(0, U64, 40000, dtype=np.uint64)], 1)
+    check(R, S)
+
+
+# ------------------------------------------------------- named workloads
+
+def test_fk_small_full_size():
+    w = workloads.make("fk_small")                # |R| = 2^20, |S| = 2^22
+    fk = oracle.fk_closed_form(w.R, w.S, w.partner)
+    got = check(w.R, w.S)
+    assert got["count"] == len(w.S) and got["checksum"] == fk.checksum
+
+
+def test_skewed_reduced():
+    w = workloads.make("skewed", scale_shift=6)   # |R| = 2^20, |S| = 2^22, Zipf(1)
+    fk = oracle.fk_closed_form(w.R, w.S, w.partner)
+    got = gpu_join(w.R, w.S)
+    assert (got["count"], got["checksum"]) == (fk.count, fk.checksum)
+
+
+def test_lognormal_reduced():
+    w = workloads.make("lognormal", scale_shift=8)   # |R| = 2^20, |S| = 2^22, duplicates
+    want, inv = oracle.join_hash(w.R, w.S)
+    got = gpu_join(w.R, w.S)
+    assert got["count"] == w.expected_count == inv
+    assert got["checksum"] == want.checksum
+
+
+def test_batch_members_reduced():
+    for w in workloads.make("batch", scale_shift=5)[:4]:
+        fk = oracle.fk_closed_form(w.R, w.S, w.partner)
+        got = gpu_join(w.R, w.S)
+        assert (got["count"], got["checksum"]) == (fk.count, fk.checksum), w.name
+
+
+# ------------------------------------------------ intermediate results
+
+def _ws_view(ws, off, n, dtype):
+    b = ws[off: off + n * np.dtype(dtype).itemsize].cpu().numpy()
+    return b.view(dtype)
+
+
+@pytest.mark.parametrize("nR,nS,bt", [(1 << 17, 1 << 19, 1024), (1 << 19, 1 << 20, 256)])
+def test_intermediate_results(nR, nS, bt):
+    rng = np.random.default_rng(nR + bt)
+    R = rel(rng, nR, 1 << 24)
+    S = rel(rng, nS, 1 << 24)
+    cfg = mpsm.config(bucket_target=bt, log2_run_len=17)
+    lay = mpsm.layout(nR, nS, cfg)
+    ws = mpsm.alloc_workspace(nR, nS, cfg)
+    got = gpu_join(R, S, cfg, workspace=ws)
+    want = oracle.join(R, S)
+    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+    torch.cuda.synchronize()
+    Q, L, NB = lay["runs"], lay["run_len"], lay["s_buckets"]
+    Ssorted = _ws_view(ws, lay["off_s_sorted"], 2 * nS, np.uint64).reshape(-1, 2)
+    ref_runs = oracle.sort_runs(S, L)
+    # phase 1: every run sorted, same keys as the oracle's run sort, same tuples
+    assert np.array_equal(Ssorted[:, 0], ref_runs[:, 0])
+    for j in range(Q):
+        a, b = j * L, min((j + 1) * L, nS)
+        x = Ssorted[a:b]
+        y = ref_runs[a:b]
+        assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], y[np.lexsort((y[:, 1], y[:, 0]))])
+    # S splitters: same seeded sample, same quantiles
+    spl = _ws_view(ws, lay["off_s_splitters"], Q * (NB - 1), np.uint64).reshape(Q, NB - 1)
+    for j in range(Q):
+        seed = oracle.splitmix_at(lay["s_level_seed"], j)
+        a, b = j * L, min((j + 1) * L, nS)
+        assert np.array_equal(spl[j], oracle.sample_splitters(S[a:b], NB, lay["s_oversample"], seed))
+    # S bucket boundaries = a stable bucket partition of each run under those splitters
+    bst = _ws_view(ws, lay["off_s_bucket_start"], Q * NB + 1, np.uint32)
+    for j in range(Q):
+        a, b = j * L, min((j + 1) * L, nS)
+        _, bs = oracle.bucket_partition(S[a:b], spl[j], NB)
+        assert np.array_equal(bst[j * NB:(j + 1) * NB].astype(np.int64) - a, bs[:NB].astype(np.int64))
+    # R level-1 splitters
+    NB1 = lay["r_buckets1"]
+    spl1 = _ws_view(ws, lay["off_r_splitters1"], NB1 - 1, np.uint64)
+    assert np.array_equal(spl1, oracle.sample_splitters(R, NB1, lay["r_oversample1"],
+                                                        oracle.splitmix_at(lay["r_level_seed1"], 0)))
+    # phase 2+3: R sorted, partitions contiguous, first keys
+    Rsorted = _ws_view(ws, lay["off_r_sorted"], 2 * nR, np.uint64).reshape(-1, 2)
+    ref_R = oracle.sort_by_key(R)
+    assert np.array_equal(Rsorted[:, 0], ref_R[:, 0])
+    P = int(_ws_view(ws, lay["off_partitions"], 1, np.uint32)[0])
+    pstart = _ws_view(ws, lay["off_part_start"], P, np.uint32).astype(np.int64)
+    plen = _ws_view(ws, lay["off_part_len"], P, np.uint32).astype(np.int64)
+    pkey = _ws_view(ws, lay["off_part_key"], P, np.uint64)
+    assert pstart[0] == 0 and np.all(pstart[1:] == pstart[:-1] + plen[:-1]) and pstart[-1] + plen[-1] == nR
+    assert np.array_equal(pkey, Rsorted[pstart, 0])
+    assert np.all(Rsorted[pstart[1:] - 1, 0] < pkey[1:])          # key-disjoint partitions
+    # phase 4: start offsets are lower bounds of the first key of every partition
+    o = _ws_view(ws, lay["off_offsets"], (P + 1) * Q, np.uint32).reshape(P + 1, Q)
+    for j in range(Q):
+        a, b = j * L, min((j + 1) * L, nS)
+        ref = np.searchsorted(ref_runs[a:b, 0], pkey, side="left")
+        assert np.array_equal(o[:P, j], ref)
+        assert o[P, j] == b - a
+    # equi-height index: every idx_stride-th key of each run
+    st, ipr = lay["idx_stride"], lay["idx_per_run"]
+    idx = _ws_view(ws, lay["off_run_index"], Q * ipr, np.uint64).reshape(Q, ipr)
+    for j in range(Q):
+        a, b = j * L, min((j + 1) * L, nS)
+        keys = ref_runs[a:b:st, 0]
+        assert np.array_equal(idx[j, :len(keys)], keys)
+
+
+# --------------------------------------------------- full-size workload
+
+def test_fk_uniform_full_size_sampled():
+    """The benchmark workload (|R| = 2^26, |S| = 2^28) in the benchmark's
+    configuration: exact count and checksum from the foreign-key closed form,
+    plus sampled runs and offsets against the oracle."""
+    w = workloads.make("fk_uniform")
+    nR, nS = len(w.R), len(w.S)
+    fk = oracle.fk_closed_form(w.R, w.S, w.partner)
+    cfg = mpsm.config()
+    lay = mpsm.layout(nR, nS, cfg)
+    ws = mpsm.alloc_workspace(nR, nS, cfg)
+    got = gpu_join(w.R, w.S, cfg, workspace=ws)
+    assert got["count"] == nS == fk.count
+    assert got["checksum"] == fk.checksum
+    torch.cuda.synchronize()
+    Q, L = lay["runs"], lay["run_len"]
+    rng = np.random.default_rng(1)
+    for j in sorted(set([0, Q - 1] + rng.integers(0, Q, 2).tolist())):
+        a, b = j * L, min((j + 1) * L, nS)
+        x = _ws_view_range(ws, lay["off_s_sorted"], a, b)
+        ref = oracle.sort_by_key(w.S[a:b])
+        assert np.array_equal(x[:, 0], ref[:, 0])
+        assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], ref[np.lexsort((ref[:, 1], ref[:, 0]))])
+        P = int(_ws_view(ws, lay["off_partitions"], 1, np.uint32)[0])
+        pkey = _ws_view(ws, lay["off_part_key"], P, np.uint64)
+        ps = rng.integers(0, P, 64)
+        o = _ws_view(ws, lay["off_offsets"], (P + 1) * Q, np.uint32).reshape(P + 1, Q)
+        assert np.array_equal(o[ps, j], np.searchsorted(ref[:, 0], pkey[ps], side="left"))
+
+
+def _ws_view_range(ws, off, a, b):
+    return ws[off + 16 * a: off + 16 * b].cpu().numpy().view(np.uint64).reshape(-1, 2)
