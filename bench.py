@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the P-MPSM equi-join on one MI355X.
+
+One step = one complete mpsm_join call (every phase: S run sort, R range
+partitioning and partition sort, start search, merge join, result) over the
+benchmark workload, with the inputs already resident in HBM.
+
+Prints one JSON line.  Fields beyond the common contract:
+  roofline      the dominant kernel's achieved algorithmic HBM bandwidth
+                against the MI355X peak, timed with HIP events recorded
+                between the kernels of the timed steps on the join's stream;
+  path_roofline the same for the whole step (algorithmic bytes of the path);
+  steps_ms      per-step device time of every launch step, averaged;
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
+                same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "join throughput (M tuples/s of |R|+|S|) + % HBM roofline; learned vs plain"
+
+# algorithmic HBM bytes of each launch step, per tuple of the relation it reads
+STEP_BYTES = {
+    "s_histogram": ("S", 16), "s_scatter": ("S", 32), "s_bucket_sort": ("S", 32),
+    "r1_histogram": ("R", 16), "r1_scatter": ("R", 32), "r2_histogram": ("R", 16), "r2_scatter": ("R", 32),
+    "r_bucket_sort": ("R", 32), "join": ("RS", 16),
+}
+KERNEL_OF_STEP = {
+    "s_histogram": "k_bucket_hist", "s_scatter": "k_bucket_scatter", "s_bucket_sort": "k_bucket_sort",
+    "r1_histogram": "k_bucket_hist", "r1_scatter": "k_bucket_scatter", "r2_histogram": "k_bucket_hist",
+    "r2_scatter": "k_bucket_scatter", "r_bucket_sort": "k_bucket_sort", "join": "k_join",
+}
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("common.h", "block_sort.h", "kernels.h", "mpsm.hip"):
+        with open(os.path.join(ROOT, "paper_1207_0145_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(step: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    return t.get("steps", {}).get(step, {}).get("hbm_bytes_per_launch")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(shift: int):
+    import oracle
+    import workloads
+    w = workloads.make("fk_uniform", scale_shift=shift)
+    t0 = time.perf_counter()
+    r = oracle.join(w.R, w.S)
+    dt = time.perf_counter() - t0
+    n = len(w.R) + len(w.S)
+    return {"value": n / dt / 1e6, "unit": "M tuples/s", "cores": 1, "kind": "oracle",
+            "sample": f"fk_uniform at 1/{1 << shift} scale: |R|=2^{26 - shift}, |S|=2^{28 - shift}, "
+                      f"same key recipe; {dt:.1f} s single-threaded sort-merge join (count {r.count})"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="fk_uniform", choices=["fk_uniform", "fk_small", "skewed"])
+    ap.add_argument("--cpu-sample-shift", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--search", default="index", choices=["index", "binary", "interp"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1207_0145_amd as mpsm
+    import workloads
+
+    log(f"generating {args.workload}")
+    w = workloads.make(args.workload)
+    nR, nS = len(w.R), len(w.S)
+    dev = torch.device("cuda", 0)
+    R = torch.from_numpy(w.R.view(np.int64)).to(dev)
+    S = torch.from_numpy(w.S.view(np.int64)).to(dev)
+    del w
+    search = {"index": mpsm.SEARCH_INDEX, "binary": mpsm.SEARCH_BINARY, "interp": mpsm.SEARCH_INTERP}[args.search]
+    cfg = mpsm.config(search=search)
+    lay = mpsm.layout(nR, nS, cfg)
+    ws = mpsm.alloc_workspace(nR, nS, cfg, dev)
+    out = torch.zeros(2, dtype=torch.int64, device=dev)
+    names = mpsm.marker_names()
+    log(f"|R|={nR} |S|={nS} workspace={ws.numel() / 2**30:.2f} GiB runs={lay['runs']} "
+        f"R levels={lay['levels']}")
+    if args.calibrate_copy:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 1073741824 bytes read and written once")
+        del x, y
+    for i in range(args.warmup):
+        mpsm.join_into(R, S, out, ws, cfg)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    evsets = [mpsm.EventSet(len(names)) for _ in range(args.steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for k in range(args.steps):
+        mpsm.join_events_into(R, S, out, ws, evsets[k], cfg)
+    t1.record()
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    ms = total_ms / args.steps
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step")
+    count, checksum = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
+
+    steps_ms = {}
+    for i in range(1, len(names)):
+        steps_ms[names[i]] = sum(e.elapsed(i - 1, i) for e in evsets) / args.steps
+    for e in evsets:
+        e.close()
+
+    def step_bytes(step):
+        rel, b = STEP_BYTES[step]
+        n = {"S": nS, "R": nR, "RS": nR + nS}[rel]
+        return b * n
+
+    dom = max((s for s in STEP_BYTES if steps_ms.get(s, 0) > 0), key=lambda s: steps_ms[s])
+    achieved = step_bytes(dom) / (steps_ms[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(dom, args.workload)
+    path_bytes = 48 * nS + 64 * nR
+    path_gbs = path_bytes / (ms * 1e-3) / 1e9
+    value = (nR + nS) / (ms * 1e-3) / 1e6
+
+    res = {
+        "metric": METRIC, "value": round(value, 2), "unit": "M tuples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: |R|=2^{nR.bit_length() - 1}, |S|=2^{nS.bit_length() - 1}, "
+                               "uniform foreign keys, 16-byte tuples (u64 key, u64 payload)",
+                   "nR": nR, "nS": nS, "variant": "plain (sampled splitters, " + args.search + " start search)",
+                   "runs": lay["runs"], "run_len": lay["run_len"], "r_levels": lay["levels"]},
+        "result": {"count": count, "checksum": f"{checksum:#018x}"},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_OF_STEP[dom], "step": dom,
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes": step_bytes(dom),
+                     "avg_launch_ms": round(steps_ms[dom], 4)},
+        "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_gbs, 1), "unit": "GB/s",
+                          "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
+        "steps_ms": {k: round(v, 4) for k, v in steps_ms.items()},
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline (oracle, 1 thread, 1/{1 << args.cpu_sample_shift} scale)")
+        res["cpu_baseline"] = cpu_baseline(args.cpu_sample_shift)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

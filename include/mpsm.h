@@ -162,6 +162,29 @@ typedef struct mpsm_layout {
 
 mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* cfg, mpsm_layout* out);
 
+/* Measurement: mpsm_join that also records events[i] (hipEvent_t handles,
+ * created with mpsm_events_create) on `stream` at marker i of the launch
+ * sequence, for i < n_events.  Marker i is placed after the step named by
+ * mpsm_marker_name(i); marker 0 is the start.  Steps that a call does not
+ * run still record their marker, so the elapsed time between consecutive
+ * markers is the device time of that step.  Same arguments, results and
+ * errors as mpsm_join otherwise. */
+mpsm_status mpsm_join_events(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS,
+                             uint64_t* d_out_count, uint64_t* d_out_checksum, mpsm_pair* d_pairs,
+                             uint64_t pairs_capacity, const mpsm_config* cfg, void* d_workspace,
+                             uint64_t workspace_bytes, void* stream, void** events, uint32_t n_events);
+
+/* Number of markers and the name of the step that ends at marker i
+ * (static string; NULL for i out of range). */
+uint32_t mpsm_marker_count(void);
+const char* mpsm_marker_name(uint32_t i);
+
+/* Create / destroy n timing events; elapsed milliseconds between two
+ * completed events (host calls; they synchronise on nothing else). */
+mpsm_status mpsm_events_create(void** events, uint32_t n);
+void mpsm_events_destroy(void** events, uint32_t n);
+mpsm_status mpsm_events_elapsed(void* start, void* stop, float* ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,8 @@ STATUS = {0: "MPSM_OK", 1: "MPSM_EINVAL", 2: "MPSM_ECAPACITY", 3: "MPSM_ENOMEM",
           5: "MPSM_EUNSUPPORTED"}
 
 EXPORTS = ("mpsm_config_default", "mpsm_workspace_bytes", "mpsm_join", "mpsm_status_string",
-           "mpsm_workspace_layout")
+           "mpsm_workspace_layout", "mpsm_join_events", "mpsm_marker_count", "mpsm_marker_name",
+           "mpsm_events_create", "mpsm_events_destroy", "mpsm_events_elapsed")
 
 
 class MpsmConfig(ctypes.Structure):
@@ -81,6 +82,19 @@ def lib():
         L.mpsm_status_string.restype = ctypes.c_char_p
         L.mpsm_workspace_layout.argtypes = [u64, u64, ctypes.POINTER(MpsmConfig), ctypes.POINTER(MpsmLayout)]
         L.mpsm_workspace_layout.restype = ctypes.c_int
+        L.mpsm_join_events.argtypes = [p, u64, p, u64, p, p, p, u64, ctypes.POINTER(MpsmConfig), p, u64, p,
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32]
+        L.mpsm_join_events.restype = ctypes.c_int
+        L.mpsm_marker_count.argtypes = []
+        L.mpsm_marker_count.restype = ctypes.c_uint32
+        L.mpsm_marker_name.argtypes = [ctypes.c_uint32]
+        L.mpsm_marker_name.restype = ctypes.c_char_p
+        L.mpsm_events_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32]
+        L.mpsm_events_create.restype = ctypes.c_int
+        L.mpsm_events_destroy.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32]
+        L.mpsm_events_destroy.restype = None
+        L.mpsm_events_elapsed.argtypes = [p, p, ctypes.POINTER(ctypes.c_float)]
+        L.mpsm_events_elapsed.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -155,6 +169,47 @@ def join_into(R, S, out, workspace, cfg: MpsmConfig | None = None, stream=None, 
                          _stream_handle(stream), None if stats is None else ctypes.byref(stats))
     if rc not in (0, 2):
         raise MpsmError(rc, "mpsm_join")
+    return rc
+
+
+def marker_names() -> list[str]:
+    L = lib()
+    return [L.mpsm_marker_name(i).decode() for i in range(L.mpsm_marker_count())]
+
+
+class EventSet:
+    """n timing events owned by the library (for mpsm_join_events)."""
+
+    def __init__(self, n: int):
+        self.n = n
+        self.arr = (ctypes.c_void_p * n)()
+        rc = lib().mpsm_events_create(self.arr, n)
+        if rc != 0:
+            raise MpsmError(rc, "mpsm_events_create")
+
+    def elapsed(self, i: int, j: int) -> float:
+        ms = ctypes.c_float(0)
+        rc = lib().mpsm_events_elapsed(self.arr[i], self.arr[j], ctypes.byref(ms))
+        if rc != 0:
+            raise MpsmError(rc, "mpsm_events_elapsed")
+        return float(ms.value)
+
+    def close(self):
+        if self.arr is not None:
+            lib().mpsm_events_destroy(self.arr, self.n)
+            self.arr = None
+
+
+def join_events_into(R, S, out, workspace, events: EventSet, cfg: MpsmConfig | None = None, stream=None) -> int:
+    """mpsm_join that records the step markers into `events`."""
+    _check_tuples(R, "R")
+    _check_tuples(S, "S")
+    rc = lib().mpsm_join_events(ctypes.c_void_p(R.data_ptr()), R.shape[0], ctypes.c_void_p(S.data_ptr()),
+                                S.shape[0], ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(out.data_ptr() + 8),
+                                None, 0, _cfg_ptr(cfg), ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                _stream_handle(stream), events.arr, events.n)
+    if rc != 0:
+        raise MpsmError(rc, "mpsm_join_events")
     return rc
 
 

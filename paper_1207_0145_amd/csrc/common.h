@@ -132,3 +132,65 @@ __device__ __forceinline__ uint32_t bucket_of(const uint64_t* spl, uint32_t nspl
   if (b >= 2 && spl[b - 1] == key && spl[b - 2] == key) b--;
   return b;
 }
+
+// A multiplier C with C <= M * 2^64 / (span + 1) (M a power of two, span >= M),
+// so that x -> mulhi(x, C) maps [0, span] monotonically into [0, M).  Taken
+// from a double-precision quotient scaled down by 2^-40, which keeps it
+// below the exact value (relative error of the quotient is ~2^-52); a wide
+// integer division is far slower on the GPU.
+__device__ __forceinline__ uint64_t interp_scale(uint32_t M, uint64_t span) {
+  const double q = ldexp((double)M, 64) / ((double)span + 1.0);
+  const double c = q * (1.0 - 0x1p-40);
+  return c >= 18446744073709551615.0 ? ~0ull : (uint64_t)c;
+}
+
+// Directory over sorted splitters for fast bucket_of: the span [spl[0],
+// spl[nspl-1]] is cut into D equal cells by a monotone map (multiply-high by
+// C); first[c] is the first splitter whose cell is >= c.  A key in cell c
+// has every splitter below first[c] under it and every splitter from
+// first[c+1] on above it, so only the splitters of its own cell (usually 0
+// or 1) are searched.  Same answer as bucket_of.
+template <int D>
+struct SplitDir {
+  uint16_t first[D + 1];
+  uint64_t lo, C;
+
+  // All threads of the block call; spl (LDS) holds nspl >= 1 sorted splitters.
+  template <int NT>
+  __device__ void build(const uint64_t* spl, uint32_t nspl) {
+    if (threadIdx.x == 0) {
+      lo = spl[0];
+      const uint64_t width = spl[nspl - 1] - spl[0];
+      C = width < (uint64_t)D ? 0ull : interp_scale(D, width);   // narrow span: every key in cell 0
+    }
+    __syncthreads();
+    const uint64_t l = lo, c = C;
+    for (uint32_t cell = threadIdx.x; cell <= (uint32_t)D; cell += NT) {
+      uint32_t a = 0, b = nspl;  // first m with cell(spl[m]) >= cell
+      while (a < b) {
+        const uint32_t m = (a + b) >> 1;
+        if ((uint32_t)__umul64hi(spl[m] - l, c) < cell) a = m + 1; else b = m;
+      }
+      first[cell] = (uint16_t)a;
+    }
+    __syncthreads();
+  }
+
+  __device__ __forceinline__ uint32_t bucket(const uint64_t* spl, uint32_t nspl, uint64_t key) const {
+    if (nspl == 0 || key < lo) return 0;
+    uint32_t b;
+    if (key >= spl[nspl - 1]) {
+      b = nspl;
+    } else {
+      const uint32_t cell = (uint32_t)__umul64hi(key - lo, C);
+      uint32_t a = first[cell], e = first[cell + 1];
+      while (a < e) {
+        const uint32_t m = (a + e) >> 1;
+        if (spl[m] <= key) a = m + 1; else e = m;
+      }
+      b = a;
+    }
+    if (b >= 2 && spl[b - 1] == key && spl[b - 2] == key) b--;
+    return b;
+  }
+};

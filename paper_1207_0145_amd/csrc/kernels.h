@@ -19,11 +19,13 @@
 #include "block_sort.h"
 
 // ------------------------------------------------------------------ config
-constexpr int SORT_NT = 512;   // bucket sort: 512 threads x 16 items = 8192 tuples
-constexpr int SORT_IPT = 16;
-constexpr int SORT_RB = 4;
-constexpr int SORT_CAP = SORT_NT * SORT_IPT;
-using BucketSorter = BlockSort<SORT_NT, SORT_IPT, SORT_RB>;
+// bucket sort instances: small tiles for S buckets, large tiles (= the join's
+// LDS partition capacity) for R partitions and for S buckets that overflow
+constexpr int BS_NT = 512, BS_IPT = 8, BS_M = 4096;      // 4096 tuples
+constexpr int BL_NT = 1024, BL_IPT = 8, BL_M = 4096;     // 8192 tuples
+constexpr int BS_CAP = BS_NT * BS_IPT;
+constexpr int BL_CAP = BL_NT * BL_IPT;
+constexpr int LSD_NT = 512, LSD_IPT = 16;                // fallback radix sort, 8192 tuples
 
 constexpr int SMP_NT = 1024;   // splitter sample sort: up to 16384 keys
 constexpr int SMP_IPT = 16;
@@ -35,14 +37,16 @@ constexpr int SMP_IPT_S = 8;
 using SampleSorterS = BlockSort<SMP_NT_S, SMP_IPT_S, 4>;
 
 constexpr int HIST_NT = 256;
-constexpr int SCAT_NT = 256;
-constexpr int SCAT_IPT = 8;
+constexpr int SCAT_NT = 512;
+constexpr int SCAT_IPT = 4;
 constexpr int SCAT_CH = SCAT_NT * SCAT_IPT;  // tuples staged in LDS per chunk
 constexpr int MAX_NB = 1024;                 // buckets per segment
+constexpr int SPLIT_DIR = 2048;              // cells of the splitter directory
 
 constexpr int JOIN_NT = 1024;
 constexpr int JOIN_CAP = 8192;               // R partition held in LDS
 constexpr int JOIN_QMAX = 2048;              // S runs
+constexpr int JOIN_DIR = 4096;               // cells of the R-partition directory
 
 constexpr int SCAN_NT = 256;
 constexpr int SCAN_IPT = 16;
@@ -219,6 +223,7 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
                                                          uint32_t* cnt) {
   __shared__ uint64_t sp[MAX_NB];
   __shared__ uint32_t h[MAX_NB];
+  __shared__ SplitDir<SPLIT_DIR> dir;
   const uint32_t g = blockIdx.x;
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
@@ -230,9 +235,18 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
   for (uint32_t i = threadIdx.x; i < nspl; i += HIST_NT) sp[i] = spl[(uint64_t)s * nspl + i];
   for (uint32_t i = threadIdx.x; i < NB; i += HIST_NT) h[i] = 0;
   __syncthreads();
-  for (uint32_t i = a + threadIdx.x; i < b; i += HIST_NT) {
-    const uint64_t k = src[i].key;
-    atomicAdd(&h[bucket_of(sp, nspl, k)], 1u);
+  if (nspl) dir.build<HIST_NT>(sp, nspl);
+  constexpr int HU = 8;   // keys per thread in flight
+  for (uint32_t base = a; base < b; base += HIST_NT * HU) {
+    uint64_t kk[HU];
+#pragma unroll
+    for (int u = 0; u < HU; u++) {
+      const uint32_t i = base + u * HIST_NT + threadIdx.x;
+      kk[u] = i < b ? src[i].key : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < HU; u++)
+      if (base + u * HIST_NT + threadIdx.x < b) atomicAdd(&h[dir.bucket(sp, nspl, kk[u])], 1u);
   }
   __syncthreads();
   uint32_t* c = cnt + seg_cnt0[s] + t;
@@ -251,6 +265,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   __shared__ tup_t stage[SCAT_CH];
   __shared__ uint16_t sid[SCAT_CH];
   __shared__ uint32_t wsum[SCAT_NT / 64 + 2];
+  __shared__ SplitDir<SPLIT_DIR> dir;
   const uint32_t g = blockIdx.x, tid = threadIdx.x;
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
@@ -263,16 +278,29 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   const uint32_t* p = pos + seg_cnt0[s] + t;
   for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] = p[(uint64_t)i * ntiles]; lcnt[i] = 0; }
   __syncthreads();
+  if (nspl) dir.build<SCAT_NT>(sp, nspl);
   constexpr int PER = (MAX_NB + SCAT_NT - 1) / SCAT_NT;
+  tup_t nv[SCAT_IPT];   // next chunk, loaded while the current one is placed
+#pragma unroll
+  for (int k = 0; k < SCAT_IPT; k++) {
+    const uint32_t i = a + k * SCAT_NT + tid;
+    if (i < b) nv[k] = load_tup(src + i);
+  }
   for (uint32_t c0 = a; c0 < b; c0 += SCAT_CH) {
     tup_t v[SCAT_IPT];
     uint32_t bk[SCAT_IPT], lr[SCAT_IPT];
 #pragma unroll
+    for (int k = 0; k < SCAT_IPT; k++) v[k] = nv[k];
+#pragma unroll
+    for (int k = 0; k < SCAT_IPT; k++) {
+      const uint32_t i = c0 + SCAT_CH + k * SCAT_NT + tid;
+      if (i < b) nv[k] = load_tup(src + i);
+    }
+#pragma unroll
     for (int k = 0; k < SCAT_IPT; k++) {
       const uint32_t i = c0 + k * SCAT_NT + tid;
       if (i < b) {
-        v[k] = load_tup(src + i);
-        bk[k] = bucket_of(sp, nspl, v[k].key);
+        bk[k] = dir.bucket(sp, nspl, v[k].key);
         lr[k] = atomicAdd(&lcnt[bk[k]], 1u);
       }
     }
@@ -332,7 +360,7 @@ struct SortOut {
   // S runs: every idx_stride-th key of each run (equi-height bounds)
   uint64_t* run_idx;
   const uint32_t* run_start;
-  uint32_t idx_stride, idx_per_run, NB;
+  uint32_t idx_stride, idx_shift, idx_per_run, NB;   // idx_stride = 2^idx_shift
   // R buckets: first (smallest) key of every bucket
   uint64_t* bkey;
 };
@@ -341,42 +369,197 @@ __device__ __forceinline__ void emit_sorted(const SortOut& so, uint32_t g, uint3
   if (so.run_idx) {
     const uint32_t s = g / so.NB;
     const uint32_t rel = a + r - so.run_start[s];
-    if (rel % so.idx_stride == 0) so.run_idx[(uint64_t)s * so.idx_per_run + rel / so.idx_stride] = key;
+    if ((rel & (so.idx_stride - 1)) == 0) so.run_idx[(uint64_t)s * so.idx_per_run + (rel >> so.idx_shift)] = key;
   }
   if (so.bkey && r == 0) so.bkey[g] = key;
 }
 
-// One workgroup per bucket: LDS radix sort of buckets up to SORT_CAP; larger
-// buckets go to the oversize list.
-__global__ void __launch_bounds__(SORT_NT) k_bucket_sort(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
-                                                         const uint32_t* bstart, uint32_t* big_list,
-                                                         unsigned long long* big_count, SortOut so) {
-  __shared__ uint64_t buf[BucketSorter::BUF_WORDS];
-  __shared__ uint32_t wsum[BucketSorter::WSUM_WORDS];
-  __shared__ uint64_t red[SORT_NT / 64 + 1];
-  const uint32_t g = blockIdx.x, tid = threadIdx.x;
-  const uint32_t a = bstart[g], n = bstart[g + 1] - a;
-  if (n == 0) return;
-  if (n > (uint32_t)SORT_CAP) {
-    if (tid == 0) big_list[atomicAdd(big_count, 1ull)] = g;
-    return;
-  }
-  uint64_t key[SORT_IPT], val[SORT_IPT];
+// Bucket sort by one counting pass plus a rank fix-up (the paper's sort is
+// an MSD radix pass whose small partitions are finished by insertion sort,
+// Section 2.3).  Keys of the bucket are mapped monotonically onto M
+// sub-buckets by linear interpolation between the bucket's smallest and
+// largest key; one LDS counting sort groups the keys by sub-bucket.  Every
+// tuple then finds its rank inside its (typically 0-3 key) sub-bucket by
+// comparing its key with the other keys of the group -- ties broken by the
+// group position, so ranks are a permutation -- and stores itself straight
+// from registers to its final position.  Payloads never pass through LDS.
+// A bucket with a sub-bucket of more than GMAX keys (keys clustered inside
+// the bucket) goes to redo_list for the LSD radix sort (k_bucket_sort_lsd).
+// Buckets larger than CAP go to over_list.  With in_list the kernel walks a
+// list of bucket ids instead of all G buckets.
+constexpr int CS_GMAX = 32;
+
+template <int NT>
+__device__ __forceinline__ void block_minmax64(uint64_t& mn, uint64_t& mx, uint64_t* red) {
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
 #pragma unroll
-  for (int k = 0; k < SORT_IPT; k++) {
-    const uint32_t i = k * SORT_NT + tid;
-    if (i < n) { const tup_t v = load_tup(src + a + i); key[k] = v.key; val[k] = v.pay; }
-    else { key[k] = ~0ull; val[k] = 0; }
+  for (int d = 32; d >= 1; d >>= 1) {
+    const uint64_t a = __shfl_xor(mn, d, 64), b = __shfl_xor(mx, d, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
   }
-  BucketSorter::sort<true>(key, val, (int)n, buf, wsum, red);
+  if (lane == 0) { red[2 * w] = mn; red[2 * w + 1] = mx; }
+  __syncthreads();
+  mn = red[0]; mx = red[1];
 #pragma unroll
-  for (int k = 0; k < SORT_IPT; k++) {
-    const uint32_t r = k * SORT_NT + tid;
-    if (r < n) {
-      tup_t v; v.key = key[k]; v.pay = val[k];
-      store_tup(dst + a + r, v);
-      emit_sorted(so, g, a, r, key[k]);
+  for (int i = 1; i < NT / 64; i++) {
+    mn = red[2 * i] < mn ? red[2 * i] : mn;
+    mx = red[2 * i + 1] > mx ? red[2 * i + 1] : mx;
+  }
+}
+
+template <int NT, int IPT, int M>
+__global__ void __launch_bounds__(NT) k_bucket_sort_cs(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
+                                                       const uint32_t* bstart, uint32_t G, const uint32_t* in_list,
+                                                       const unsigned long long* in_count, uint32_t* over_list,
+                                                       unsigned long long* over_count, uint32_t* redo_list,
+                                                       unsigned long long* redo_count, SortOut so) {
+  constexpr int CAP = NT * IPT;
+  constexpr int PER = M / NT;
+  static_assert(M % NT == 0, "sub-buckets per thread");
+  __shared__ uint64_t sk[CAP];               // keys grouped by sub-bucket
+  __shared__ uint32_t cnt[M + 1];
+  __shared__ uint32_t wsum[NT / 64 + 2];
+  __shared__ uint64_t red[2 * (NT / 64) + 2];
+  __shared__ uint64_t scale;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nitems = in_list ? (uint32_t)*in_count : G;
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const uint32_t g = in_list ? in_list[it] : it;
+    const uint32_t a = bstart[g], n = bstart[g + 1] - a;
+    if (n == 0) continue;
+    if (n > (uint32_t)CAP) {
+      if (tid == 0) over_list[atomicAdd(over_count, 1ull)] = g;
+      continue;
     }
+    uint64_t key[IPT], val[IPT];
+    uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+    for (int k = 0; k < IPT; k++) {
+      const uint32_t i = k * NT + tid;
+      if (i < n) {
+        const tup_t v = load_tup(src + a + i);
+        key[k] = v.key; val[k] = v.pay;
+        mn = v.key < mn ? v.key : mn;
+        mx = v.key > mx ? v.key : mx;
+      } else {
+        key[k] = ~0ull; val[k] = 0;
+      }
+    }
+    __syncthreads();   // LDS of the previous bucket is free
+    block_minmax64<NT>(mn, mx, red);
+    uint32_t fin[IPT];
+    if (mn == mx) {  // one key: input order is sorted order
+#pragma unroll
+      for (int k = 0; k < IPT; k++) fin[k] = k * NT + tid;
+    } else {
+      const uint64_t span = mx - mn;
+      const bool exact = span < (uint64_t)M;   // one key per sub-bucket
+      if (tid == 0) scale = exact ? 0ull : interp_scale(M, span);
+      for (uint32_t b = tid; b <= (uint32_t)M; b += NT) cnt[b] = 0;
+      __syncthreads();
+      const uint64_t C = scale;
+      uint32_t d[IPT], pos[IPT];
+#pragma unroll
+      for (int k = 0; k < IPT; k++) {
+        if (k * NT + tid < n) {
+          const uint64_t x = key[k] - mn;
+          d[k] = exact ? (uint32_t)x : (uint32_t)__umul64hi(x, C);
+          pos[k] = atomicAdd(&cnt[d[k]], 1u);
+        }
+      }
+      __syncthreads();
+      {
+        uint32_t loc[PER], run = 0;
+#pragma unroll
+        for (int q = 0; q < PER; q++) { loc[q] = run; run += cnt[tid * PER + q]; }
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<NT>(run, wsum, &tot);
+#pragma unroll
+        for (int q = 0; q < PER; q++) cnt[tid * PER + q] = loc[q] + ex;
+        if (tid == 0) cnt[M] = n;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < IPT; k++) {
+        if (k * NT + tid < n) {
+          fin[k] = cnt[d[k]] + pos[k];
+          if (!exact) sk[fin[k]] = key[k];
+        }
+      }
+      bool bad = false;
+      if (!exact) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < IPT; k++) {
+          if (k * NT + tid < n) {
+            const uint32_t lo = cnt[d[k]], hi = cnt[d[k] + 1], p = fin[k];
+            if (hi - lo > (uint32_t)CS_GMAX) {
+              bad = true;
+            } else {
+              uint32_t r = lo;
+              for (uint32_t q = lo; q < hi; q++) {
+                const uint64_t kq = sk[q];
+                r += (kq < key[k]) || (kq == key[k] && q < p);
+              }
+              fin[k] = r;
+            }
+          }
+        }
+      }
+      if (__syncthreads_or(bad)) {
+        if (tid == 0) redo_list[atomicAdd(redo_count, 1ull)] = g;
+        continue;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < IPT; k++) {
+      if (k * NT + tid < n) {
+        tup_t v; v.key = key[k]; v.pay = val[k];
+        store_tup(dst + a + fin[k], v);
+        emit_sorted(so, g, a, fin[k], key[k]);
+      }
+    }
+  }
+}
+
+// LSD radix sort (BlockSort) of the buckets on a list, one workgroup per
+// bucket; buckets larger than the tile go to over_list.
+__global__ void __launch_bounds__(LSD_NT) k_bucket_sort_lsd(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
+                                                            const uint32_t* bstart, const uint32_t* in_list,
+                                                            const unsigned long long* in_count, uint32_t* over_list,
+                                                            unsigned long long* over_count, SortOut so) {
+  using Sorter = BlockSort<LSD_NT, LSD_IPT, 4>;
+  __shared__ uint64_t buf[Sorter::BUF_WORDS];
+  __shared__ uint32_t wsum[Sorter::WSUM_WORDS];
+  __shared__ uint64_t red[LSD_NT / 64 + 1];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nitems = (uint32_t)*in_count;
+  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const uint32_t g = in_list[it];
+    const uint32_t a = bstart[g], n = bstart[g + 1] - a;
+    if (n > (uint32_t)(LSD_NT * LSD_IPT)) {
+      if (tid == 0) over_list[atomicAdd(over_count, 1ull)] = g;
+      continue;
+    }
+    uint64_t key[LSD_IPT], val[LSD_IPT];
+#pragma unroll
+    for (int k = 0; k < LSD_IPT; k++) {
+      const uint32_t i = k * LSD_NT + tid;
+      if (i < n) { const tup_t v = load_tup(src + a + i); key[k] = v.key; val[k] = v.pay; }
+      else { key[k] = ~0ull; val[k] = 0; }
+    }
+    Sorter::sort<true>(key, val, (int)n, buf, wsum, red);
+#pragma unroll
+    for (int k = 0; k < LSD_IPT; k++) {
+      const uint32_t r = k * LSD_NT + tid;
+      if (r < n) {
+        tup_t v; v.key = key[k]; v.pay = val[k];
+        store_tup(dst + a + r, v);
+        emit_sorted(so, g, a, r, key[k]);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -502,9 +685,9 @@ __device__ __forceinline__ uint32_t interp_search(const tup_t* run, uint32_t n, 
       m = lo + ((hi - lo) >> 1);
     } else {
       const uint64_t klo = run[lo].key, khi = run[hi].key;
-      const unsigned __int128 num = (unsigned __int128)(hi - lo) * (key - klo);
-      uint64_t q = (uint64_t)(num / (unsigned __int128)(khi - klo));
-      m = lo + (uint32_t)q;
+      // the proportion only picks the probe; the invariant keeps the answer exact
+      const double f = (double)(key - klo) / (double)(khi - klo);
+      m = lo + (uint32_t)(f * (double)(hi - lo));
       if (m <= lo) m = lo + 1;
       if (m >= hi) m = hi - 1;
     }
@@ -610,18 +793,30 @@ __device__ __forceinline__ uint32_t item_partition(const uint32_t* item_pre, uin
   return lo;
 }
 
-// Join kernel.  MODE 0: count + checksum (+max); MODE 1: count pairs per item;
-// MODE 2: write pairs.  VM: what the LDS holds next to each R key.
+// Join kernel (phase 4).  A work item is a range of partition p's S tuples,
+// counted along the concatenation of its slices S_j[o[p][j], o[p+1][j]).  The
+// workgroup holds R_p in LDS (keys plus, per key, either the R-side hash
+// prefix or the raw payload), with a directory over R_p's key range; every S
+// tuple of the item is matched by a lower-bound search that the directory
+// narrows to a few keys, and each match adds one pair.  Every S tuple belongs
+// to exactly one slice of one partition, so each pair is produced once.
+// Partitions larger than the LDS tile are searched in global memory.
+// MODE 0: count + checksum (+max); MODE 1: count pairs per item; MODE 2: write
+// pairs.  VM: what the LDS holds next to each R key.
+constexpr int JOIN_U = 8;     // S tuples in flight per thread
+
 template <int MODE, int VM>
 __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
   __shared__ uint64_t rk[JOIN_CAP];
   __shared__ uint64_t rv[JOIN_CAP];
   __shared__ uint32_t cum[JOIN_QMAX + 1];
+  __shared__ uint32_t sbase[JOIN_QMAX];
+  __shared__ uint16_t jdir[JOIN_DIR + 1];
   __shared__ uint32_t wsum[JOIN_NT / 64 + 2];
   __shared__ uint64_t red[JOIN_NT / 64 + 1];
   __shared__ unsigned long long item_acc;
-  const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  constexpr uint32_t NW = JOIN_NT / 64;
+  __shared__ uint64_t jlo, jhi, jC;
+  const uint32_t tid = threadIdx.x;
   const uint32_t Q = A.Q;
   const uint32_t np2 = A.Pmax + 2;
   const uint32_t total = A.item_pre[np2 - 1];
@@ -633,14 +828,17 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
     const uint32_t rs = A.pstart[p], rn = A.plen[p];
     const uint32_t* oa = A.o + (uint64_t)p * Q;
     const uint32_t* ob = oa + Q;
-    // exclusive prefix of slice lengths over runs
+    __syncthreads();   // LDS of the previous item is free
+    // prefix of slice lengths over the runs; sbase[j] + x = S position of
+    // concatenated index x when x falls in run j
     uint32_t carry = 0;
     for (uint32_t j0 = 0; j0 < Q; j0 += JOIN_NT) {
       const uint32_t j = j0 + tid;
-      const uint32_t len = j < Q ? ob[j] - oa[j] : 0;
+      const uint32_t oj = j < Q ? oa[j] : 0;
+      const uint32_t len = j < Q ? ob[j] - oj : 0;
       uint32_t tot;
       const uint32_t ex = block_excl_scan<JOIN_NT>(len, wsum, &tot);
-      if (j < Q) cum[j] = carry + ex;
+      if (j < Q) { cum[j] = carry + ex; sbase[j] = A.run_start[j] + oj - (carry + ex); }
       carry += tot;
       __syncthreads();
     }
@@ -654,20 +852,59 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
       }
     }
     __syncthreads();
+    // directory over R_p's key range: jdir[c] = first position whose cell is
+    // >= c (cells are monotone in the key); a key in cell c has its lower
+    // bound in [jdir[c], jdir[c+1]].  Built in one pass over the keys.
+    if (in_lds) {
+      if (tid == 0) {
+        jlo = rk[0]; jhi = rk[rn - 1];
+        const uint64_t width = jhi - jlo;
+        jC = width < (uint64_t)JOIN_DIR ? 0ull : interp_scale(JOIN_DIR, width);
+      }
+      __syncthreads();
+      const uint64_t l = jlo, c = jC;
+      for (uint32_t i = tid; i < rn; i += JOIN_NT) {
+        const int ci = (int)__umul64hi(rk[i] - l, c);
+        const int cp = i ? (int)__umul64hi(rk[i - 1] - l, c) : -1;
+        for (int cc = cp + 1; cc <= ci; cc++) jdir[cc] = (uint16_t)i;
+      }
+      const int clast = (int)__umul64hi(rk[rn - 1] - l, c);
+      for (int cc = (int)tid; cc <= JOIN_DIR; cc += JOIN_NT)
+        if (cc > clast) jdir[cc] = (uint16_t)rn;
+      __syncthreads();
+    }
+    const uint64_t dlo = jlo, dhi = jhi, dC = jC;
     const uint32_t lo_item = k * A.JCH;
     const uint32_t hi_item = min(lo_item + A.JCH, cum[Q]);
     const tup_t* Rg = A.Rs + rs;
-    for (uint32_t j = w; j < Q; j += NW) {
-      const uint32_t c0 = cum[j], c1 = cum[j + 1];
-      const uint32_t x0 = max(c0, lo_item), x1 = min(c1, hi_item);
-      if (x0 >= x1) continue;
-      const tup_t* sb = A.U + A.run_start[j] + oa[j] - c0;
-      for (uint32_t x = x0 + lane; x < x1; x += 64) {
-        const tup_t s = load_tup(sb + x);
-        // first R position with key >= s.key
+    for (uint32_t base = lo_item; base < hi_item; base += JOIN_NT * JOIN_U) {
+      tup_t sv[JOIN_U];
+#pragma unroll
+      for (int u = 0; u < JOIN_U; u++) {
+        const uint32_t x = base + u * JOIN_NT + tid;
+        if (x < hi_item) {
+          uint32_t a0 = 0, b0 = Q;   // run j: cum[j] <= x < cum[j+1]
+          while (b0 - a0 > 1) { const uint32_t m = (a0 + b0) >> 1; if (cum[m] <= x) a0 = m; else b0 = m; }
+          sv[u] = load_tup(A.U + sbase[a0] + x);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < JOIN_U; u++) {
+        const uint32_t x = base + u * JOIN_NT + tid;
+        if (x >= hi_item) continue;
+        const tup_t s = sv[u];
         uint32_t lo = 0, hi = rn;
         if (in_lds) {
-          while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (rk[mid] < s.key) lo = mid + 1; else hi = mid; }
+          if (s.key <= dlo) {
+            hi = 0;
+          } else if (s.key > dhi) {
+            lo = rn;
+          } else {
+            const uint32_t cell = (uint32_t)__umul64hi(s.key - dlo, dC);
+            lo = jdir[cell];
+            hi = jdir[cell + 1];
+            while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (rk[mid] < s.key) lo = mid + 1; else hi = mid; }
+          }
         } else {
           while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (Rg[mid].key < s.key) lo = mid + 1; else hi = mid; }
         }
@@ -705,7 +942,6 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
       if (tid == 0) A.item_cnt[item] = (uint32_t)c;
       cnt = 0;
     }
-    __syncthreads();
   }
   if (MODE == 0) {
     const uint64_t c = block_sum64<JOIN_NT>(cnt, red);

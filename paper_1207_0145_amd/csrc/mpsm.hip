@@ -41,7 +41,7 @@ struct Plan {
   uint64_t segS, segR1, segR2;             // 4 arrays each: start, len, tile0, cnt0
   uint64_t splS, splR1, splR2;
   uint64_t bstS, bstR1, bstR2;
-  uint64_t bigS, bigR, ctr;
+  uint64_t bigS, midS, redoS, redoR, bigR, ctr;
   uint64_t bkey, Pc, pstart, plen, pkey;
   uint64_t ridx, o, items, item_pre, item_cnt, res;
   uint64_t total;
@@ -73,7 +73,8 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->splitter = cfg->splitter;
   P->want_max = cfg->want_max ? 1 : 0;
   P->seed = cfg->seed;
-  const uint32_t BT = cfg->bucket_target ? cfg->bucket_target : 4096u;
+  const uint32_t BT = cfg->bucket_target ? cfg->bucket_target : 4096u;   // R partitions
+  const uint32_t BTs = BT < 2048u ? BT : 2048u;                           // S buckets
   // S runs
   uint64_t L;
   if (cfg->log2_run_len) L = 1ull << cfg->log2_run_len;
@@ -85,7 +86,7 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->L = (uint32_t)L;
   P->Q = P->nS ? (uint32_t)cdiv(P->nS, L) : 1;
   if (P->Q > (uint32_t)JOIN_QMAX) return false;
-  P->NBs = next_pow2(cdiv(L, BT));
+  P->NBs = next_pow2(cdiv(L, BTs));
   if (P->NBs > (uint32_t)MAX_NB) P->NBs = MAX_NB;
   const uint32_t OSreq = cfg->oversample ? cfg->oversample : 32u;
   auto os_for = [&](uint32_t NB) { return NB > 1 ? (SMP_CAP / NB < OSreq ? SMP_CAP / NB : OSreq) : 1u; };
@@ -144,6 +145,9 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->bstR1 = take(((uint64_t)P->NB1 + 1) * 4);
   P->bstR2 = take(((uint64_t)P->Gr + 1) * 4);
   P->bigS = take((uint64_t)P->Gs * 4);
+  P->midS = take((uint64_t)P->Gs * 4);
+  P->redoS = take((uint64_t)P->Gs * 4);
+  P->redoR = take((uint64_t)P->Gr * 4);
   P->bigR = take((uint64_t)P->Gr * 4);
   P->ctr = take(8 * 8);
   P->bkey = take((uint64_t)P->Gr * 8);
@@ -189,10 +193,37 @@ mpsm_status scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* bs
   return MPSM_OK;
 }
 
+// Step markers of the launch sequence (events recorded after each step).
+const char* const kMarkers[] = {
+    "start",        "init",          "s_splitters",   "s_histogram", "s_scan",          "s_scatter",
+    "s_bucket_sort", "s_oversize_sort", "r1_splitters", "r1_histogram", "r1_scan",       "r1_scatter",
+    "r2_splitters", "r2_histogram",  "r2_scan",       "r2_scatter",  "r_bucket_sort",   "r_oversize_sort",
+    "partitions",   "search",        "join_plan",     "join",        "finalize"};
+constexpr uint32_t kNumMarkers = sizeof(kMarkers) / sizeof(kMarkers[0]);
+enum {
+  MK_START, MK_INIT, MK_S_SPL, MK_S_HIST, MK_S_SCAN, MK_S_SCAT, MK_S_SORT, MK_S_BIG, MK_R1_SPL, MK_R1_HIST,
+  MK_R1_SCAN, MK_R1_SCAT, MK_R2_SPL, MK_R2_HIST, MK_R2_SCAN, MK_R2_SCAT, MK_R_SORT, MK_R_BIG, MK_PART, MK_SEARCH,
+  MK_ITEMS, MK_JOIN, MK_FIN
+};
+
+struct Marker {
+  void** ev;
+  uint32_t n;
+  hipStream_t st;
+  bool ok = true;
+  void mark(uint32_t i) {
+    if (ev && i < n && hipEventRecord((hipEvent_t)ev[i], st) != hipSuccess) ok = false;
+  }
+  void mark_range(uint32_t a, uint32_t b) {  // steps a..b that were not run
+    for (uint32_t i = a; i <= b; i++) mark(i);
+  }
+};
+
 // One bucket pass over segments: splitters, histogram, scan, scatter, table.
+// Markers mk0 .. mk0+3 follow splitters, histogram, scan and scatter.
 mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, Seg seg, uint32_t nseg, uint32_t NB, uint32_t OS,
                         uint64_t level_seed, uint64_t* spl, uint32_t* cnt, uint64_t ncnt, uint32_t* bsum,
-                        uint32_t max_tiles, uint32_t* bstart, hipStream_t st) {
+                        uint32_t max_tiles, uint32_t* bstart, hipStream_t st, Marker& mk, uint32_t mk0) {
   k_seg_plan<<<1, 1024, 0, st>>>(nseg, NB, HIST_TILE, seg.len, seg.tile0, seg.cnt0);
   LAUNCH_CHECK();
   if (NB > 1) {
@@ -202,20 +233,26 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, Seg seg, uint3
       k_sample_splitters<SMP_NT, SMP_IPT><<<nseg, SMP_NT, 0, st>>>(src, seg.start, seg.len, NB, OS, level_seed, spl);
     LAUNCH_CHECK();
   }
+  mk.mark(mk0);
   if (max_tiles) {
     k_bucket_hist<<<max_tiles, HIST_NT, 0, st>>>(src, seg.start, seg.len, seg.tile0, seg.cnt0, nseg, spl, NB,
                                                  HIST_TILE, cnt);
     LAUNCH_CHECK();
+    mk.mark(mk0 + 1);
     mpsm_status rc = scan_u32(cnt, cnt, ncnt, bsum, st);
     if (rc != MPSM_OK) return rc;
+    mk.mark(mk0 + 2);
     k_bucket_scatter<<<max_tiles, SCAT_NT, 0, st>>>(src, dst, seg.start, seg.len, seg.tile0, seg.cnt0, nseg, spl, NB,
                                                     HIST_TILE, cnt);
     LAUNCH_CHECK();
+  } else {
+    mk.mark_range(mk0 + 1, mk0 + 2);
   }
   const uint32_t G = nseg * NB;
   k_bucket_table<<<(uint32_t)cdiv(G + 1, 256), 256, 0, st>>>(nseg, NB, seg.start, seg.tile0, seg.cnt0, cnt, n,
                                                              bstart);
   LAUNCH_CHECK();
+  mk.mark(mk0 + 3);
   return MPSM_OK;
 }
 
@@ -296,9 +333,14 @@ mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* c
   return MPSM_OK;
 }
 
-mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS, uint64_t* d_out_count,
+}  // extern "C"
+
+namespace {
+
+mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS, uint64_t* d_out_count,
                       uint64_t* d_out_checksum, mpsm_pair* d_pairs, uint64_t pairs_capacity, const mpsm_config* cfg,
-                      void* d_workspace, uint64_t workspace_bytes, void* stream, mpsm_stats* stats) {
+                      void* d_workspace, uint64_t workspace_bytes, void* stream, mpsm_stats* stats, void** events,
+                      uint32_t n_events) {
   mpsm_config def;
   if (!cfg) { mpsm_config_default(&def); cfg = &def; }
   if (!config_valid(cfg)) return MPSM_EINVAL;
@@ -323,6 +365,8 @@ mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     HIP_TRY(hipEventCreate(&ev1));
     HIP_TRY(hipEventRecord(ev0, st));
   }
+  Marker mk{events, n_events, st};
+  mk.mark(MK_START);
   char* ws = static_cast<char*>(d_workspace);
   const tup_t* Rin = reinterpret_cast<const tup_t*>(P.swapped ? d_S : d_R);
   const tup_t* Sin = reinterpret_cast<const tup_t*>(P.swapped ? d_R : d_S);
@@ -336,9 +380,12 @@ mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
 
   k_init_result<<<1, 64, 0, st>>>(res, reinterpret_cast<uint32_t*>(ctr), 16);
   LAUNCH_CHECK();
+  mk.mark(MK_INIT);
   if (P.nR == 0 || P.nS == 0) {
+    mk.mark_range(MK_S_SPL, MK_JOIN);
     k_finalize<<<1, 64, 0, st>>>(res, d_out_count, d_out_checksum);
     LAUNCH_CHECK();
+    mk.mark(MK_FIN);
   } else {
     mpsm_status rc;
     // ---- phase 1: sort S into Q runs of L tuples
@@ -348,19 +395,31 @@ mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     uint32_t* bstS = reinterpret_cast<uint32_t*>(ws + P.bstS);
     rc = bucket_pass(Sin, T, (uint32_t)P.nS, sS, P.Q, P.NBs, P.OSs, P.seed ^ TAG_S,
                      reinterpret_cast<uint64_t*>(ws + P.splS), reinterpret_cast<uint32_t*>(ws + P.cS), P.cntS, bsum,
-                     P.tilesS, bstS, st);
+                     P.tilesS, bstS, st, mk, MK_S_SPL);
     if (rc != MPSM_OK) return rc;
     SortOut soS;
     soS.run_idx = reinterpret_cast<uint64_t*>(ws + P.ridx);
     soS.run_start = sS.start;
     soS.idx_stride = IDX_STRIDE;
+    soS.idx_shift = __builtin_ctz(IDX_STRIDE);
     soS.idx_per_run = P.idx_per_run;
     soS.NB = P.NBs;
     soS.bkey = nullptr;
-    k_bucket_sort<<<P.Gs, SORT_NT, 0, st>>>(T, U, bstS, reinterpret_cast<uint32_t*>(ws + P.bigS), ctr + 0, soS);
+    uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
+    uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
+    uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M><<<P.Gs, BS_NT, 0, st>>>(T, U, bstS, P.Gs, nullptr, nullptr, midS, ctr + 2,
+                                                                 redoS, ctr + 3, soS);
     LAUNCH_CHECK();
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M><<<g_num_cus, BL_NT, 0, st>>>(T, U, bstS, 0, midS, ctr + 2, bigS, ctr + 0,
+                                                                      redoS, ctr + 3, soS);
+    LAUNCH_CHECK();
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, bstS, redoS, ctr + 3, bigS, ctr + 0, soS);
+    LAUNCH_CHECK();
+    mk.mark(MK_S_SORT);
     k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, bstS, reinterpret_cast<uint32_t*>(ws + P.bigS), ctr + 0, soS);
     LAUNCH_CHECK();
+    mk.mark(MK_S_BIG);
 
     // ---- phase 2: range-partition R (one or two levels); phase 3: sort partitions
     Seg sR1 = seg_at(ws, P.segR1, 1);
@@ -369,17 +428,19 @@ mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     uint32_t* bstR1 = reinterpret_cast<uint32_t*>(ws + P.bstR1);
     rc = bucket_pass(Rin, R1, (uint32_t)P.nR, sR1, 1, P.NB1, P.OS1, P.seed ^ TAG_R1,
                      reinterpret_cast<uint64_t*>(ws + P.splR1), reinterpret_cast<uint32_t*>(ws + P.cR1), P.cntR1,
-                     bsum, P.tilesR1, bstR1, st);
+                     bsum, P.tilesR1, bstR1, st, mk, MK_R1_SPL);
     if (rc != MPSM_OK) return rc;
     SortOut soR;
     soR.run_idx = nullptr;
     soR.run_start = nullptr;
     soR.idx_stride = 1;
+    soR.idx_shift = 0;
     soR.idx_per_run = 0;
     soR.NB = 1;
     soR.bkey = reinterpret_cast<uint64_t*>(ws + P.bkey);
     const tup_t* Rsorted;
     const uint32_t* bstR;
+    uint32_t* redoR = reinterpret_cast<uint32_t*>(ws + P.redoR);
     if (P.levels == 2) {
       Seg sR2 = seg_at(ws, P.segR2, P.NB1);
       k_seg_from_buckets<<<(uint32_t)cdiv(P.NB1, 256), 256, 0, st>>>(bstR1, P.NB1, sR2.start, sR2.len);
@@ -387,19 +448,34 @@ mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       uint32_t* bstR2 = reinterpret_cast<uint32_t*>(ws + P.bstR2);
       rc = bucket_pass(R1, R2, (uint32_t)P.nR, sR2, P.NB1, P.NB2, P.OS2, P.seed ^ TAG_R2,
                        reinterpret_cast<uint64_t*>(ws + P.splR2), reinterpret_cast<uint32_t*>(ws + P.cR2), P.cntR2,
-                       bsum, P.tilesR2, bstR2, st);
+                       bsum, P.tilesR2, bstR2, st, mk, MK_R2_SPL);
       if (rc != MPSM_OK) return rc;
-      k_bucket_sort<<<P.Gr, SORT_NT, 0, st>>>(R2, R1, bstR2, reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
+      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M><<<P.Gr, BL_NT, 0, st>>>(R2, R1, bstR2, P.Gr, nullptr, nullptr,
+                                                                   reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1,
+                                                                   redoR, ctr + 4, soR);
       LAUNCH_CHECK();
+      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(R2, R1, bstR2, redoR, ctr + 4,
+                                                      reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
+      LAUNCH_CHECK();
+      mk.mark(MK_R_SORT);
       k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(R2, R1, bstR2, reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
       LAUNCH_CHECK();
+      mk.mark(MK_R_BIG);
       Rsorted = R1;
       bstR = bstR2;
     } else {
-      k_bucket_sort<<<P.Gr, SORT_NT, 0, st>>>(R1, R2, bstR1, reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
+      mk.mark_range(MK_R2_SPL, MK_R2_SCAT);
+      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M><<<P.Gr, BL_NT, 0, st>>>(R1, R2, bstR1, P.Gr, nullptr, nullptr,
+                                                                   reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1,
+                                                                   redoR, ctr + 4, soR);
       LAUNCH_CHECK();
+      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(R1, R2, bstR1, redoR, ctr + 4,
+                                                      reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
+      LAUNCH_CHECK();
+      mk.mark(MK_R_SORT);
       k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(R1, R2, bstR1, reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
       LAUNCH_CHECK();
+      mk.mark(MK_R_BIG);
       Rsorted = R2;
       bstR = bstR1;
     }
@@ -409,6 +485,7 @@ mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + P.pkey);
     k_partitions<<<1, 1024, 0, st>>>(bstR, soR.bkey, P.Gr, Pc, pstart, plen, pkey);
     LAUNCH_CHECK();
+    mk.mark(MK_PART);
 
     // ---- phase 4: merge starts of every partition in every run, then the join
     uint32_t* o = reinterpret_cast<uint32_t*>(ws + P.o);
@@ -418,12 +495,14 @@ mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
                                                           P.idx_per_run, Pc, pkey, P.Pmax, o, P.search,
                                                           stats ? res : nullptr);
     LAUNCH_CHECK();
+    mk.mark(MK_SEARCH);
     uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
     uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
     k_join_items<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, o, P.Q, P.Pmax, P.JCH, items);
     LAUNCH_CHECK();
     rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
     if (rc != MPSM_OK) return rc;
+    mk.mark(MK_ITEMS);
 
     JoinArgs A;
     A.Rs = Rsorted;
@@ -454,9 +533,12 @@ mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       k_join<2, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
       LAUNCH_CHECK();
     }
+    mk.mark(MK_JOIN);
     k_finalize<<<1, 64, 0, st>>>(res, d_out_count, d_out_checksum);
     LAUNCH_CHECK();
+    mk.mark(MK_FIN);
   }
+  if (!mk.ok) return MPSM_EHIP;
   if (stats) {
     HIP_TRY(hipEventRecord(ev1, st));
     HIP_TRY(hipEventSynchronize(ev1));
@@ -482,6 +564,50 @@ mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     if (d_pairs && r.count > pairs_capacity) return MPSM_ECAPACITY;
   }
   return MPSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS, uint64_t* d_out_count,
+                      uint64_t* d_out_checksum, mpsm_pair* d_pairs, uint64_t pairs_capacity, const mpsm_config* cfg,
+                      void* d_workspace, uint64_t workspace_bytes, void* stream, mpsm_stats* stats) {
+  return join_impl(d_R, nR, d_S, nS, d_out_count, d_out_checksum, d_pairs, pairs_capacity, cfg, d_workspace,
+                   workspace_bytes, stream, stats, nullptr, 0);
+}
+
+mpsm_status mpsm_join_events(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS,
+                             uint64_t* d_out_count, uint64_t* d_out_checksum, mpsm_pair* d_pairs,
+                             uint64_t pairs_capacity, const mpsm_config* cfg, void* d_workspace,
+                             uint64_t workspace_bytes, void* stream, void** events, uint32_t n_events) {
+  if (n_events && !events) return MPSM_EINVAL;
+  return join_impl(d_R, nR, d_S, nS, d_out_count, d_out_checksum, d_pairs, pairs_capacity, cfg, d_workspace,
+                   workspace_bytes, stream, nullptr, events, n_events);
+}
+
+uint32_t mpsm_marker_count(void) { return kNumMarkers; }
+
+const char* mpsm_marker_name(uint32_t i) { return i < kNumMarkers ? kMarkers[i] : nullptr; }
+
+mpsm_status mpsm_events_create(void** events, uint32_t n) {
+  if (n && !events) return MPSM_EINVAL;
+  for (uint32_t i = 0; i < n; i++) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return MPSM_EHIP;
+    events[i] = e;
+  }
+  return MPSM_OK;
+}
+
+void mpsm_events_destroy(void** events, uint32_t n) {
+  for (uint32_t i = 0; events && i < n; i++)
+    if (events[i]) { (void)hipEventDestroy((hipEvent_t)events[i]); events[i] = nullptr; }
+}
+
+mpsm_status mpsm_events_elapsed(void* start, void* stop, float* ms) {
+  if (!start || !stop || !ms) return MPSM_EINVAL;
+  return hipEventElapsedTime(ms, (hipEvent_t)start, (hipEvent_t)stop) == hipSuccess ? MPSM_OK : MPSM_EHIP;
 }
 
 }  // extern "C"
