@@ -21,7 +21,7 @@
 // ------------------------------------------------------------------ config
 // bucket sort instances: small tiles for S buckets, large tiles (= the join's
 // LDS partition capacity) for R partitions and for S buckets that overflow
-constexpr int BS_NT = 512, BS_IPT = 8, BS_M = 4096;      // 4096 tuples
+constexpr int BS_NT = 1024, BS_IPT = 4, BS_M = 2048;     // 4096 tuples
 constexpr int BL_NT = 1024, BL_IPT = 8, BL_M = 4096;     // 8192 tuples
 constexpr int BS_CAP = BS_NT * BS_IPT;
 constexpr int BL_CAP = BL_NT * BL_IPT;
@@ -92,21 +92,35 @@ __global__ void k_seg_from_buckets(const uint32_t* bstart, uint32_t nseg, uint32
   seg_len[s] = bstart[s + 1] - bstart[s];
 }
 
-// seg_tile0 = prefix of tile counts, seg_cnt0 = prefix of NB * tiles.
-__global__ void __launch_bounds__(1024) k_seg_plan(uint32_t nseg, uint32_t NB, uint32_t TILE, const uint32_t* seg_len,
-                                                   uint32_t* seg_tile0, uint32_t* seg_cnt0) {
-  __shared__ uint32_t wsum[1024 / 64 + 2];
-  uint32_t carry = 0;
+// Per-segment plan: tiles, bucket count and their prefixes.
+//   seg_nb[s]    buckets of segment s: NBmax, or (BT != 0) ceil(len/BT)
+//                clamped to [1, NBmax], so buckets average at most BT tuples
+//   seg_tile0    prefix of tile counts (nseg + 1 entries)
+//   seg_cnt0     prefix of seg_nb * tiles (count-matrix offsets)
+//   seg_b0       prefix of seg_nb (global bucket ids)
+__global__ void __launch_bounds__(1024) k_seg_plan(uint32_t nseg, uint32_t NBmax, uint32_t BT, uint32_t TILE,
+                                                   const uint32_t* seg_len, uint32_t* seg_tile0, uint32_t* seg_cnt0,
+                                                   uint32_t* seg_nb, uint32_t* seg_b0) {
+  __shared__ uint32_t wsum[3][1024 / 64 + 2];
+  uint32_t c1 = 0, c2 = 0, c3 = 0;
   for (uint32_t b = 0; b < nseg; b += 1024) {
     const uint32_t s = b + threadIdx.x;
-    const uint32_t nt = s < nseg ? (seg_len[s] + TILE - 1) / TILE : 0;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<1024>(nt, wsum, &tot);
-    if (s < nseg) { seg_tile0[s] = carry + ex; seg_cnt0[s] = (carry + ex) * NB; }
-    carry += tot;
+    const uint32_t len = s < nseg ? seg_len[s] : 0;
+    const uint32_t nt = (len + TILE - 1) / TILE;
+    uint32_t nb = 0;
+    if (s < nseg) {
+      nb = BT ? (len + BT - 1) / BT : NBmax;
+      nb = nb < 1 ? 1 : (nb > NBmax ? NBmax : nb);
+    }
+    uint32_t t1, t2, t3;
+    const uint32_t e1 = block_excl_scan<1024>(nt, wsum[0], &t1);
+    const uint32_t e2 = block_excl_scan<1024>(nt * nb, wsum[1], &t2);
+    const uint32_t e3 = block_excl_scan<1024>(nb, wsum[2], &t3);
+    if (s < nseg) { seg_tile0[s] = c1 + e1; seg_cnt0[s] = c2 + e2; seg_nb[s] = nb; seg_b0[s] = c3 + e3; }
+    c1 += t1; c2 += t2; c3 += t3;
     __syncthreads();
   }
-  if (threadIdx.x == 0) { seg_tile0[nseg] = carry; seg_cnt0[nseg] = carry * NB; }
+  if (threadIdx.x == 0) { seg_tile0[nseg] = c1; seg_cnt0[nseg] = c2; seg_b0[nseg] = c3; }
 }
 
 // ------------------------------------------------------------------- scan
@@ -164,25 +178,24 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const uint32_t* in, uint
 
 // ------------------------------------------------------- sampled splitters
 
-// One workgroup per segment: draw NB*OS keys at uniform positions of the
+// One workgroup per segment: draw nb*OS keys at uniform positions of the
 // segment (SplitMix64 stream seg_seed = splitmix_at(level_seed, s)), sort
-// them, and keep every OS-th as the NB-1 splitters of the segment.
+// them, and keep every OS-th as the nb-1 splitters of the segment
+// (nb = seg_nb[s]; splitters of segment s start at s*(NBmax-1)).
 template <int NT, int IPT>
 __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict__ src, const uint32_t* seg_start,
-                                                         const uint32_t* seg_len, uint32_t NB, uint32_t OS,
-                                                         uint64_t level_seed, uint64_t* spl) {
+                                                         const uint32_t* seg_len, const uint32_t* seg_nb,
+                                                         uint32_t NBmax, uint32_t OS, uint64_t level_seed,
+                                                         uint64_t* spl) {
   using Sorter = BlockSort<NT, IPT, 4>;
   __shared__ uint64_t buf[Sorter::BUF_WORDS];
   __shared__ uint32_t wsum[Sorter::WSUM_WORDS];
   __shared__ uint64_t red[NT / 64 + 1];
   const uint32_t s = blockIdx.x, tid = threadIdx.x;
-  const uint32_t len = seg_len[s], start = seg_start[s];
-  const uint32_t M = NB * OS;
-  uint64_t* out = spl + (uint64_t)s * (NB - 1);
-  if (len == 0) {
-    for (uint32_t b = tid; b + 1 < NB; b += NT) out[b] = 0;
-    return;
-  }
+  const uint32_t len = seg_len[s], start = seg_start[s], nb = seg_nb[s];
+  if (len == 0 || nb < 2) return;
+  const uint32_t M = nb * OS;
+  uint64_t* out = spl + (uint64_t)s * (NBmax - 1);
   const uint64_t seed = splitmix_at(level_seed, s);
   uint64_t key[IPT], dummy[IPT];
 #pragma unroll
@@ -218,9 +231,9 @@ __device__ __forceinline__ uint32_t seg_of_tile(const uint32_t* seg_tile0, uint3
 // Per-tile bucket histogram; cnt layout [segment][bucket][tile].
 __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict__ src, const uint32_t* seg_start,
                                                          const uint32_t* seg_len, const uint32_t* seg_tile0,
-                                                         const uint32_t* seg_cnt0, uint32_t nseg,
-                                                         const uint64_t* spl, uint32_t NB, uint32_t TILE,
-                                                         uint32_t* cnt) {
+                                                         const uint32_t* seg_cnt0, const uint32_t* seg_nb,
+                                                         uint32_t nseg, const uint64_t* spl, uint32_t NBmax,
+                                                         uint32_t TILE, uint32_t* cnt) {
   __shared__ uint64_t sp[MAX_NB];
   __shared__ uint32_t h[MAX_NB];
   __shared__ SplitDir<SPLIT_DIR> dir;
@@ -231,8 +244,8 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
   const uint32_t segend = seg_start[s] + seg_len[s];
   const uint32_t a = seg_start[s] + t * TILE;
   const uint32_t b = min(a + TILE, segend);
-  const uint32_t nspl = NB - 1;
-  for (uint32_t i = threadIdx.x; i < nspl; i += HIST_NT) sp[i] = spl[(uint64_t)s * nspl + i];
+  const uint32_t NB = seg_nb[s], nspl = NB - 1;
+  for (uint32_t i = threadIdx.x; i < nspl; i += HIST_NT) sp[i] = spl[(uint64_t)s * (NBmax - 1) + i];
   for (uint32_t i = threadIdx.x; i < NB; i += HIST_NT) h[i] = 0;
   __syncthreads();
   if (nspl) dir.build<HIST_NT>(sp, nspl);
@@ -258,8 +271,8 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
 __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
                                                             const uint32_t* seg_start, const uint32_t* seg_len,
                                                             const uint32_t* seg_tile0, const uint32_t* seg_cnt0,
-                                                            uint32_t nseg, const uint64_t* spl, uint32_t NB,
-                                                            uint32_t TILE, const uint32_t* pos) {
+                                                            const uint32_t* seg_nb, uint32_t nseg, const uint64_t* spl,
+                                                            uint32_t NBmax, uint32_t TILE, const uint32_t* pos) {
   __shared__ uint64_t sp[MAX_NB];
   __shared__ uint32_t cursor[MAX_NB], lcnt[MAX_NB], lofs[MAX_NB];
   __shared__ tup_t stage[SCAT_CH];
@@ -273,8 +286,8 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   const uint32_t segend = seg_start[s] + seg_len[s];
   const uint32_t a = seg_start[s] + t * TILE;
   const uint32_t b = min(a + TILE, segend);
-  const uint32_t nspl = NB - 1;
-  for (uint32_t i = tid; i < nspl; i += SCAT_NT) sp[i] = spl[(uint64_t)s * nspl + i];
+  const uint32_t NB = seg_nb[s], nspl = NB - 1;
+  for (uint32_t i = tid; i < nspl; i += SCAT_NT) sp[i] = spl[(uint64_t)s * (NBmax - 1) + i];
   const uint32_t* p = pos + seg_cnt0[s] + t;
   for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] = p[(uint64_t)i * ntiles]; lcnt[i] = 0; }
   __syncthreads();
@@ -342,16 +355,31 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   }
 }
 
-// Start of every global bucket g = s*NB + b (bstart has nseg*NB + 1 entries).
-__global__ void k_bucket_table(uint32_t nseg, uint32_t NB, const uint32_t* seg_start, const uint32_t* seg_tile0,
-                               const uint32_t* seg_cnt0, const uint32_t* pos, uint32_t n, uint32_t* bstart) {
+// Start and key bounds of every global bucket g = seg_b0[s] + b.  bstart has
+// G + 1 entries, G = seg_b0[nseg].  Every key of bucket b of segment s lies
+// in [blo[g], bhi[g]]: the splitters around it (bucket b holds keys from
+// spl[b-1] up to spl[b], the upper end for a key moved down by the
+// equal-splitter rule), or the bounds of the enclosing segment, which are
+// the splitters of the previous level (outer, with outer_nspl entries), or
+// [0, 2^64-1] at the first level.
+__global__ void k_bucket_table(uint32_t nseg, uint32_t NBmax, const uint32_t* seg_start, const uint32_t* seg_tile0,
+                               const uint32_t* seg_cnt0, const uint32_t* seg_nb, const uint32_t* seg_b0,
+                               const uint32_t* pos, uint32_t n, const uint64_t* spl, const uint64_t* outer,
+                               uint32_t outer_nspl, uint32_t* bstart, uint64_t* blo, uint64_t* bhi) {
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t G = nseg * NB;
+  const uint32_t G = seg_b0[nseg];
   if (g > G) return;
   if (g == G) { bstart[G] = n; return; }
-  const uint32_t s = g / NB, b = g % NB;
+  uint32_t lo = 0, hi = nseg;   // last s with seg_b0[s] <= g
+  while (hi - lo > 1) { const uint32_t m = (lo + hi) >> 1; if (seg_b0[m] <= g) lo = m; else hi = m; }
+  const uint32_t s = lo, b = g - seg_b0[s], nb = seg_nb[s];
   const uint32_t nt = seg_tile0[s + 1] - seg_tile0[s];
   bstart[g] = nt ? pos[seg_cnt0[s] + b * nt] : seg_start[s];
+  const uint64_t olo = (outer && s > 0) ? outer[s - 1] : 0ull;
+  const uint64_t ohi = (outer && s < outer_nspl) ? outer[s] : ~0ull;
+  const uint64_t* sp = spl + (uint64_t)s * (NBmax - 1);
+  blo[g] = b > 0 ? sp[b - 1] : olo;
+  bhi[g] = b + 1 < nb ? sp[b] : ohi;
 }
 
 // ------------------------------------------------------------ bucket sort
@@ -389,41 +417,22 @@ __device__ __forceinline__ void emit_sorted(const SortOut& so, uint32_t g, uint3
 // list of bucket ids instead of all G buckets.
 constexpr int CS_GMAX = 32;
 
-template <int NT>
-__device__ __forceinline__ void block_minmax64(uint64_t& mn, uint64_t& mx, uint64_t* red) {
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) {
-    const uint64_t a = __shfl_xor(mn, d, 64), b = __shfl_xor(mx, d, 64);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
-  }
-  if (lane == 0) { red[2 * w] = mn; red[2 * w + 1] = mx; }
-  __syncthreads();
-  mn = red[0]; mx = red[1];
-#pragma unroll
-  for (int i = 1; i < NT / 64; i++) {
-    mn = red[2 * i] < mn ? red[2 * i] : mn;
-    mx = red[2 * i + 1] > mx ? red[2 * i + 1] : mx;
-  }
-}
-
-template <int NT, int IPT, int M>
-__global__ void __launch_bounds__(NT) k_bucket_sort_cs(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
-                                                       const uint32_t* bstart, uint32_t G, const uint32_t* in_list,
-                                                       const unsigned long long* in_count, uint32_t* over_list,
-                                                       unsigned long long* over_count, uint32_t* redo_list,
-                                                       unsigned long long* redo_count, SortOut so) {
+template <int NT, int IPT, int M, int MINB>
+__global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
+                                                       const uint32_t* bstart, const uint64_t* blo,
+                                                       const uint64_t* bhi, const uint32_t* Gcount,
+                                                       const uint32_t* in_list, const unsigned long long* in_count,
+                                                       uint32_t* over_list, unsigned long long* over_count,
+                                                       uint32_t* redo_list, unsigned long long* redo_count,
+                                                       SortOut so) {
   constexpr int CAP = NT * IPT;
   constexpr int PER = M / NT;
   static_assert(M % NT == 0, "sub-buckets per thread");
   __shared__ uint64_t sk[CAP];               // keys grouped by sub-bucket
   __shared__ uint32_t cnt[M + 1];
   __shared__ uint32_t wsum[NT / 64 + 2];
-  __shared__ uint64_t red[2 * (NT / 64) + 2];
-  __shared__ uint64_t scale;
   const uint32_t tid = threadIdx.x;
-  const uint32_t nitems = in_list ? (uint32_t)*in_count : G;
+  const uint32_t nitems = in_list ? (uint32_t)*in_count : *Gcount;
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
     const uint32_t g = in_list ? in_list[it] : it;
     const uint32_t a = bstart[g], n = bstart[g + 1] - a;
@@ -432,39 +441,37 @@ __global__ void __launch_bounds__(NT) k_bucket_sort_cs(const tup_t* __restrict__
       if (tid == 0) over_list[atomicAdd(over_count, 1ull)] = g;
       continue;
     }
+    const uint64_t lo = blo[g], span = bhi[g] - lo;
     uint64_t key[IPT], val[IPT];
-    uint64_t mn = ~0ull, mx = 0;
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
       const uint32_t i = k * NT + tid;
       if (i < n) {
         const tup_t v = load_tup(src + a + i);
         key[k] = v.key; val[k] = v.pay;
-        mn = v.key < mn ? v.key : mn;
-        mx = v.key > mx ? v.key : mx;
       } else {
         key[k] = ~0ull; val[k] = 0;
       }
     }
-    __syncthreads();   // LDS of the previous bucket is free
-    block_minmax64<NT>(mn, mx, red);
     uint32_t fin[IPT];
-    if (mn == mx) {  // one key: input order is sorted order
+    bool bad = false;
+    if (span == 0) {  // one key: input order is sorted order
 #pragma unroll
       for (int k = 0; k < IPT; k++) fin[k] = k * NT + tid;
     } else {
-      const uint64_t span = mx - mn;
       const bool exact = span < (uint64_t)M;   // one key per sub-bucket
-      if (tid == 0) scale = exact ? 0ull : interp_scale(M, span);
+      const uint64_t C = exact ? 0ull : interp_scale(M, span);
+      __syncthreads();   // LDS of the previous bucket is free
       for (uint32_t b = tid; b <= (uint32_t)M; b += NT) cnt[b] = 0;
       __syncthreads();
-      const uint64_t C = scale;
       uint32_t d[IPT], pos[IPT];
 #pragma unroll
       for (int k = 0; k < IPT; k++) {
         if (k * NT + tid < n) {
-          const uint64_t x = key[k] - mn;
-          d[k] = exact ? (uint32_t)x : (uint32_t)__umul64hi(x, C);
+          const uint64_t x = key[k] - lo;
+          bad |= x > span;                      // outside the bucket's bounds: never expected
+          uint32_t dd = exact ? (uint32_t)x : (uint32_t)__umul64hi(x, C);
+          d[k] = dd < (uint32_t)M ? dd : (uint32_t)(M - 1);
           pos[k] = atomicAdd(&cnt[d[k]], 1u);
         }
       }
@@ -487,30 +494,37 @@ __global__ void __launch_bounds__(NT) k_bucket_sort_cs(const tup_t* __restrict__
           if (!exact) sk[fin[k]] = key[k];
         }
       }
-      bool bad = false;
       if (!exact) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < IPT; k++) {
           if (k * NT + tid < n) {
-            const uint32_t lo = cnt[d[k]], hi = cnt[d[k] + 1], p = fin[k];
-            if (hi - lo > (uint32_t)CS_GMAX) {
+            const uint32_t gl = cnt[d[k]], gs = cnt[d[k] + 1] - gl, p = fin[k];
+            if (gs > (uint32_t)CS_GMAX) {
               bad = true;
-            } else {
-              uint32_t r = lo;
-              for (uint32_t q = lo; q < hi; q++) {
-                const uint64_t kq = sk[q];
-                r += (kq < key[k]) || (kq == key[k] && q < p);
+            } else if (gs > 1) {
+              uint32_t r = gl;
+              if (gs <= 4) {   // common case: independent reads
+#pragma unroll
+                for (uint32_t t = 0; t < 4; t++) {
+                  const uint32_t q = gl + t;
+                  if (t < gs) { const uint64_t kq = sk[q]; r += (kq < key[k]) || (kq == key[k] && q < p); }
+                }
+              } else {
+                for (uint32_t q = gl; q < gl + gs; q++) {
+                  const uint64_t kq = sk[q];
+                  r += (kq < key[k]) || (kq == key[k] && q < p);
+                }
               }
               fin[k] = r;
             }
           }
         }
       }
-      if (__syncthreads_or(bad)) {
-        if (tid == 0) redo_list[atomicAdd(redo_count, 1ull)] = g;
-        continue;
-      }
+    }
+    if (__syncthreads_or(bad)) {
+      if (tid == 0) redo_list[atomicAdd(redo_count, 1ull)] = g;
+      continue;
     }
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
@@ -635,10 +649,11 @@ __global__ void __launch_bounds__(BIG_NT) k_big_sort(tup_t* __restrict__ src, tu
 
 // Compact the non-empty R buckets into partitions p = 0..P-1 (start, length,
 // first key).  Single workgroup.
-__global__ void __launch_bounds__(1024) k_partitions(const uint32_t* bstart, const uint64_t* bkey, uint32_t G,
-                                                     uint32_t* Pcount, uint32_t* pstart, uint32_t* plen,
-                                                     uint64_t* pkey) {
+__global__ void __launch_bounds__(1024) k_partitions(const uint32_t* bstart, const uint64_t* bkey,
+                                                     const uint32_t* Gcount, uint32_t* Pcount, uint32_t* pstart,
+                                                     uint32_t* plen, uint64_t* pkey) {
   __shared__ uint32_t wsum[1024 / 64 + 2];
+  const uint32_t G = *Gcount;
   uint32_t carry = 0;
   for (uint32_t b = 0; b < G; b += 1024) {
     const uint32_t g = b + threadIdx.x;
@@ -822,6 +837,9 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
   const uint32_t total = A.item_pre[np2 - 1];
   unsigned long long cnt = 0, sum = 0, mx = 0;
   bool any = false;
+  constexpr int JPF = JOIN_CAP / JOIN_NT;   // R tuples per thread
+  tup_t pre[JPF];                          // next item's R partition, loaded during this item
+  bool have_pre = false;
   for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
     const uint32_t p = item_partition(A.item_pre, np2, item);
     const uint32_t k = item - A.item_pre[p];
@@ -845,10 +863,31 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
     if (tid == 0) { cum[Q] = carry; item_acc = 0; }
     const bool in_lds = rn <= (uint32_t)JOIN_CAP;
     if (in_lds) {
-      for (uint32_t i = tid; i < rn; i += JOIN_NT) {
-        const tup_t t = load_tup(A.Rs + rs + i);
-        rk[i] = t.key;
-        rv[i] = (VM == VAL_HR) ? r_prefix_hash(t.key, t.pay) : t.pay;
+#pragma unroll
+      for (int r = 0; r < JPF; r++) {
+        const uint32_t i = r * JOIN_NT + tid;
+        if (i < rn) {
+          const tup_t t = have_pre ? pre[r] : load_tup(A.Rs + rs + i);
+          rk[i] = t.key;
+          rv[i] = (VM == VAL_HR) ? r_prefix_hash(t.key, t.pay) : t.pay;
+        }
+      }
+    }
+    // start loading the next item's partition; it arrives while this one is joined
+    have_pre = false;
+    {
+      const uint32_t nxt = item + gridDim.x;
+      if (nxt < total) {
+        const uint32_t p2 = item_partition(A.item_pre, np2, nxt);
+        const uint32_t rs2 = A.pstart[p2], rn2 = A.plen[p2];
+        if (rn2 <= (uint32_t)JOIN_CAP) {
+#pragma unroll
+          for (int r = 0; r < JPF; r++) {
+            const uint32_t i = r * JOIN_NT + tid;
+            if (i < rn2) pre[r] = load_tup(A.Rs + rs2 + i);
+          }
+          have_pre = true;
+        }
       }
     }
     __syncthreads();

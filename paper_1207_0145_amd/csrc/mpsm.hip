@@ -29,7 +29,7 @@ struct Plan {
   uint32_t levels, NB1, OS1, NB2, OS2;
   uint32_t Gs, Gr, Pmax;
   uint32_t idx_per_run;
-  uint32_t JCH;
+  uint32_t JCH, BT;
   int search, splitter, want_max;
   uint64_t seed;
   uint32_t tilesS, tilesR1, tilesR2;       // upper bounds of histogram tiles
@@ -41,14 +41,15 @@ struct Plan {
   uint64_t segS, segR1, segR2;             // 4 arrays each: start, len, tile0, cnt0
   uint64_t splS, splR1, splR2;
   uint64_t bstS, bstR1, bstR2;
+  uint64_t bndS, bndR1, bndR2;             // per-bucket key bounds (lo array, then hi array)
   uint64_t bigS, midS, redoS, redoR, bigR, ctr;
   uint64_t bkey, Pc, pstart, plen, pkey;
   uint64_t ridx, o, items, item_pre, item_cnt, res;
   uint64_t total;
 };
 
-struct Seg {  // device pointers of one segment table
-  uint32_t *start, *len, *tile0, *cnt0;
+struct Seg {  // device pointers of one segment table (nseg + 1 entries each)
+  uint32_t *start, *len, *tile0, *cnt0, *nb, *b0;
 };
 
 bool config_valid(const mpsm_config* c) {
@@ -103,7 +104,9 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
     P->levels = 2;
     P->NB1 = MAX_NB;
     P->OS1 = cfg->oversample ? os_for(P->NB1) : 16u;
-    P->NB2 = next_pow2(cdiv(F, MAX_NB));
+    // level-2 buckets per level-1 bucket: ceil(len / BT), at most twice the
+    // average need (level-1 buckets are sampled, so their sizes vary)
+    P->NB2 = 2 * next_pow2(cdiv(F, MAX_NB));
     if (P->NB2 > (uint32_t)MAX_NB) P->NB2 = MAX_NB;
     P->OS2 = os_for(P->NB2);
   }
@@ -112,6 +115,7 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->Pmax = P->Gr;
   P->idx_per_run = (uint32_t)cdiv(L, IDX_STRIDE);
   P->JCH = cfg->join_chunk ? cfg->join_chunk : 32768u;
+  P->BT = BT;
   P->tilesS = (uint32_t)(P->nS / HIST_TILE + P->Q);
   P->tilesR1 = (uint32_t)(P->nR / HIST_TILE + 1);
   P->tilesR2 = (uint32_t)(P->nR / HIST_TILE + P->NB1);
@@ -135,15 +139,18 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   if (P->cntR2 > maxscan) maxscan = P->cntR2;
   if (P->item_cap > maxscan) maxscan = P->item_cap;
   P->bsum = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);
-  P->segS = take(4ull * (P->Q + 1) * 4);
-  P->segR1 = take(4ull * 2 * 4);
-  P->segR2 = take(4ull * (P->NB1 + 1) * 4);
+  P->segS = take(6ull * (P->Q + 1) * 4);
+  P->segR1 = take(6ull * 2 * 4);
+  P->segR2 = take(6ull * (P->NB1 + 1) * 4);
   P->splS = take((uint64_t)P->Q * P->NBs * 8);
   P->splR1 = take((uint64_t)P->NB1 * 8);
   P->splR2 = take((uint64_t)P->NB1 * P->NB2 * 8);
   P->bstS = take(((uint64_t)P->Gs + 1) * 4);
   P->bstR1 = take(((uint64_t)P->NB1 + 1) * 4);
   P->bstR2 = take(((uint64_t)P->Gr + 1) * 4);
+  P->bndS = take((uint64_t)P->Gs * 16);
+  P->bndR1 = take((uint64_t)P->NB1 * 16);
+  P->bndR2 = take((uint64_t)P->Gr * 16);
   P->bigS = take((uint64_t)P->Gs * 4);
   P->midS = take((uint64_t)P->Gs * 4);
   P->redoS = take((uint64_t)P->Gs * 4);
@@ -172,6 +179,8 @@ Seg seg_at(char* ws, uint64_t off, uint32_t nseg) {
   s.len = b + (nseg + 1);
   s.tile0 = b + 2 * (nseg + 1);
   s.cnt0 = b + 3 * (nseg + 1);
+  s.nb = b + 4 * (nseg + 1);
+  s.b0 = b + 5 * (nseg + 1);
   return s;
 }
 
@@ -219,38 +228,73 @@ struct Marker {
   }
 };
 
+// Buffers of one bucket pass.
+struct Level {
+  Seg seg;
+  uint32_t nseg, NBmax, BT, OS, max_tiles, Gmax;
+  uint64_t level_seed;
+  uint64_t* spl;
+  uint32_t* cnt;
+  uint64_t ncnt;
+  uint32_t* bstart;
+  uint64_t *blo, *bhi;
+  const uint64_t* outer;     // splitters of the previous level (NULL at the first level)
+  uint32_t outer_nspl;
+  const uint32_t* Gcount() const { return seg.b0 + nseg; }
+};
+
+Level make_level(char* ws, uint64_t seg_off, uint32_t nseg, uint32_t NBmax, uint32_t BT, uint32_t OS,
+                 uint32_t max_tiles, uint64_t level_seed, uint64_t spl_off, uint64_t cnt_off, uint64_t ncnt,
+                 uint64_t bst_off, uint64_t bnd_off, uint32_t Gmax) {
+  Level L;
+  L.seg = seg_at(ws, seg_off, nseg);
+  L.nseg = nseg; L.NBmax = NBmax; L.BT = BT; L.OS = OS; L.max_tiles = max_tiles; L.Gmax = Gmax;
+  L.level_seed = level_seed;
+  L.spl = reinterpret_cast<uint64_t*>(ws + spl_off);
+  L.cnt = reinterpret_cast<uint32_t*>(ws + cnt_off);
+  L.ncnt = ncnt;
+  L.bstart = reinterpret_cast<uint32_t*>(ws + bst_off);
+  L.blo = reinterpret_cast<uint64_t*>(ws + bnd_off);
+  L.bhi = L.blo + Gmax;
+  L.outer = nullptr;
+  L.outer_nspl = 0;
+  return L;
+}
+
 // One bucket pass over segments: splitters, histogram, scan, scatter, table.
 // Markers mk0 .. mk0+3 follow splitters, histogram, scan and scatter.
-mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, Seg seg, uint32_t nseg, uint32_t NB, uint32_t OS,
-                        uint64_t level_seed, uint64_t* spl, uint32_t* cnt, uint64_t ncnt, uint32_t* bsum,
-                        uint32_t max_tiles, uint32_t* bstart, hipStream_t st, Marker& mk, uint32_t mk0) {
-  k_seg_plan<<<1, 1024, 0, st>>>(nseg, NB, HIST_TILE, seg.len, seg.tile0, seg.cnt0);
+mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L, uint32_t* bsum, hipStream_t st,
+                        Marker& mk, uint32_t mk0) {
+  const Seg& sg = L.seg;
+  k_seg_plan<<<1, 1024, 0, st>>>(L.nseg, L.NBmax, L.BT, HIST_TILE, sg.len, sg.tile0, sg.cnt0, sg.nb, sg.b0);
   LAUNCH_CHECK();
-  if (NB > 1) {
-    if (NB * OS <= (uint32_t)(SMP_NT_S * SMP_IPT_S))
-      k_sample_splitters<SMP_NT_S, SMP_IPT_S><<<nseg, SMP_NT_S, 0, st>>>(src, seg.start, seg.len, NB, OS, level_seed, spl);
+  if (L.NBmax > 1) {
+    if (L.NBmax * L.OS <= (uint32_t)(SMP_NT_S * SMP_IPT_S))
+      k_sample_splitters<SMP_NT_S, SMP_IPT_S><<<L.nseg, SMP_NT_S, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax,
+                                                                           L.OS, L.level_seed, L.spl);
     else
-      k_sample_splitters<SMP_NT, SMP_IPT><<<nseg, SMP_NT, 0, st>>>(src, seg.start, seg.len, NB, OS, level_seed, spl);
+      k_sample_splitters<SMP_NT, SMP_IPT><<<L.nseg, SMP_NT, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax, L.OS,
+                                                                     L.level_seed, L.spl);
     LAUNCH_CHECK();
   }
   mk.mark(mk0);
-  if (max_tiles) {
-    k_bucket_hist<<<max_tiles, HIST_NT, 0, st>>>(src, seg.start, seg.len, seg.tile0, seg.cnt0, nseg, spl, NB,
-                                                 HIST_TILE, cnt);
+  if (L.max_tiles) {
+    k_bucket_hist<<<L.max_tiles, HIST_NT, 0, st>>>(src, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb, L.nseg, L.spl,
+                                                   L.NBmax, HIST_TILE, L.cnt);
     LAUNCH_CHECK();
     mk.mark(mk0 + 1);
-    mpsm_status rc = scan_u32(cnt, cnt, ncnt, bsum, st);
+    mpsm_status rc = scan_u32(L.cnt, L.cnt, L.ncnt, bsum, st);
     if (rc != MPSM_OK) return rc;
     mk.mark(mk0 + 2);
-    k_bucket_scatter<<<max_tiles, SCAT_NT, 0, st>>>(src, dst, seg.start, seg.len, seg.tile0, seg.cnt0, nseg, spl, NB,
-                                                    HIST_TILE, cnt);
+    k_bucket_scatter<<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb, L.nseg,
+                                                      L.spl, L.NBmax, HIST_TILE, L.cnt);
     LAUNCH_CHECK();
   } else {
     mk.mark_range(mk0 + 1, mk0 + 2);
   }
-  const uint32_t G = nseg * NB;
-  k_bucket_table<<<(uint32_t)cdiv(G + 1, 256), 256, 0, st>>>(nseg, NB, seg.start, seg.tile0, seg.cnt0, cnt, n,
-                                                             bstart);
+  k_bucket_table<<<(uint32_t)cdiv((uint64_t)L.Gmax + 1, 256), 256, 0, st>>>(
+      L.nseg, L.NBmax, sg.start, sg.tile0, sg.cnt0, sg.nb, sg.b0, L.cnt, n, L.spl, L.outer, L.outer_nspl, L.bstart,
+      L.blo, L.bhi);
   LAUNCH_CHECK();
   mk.mark(mk0 + 3);
   return MPSM_OK;
@@ -389,17 +433,15 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
   } else {
     mpsm_status rc;
     // ---- phase 1: sort S into Q runs of L tuples
-    Seg sS = seg_at(ws, P.segS, P.Q);
-    k_seg_uniform<<<(uint32_t)cdiv(P.Q, 256), 256, 0, st>>>((uint32_t)P.nS, P.L, P.Q, sS.start, sS.len);
+    Level LS = make_level(ws, P.segS, P.Q, P.NBs, 0, P.OSs, P.tilesS, P.seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
+                          P.bndS, P.Gs);
+    k_seg_uniform<<<(uint32_t)cdiv(P.Q, 256), 256, 0, st>>>((uint32_t)P.nS, P.L, P.Q, LS.seg.start, LS.seg.len);
     LAUNCH_CHECK();
-    uint32_t* bstS = reinterpret_cast<uint32_t*>(ws + P.bstS);
-    rc = bucket_pass(Sin, T, (uint32_t)P.nS, sS, P.Q, P.NBs, P.OSs, P.seed ^ TAG_S,
-                     reinterpret_cast<uint64_t*>(ws + P.splS), reinterpret_cast<uint32_t*>(ws + P.cS), P.cntS, bsum,
-                     P.tilesS, bstS, st, mk, MK_S_SPL);
+    rc = bucket_pass(Sin, T, (uint32_t)P.nS, LS, bsum, st, mk, MK_S_SPL);
     if (rc != MPSM_OK) return rc;
     SortOut soS;
     soS.run_idx = reinterpret_cast<uint64_t*>(ws + P.ridx);
-    soS.run_start = sS.start;
+    soS.run_start = LS.seg.start;
     soS.idx_stride = IDX_STRIDE;
     soS.idx_shift = __builtin_ctz(IDX_STRIDE);
     soS.idx_per_run = P.idx_per_run;
@@ -408,27 +450,26 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
     uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
     uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
-    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M><<<P.Gs, BS_NT, 0, st>>>(T, U, bstS, P.Gs, nullptr, nullptr, midS, ctr + 2,
-                                                                 redoS, ctr + 3, soS);
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+                                                                 nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
     LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M><<<g_num_cus, BL_NT, 0, st>>>(T, U, bstS, 0, midS, ctr + 2, bigS, ctr + 0,
-                                                                      redoS, ctr + 3, soS);
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+                                                                      midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
+                                                                      soS);
     LAUNCH_CHECK();
-    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, bstS, redoS, ctr + 3, bigS, ctr + 0, soS);
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, redoS, ctr + 3, bigS, ctr + 0, soS);
     LAUNCH_CHECK();
     mk.mark(MK_S_SORT);
-    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, bstS, reinterpret_cast<uint32_t*>(ws + P.bigS), ctr + 0, soS);
+    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, bigS, ctr + 0, soS);
     LAUNCH_CHECK();
     mk.mark(MK_S_BIG);
 
     // ---- phase 2: range-partition R (one or two levels); phase 3: sort partitions
-    Seg sR1 = seg_at(ws, P.segR1, 1);
-    k_seg_uniform<<<1, 64, 0, st>>>((uint32_t)P.nR, (uint32_t)P.nR, 1, sR1.start, sR1.len);
+    Level LR1 = make_level(ws, P.segR1, 1, P.NB1, 0, P.OS1, P.tilesR1, P.seed ^ TAG_R1, P.splR1, P.cR1, P.cntR1,
+                           P.bstR1, P.bndR1, P.NB1);
+    k_seg_uniform<<<1, 64, 0, st>>>((uint32_t)P.nR, (uint32_t)P.nR, 1, LR1.seg.start, LR1.seg.len);
     LAUNCH_CHECK();
-    uint32_t* bstR1 = reinterpret_cast<uint32_t*>(ws + P.bstR1);
-    rc = bucket_pass(Rin, R1, (uint32_t)P.nR, sR1, 1, P.NB1, P.OS1, P.seed ^ TAG_R1,
-                     reinterpret_cast<uint64_t*>(ws + P.splR1), reinterpret_cast<uint32_t*>(ws + P.cR1), P.cntR1,
-                     bsum, P.tilesR1, bstR1, st, mk, MK_R1_SPL);
+    rc = bucket_pass(Rin, R1, (uint32_t)P.nR, LR1, bsum, st, mk, MK_R1_SPL);
     if (rc != MPSM_OK) return rc;
     SortOut soR;
     soR.run_idx = nullptr;
@@ -438,59 +479,50 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     soR.idx_per_run = 0;
     soR.NB = 1;
     soR.bkey = reinterpret_cast<uint64_t*>(ws + P.bkey);
-    const tup_t* Rsorted;
-    const uint32_t* bstR;
     uint32_t* redoR = reinterpret_cast<uint32_t*>(ws + P.redoR);
+    uint32_t* bigR = reinterpret_cast<uint32_t*>(ws + P.bigR);
+    const Level* LRf = &LR1;   // level whose buckets are the R partitions
+    Level LR2;
+    tup_t* Rsrc = R1;          // partitioned, unsorted
+    tup_t* Rsorted = R2;
     if (P.levels == 2) {
-      Seg sR2 = seg_at(ws, P.segR2, P.NB1);
-      k_seg_from_buckets<<<(uint32_t)cdiv(P.NB1, 256), 256, 0, st>>>(bstR1, P.NB1, sR2.start, sR2.len);
+      LR2 = make_level(ws, P.segR2, P.NB1, P.NB2, P.BT, P.OS2, P.tilesR2, P.seed ^ TAG_R2, P.splR2, P.cR2, P.cntR2,
+                       P.bstR2, P.bndR2, P.Gr);
+      LR2.outer = LR1.spl;
+      LR2.outer_nspl = P.NB1 - 1;
+      k_seg_from_buckets<<<(uint32_t)cdiv(P.NB1, 256), 256, 0, st>>>(LR1.bstart, P.NB1, LR2.seg.start,
+                                                                     LR2.seg.len);
       LAUNCH_CHECK();
-      uint32_t* bstR2 = reinterpret_cast<uint32_t*>(ws + P.bstR2);
-      rc = bucket_pass(R1, R2, (uint32_t)P.nR, sR2, P.NB1, P.NB2, P.OS2, P.seed ^ TAG_R2,
-                       reinterpret_cast<uint64_t*>(ws + P.splR2), reinterpret_cast<uint32_t*>(ws + P.cR2), P.cntR2,
-                       bsum, P.tilesR2, bstR2, st, mk, MK_R2_SPL);
+      rc = bucket_pass(R1, R2, (uint32_t)P.nR, LR2, bsum, st, mk, MK_R2_SPL);
       if (rc != MPSM_OK) return rc;
-      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M><<<P.Gr, BL_NT, 0, st>>>(R2, R1, bstR2, P.Gr, nullptr, nullptr,
-                                                                   reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1,
-                                                                   redoR, ctr + 4, soR);
-      LAUNCH_CHECK();
-      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(R2, R1, bstR2, redoR, ctr + 4,
-                                                      reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
-      LAUNCH_CHECK();
-      mk.mark(MK_R_SORT);
-      k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(R2, R1, bstR2, reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
-      LAUNCH_CHECK();
-      mk.mark(MK_R_BIG);
+      LRf = &LR2;
+      Rsrc = R2;
       Rsorted = R1;
-      bstR = bstR2;
     } else {
       mk.mark_range(MK_R2_SPL, MK_R2_SCAT);
-      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M><<<P.Gr, BL_NT, 0, st>>>(R1, R2, bstR1, P.Gr, nullptr, nullptr,
-                                                                   reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1,
-                                                                   redoR, ctr + 4, soR);
-      LAUNCH_CHECK();
-      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(R1, R2, bstR1, redoR, ctr + 4,
-                                                      reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
-      LAUNCH_CHECK();
-      mk.mark(MK_R_SORT);
-      k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(R1, R2, bstR1, reinterpret_cast<uint32_t*>(ws + P.bigR), ctr + 1, soR);
-      LAUNCH_CHECK();
-      mk.mark(MK_R_BIG);
-      Rsorted = R2;
-      bstR = bstR1;
     }
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1><<<LRf->Gmax, BL_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
+                                                                      LRf->Gcount(), nullptr, nullptr, bigR, ctr + 1,
+                                                                      redoR, ctr + 4, soR);
+    LAUNCH_CHECK();
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, redoR, ctr + 4, bigR, ctr + 1, soR);
+    LAUNCH_CHECK();
+    mk.mark(MK_R_SORT);
+    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, bigR, ctr + 1, soR);
+    LAUNCH_CHECK();
+    mk.mark(MK_R_BIG);
     uint32_t* Pc = reinterpret_cast<uint32_t*>(ws + P.Pc);
     uint32_t* pstart = reinterpret_cast<uint32_t*>(ws + P.pstart);
     uint32_t* plen = reinterpret_cast<uint32_t*>(ws + P.plen);
     uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + P.pkey);
-    k_partitions<<<1, 1024, 0, st>>>(bstR, soR.bkey, P.Gr, Pc, pstart, plen, pkey);
+    k_partitions<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), Pc, pstart, plen, pkey);
     LAUNCH_CHECK();
     mk.mark(MK_PART);
 
     // ---- phase 4: merge starts of every partition in every run, then the join
     uint32_t* o = reinterpret_cast<uint32_t*>(ws + P.o);
     const uint64_t nsearch = ((uint64_t)P.Pmax + 1) * P.Q;
-    k_search<<<(uint32_t)cdiv(nsearch, 256), 256, 0, st>>>(U, sS.start, sS.len, P.Q,
+    k_search<<<(uint32_t)cdiv(nsearch, 256), 256, 0, st>>>(U, LS.seg.start, LS.seg.len, P.Q,
                                                           reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
                                                           P.idx_per_run, Pc, pkey, P.Pmax, o, P.search,
                                                           stats ? res : nullptr);
@@ -507,7 +539,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     JoinArgs A;
     A.Rs = Rsorted;
     A.U = U;
-    A.run_start = sS.start;
+    A.run_start = LS.seg.start;
     A.Q = P.Q;
     A.Pcount = Pc;
     A.pstart = pstart;
