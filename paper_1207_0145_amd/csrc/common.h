@@ -44,15 +44,20 @@ __device__ __forceinline__ void store_tup(tup_t* p, tup_t t) {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-// Inclusive scan of a u32 across the 64 lanes of a wave.
+// Inclusive scan of a u32 across the 64 lanes of a wave, with DPP lane
+// moves (no LDS round trip): shifts by 1, 2, 4, 8 inside each row of 16
+// lanes, then the row totals are carried with the row broadcasts of lane 15
+// (into rows 1 and 3) and lane 31 (into rows 2 and 3).  Lanes whose source
+// is outside the row receive 0.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t o = __shfl_up(v, d, 64);
-    if (lane >= d) v += o;
-  }
-  return v;
+  int x = (int)v;
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+  return (uint32_t)x;
 }
 
 __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v) {

@@ -818,7 +818,7 @@ __device__ __forceinline__ uint32_t item_partition(const uint32_t* item_pre, uin
 // Partitions larger than the LDS tile are searched in global memory.
 // MODE 0: count + checksum (+max); MODE 1: count pairs per item; MODE 2: write
 // pairs.  VM: what the LDS holds next to each R key.
-constexpr int JOIN_U = 8;     // S tuples in flight per thread
+constexpr int JOIN_U = 4;     // S tuples per thread per batch (two batches in flight)
 
 template <int MODE, int VM>
 __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
@@ -916,8 +916,9 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
     const uint32_t lo_item = k * A.JCH;
     const uint32_t hi_item = min(lo_item + A.JCH, cum[Q]);
     const tup_t* Rg = A.Rs + rs;
-    for (uint32_t base = lo_item; base < hi_item; base += JOIN_NT * JOIN_U) {
-      tup_t sv[JOIN_U];
+    // S tuples of the item, JOIN_U per thread per batch; the next batch is
+    // loaded while the current one is matched
+    auto load_batch = [&](uint32_t base, tup_t (&sv)[JOIN_U]) {
 #pragma unroll
       for (int u = 0; u < JOIN_U; u++) {
         const uint32_t x = base + u * JOIN_NT + tid;
@@ -927,6 +928,14 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
           sv[u] = load_tup(A.U + sbase[a0] + x);
         }
       }
+    };
+    tup_t nsv[JOIN_U];
+    if (lo_item < hi_item) load_batch(lo_item, nsv);
+    for (uint32_t base = lo_item; base < hi_item; base += JOIN_NT * JOIN_U) {
+      tup_t sv[JOIN_U];
+#pragma unroll
+      for (int u = 0; u < JOIN_U; u++) sv[u] = nsv[u];
+      if (base + JOIN_NT * JOIN_U < hi_item) load_batch(base + JOIN_NT * JOIN_U, nsv);
 #pragma unroll
       for (int u = 0; u < JOIN_U; u++) {
         const uint32_t x = base + u * JOIN_NT + tid;

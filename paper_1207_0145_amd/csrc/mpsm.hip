@@ -101,14 +101,17 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
     P->NB2 = 1;
     P->OS2 = 1;
   } else {
+    // first level: a modest fan-out (long write segments in the scatter);
+    // second level: buckets sized from the data
     P->levels = 2;
-    P->NB1 = MAX_NB;
-    P->OS1 = cfg->oversample ? os_for(P->NB1) : 16u;
+    P->NB1 = 256;
+    P->OS1 = os_for(P->NB1);
     // level-2 buckets per level-1 bucket: ceil(len / BT), at most twice the
     // average need (level-1 buckets are sampled, so their sizes vary)
-    P->NB2 = 2 * next_pow2(cdiv(F, MAX_NB));
+    P->NB2 = 2 * next_pow2(cdiv(F, P->NB1));
     if (P->NB2 > (uint32_t)MAX_NB) P->NB2 = MAX_NB;
-    P->OS2 = os_for(P->NB2);
+    P->OS2 = SMP_NT_S * SMP_IPT_S / P->NB2 < 16u ? SMP_NT_S * SMP_IPT_S / P->NB2 : 16u;
+    if (P->OS2 < 4) P->OS2 = os_for(P->NB2);
   }
   P->Gs = P->Q * P->NBs;
   P->Gr = P->NB1 * P->NB2;
@@ -486,7 +489,8 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     tup_t* Rsrc = R1;          // partitioned, unsorted
     tup_t* Rsorted = R2;
     if (P.levels == 2) {
-      LR2 = make_level(ws, P.segR2, P.NB1, P.NB2, P.BT, P.OS2, P.tilesR2, P.seed ^ TAG_R2, P.splR2, P.cR2, P.cntR2,
+      // 3/4 of the target so that sampling noise rarely pushes a partition past the LDS tile
+      LR2 = make_level(ws, P.segR2, P.NB1, P.NB2, P.BT * 3 / 4, P.OS2, P.tilesR2, P.seed ^ TAG_R2, P.splR2, P.cR2, P.cntR2,
                        P.bstR2, P.bndR2, P.Gr);
       LR2.outer = LR1.spl;
       LR2.outer_nspl = P.NB1 - 1;
