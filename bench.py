@@ -42,7 +42,7 @@ KERNEL_OF_STEP = {
 
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
-    for f in ("common.h", "block_sort.h", "kernels.h", "mpsm.hip"):
+    for f in ("common.h", "block_sort.h", "kernels.h", "learned.h", "mpsm.hip"):
         with open(os.path.join(ROOT, "paper_1207_0145_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -78,6 +78,45 @@ def cpu_baseline(shift: int):
                       f"same key recipe; {dt:.1f} s single-threaded sort-merge join (count {r.count})"}
 
 
+def variant_stats(mpsm, torch, R, S, cfg, dev):
+    """One extra call with statistics (synchronising; outside the timed steps)."""
+    ws = mpsm.alloc_workspace(R.shape[0], S.shape[0], cfg, dev)
+    st = mpsm.MpsmStats()
+    out = torch.zeros(2, dtype=torch.int64, device=dev)
+    mpsm.join_into(R, S, out, ws, cfg, stats=st)
+    d = {name: getattr(st, name) for name, _ in st._fields_}
+    del ws
+    return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in d.items()}
+
+
+def run_variant(mpsm, torch, R, S, out, cfg, args, names, nR, nS, label):
+    """Time args.steps calls of another configuration, same inputs."""
+    dev = R.device
+    ws = mpsm.alloc_workspace(nR, nS, cfg, dev)
+    for _ in range(args.warmup):
+        mpsm.join_into(R, S, out, ws, cfg)
+    evsets = [mpsm.EventSet(len(names)) for _ in range(args.steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for k in range(args.steps):
+        mpsm.join_events_into(R, S, out, ws, evsets[k], cfg)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    steps_ms = {names[i]: sum(e.elapsed(i - 1, i) for e in evsets) / args.steps for i in range(1, len(names))}
+    for e in evsets:
+        e.close()
+    count, checksum = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
+    del ws
+    log(f"{label}: {ms:.3f} ms/step")
+    return {"ms_per_step": round(ms, 4), "value": round((nR + nS) / (ms * 1e-3) / 1e6, 2),
+            "result": {"count": count, "checksum": f"{checksum:#018x}"},
+            "steps_ms": {k: round(v, 4) for k, v in steps_ms.items() if v > 0.0005},
+            "stats": variant_stats(mpsm, torch, R, S, cfg, dev)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +125,7 @@ def main():
     ap.add_argument("--workload", default="fk_uniform", choices=["fk_uniform", "fk_small", "skewed"])
     ap.add_argument("--cpu-sample-shift", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-CDF variant")
     ap.add_argument("--search", default="index", choices=["index", "binary", "interp"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
@@ -109,6 +149,7 @@ def main():
     del w
     search = {"index": mpsm.SEARCH_INDEX, "binary": mpsm.SEARCH_BINARY, "interp": mpsm.SEARCH_INTERP}[args.search]
     cfg = mpsm.config(search=search)
+    cfg_learned = mpsm.config(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED)
     lay = mpsm.layout(nR, nS, cfg)
     ws = mpsm.alloc_workspace(nR, nS, cfg, dev)
     out = torch.zeros(2, dtype=torch.int64, device=dev)
@@ -177,6 +218,9 @@ def main():
                           "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
         "steps_ms": {k: round(v, 4) for k, v in steps_ms.items()},
     }
+    if not args.no_learned:
+        res["learned"] = run_variant(mpsm, torch, R, S, out, cfg_learned, args, names, nR, nS, "learned")
+        res["plain_stats"] = variant_stats(mpsm, torch, R, S, cfg, dev)
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle, 1 thread, 1/{1 << args.cpu_sample_shift} scale)")
         res["cpu_baseline"] = cpu_baseline(args.cpu_sample_shift)

@@ -59,7 +59,19 @@ typedef enum mpsm_status {
 } mpsm_status;
 
 enum { MPSM_ROLE_AUTO = 0, MPSM_ROLE_AS_GIVEN = 1, MPSM_ROLE_SWAP = 2 };
+/* Splitters of the range partitioning of R:
+ *   SAMPLED  equi-depth quantiles of a seeded sample, per segment;
+ *   LEARNED  first level from the inverse of a learned CDF of R (a
+ *            piecewise-linear CDF over sample quantiles plus a small residual
+ *            network, trained on the GPU from 2^16 keys the call draws); the
+ *            second level, when R needs one, stays sampled. */
 enum { MPSM_SPLIT_SAMPLED = 0, MPSM_SPLIT_LEARNED = 1 };
+/* Start search of every R partition in every S run (Section 3.2.2):
+ *   BINARY   bisection of the run;  INTERP  the paper's interpolation search;
+ *   INDEX    bisection of the run's equi-height index, then of one window;
+ *   LEARNED  INDEX narrowed to an error-bounded window around the slot the
+ *            learned CDF of S predicts, with the full index bisection as the
+ *            fallback when the window does not bracket the answer. */
 enum { MPSM_SEARCH_BINARY = 0, MPSM_SEARCH_INTERP = 1, MPSM_SEARCH_LEARNED = 2, MPSM_SEARCH_INDEX = 3 };
 
 /* Tuning and variant choices.  Zero in a numeric field means "automatic".
@@ -88,6 +100,10 @@ typedef struct mpsm_stats {
   uint64_t search_probes;     /* key reads made by the start search */
   uint64_t swapped;           /* 1 if the caller's S was used as the private input */
   double ms_total;            /* device time of the whole call */
+  uint64_t search_fallbacks;  /* learned search: predictions whose window failed the bracket check */
+  uint64_t max_partition;     /* tuples in the largest R partition */
+  double cdf_eps_r;           /* learned CDF of R: largest error on its sample (-1 if not trained) */
+  double cdf_eps_s;           /* learned CDF of S: same */
 } mpsm_stats;
 
 /* Fill *cfg with defaults (all automatic, role AUTO, sampled splitters,

@@ -36,7 +36,9 @@ class MpsmConfig(ctypes.Structure):
 class MpsmStats(ctypes.Structure):
     _fields_ = [("max_payload_sum", ctypes.c_uint64), ("nonempty", ctypes.c_uint64),
                 ("partitions", ctypes.c_uint64), ("runs", ctypes.c_uint64), ("oversize_buckets", ctypes.c_uint64),
-                ("search_probes", ctypes.c_uint64), ("swapped", ctypes.c_uint64), ("ms_total", ctypes.c_double)]
+                ("search_probes", ctypes.c_uint64), ("swapped", ctypes.c_uint64), ("ms_total", ctypes.c_double),
+                ("search_fallbacks", ctypes.c_uint64), ("max_partition", ctypes.c_uint64),
+                ("cdf_eps_r", ctypes.c_double), ("cdf_eps_s", ctypes.c_double)]
 
 
 class MpsmLayout(ctypes.Structure):

@@ -17,6 +17,7 @@
 // (Section 3.2.2) and joins each R partition, held in LDS, with its slices.
 #pragma once
 #include "block_sort.h"
+#include "learned.h"
 
 // ------------------------------------------------------------------ config
 // bucket sort instances: small tiles for S buckets, large tiles (= the join's
@@ -56,7 +57,7 @@ constexpr int SCAN_BLOCK = SCAN_NT * SCAN_IPT;
 
 struct Result {              // device result block
   unsigned long long count, checksum, maxsum, nonempty;
-  unsigned long long big_buckets, search_probes, fallbacks, spare;
+  unsigned long long big_buckets, search_probes, fallbacks, spare;   // spare: largest R partition
 };
 
 __global__ void k_init_result(Result* res, uint32_t* zero_words, uint32_t nzero) {
@@ -651,7 +652,7 @@ __global__ void __launch_bounds__(BIG_NT) k_big_sort(tup_t* __restrict__ src, tu
 // first key).  Single workgroup.
 __global__ void __launch_bounds__(1024) k_partitions(const uint32_t* bstart, const uint64_t* bkey,
                                                      const uint32_t* Gcount, uint32_t* Pcount, uint32_t* pstart,
-                                                     uint32_t* plen, uint64_t* pkey) {
+                                                     uint32_t* plen, uint64_t* pkey, Result* res) {
   __shared__ uint32_t wsum[1024 / 64 + 2];
   const uint32_t G = *Gcount;
   uint32_t carry = 0;
@@ -663,6 +664,7 @@ __global__ void __launch_bounds__(1024) k_partitions(const uint32_t* bstart, con
     if (len) {
       const uint32_t p = carry + ex;
       pstart[p] = bstart[g]; plen[p] = len; pkey[p] = bkey[g];
+      if (res) atomicMax(&res->spare, (unsigned long long)len);
     }
     carry += tot;
     __syncthreads();
@@ -715,45 +717,81 @@ __device__ __forceinline__ uint32_t interp_search(const tup_t* run, uint32_t n, 
 }
 
 // o[p][j] = first position of run j whose key >= pkey[p]; o[P][j] = |S_j|.
-__global__ void k_search(const tup_t* __restrict__ U, const uint32_t* run_start, const uint32_t* run_len, uint32_t Q,
-                         const uint64_t* run_idx, uint32_t idx_stride, uint32_t idx_per_run, const uint32_t* Pcount,
-                         const uint64_t* pkey, uint32_t Pmax, uint32_t* o, int mode, Result* res) {
+// Modes: BINARY bisects the run; INTERP is the paper's interpolation search;
+// INDEX bisects the run's equi-height index (every idx_stride-th key) and
+// then the idx_stride-wide window; LEARNED predicts the index slot from the
+// learned CDF of S, checks that the answer is bracketed by a window of
+// +-eps slots around the prediction, bisects that window (or, when the check
+// fails, the whole index), then the run window.  All modes return the same
+// lower bound.
+__global__ void __launch_bounds__(256) k_search(const tup_t* __restrict__ U, const uint32_t* run_start,
+                                                const uint32_t* run_len, uint32_t Q, const uint64_t* run_idx,
+                                                uint32_t idx_stride, uint32_t idx_per_run, const uint32_t* Pcount,
+                                                const uint64_t* pkey, uint32_t Pmax, uint32_t* o, int mode,
+                                                const CdfModel* model, Result* res) {
+  __shared__ CdfModel m;
+  const bool learned = mode == SEARCH_LEARNED;
+  if (learned) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(model);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&m);
+    for (uint32_t i = threadIdx.x; i < sizeof(CdfModel) / 4; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+  }
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t P = *Pcount;
-  if (gid >= (uint64_t)(P + 1) * Q) return;
-  const uint32_t p = (uint32_t)(gid / Q), j = (uint32_t)(gid % Q);
-  const uint32_t n = run_len[j];
-  const tup_t* run = U + run_start[j];
-  uint32_t probes = 0, r;
-  if (p == P) {
-    r = n;
-  } else {
-    const uint64_t key = pkey[p];
-    if (mode == SEARCH_BINARY) {
-      r = lb_keys(run, 0, n, key, &probes);
-    } else if (mode == SEARCH_INTERP) {
-      r = interp_search(run, n, key, &probes);
+  uint32_t probes = 0, fallbacks = 0;
+  if (gid < (uint64_t)(P + 1) * Q) {
+    const uint32_t p = (uint32_t)(gid / Q), j = (uint32_t)(gid % Q);
+    const uint32_t n = run_len[j];
+    const tup_t* run = U + run_start[j];
+    uint32_t r;
+    if (p == P) {
+      r = n;
     } else {
-      // equi-height index: idx[t] = run[t*stride].key
-      const uint64_t* idx = run_idx + (uint64_t)j * idx_per_run;
-      const uint32_t nidx = (n + idx_stride - 1) / idx_stride;
-      uint32_t lo = 0, hi = nidx;
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        probes++;
-        if (idx[mid] < key) lo = mid + 1; else hi = mid;
+      const uint64_t key = pkey[p];
+      if (mode == SEARCH_BINARY) {
+        r = lb_keys(run, 0, n, key, &probes);
+      } else if (mode == SEARCH_INTERP) {
+        r = interp_search(run, n, key, &probes);
+      } else {
+        const uint64_t* idx = run_idx + (uint64_t)j * idx_per_run;
+        const uint32_t nidx = (n + idx_stride - 1) / idx_stride;
+        uint32_t lo = 0, hi = nidx;
+        if (learned && m.valid) {
+          // window: the model's error on its sample, plus the sampling error of
+          // a 2^16-key sample and of this run (two standard deviations each)
+          const float q = cdf_eval(m, key);
+          const float sd = sqrtf(q * (1.f - q) + 1e-4f);
+          const float err = m.eps + 2.f * sd * (1.f / 256.f + rsqrtf((float)n + 1.f));
+          const int64_t t = (int64_t)(q * (float)nidx);
+          const int64_t w = (int64_t)(err * (float)nidx) + 2;
+          const uint32_t a = (uint32_t)(t - w < 0 ? 0 : (t - w > (int64_t)nidx ? (int64_t)nidx : t - w));
+          const uint32_t b = (uint32_t)(t + w > (int64_t)nidx ? (int64_t)nidx : (t + w < (int64_t)a ? (int64_t)a : t + w));
+          bool ok = true;
+          if (a > 0) { probes++; ok = idx[a - 1] < key; }
+          if (ok && b < nidx) { probes++; ok = idx[b] >= key; }
+          if (ok) { lo = a; hi = b; } else { fallbacks++; }
+        }
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          probes++;
+          if (idx[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        const uint32_t a = lo ? (lo - 1) * idx_stride + 1 : 0;
+        const uint32_t b = lo < nidx ? lo * idx_stride : n;
+        r = lb_keys(run, a, b, key, &probes);
       }
-      const uint32_t a = lo ? (lo - 1) * idx_stride + 1 : 0;
-      const uint32_t b = lo < nidx ? lo * idx_stride : n;
-      r = lb_keys(run, a, b, key, &probes);
     }
+    o[(uint64_t)p * Q + j] = r;
   }
-  o[(uint64_t)p * Q + j] = r;
   if (res) {  // statistics only: one atomic per wave
-    unsigned long long pr = probes;
+    unsigned long long pr = probes, fb = fallbacks;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) pr += __shfl_xor(pr, d, 64);
-    if ((threadIdx.x & 63) == 0 && pr) atomicAdd(&res->search_probes, pr);
+    for (int d = 32; d >= 1; d >>= 1) { pr += __shfl_xor(pr, d, 64); fb += __shfl_xor(fb, d, 64); }
+    if ((threadIdx.x & 63) == 0) {
+      if (pr) atomicAdd(&res->search_probes, pr);
+      if (fb) atomicAdd(&res->fallbacks, fb);
+    }
   }
 }
 

@@ -14,6 +14,7 @@ constexpr uint32_t HIST_TILE = 1u << 16;      // tuples per histogram / scatter 
 constexpr uint32_t IDX_STRIDE = 256;          // equi-height index stride of S runs
 constexpr uint64_t DEFAULT_SEED = 0x1207014500000000ull;
 constexpr uint64_t TAG_S = 0x5300000000000001ull, TAG_R1 = 0x5200000000000001ull, TAG_R2 = 0x5200000000000002ull;
+constexpr uint64_t TAG_CR = 0x4352000000000001ull, TAG_CS = 0x4353000000000001ull;  // learned-CDF samples
 
 uint32_t next_pow2(uint64_t x) {
   uint32_t p = 1;
@@ -45,6 +46,7 @@ struct Plan {
   uint64_t bigS, midS, redoS, redoR, bigR, ctr;
   uint64_t bkey, Pc, pstart, plen, pkey;
   uint64_t ridx, o, items, item_pre, item_cnt, res;
+  uint64_t cdf_chunks, cdf_sorted, modelR, modelS;  // learned CDF samples and models
   uint64_t total;
 };
 
@@ -55,8 +57,8 @@ struct Seg {  // device pointers of one segment table (nseg + 1 entries each)
 bool config_valid(const mpsm_config* c) {
   if (c->struct_size != sizeof(mpsm_config)) return false;
   if (c->role < 0 || c->role > 2) return false;
-  if (c->splitter != MPSM_SPLIT_SAMPLED) return false;   // learned splitters: not built yet
-  if (c->search < 0 || c->search > 3 || c->search == MPSM_SEARCH_LEARNED) return false;
+  if (c->splitter != MPSM_SPLIT_SAMPLED && c->splitter != MPSM_SPLIT_LEARNED) return false;
+  if (c->search < 0 || c->search > 3) return false;
   if (c->log2_run_len && (c->log2_run_len < 12 || c->log2_run_len > 24)) return false;
   if (c->bucket_target && (c->bucket_target < 256 || c->bucket_target > 4096)) return false;
   if (c->join_chunk && c->join_chunk < 1024) return false;
@@ -170,6 +172,10 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->items = take(((uint64_t)P->Pmax + 2) * 4);
   P->item_pre = take(((uint64_t)P->Pmax + 2) * 4);
   P->item_cnt = take((P->item_cap + 1) * 4);
+  P->cdf_chunks = take((uint64_t)CDF_M * 8);
+  P->cdf_sorted = take((uint64_t)CDF_M * 8);
+  P->modelR = take(sizeof(CdfModel));
+  P->modelS = take(sizeof(CdfModel));
   P->res = take(sizeof(Result));
   P->total = off;
   return true;
@@ -207,13 +213,13 @@ mpsm_status scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* bs
 
 // Step markers of the launch sequence (events recorded after each step).
 const char* const kMarkers[] = {
-    "start",        "init",          "s_splitters",   "s_histogram", "s_scan",          "s_scatter",
+    "start",        "init",          "cdf_models",    "s_splitters",   "s_histogram", "s_scan",          "s_scatter",
     "s_bucket_sort", "s_oversize_sort", "r1_splitters", "r1_histogram", "r1_scan",       "r1_scatter",
     "r2_splitters", "r2_histogram",  "r2_scan",       "r2_scatter",  "r_bucket_sort",   "r_oversize_sort",
     "partitions",   "search",        "join_plan",     "join",        "finalize"};
 constexpr uint32_t kNumMarkers = sizeof(kMarkers) / sizeof(kMarkers[0]);
 enum {
-  MK_START, MK_INIT, MK_S_SPL, MK_S_HIST, MK_S_SCAN, MK_S_SCAT, MK_S_SORT, MK_S_BIG, MK_R1_SPL, MK_R1_HIST,
+  MK_START, MK_INIT, MK_CDF, MK_S_SPL, MK_S_HIST, MK_S_SCAN, MK_S_SCAT, MK_S_SORT, MK_S_BIG, MK_R1_SPL, MK_R1_HIST,
   MK_R1_SCAN, MK_R1_SCAT, MK_R2_SPL, MK_R2_HIST, MK_R2_SCAN, MK_R2_SCAT, MK_R_SORT, MK_R_BIG, MK_PART, MK_SEARCH,
   MK_ITEMS, MK_JOIN, MK_FIN
 };
@@ -243,6 +249,7 @@ struct Level {
   uint64_t *blo, *bhi;
   const uint64_t* outer;     // splitters of the previous level (NULL at the first level)
   uint32_t outer_nspl;
+  const CdfModel* model;     // learned splitters from this model (one segment only), or NULL
   const uint32_t* Gcount() const { return seg.b0 + nseg; }
 };
 
@@ -261,6 +268,7 @@ Level make_level(char* ws, uint64_t seg_off, uint32_t nseg, uint32_t NBmax, uint
   L.bhi = L.blo + Gmax;
   L.outer = nullptr;
   L.outer_nspl = 0;
+  L.model = nullptr;
   return L;
 }
 
@@ -271,7 +279,10 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
   const Seg& sg = L.seg;
   k_seg_plan<<<1, 1024, 0, st>>>(L.nseg, L.NBmax, L.BT, HIST_TILE, sg.len, sg.tile0, sg.cnt0, sg.nb, sg.b0);
   LAUNCH_CHECK();
-  if (L.NBmax > 1) {
+  if (L.NBmax > 1 && L.model) {
+    k_learned_splitters<<<1, 256, 0, st>>>(L.model, L.NBmax, L.spl);
+    LAUNCH_CHECK();
+  } else if (L.NBmax > 1) {
     if (L.NBmax * L.OS <= (uint32_t)(SMP_NT_S * SMP_IPT_S))
       k_sample_splitters<SMP_NT_S, SMP_IPT_S><<<L.nseg, SMP_NT_S, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax,
                                                                            L.OS, L.level_seed, L.spl);
@@ -300,6 +311,20 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
       L.blo, L.bhi);
   LAUNCH_CHECK();
   mk.mark(mk0 + 3);
+  return MPSM_OK;
+}
+
+// Sample CDF_M keys of a relation, sort them, fit the learned CDF.
+mpsm_status train_cdf(const tup_t* src, uint32_t n, uint64_t seed, uint64_t* chunks, uint64_t* sorted,
+                      CdfModel* model, hipStream_t st) {
+  k_cdf_sample<<<CDF_M / 256, 256, 0, st>>>(src, n, seed, chunks);
+  LAUNCH_CHECK();
+  k_cdf_sort_chunks<<<CDF_M / CDF_CHUNK, 1024, 0, st>>>(chunks);
+  LAUNCH_CHECK();
+  k_cdf_merge<<<CDF_M / 256, 256, 0, st>>>(chunks, sorted);
+  LAUNCH_CHECK();
+  k_cdf_train<<<1, 1024, 0, st>>>(sorted, n, model);
+  LAUNCH_CHECK();
   return MPSM_OK;
 }
 
@@ -428,8 +453,23 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
   k_init_result<<<1, 64, 0, st>>>(res, reinterpret_cast<uint32_t*>(ctr), 16);
   LAUNCH_CHECK();
   mk.mark(MK_INIT);
+  CdfModel* modelR = reinterpret_cast<CdfModel*>(ws + P.modelR);
+  CdfModel* modelS = reinterpret_cast<CdfModel*>(ws + P.modelS);
+  const bool learn_r = P.splitter == MPSM_SPLIT_LEARNED && P.nR && P.nS;
+  const bool learn_s = P.search == MPSM_SEARCH_LEARNED && P.nR && P.nS;
+  if (learn_r) {
+    mpsm_status rc = train_cdf(Rin, (uint32_t)P.nR, P.seed ^ TAG_CR, reinterpret_cast<uint64_t*>(ws + P.cdf_chunks),
+                               reinterpret_cast<uint64_t*>(ws + P.cdf_sorted), modelR, st);
+    if (rc != MPSM_OK) return rc;
+  }
+  if (learn_s) {
+    mpsm_status rc = train_cdf(Sin, (uint32_t)P.nS, P.seed ^ TAG_CS, reinterpret_cast<uint64_t*>(ws + P.cdf_chunks),
+                               reinterpret_cast<uint64_t*>(ws + P.cdf_sorted), modelS, st);
+    if (rc != MPSM_OK) return rc;
+  }
+  mk.mark(MK_CDF);
   if (P.nR == 0 || P.nS == 0) {
-    mk.mark_range(MK_S_SPL, MK_JOIN);
+    mk.mark_range(MK_S_SPL, MK_JOIN);  // MK_CDF was recorded above
     k_finalize<<<1, 64, 0, st>>>(res, d_out_count, d_out_checksum);
     LAUNCH_CHECK();
     mk.mark(MK_FIN);
@@ -470,6 +510,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     // ---- phase 2: range-partition R (one or two levels); phase 3: sort partitions
     Level LR1 = make_level(ws, P.segR1, 1, P.NB1, 0, P.OS1, P.tilesR1, P.seed ^ TAG_R1, P.splR1, P.cR1, P.cntR1,
                            P.bstR1, P.bndR1, P.NB1);
+    if (learn_r) LR1.model = modelR;
     k_seg_uniform<<<1, 64, 0, st>>>((uint32_t)P.nR, (uint32_t)P.nR, 1, LR1.seg.start, LR1.seg.len);
     LAUNCH_CHECK();
     rc = bucket_pass(Rin, R1, (uint32_t)P.nR, LR1, bsum, st, mk, MK_R1_SPL);
@@ -519,7 +560,8 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     uint32_t* pstart = reinterpret_cast<uint32_t*>(ws + P.pstart);
     uint32_t* plen = reinterpret_cast<uint32_t*>(ws + P.plen);
     uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + P.pkey);
-    k_partitions<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), Pc, pstart, plen, pkey);
+    k_partitions<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), Pc, pstart, plen, pkey,
+                                     stats ? res : nullptr);
     LAUNCH_CHECK();
     mk.mark(MK_PART);
 
@@ -528,8 +570,11 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     const uint64_t nsearch = ((uint64_t)P.Pmax + 1) * P.Q;
     k_search<<<(uint32_t)cdiv(nsearch, 256), 256, 0, st>>>(U, LS.seg.start, LS.seg.len, P.Q,
                                                           reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
-                                                          P.idx_per_run, Pc, pkey, P.Pmax, o, P.search,
-                                                          stats ? res : nullptr);
+                                                          P.idx_per_run, Pc, pkey, P.Pmax, o,
+                                                          learn_s ? MPSM_SEARCH_LEARNED
+                                                                  : (P.search == MPSM_SEARCH_LEARNED ? MPSM_SEARCH_INDEX
+                                                                                                     : P.search),
+                                                          modelS, stats ? res : nullptr);
     LAUNCH_CHECK();
     mk.mark(MK_SEARCH);
     uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
@@ -595,6 +640,15 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     stats->runs = P.Q;
     stats->oversize_buckets = c[0] + c[1];
     stats->search_probes = r.search_probes;
+    stats->search_fallbacks = r.fallbacks;
+    stats->max_partition = r.spare;
+    CdfModel mdl_r, mdl_s;
+    memset(&mdl_r, 0, sizeof(mdl_r));
+    memset(&mdl_s, 0, sizeof(mdl_s));
+    if (learn_r) HIP_TRY(hipMemcpy(&mdl_r, modelR, sizeof(mdl_r), hipMemcpyDeviceToHost));
+    if (learn_s) HIP_TRY(hipMemcpy(&mdl_s, modelS, sizeof(mdl_s), hipMemcpyDeviceToHost));
+    stats->cdf_eps_r = learn_r ? mdl_r.eps : -1.0;
+    stats->cdf_eps_s = learn_s ? mdl_s.eps : -1.0;
     stats->swapped = (uint64_t)P.swapped;
     stats->ms_total = ms;
     if (d_pairs && r.count > pairs_capacity) return MPSM_ECAPACITY;

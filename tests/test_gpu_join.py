@@ -108,6 +108,8 @@ CONFIGS = [
     dict(role=mpsm.ROLE_AS_GIVEN), dict(role=mpsm.ROLE_SWAP), dict(search=mpsm.SEARCH_BINARY),
     dict(search=mpsm.SEARCH_INTERP), dict(log2_run_len=12), dict(log2_run_len=16, bucket_target=256),
     dict(bucket_target=1024, join_chunk=1024), dict(seed=12345), dict(want_max=1),
+    dict(splitter=mpsm.SPLIT_LEARNED), dict(search=mpsm.SEARCH_LEARNED),
+    dict(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED, bucket_target=1024),
 ]
 
 
@@ -127,6 +129,35 @@ def test_want_max_matches_query_aggregate():
     got = gpu_join(R, S, mpsm.config(want_max=1), stats=True)
     assert got["count"] == want.count and got["stats"]["max_payload_sum"] == want.maxsum
     assert got["stats"]["nonempty"] == int(want.nonempty)
+
+
+@pytest.mark.parametrize("workload,shift", [("fk_uniform", 8), ("skewed", 8), ("lognormal", 10)])
+def test_learned_modes_exact_and_model_sane(workload, shift):
+    w = workloads.make(workload, scale_shift=shift)
+    want, _ = oracle.join_hash(w.R, w.S)
+    for kw in (dict(), dict(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED)):
+        got = gpu_join(w.R, w.S, mpsm.config(**kw), stats=True)
+        assert (got["count"], got["checksum"]) == (want.count, want.checksum), kw
+        st = got["stats"]
+        if kw:
+            # the model is fitted to its own sample; a continuous fit cannot follow a
+            # jump of the CDF, so its error there is about the heaviest key's share
+            top_s = np.unique(w.S[:, 0], return_counts=True)[1].max() / len(w.S)
+            top_r = np.unique(w.R[:, 0], return_counts=True)[1].max() / len(w.R)
+            assert 0.0 <= st["cdf_eps_r"] < 0.02 + 1.5 * top_r, st
+            assert 0.0 <= st["cdf_eps_s"] < 0.02 + 1.5 * top_s, st
+            assert st["search_fallbacks"] <= st["partitions"] * st["runs"]
+        else:
+            assert st["cdf_eps_r"] == -1.0 and st["search_fallbacks"] == 0
+
+
+def test_learned_search_with_bad_window_falls_back():
+    # tiny R with a handful of distinct keys: the model sees a step function;
+    # whatever it predicts, the bracket check keeps the offsets exact
+    rng = np.random.default_rng(21)
+    R = rel(rng, 3000, 7)
+    S = rel(rng, 200000, 7)
+    check(R, S, cfg=mpsm.config(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED))
 
 
 def test_oversize_bucket_fallback():
