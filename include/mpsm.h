@@ -104,6 +104,7 @@ typedef struct mpsm_stats {
   uint64_t max_partition;     /* tuples in the largest R partition */
   double cdf_eps_r;           /* learned CDF of R: largest error on its sample (-1 if not trained) */
   double cdf_eps_s;           /* learned CDF of S: same */
+  uint64_t resorted_buckets;  /* buckets whose one-pass sort gave up, re-sorted by LSD radix passes */
 } mpsm_stats;
 
 /* Fill *cfg with defaults (all automatic, role AUTO, sampled splitters,

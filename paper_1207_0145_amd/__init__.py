@@ -38,7 +38,8 @@ class MpsmStats(ctypes.Structure):
                 ("partitions", ctypes.c_uint64), ("runs", ctypes.c_uint64), ("oversize_buckets", ctypes.c_uint64),
                 ("search_probes", ctypes.c_uint64), ("swapped", ctypes.c_uint64), ("ms_total", ctypes.c_double),
                 ("search_fallbacks", ctypes.c_uint64), ("max_partition", ctypes.c_uint64),
-                ("cdf_eps_r", ctypes.c_double), ("cdf_eps_s", ctypes.c_double)]
+                ("cdf_eps_r", ctypes.c_double), ("cdf_eps_s", ctypes.c_double),
+                ("resorted_buckets", ctypes.c_uint64)]
 
 
 class MpsmLayout(ctypes.Structure):

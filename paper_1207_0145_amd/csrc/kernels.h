@@ -406,17 +406,49 @@ __device__ __forceinline__ void emit_sorted(const SortOut& so, uint32_t g, uint3
 // Bucket sort by one counting pass plus a rank fix-up (the paper's sort is
 // an MSD radix pass whose small partitions are finished by insertion sort,
 // Section 2.3).  Keys of the bucket are mapped monotonically onto M
-// sub-buckets by linear interpolation between the bucket's smallest and
-// largest key; one LDS counting sort groups the keys by sub-bucket.  Every
-// tuple then finds its rank inside its (typically 0-3 key) sub-bucket by
-// comparing its key with the other keys of the group -- ties broken by the
-// group position, so ranks are a permutation -- and stores itself straight
-// from registers to its final position.  Payloads never pass through LDS.
-// A bucket with a sub-bucket of more than GMAX keys (keys clustered inside
-// the bucket) goes to redo_list for the LSD radix sort (k_bucket_sort_lsd).
-// Buckets larger than CAP go to over_list.  With in_list the kernel walks a
-// list of bucket ids instead of all G buckets.
+// sub-buckets by linear interpolation over the bucket's key bounds; one LDS
+// counting sort groups the keys by sub-bucket, and every tuple is stored
+// straight from registers to its final position (payloads never pass
+// through LDS).  Inside a group a tuple's rank is the number of smaller
+// keys plus the number of equal keys placed before it, so ranks form a
+// permutation.  By group size:
+//   * at most GMAX keys: ranked by comparing with every key of the group;
+//   * all keys equal (found from the group's min and max): positions stand;
+//   * otherwise the group is sorted by a second counting pass that
+//     interpolates over the group's own [min, max] into as many cells as it
+//     has keys (keys clustered inside the bucket, duplicates of several
+//     keys).  A second-level cell of more than GMAX keys is split three ways
+//     around a pivot key taken from the cell: the copies of the pivot take
+//     the middle, the at most SIDE other keys are ranked by comparison.
+// A bucket that still has an unresolved cell, or more large groups than
+// there are slots, goes to redo_list for the LSD radix sort
+// (k_bucket_sort_lsd).  A bucket whose bounds admit one key is copied as is,
+// whatever its size; other buckets larger than CAP go to over_list.  With
+// in_list the kernel walks a list of bucket ids instead of all G buckets.
 constexpr int CS_GMAX = 32;
+constexpr int CS_SIDE = 64;
+constexpr int CS_SLOTS = 128;
+
+enum : uint8_t { CS_DONE = 0, CS_BIG = 1, CS_SMALL2 = 2, CS_PIVOT = 3, CS_OTHER = 4 };
+
+// Rank of key (at group position p) among the gs keys sk[gl, gl+gs).
+__device__ __forceinline__ uint32_t cs_group_rank(const uint64_t* sk, uint32_t gl, uint32_t gs, uint32_t p,
+                                                  uint64_t key) {
+  uint32_t r = gl;
+  if (gs <= 4) {   // common case: independent reads
+#pragma unroll
+    for (uint32_t t = 0; t < 4; t++) {
+      const uint32_t q = gl + t;
+      if (t < gs) { const uint64_t kq = sk[q]; r += (kq < key) || (kq == key && q < p); }
+    }
+  } else {
+    for (uint32_t q = gl; q < gl + gs; q++) {
+      const uint64_t kq = sk[q];
+      r += (kq < key) || (kq == key && q < p);
+    }
+  }
+  return r;
+}
 
 template <int NT, int IPT, int M, int MINB>
 __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
@@ -429,8 +461,17 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
   constexpr int CAP = NT * IPT;
   constexpr int PER = M / NT;
   static_assert(M % NT == 0, "sub-buckets per thread");
-  __shared__ uint64_t sk[CAP];               // keys grouped by sub-bucket
-  __shared__ uint32_t cnt[M + 1];
+  static_assert(CAP < (1 << 16), "positions fit 16 bits");
+  __shared__ uint64_t sk[CAP];               // keys grouped by (sub-)group
+  __shared__ uint32_t cnt[M + 1];            // first-level counters, then group starts
+  __shared__ uint32_t cnt2[CAP + 1];         // second-level counters, indexed by bucket position
+  __shared__ uint16_t slot1[M];              // slot of a large first-level group
+  __shared__ uint16_t slot2[CAP];            // slot of a large second-level cell, by its first position
+  __shared__ uint64_t smin[CS_SLOTS], smax[CS_SLOTS], sC[CS_SLOTS];
+  __shared__ uint32_t sgs[CS_SLOTS];
+  __shared__ uint64_t spiv[CS_SLOTS];
+  __shared__ uint32_t sE[CS_SLOTS], sL[CS_SLOTS], sN[CS_SLOTS];
+  __shared__ uint32_t nslot[2];
   __shared__ uint32_t wsum[NT / 64 + 2];
   const uint32_t tid = threadIdx.x;
   const uint32_t nitems = in_list ? (uint32_t)*in_count : *Gcount;
@@ -438,11 +479,18 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
     const uint32_t g = in_list ? in_list[it] : it;
     const uint32_t a = bstart[g], n = bstart[g + 1] - a;
     if (n == 0) continue;
+    const uint64_t lo = blo[g], span = bhi[g] - lo;
+    if (span == 0) {   // one key: input order is sorted order
+      for (uint32_t i = tid; i < n; i += NT) {
+        store_tup(dst + a + i, load_tup(src + a + i));
+        emit_sorted(so, g, a, i, lo);
+      }
+      continue;
+    }
     if (n > (uint32_t)CAP) {
       if (tid == 0) over_list[atomicAdd(over_count, 1ull)] = g;
       continue;
     }
-    const uint64_t lo = blo[g], span = bhi[g] - lo;
     uint64_t key[IPT], val[IPT];
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
@@ -454,74 +502,208 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
         key[k] = ~0ull; val[k] = 0;
       }
     }
+    const bool exact = span < (uint64_t)M;   // one key per sub-bucket
+    const uint64_t C = exact ? 0ull : interp_scale(M, span);
+    auto sub = [&](uint64_t k) -> uint32_t {
+      const uint64_t x = k - lo;
+      const uint32_t dd = exact ? (uint32_t)x : (uint32_t)__umul64hi(x, C);
+      return dd < (uint32_t)M ? dd : (uint32_t)(M - 1);
+    };
     uint32_t fin[IPT];
     bool bad = false;
-    if (span == 0) {  // one key: input order is sorted order
+    __syncthreads();   // LDS of the previous bucket is free
+    for (uint32_t b = tid; b <= (uint32_t)M; b += NT) cnt[b] = 0;
+    if (tid < 2) nslot[tid] = 0;
+    __syncthreads();
 #pragma unroll
-      for (int k = 0; k < IPT; k++) fin[k] = k * NT + tid;
-    } else {
-      const bool exact = span < (uint64_t)M;   // one key per sub-bucket
-      const uint64_t C = exact ? 0ull : interp_scale(M, span);
-      __syncthreads();   // LDS of the previous bucket is free
-      for (uint32_t b = tid; b <= (uint32_t)M; b += NT) cnt[b] = 0;
+    for (int k = 0; k < IPT; k++) {
+      if (k * NT + tid < n) {
+        bad |= key[k] - lo > span;            // outside the bucket's bounds: never expected
+        fin[k] = atomicAdd(&cnt[sub(key[k])], 1u);
+      }
+    }
+    __syncthreads();
+    {
+      uint32_t loc[PER], run = 0;
+#pragma unroll
+      for (int q = 0; q < PER; q++) { loc[q] = run; run += cnt[tid * PER + q]; }
+      uint32_t tot;
+      const uint32_t ex = block_excl_scan<NT>(run, wsum, &tot);
+#pragma unroll
+      for (int q = 0; q < PER; q++) cnt[tid * PER + q] = loc[q] + ex;
+      if (tid == 0) cnt[M] = n;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; k++) {
+      if (k * NT + tid < n) {
+        fin[k] += cnt[sub(key[k])];
+        if (!exact) sk[fin[k]] = key[k];
+      }
+    }
+    if (!exact) {
+      // gs_[k]: start of the item's current group (bits 0..27) and its state
+      // (bits 28..31); aux[k]: arrival index inside the current cell
+      uint32_t gs_[IPT], aux[IPT];
+      bool big = false;
       __syncthreads();
-      uint32_t d[IPT], pos[IPT];
 #pragma unroll
       for (int k = 0; k < IPT; k++) {
+        gs_[k] = 0;
+        aux[k] = 0;
         if (k * NT + tid < n) {
-          const uint64_t x = key[k] - lo;
-          bad |= x > span;                      // outside the bucket's bounds: never expected
-          uint32_t dd = exact ? (uint32_t)x : (uint32_t)__umul64hi(x, C);
-          d[k] = dd < (uint32_t)M ? dd : (uint32_t)(M - 1);
-          pos[k] = atomicAdd(&cnt[d[k]], 1u);
+          const uint32_t dd = sub(key[k]);
+          const uint32_t l = cnt[dd], gs = cnt[dd + 1] - l;
+          cnt2[fin[k]] = 0;
+          gs_[k] = l;
+          if (gs > (uint32_t)CS_GMAX) {
+            gs_[k] = l | ((uint32_t)CS_BIG << 28);
+            big = true;
+            if (fin[k] == l) {   // the item at the group's first position opens its slot
+              const uint32_t s = atomicAdd(&nslot[0], 1u);
+              if (s < (uint32_t)CS_SLOTS) {
+                slot1[dd] = (uint16_t)s; smin[s] = key[k]; smax[s] = key[k]; sgs[s] = gs;
+              }
+            }
+          } else if (gs > 1) {
+            fin[k] = cs_group_rank(sk, l, gs, fin[k], key[k]);
+          }
         }
       }
-      __syncthreads();
-      {
-        uint32_t loc[PER], run = 0;
+#define GL(k) (gs_[k] & 0x0FFFFFFFu)
+#define ST(k) (gs_[k] >> 28)
+#define SET(k, v) (gs_[k] = GL(k) | ((uint32_t)(v) << 28))
+      if (__syncthreads_or(big)) {
+        const uint32_t nbig = nslot[0];
+        if (nbig > (uint32_t)CS_SLOTS) {
+          bad = true;
+        } else {
+          // group bounds
 #pragma unroll
-        for (int q = 0; q < PER; q++) { loc[q] = run; run += cnt[tid * PER + q]; }
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<NT>(run, wsum, &tot);
+          for (int k = 0; k < IPT; k++)
+            if (ST(k) == CS_BIG) {
+              const uint32_t s = slot1[sub(key[k])];
+              atomicMin(reinterpret_cast<unsigned long long*>(&smin[s]), (unsigned long long)key[k]);
+              atomicMax(reinterpret_cast<unsigned long long*>(&smax[s]), (unsigned long long)key[k]);
+            }
+          __syncthreads();
+          // second-level cells, as many as the group has keys; C = 0 marks a
+          // span narrower than that (one key per cell)
+          for (uint32_t s = tid; s < nbig; s += NT) {
+            const uint64_t sp2 = smax[s] - smin[s];
+            sC[s] = sp2 < (uint64_t)sgs[s] ? 0ull : interp_scale(sgs[s], sp2);
+          }
+          __syncthreads();
+          auto cell = [&](uint32_t s, uint64_t k) -> uint32_t {
+            const uint64_t x = k - smin[s], c = sC[s];
+            const uint32_t c2 = c ? (uint32_t)__umul64hi(x, c) : (uint32_t)x;
+            return c2 < sgs[s] ? c2 : sgs[s] - 1;
+          };
 #pragma unroll
-        for (int q = 0; q < PER; q++) cnt[tid * PER + q] = loc[q] + ex;
-        if (tid == 0) cnt[M] = n;
-      }
-      __syncthreads();
+          for (int k = 0; k < IPT; k++)
+            if (ST(k) == CS_BIG) {
+              const uint32_t s = slot1[sub(key[k])];
+              if (smin[s] == smax[s]) { SET(k, CS_DONE); continue; }   // one key: positions stand
+              aux[k] = atomicAdd(&cnt2[GL(k) + cell(s, key[k])], 1u);
+            }
+          __syncthreads();
+          // exclusive scan of the second-level counters over the bucket
+          {
+            uint32_t loc[IPT], run = 0;
 #pragma unroll
-      for (int k = 0; k < IPT; k++) {
-        if (k * NT + tid < n) {
-          fin[k] = cnt[d[k]] + pos[k];
-          if (!exact) sk[fin[k]] = key[k];
-        }
-      }
-      if (!exact) {
-        __syncthreads();
+            for (int q = 0; q < IPT; q++) {
+              const uint32_t i = tid * IPT + q;
+              loc[q] = run;
+              run += i < n ? cnt2[i] : 0u;
+            }
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan<NT>(run, wsum, &tot);
 #pragma unroll
-        for (int k = 0; k < IPT; k++) {
-          if (k * NT + tid < n) {
-            const uint32_t gl = cnt[d[k]], gs = cnt[d[k] + 1] - gl, p = fin[k];
-            if (gs > (uint32_t)CS_GMAX) {
-              bad = true;
-            } else if (gs > 1) {
-              uint32_t r = gl;
-              if (gs <= 4) {   // common case: independent reads
+            for (int q = 0; q < IPT; q++) {
+              const uint32_t i = tid * IPT + q;
+              if (i < n) cnt2[i] = loc[q] + ex;
+            }
+            if (tid == 0) cnt2[n] = tot;
+          }
+          __syncthreads();
+          bool three = false;
 #pragma unroll
-                for (uint32_t t = 0; t < 4; t++) {
-                  const uint32_t q = gl + t;
-                  if (t < gs) { const uint64_t kq = sk[q]; r += (kq < key[k]) || (kq == key[k] && q < p); }
-                }
+          for (int k = 0; k < IPT; k++)
+            if (ST(k) == CS_BIG) {
+              const uint32_t s = slot1[sub(key[k])];
+              const uint32_t c2 = GL(k) + cell(s, key[k]);
+              const uint32_t c0 = cnt2[c2];
+              const uint32_t g2 = GL(k) + (c0 - cnt2[GL(k)]), gs2 = cnt2[c2 + 1] - c0;
+              fin[k] = g2 + aux[k];
+              sk[fin[k]] = key[k];
+              if (gs2 <= 1) {
+                SET(k, CS_DONE);
+              } else if (gs2 <= (uint32_t)CS_GMAX) {
+                gs_[k] = g2 | ((uint32_t)CS_SMALL2 << 28);
+                aux[k] = gs2;
               } else {
-                for (uint32_t q = gl; q < gl + gs; q++) {
-                  const uint64_t kq = sk[q];
-                  r += (kq < key[k]) || (kq == key[k] && q < p);
+                gs_[k] = g2 | ((uint32_t)CS_PIVOT << 28);
+                three = true;
+                if (aux[k] == 0) {   // first arrival opens the cell's slot; its key is the pivot
+                  const uint32_t s2 = atomicAdd(&nslot[1], 1u);
+                  if (s2 < (uint32_t)CS_SLOTS) {
+                    slot2[g2] = (uint16_t)s2; spiv[s2] = key[k]; sE[s2] = 0; sL[s2] = 0; sN[s2] = 0;
+                  }
                 }
               }
-              fin[k] = r;
+            }
+          __syncthreads();
+#pragma unroll
+          for (int k = 0; k < IPT; k++)
+            if (ST(k) == CS_SMALL2) {
+              fin[k] = cs_group_rank(sk, GL(k), aux[k], fin[k], key[k]);
+              SET(k, CS_DONE);
+            }
+          if (__syncthreads_or(three)) {
+            if (nslot[1] > (uint32_t)CS_SLOTS) {
+              bad = true;
+            } else {
+              // three-way split: copies of the pivot count themselves, the
+              // other keys are packed at the front of the cell
+#pragma unroll
+              for (int k = 0; k < IPT; k++)
+                if (ST(k) == CS_PIVOT) {
+                  const uint32_t s2 = slot2[GL(k)];
+                  const uint64_t pv = spiv[s2];
+                  if (key[k] == pv) {
+                    aux[k] = atomicAdd(&sE[s2], 1u);
+                  } else {
+                    if (key[k] < pv) atomicAdd(&sL[s2], 1u);
+                    const uint32_t q = atomicAdd(&sN[s2], 1u);
+                    aux[k] = q;
+                    SET(k, CS_OTHER);
+                    if (q < (uint32_t)CS_SIDE) sk[GL(k) + q] = key[k];
+                  }
+                }
+              __syncthreads();
+#pragma unroll
+              for (int k = 0; k < IPT; k++) {
+                if (ST(k) == CS_PIVOT) {
+                  fin[k] = GL(k) + sL[slot2[GL(k)]] + aux[k];
+                } else if (ST(k) == CS_OTHER) {
+                  const uint32_t s2 = slot2[GL(k)];
+                  const uint32_t no = sN[s2];
+                  if (no > (uint32_t)CS_SIDE) { bad = true; continue; }
+                  uint32_t r = GL(k) + (key[k] > spiv[s2] ? sE[s2] : 0u);
+                  for (uint32_t q = 0; q < no; q++) {
+                    const uint64_t kq = sk[GL(k) + q];
+                    r += (kq < key[k]) || (kq == key[k] && q < aux[k]);
+                  }
+                  fin[k] = r;
+                }
+              }
             }
           }
         }
       }
+#undef GL
+#undef ST
+#undef SET
     }
     if (__syncthreads_or(bad)) {
       if (tid == 0) redo_list[atomicAdd(redo_count, 1ull)] = g;

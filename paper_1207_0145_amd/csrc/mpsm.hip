@@ -629,7 +629,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     (void)hipEventDestroy(ev1);
     Result r;
     HIP_TRY(hipMemcpy(&r, res, sizeof(r), hipMemcpyDeviceToHost));
-    unsigned long long c[2];
+    unsigned long long c[5];
     HIP_TRY(hipMemcpy(c, ctr, sizeof(c), hipMemcpyDeviceToHost));
     uint32_t pc = 0;
     if (P.nR && P.nS) HIP_TRY(hipMemcpy(&pc, ws + P.Pc, 4, hipMemcpyDeviceToHost));
@@ -639,6 +639,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     stats->partitions = pc;
     stats->runs = P.Q;
     stats->oversize_buckets = c[0] + c[1];
+    stats->resorted_buckets = c[3] + c[4];
     stats->search_probes = r.search_probes;
     stats->search_fallbacks = r.fallbacks;
     stats->max_partition = r.spare;

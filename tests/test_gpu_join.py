@@ -5,6 +5,8 @@ Intermediate results are compared where they are unique: sorted key
 sequences, the multiset of tuples per run/bucket, splitters (same seeded
 sample on both sides), bucket boundaries, and merge-start offsets (unique
 lower bounds)."""
+import zlib
+
 import numpy as np
 import pytest
 import torch
@@ -179,6 +181,68 @@ def test_few_distinct_keys_oversize_equal_buckets():
     R = np.stack([keys[rng.integers(0, 3, 30000)], rng.integers(0, U64, 30000, dtype=np.uint64)], 1)
     S = np.stack([keys[rng.integers(0, 3, 40000)], rng.integers(0, U64, 40000, dtype=np.uint64)], 1)
     check(R, S)
+
+
+def _dup_pattern(name, rng, n):
+    """Key columns that stress the one-pass bucket sort: duplicates inside
+    interpolation cells, clusters inside a bucket, heavy keys with light
+    neighbours, and two heavy neighbours (which must fall back)."""
+    if name == "zipf_copies":          # many keys with tens to thousands of copies
+        base = rng.integers(0, U64, 1 << 16, dtype=np.uint64)
+        return base[(len(base) * rng.random(n) ** 2).astype(np.int64)]
+    if name == "two_clusters":         # two narrow clusters far apart, some repeats
+        k = rng.integers(0, 1 << 30, n, dtype=np.uint64)
+        k[rng.random(n) < 0.5] += np.uint64(1 << 62)
+        k[: n // 8] = k[n // 8: n // 4]
+        return k
+    if name == "heavy_with_neighbours":  # heavy keys with light keys right next to them
+        h = rng.integers(1 << 20, 1 << 60, 512, dtype=np.uint64)
+        k = h[rng.integers(0, len(h), n)]
+        light = rng.random(n) < 0.3
+        k[light] += rng.integers(1, 2000, int(light.sum()), dtype=np.uint64)
+        return k
+    if name == "geometric":            # distinct-ish keys packed towards zero
+        return np.floor(np.exp2(rng.random(n) * 60.0)).astype(np.uint64)
+    if name == "heavy_pairs":          # adjacent heavy keys share every cell: fallback path
+        h = rng.integers(1 << 20, 1 << 60, 256, dtype=np.uint64)
+        k = h[rng.integers(0, len(h), n)]
+        k[rng.random(n) < 0.5] += np.uint64(1)
+        return k
+    raise ValueError(name)
+
+
+@pytest.mark.parametrize("pattern", ["zipf_copies", "two_clusters", "heavy_with_neighbours", "geometric",
+                                     "heavy_pairs"])
+def test_bucket_sort_duplicates_and_clusters(pattern):
+    rng = np.random.default_rng(zlib.crc32(pattern.encode()))
+    nS = 1 << 20
+    S = np.stack([_dup_pattern(pattern, rng, nS), rng.integers(0, U64, nS, dtype=np.uint64, endpoint=True)], 1)
+    rk = np.unique(S[:, 0])
+    rk = rk[rng.random(len(rk)) < 0.7]
+    R = np.stack([np.concatenate([rk, rk[: len(rk) // 4]]),
+                  rng.integers(0, U64, len(rk) + len(rk) // 4, dtype=np.uint64, endpoint=True)], 1)
+    R = R[rng.permutation(len(R))]
+    cfg = mpsm.config(log2_run_len=17)
+    lay = mpsm.layout(len(R), nS, cfg)
+    ws = mpsm.alloc_workspace(len(R), nS, cfg)
+    got = gpu_join(R, S, cfg, workspace=ws, stats=True)
+    want = oracle.join(R, S)
+    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+    torch.cuda.synchronize()
+    L = lay["run_len"]
+    Ssorted = _ws_view(ws, lay["off_s_sorted"], 2 * nS, np.uint64).reshape(-1, 2)
+    ref = oracle.sort_runs(S, L)
+    assert np.array_equal(Ssorted[:, 0], ref[:, 0])
+    for j in range(lay["runs"]):
+        x, y = Ssorted[j * L:(j + 1) * L], ref[j * L:(j + 1) * L]
+        assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], y[np.lexsort((y[:, 1], y[:, 0]))])
+    Rsorted = _ws_view(ws, lay["off_r_sorted"], 2 * len(R), np.uint64).reshape(-1, 2)
+    assert np.array_equal(Rsorted[:, 0], np.sort(R[:, 0]))
+    st = got["stats"]
+    _say(f"{pattern}: resorted buckets {st['resorted_buckets']} of {lay['runs'] * lay['s_buckets']} S buckets, "
+         f"oversize {st['oversize_buckets']}")
+    if pattern == "heavy_pairs":
+        assert st["resorted_buckets"] > 0
 
 
 # ------------------------------------------------------- named workloads
