@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libmpsm.so")
 SOURCES = [os.path.join(HERE, "csrc", "mpsm.hip")]
-HEADERS = ["common.h", "block_sort.h", "kernels.h"]
+HEADERS = ["common.h", "block_sort.h", "kernels.h", "learned.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

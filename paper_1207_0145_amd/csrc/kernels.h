@@ -481,7 +481,18 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
     if (n == 0) continue;
     const uint64_t lo = blo[g], span = bhi[g] - lo;
     if (span == 0) {   // one key: input order is sorted order
-      for (uint32_t i = tid; i < n; i += NT) {
+      uint32_t i = tid;
+      for (; i + 3 * NT < n; i += 4 * NT) {   // four loads in flight
+        tup_t t[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) t[u] = load_tup(src + a + i + u * NT);
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          store_tup(dst + a + i + u * NT, t[u]);
+          emit_sorted(so, g, a, i + u * NT, lo);
+        }
+      }
+      for (; i < n; i += NT) {
         store_tup(dst + a + i, load_tup(src + a + i));
         emit_sorted(so, g, a, i, lo);
       }
@@ -589,23 +600,30 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
           __syncthreads();
           // second-level cells, as many as the group has keys; C = 0 marks a
           // span narrower than that (one key per cell)
+          bool mixed = false;
           for (uint32_t s = tid; s < nbig; s += NT) {
             const uint64_t sp2 = smax[s] - smin[s];
+            mixed |= sp2 != 0;
             sC[s] = sp2 < (uint64_t)sgs[s] ? 0ull : interp_scale(sgs[s], sp2);
           }
-          __syncthreads();
+          // when every large group holds one key, their positions stand
+          if (__syncthreads_or(mixed)) {
           auto cell = [&](uint32_t s, uint64_t k) -> uint32_t {
             const uint64_t x = k - smin[s], c = sC[s];
             const uint32_t c2 = c ? (uint32_t)__umul64hi(x, c) : (uint32_t)x;
             return c2 < sgs[s] ? c2 : sgs[s] - 1;
           };
 #pragma unroll
-          for (int k = 0; k < IPT; k++)
+          for (int k = 0; k < IPT; k++) {
+            bool w = false;
+            uint32_t c = 0;
             if (ST(k) == CS_BIG) {
               const uint32_t s = slot1[sub(key[k])];
-              if (smin[s] == smax[s]) { SET(k, CS_DONE); continue; }   // one key: positions stand
-              aux[k] = atomicAdd(&cnt2[GL(k) + cell(s, key[k])], 1u);
+              if (smin[s] == smax[s]) SET(k, CS_DONE);   // one key: positions stand
+              else { w = true; c = GL(k) + cell(s, key[k]); }
             }
+            if (w) aux[k] = atomicAdd(&cnt2[c], 1u);
+          }
           __syncthreads();
           // exclusive scan of the second-level counters over the bucket
           {
@@ -666,10 +684,11 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
               // three-way split: copies of the pivot count themselves, the
               // other keys are packed at the front of the cell
 #pragma unroll
-              for (int k = 0; k < IPT; k++)
-                if (ST(k) == CS_PIVOT) {
-                  const uint32_t s2 = slot2[GL(k)];
-                  const uint64_t pv = spiv[s2];
+              for (int k = 0; k < IPT; k++) {
+                const bool piv = ST(k) == CS_PIVOT;
+                const uint32_t s2 = piv ? slot2[GL(k)] : 0u;
+                const uint64_t pv = piv ? spiv[s2] : 0ull;
+                if (piv) {
                   if (key[k] == pv) {
                     aux[k] = atomicAdd(&sE[s2], 1u);
                   } else {
@@ -680,6 +699,7 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
                     if (q < (uint32_t)CS_SIDE) sk[GL(k) + q] = key[k];
                   }
                 }
+              }
               __syncthreads();
 #pragma unroll
               for (int k = 0; k < IPT; k++) {
@@ -698,6 +718,7 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
                 }
               }
             }
+          }
           }
         }
       }
@@ -1122,12 +1143,18 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
       }
       __syncthreads();
       const uint64_t l = jlo, c = jC;
+      // cells are clamped to the directory, so the fill stays bounded even
+      // if the partition were not sorted
+      auto cell_of = [&](uint64_t key) -> int {
+        const uint64_t x = __umul64hi(key - l, c);
+        return x < (uint64_t)JOIN_DIR ? (int)x : JOIN_DIR - 1;
+      };
       for (uint32_t i = tid; i < rn; i += JOIN_NT) {
-        const int ci = (int)__umul64hi(rk[i] - l, c);
-        const int cp = i ? (int)__umul64hi(rk[i - 1] - l, c) : -1;
+        const int ci = cell_of(rk[i]);
+        const int cp = i ? cell_of(rk[i - 1]) : -1;
         for (int cc = cp + 1; cc <= ci; cc++) jdir[cc] = (uint16_t)i;
       }
-      const int clast = (int)__umul64hi(rk[rn - 1] - l, c);
+      const int clast = cell_of(rk[rn - 1]);
       for (int cc = (int)tid; cc <= JOIN_DIR; cc += JOIN_NT)
         if (cc > clast) jdir[cc] = (uint16_t)rn;
       __syncthreads();
