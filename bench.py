@@ -61,6 +61,74 @@ def measured_traffic(step: str, workload: str):
     return t.get("steps", {}).get(step, {}).get("hbm_bytes_per_launch")
 
 
+# launch steps -> (kernel name prefix, occurrence of that kernel inside one join)
+STEP_DISPATCH = {
+    "s_histogram": ("k_bucket_hist", 0), "s_scatter": ("k_bucket_scatter", 0),
+    "r1_histogram": ("k_bucket_hist", 1), "r1_scatter": ("k_bucket_scatter", 1),
+    "r2_histogram": ("k_bucket_hist", 2), "r2_scatter": ("k_bucket_scatter", 2),
+    "s_bucket_sort": ("void k_bucket_sort_cs<1024, 4", 0), "r_bucket_sort": ("void k_bucket_sort_cs<1024, 8", 1),
+    "search": ("k_search", 0), "join": ("void k_join<0", 0),
+}
+
+
+def _read_csv(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _per_join(rows, name_key, start_key):
+    """Split dispatch rows (in dispatch order) into joins at k_init_result."""
+    rows = sorted(rows, key=lambda r: int(r["Dispatch_Id"]))
+    joins, cur = [], None
+    for r in rows:
+        if r[name_key].startswith("k_init_result"):
+            cur = []
+            joins.append(cur)
+        if cur is not None:
+            cur.append(r)
+    return joins
+
+
+def _nth(join, prefix, k):
+    hits = [r for r in join if r["Kernel_Name"].startswith(prefix)]
+    return hits[k] if k < len(hits) else None
+
+
+def summarize_profiles(kt_csv, fetch_csv, write_csv, workload, nR, nS, command):
+    """HBM bytes and durations per launch step from a rocprofv3 kernel trace
+    and two counter runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), scaled
+    by what the counters read for a 1 GiB device copy in the same runs."""
+    kt = _per_join(_read_csv(kt_csv), "Kernel_Name", "Start_Timestamp")
+    cal = {}
+    for label, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = _read_csv(path)
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"] or "copy" in r["Kernel_Name"].lower()]
+        big = max(copies, key=lambda r: float(r["Counter_Value"]))
+        cal[label] = {"copy_kib": float(big["Counter_Value"]), "factor": (1 << 30) / (1024.0 * float(big["Counter_Value"]))}
+        cal[label]["joins"] = _per_join(rows, "Kernel_Name", "Start_Timestamp")
+    steps = {}
+    for step, (prefix, k) in STEP_DISPATCH.items():
+        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+                for j in kt for r in [_nth(j, prefix, k)] if r is not None]
+        f = _nth(cal["fetch"]["joins"][0], prefix, k)
+        w = _nth(cal["write"]["joins"][0], prefix, k)
+        if not durs or f is None or w is None:
+            continue
+        fb = float(f["Counter_Value"]) * 1024 * cal["fetch"]["factor"]
+        wb = float(w["Counter_Value"]) * 1024 * cal["write"]["factor"]
+        rel, per = STEP_BYTES.get(step, ("RS", 0))
+        alg = per * {"S": nS, "R": nR, "RS": nR + nS}[rel]
+        steps[step] = {"kernel": f["Kernel_Name"][:80], "avg_launch_ms": round(sum(durs) / len(durs), 4),
+                       "launches": len(durs), "fetch_bytes": round(fb), "write_bytes": round(wb),
+                       "hbm_bytes_per_launch": round(fb + wb), "algorithmic_bytes": alg or None,
+                       "traffic_over_algorithmic": round((fb + wb) / alg, 3) if alg else None}
+    return {"workload": workload, "nR": nR, "nS": nS, "kernel_source_digest": kernel_source_digest(),
+            "calibration": {k: {"copy_counter_kib": v["copy_kib"], "bytes_per_counter_byte": round(v["factor"], 4)}
+                            for k, v in cal.items()},
+            "command": command, "steps": steps}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -129,7 +197,19 @@ def main():
     ap.add_argument("--search", default="index", choices=["index", "binary", "interp"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--summarize-profiles", nargs=3, metavar=("KERNEL_TRACE_CSV", "FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic_<workload>.json from rocprofv3 output (no GPU needed)")
+    ap.add_argument("--profile-command", default="", help="command line recorded in the summary")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        sizes = {"fk_uniform": (1 << 26, 1 << 28), "skewed": (1 << 26, 1 << 28), "fk_small": (1 << 20, 1 << 22)}
+        nR, nS = sizes[args.workload]
+        t = summarize_profiles(*args.summarize_profiles, args.workload, nR, nS, args.profile_command)
+        out = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
+        with open(out, "w") as f:
+            json.dump(t, f, indent=1)
+        print(json.dumps(t, indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
