@@ -202,6 +202,77 @@ mpsm_status mpsm_events_create(void** events, uint32_t n);
 void mpsm_events_destroy(void** events, uint32_t n);
 mpsm_status mpsm_events_elapsed(void* start, void* stop, float* ms);
 
+
+/* ---- Batched joins --------------------------------------------------------
+ * Many independent equi-joins of uneven sizes as ONE launch sequence: every
+ * phase of the method is a single kernel launch over all joins of the batch
+ * (segment tables span the joins; each join's inputs are read in place), so
+ * the per-launch cost is paid once per batch instead of once per join, and
+ * the whole sequence can be captured once into a hipGraph and replayed.
+ * Each join's result is the one mpsm_join gives (count and checksum as
+ * documented there).  In a batch R is always the private input (no role
+ * swap), splitters are sampled and the start search is BINARY, INTERP or
+ * INDEX; pairs and the max aggregate are not produced. */
+typedef struct mpsm_join_desc {
+  const mpsm_tuple* d_R;   /* device, nR tuples, 16-byte aligned (NULL if nR == 0) */
+  uint64_t nR;
+  const mpsm_tuple* d_S;   /* device, nS tuples, 16-byte aligned (NULL if nS == 0) */
+  uint64_t nS;
+  uint64_t* d_out_count;   /* device u64 */
+  uint64_t* d_out_checksum;/* device u64 */
+  uint64_t* d_out_times;   /* device u64[3] or NULL: batch start, start of the join's first work item,
+                              end of its last work item (GPU wall clock, mpsm_clock_hz() ticks per second;
+                              a join without work items reports the batch start three times) */
+} mpsm_join_desc;
+
+/* Host-side plan of a batch (opaque).  Holds a copy of the descriptors, the
+ * segment tables, the current tuning and, once used, a captured hipGraph. */
+typedef struct mpsm_batch mpsm_batch;
+
+/* Tuning of a batch: the S run length, the mean bucket / partition size
+ * (which fixes the number of buckets, i.e. the radix fan-out of every
+ * pass) and the S tuples per join work item (the join's work split). */
+typedef struct mpsm_batch_tuning {
+  uint32_t log2_run_len;   /* 16..22 */
+  uint32_t bucket_target;  /* 1024..4096 */
+  uint32_t join_chunk;     /* 4096..262144 */
+  uint32_t from_cache;     /* set by mpsm_batch_autotune: 1 if read from the cache file */
+  float ms;                /* set by mpsm_batch_autotune: measured batch time of the choice (0 if cached) */
+} mpsm_batch_tuning;
+
+/* Plan a batch of n >= 1 joins (descs: host array, copied).  Sums of nR and
+ * of nS must each stay below 2^32.  cfg may be NULL; its log2_run_len,
+ * bucket_target and join_chunk, when non-zero, are the initial tuning.
+ * Touches no device.  Returns MPSM_EINVAL / MPSM_EUNSUPPORTED on bad input. */
+mpsm_status mpsm_batch_create(const mpsm_join_desc* descs, uint32_t n, const mpsm_config* cfg, mpsm_batch** out);
+void mpsm_batch_destroy(mpsm_batch* b);
+
+/* Workspace bytes that serve every tuning the autotuner may pick. */
+uint64_t mpsm_batch_workspace_bytes(const mpsm_batch* b);
+
+/* Enqueue the batch on `stream`.  The first call with a workspace (or after
+ * a tuning change) copies the batch's tables into it; with use_graph != 0 the
+ * launch sequence is captured into a hipGraph on first use (on a stream the
+ * batch owns, after synchronising `stream`) and replayed on `stream`
+ * afterwards (the graph is bound to that workspace).  Calls on one workspace
+ * must not overlap. */
+mpsm_status mpsm_batch_run(mpsm_batch* b, void* d_workspace, uint64_t workspace_bytes, void* stream, int use_graph);
+
+/* Pick the tuning of this batch: from cache_path (a text file, may be NULL)
+ * when it holds an entry for a batch of this shape, else by timing every
+ * candidate tuning that fits the workspace on `stream` (synchronising) and
+ * appending the fastest to the cache.  Unreadable or malformed cache entries
+ * are ignored.  Sets the batch's tuning and fills *chosen (may be NULL). */
+mpsm_status mpsm_batch_autotune(mpsm_batch* b, void* d_workspace, uint64_t workspace_bytes, void* stream,
+                                const char* cache_path, mpsm_batch_tuning* chosen);
+
+/* Current tuning; set a tuning explicitly (validated; drops the graph). */
+mpsm_status mpsm_batch_get_tuning(const mpsm_batch* b, mpsm_batch_tuning* t);
+mpsm_status mpsm_batch_set_tuning(mpsm_batch* b, const mpsm_batch_tuning* t);
+
+/* Ticks per second of the GPU wall clock used by d_out_times. */
+uint64_t mpsm_clock_hz(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,7 +23,9 @@ STATUS = {0: "MPSM_OK", 1: "MPSM_EINVAL", 2: "MPSM_ECAPACITY", 3: "MPSM_ENOMEM",
 
 EXPORTS = ("mpsm_config_default", "mpsm_workspace_bytes", "mpsm_join", "mpsm_status_string",
            "mpsm_workspace_layout", "mpsm_join_events", "mpsm_marker_count", "mpsm_marker_name",
-           "mpsm_events_create", "mpsm_events_destroy", "mpsm_events_elapsed")
+           "mpsm_events_create", "mpsm_events_destroy", "mpsm_events_elapsed", "mpsm_batch_create",
+           "mpsm_batch_destroy", "mpsm_batch_workspace_bytes", "mpsm_batch_run", "mpsm_batch_autotune",
+           "mpsm_batch_get_tuning", "mpsm_batch_set_tuning", "mpsm_clock_hz")
 
 
 class MpsmConfig(ctypes.Structure):
@@ -57,6 +59,20 @@ class MpsmLayout(ctypes.Structure):
                 ("off_part_key", ctypes.c_uint64), ("off_offsets", ctypes.c_uint64), ("p_max", ctypes.c_uint32),
                 ("idx_stride", ctypes.c_uint32), ("off_run_index", ctypes.c_uint64),
                 ("idx_per_run", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class MpsmJoinDesc(ctypes.Structure):
+    _fields_ = [("d_R", ctypes.c_void_p), ("nR", ctypes.c_uint64), ("d_S", ctypes.c_void_p), ("nS", ctypes.c_uint64),
+                ("d_out_count", ctypes.c_void_p), ("d_out_checksum", ctypes.c_void_p),
+                ("d_out_times", ctypes.c_void_p)]
+
+
+class MpsmBatchTuning(ctypes.Structure):
+    _fields_ = [("log2_run_len", ctypes.c_uint32), ("bucket_target", ctypes.c_uint32),
+                ("join_chunk", ctypes.c_uint32), ("from_cache", ctypes.c_uint32), ("ms", ctypes.c_float)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -98,6 +114,23 @@ def lib():
         L.mpsm_events_destroy.restype = None
         L.mpsm_events_elapsed.argtypes = [p, p, ctypes.POINTER(ctypes.c_float)]
         L.mpsm_events_elapsed.restype = ctypes.c_int
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        L.mpsm_batch_create.argtypes = [ctypes.POINTER(MpsmJoinDesc), ctypes.c_uint32, ctypes.POINTER(MpsmConfig), pp]
+        L.mpsm_batch_create.restype = ctypes.c_int
+        L.mpsm_batch_destroy.argtypes = [p]
+        L.mpsm_batch_destroy.restype = None
+        L.mpsm_batch_workspace_bytes.argtypes = [p]
+        L.mpsm_batch_workspace_bytes.restype = u64
+        L.mpsm_batch_run.argtypes = [p, p, u64, p, ctypes.c_int]
+        L.mpsm_batch_run.restype = ctypes.c_int
+        L.mpsm_batch_autotune.argtypes = [p, p, u64, p, ctypes.c_char_p, ctypes.POINTER(MpsmBatchTuning)]
+        L.mpsm_batch_autotune.restype = ctypes.c_int
+        L.mpsm_batch_get_tuning.argtypes = [p, ctypes.POINTER(MpsmBatchTuning)]
+        L.mpsm_batch_get_tuning.restype = ctypes.c_int
+        L.mpsm_batch_set_tuning.argtypes = [p, ctypes.POINTER(MpsmBatchTuning)]
+        L.mpsm_batch_set_tuning.restype = ctypes.c_int
+        L.mpsm_clock_hz.argtypes = []
+        L.mpsm_clock_hz.restype = u64
         _lib = L
     return _lib
 
@@ -251,3 +284,83 @@ def join(R, S, cfg: MpsmConfig | None = None, pairs: bool = False, pairs_capacit
     if st is not None:
         res["stats"] = {name: getattr(st, name) for name, _ in st._fields_}
     return res
+
+
+class Batch:
+    """A batch of independent joins run as one launch sequence
+    (mpsm_batch_*).  joins: list of (R, S) tensors (``[n, 2]`` on the GPU,
+    n may be 0).  Results land in ``self.out`` (int64 [n_joins, 2]: count,
+    checksum) and ``self.times`` (int64 [n_joins, 3] GPU wall-clock ticks:
+    batch start, first work item, last work item)."""
+
+    def __init__(self, joins, cfg: MpsmConfig | None = None, device=None):
+        import torch
+        self.joins = list(joins)
+        dev = device or (self.joins[0][0].device if self.joins else torch.device("cuda", 0))
+        self.out = torch.zeros((len(self.joins), 2), dtype=torch.int64, device=dev)
+        self.times = torch.zeros((len(self.joins), 3), dtype=torch.int64, device=dev)
+        descs = (MpsmJoinDesc * len(self.joins))()
+        for i, (R, S) in enumerate(self.joins):
+            _check_tuples(R, "R")
+            _check_tuples(S, "S")
+            d = descs[i]
+            d.d_R = R.data_ptr() if R.shape[0] else None
+            d.nR = R.shape[0]
+            d.d_S = S.data_ptr() if S.shape[0] else None
+            d.nS = S.shape[0]
+            d.d_out_count = self.out.data_ptr() + 16 * i
+            d.d_out_checksum = self.out.data_ptr() + 16 * i + 8
+            d.d_out_times = self.times.data_ptr() + 24 * i
+        self.handle = ctypes.c_void_p()
+        rc = lib().mpsm_batch_create(descs, len(self.joins), _cfg_ptr(cfg), ctypes.byref(self.handle))
+        if rc != 0:
+            raise MpsmError(rc, "mpsm_batch_create")
+        nbytes = int(lib().mpsm_batch_workspace_bytes(self.handle))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+    def run(self, use_graph: bool = False, stream=None):
+        rc = lib().mpsm_batch_run(self.handle, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                  _stream_handle(stream), 1 if use_graph else 0)
+        if rc != 0:
+            raise MpsmError(rc, "mpsm_batch_run")
+
+    def autotune(self, cache_path: str | None = None, stream=None) -> dict:
+        t = MpsmBatchTuning()
+        rc = lib().mpsm_batch_autotune(self.handle, ctypes.c_void_p(self.workspace.data_ptr()),
+                                       self.workspace.numel(), _stream_handle(stream),
+                                       cache_path.encode() if cache_path else None, ctypes.byref(t))
+        if rc != 0:
+            raise MpsmError(rc, "mpsm_batch_autotune")
+        return t.as_dict()
+
+    def tuning(self) -> dict:
+        t = MpsmBatchTuning()
+        rc = lib().mpsm_batch_get_tuning(self.handle, ctypes.byref(t))
+        if rc != 0:
+            raise MpsmError(rc, "mpsm_batch_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, log2_run_len: int, bucket_target: int, join_chunk: int):
+        t = MpsmBatchTuning(log2_run_len, bucket_target, join_chunk, 0, 0.0)
+        rc = lib().mpsm_batch_set_tuning(self.handle, ctypes.byref(t))
+        if rc != 0:
+            raise MpsmError(rc, "mpsm_batch_set_tuning")
+
+    def results(self):
+        """[(count, checksum)] as Python uint64 ints (synchronises)."""
+        return [(c & 0xFFFFFFFFFFFFFFFF, s & 0xFFFFFFFFFFFFFFFF) for c, s in self.out.cpu().tolist()]
+
+    def close(self):
+        if self.handle:
+            lib().mpsm_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def clock_hz() -> int:
+    return int(lib().mpsm_clock_hz())

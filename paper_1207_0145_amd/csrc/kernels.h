@@ -60,6 +60,21 @@ struct Result {              // device result block
   unsigned long long big_buckets, search_probes, fallbacks, spare;   // spare: largest R partition
 };
 
+// One join of a batch (device table).  The host fills the run and bucket
+// ranges and the output pointers; the kernels fill the rest.
+struct BatchJoin {
+  uint32_t r0, Q;                     // S runs [r0, r0 + Q)
+  uint32_t g0, G;                     // R buckets [g0, g0 + G)
+  uint32_t p0, P;                     // partitions [p0, p0 + P)
+  unsigned long long obase;           // first entry of the join's (P + 1) x Q block of start offsets
+  uint32_t items, done;               // join work items; items finished
+  unsigned long long count, checksum;
+  unsigned long long t_first, t_done; // wall clock: first work item started, last one finished
+  uint64_t* out_count;
+  uint64_t* out_checksum;
+  uint64_t* out_times;                // NULL, or 3 u64: batch start, t_first, t_done
+};
+
 __global__ void k_init_result(Result* res, uint32_t* zero_words, uint32_t nzero) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
@@ -187,7 +202,7 @@ template <int NT, int IPT>
 __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict__ src, const uint32_t* seg_start,
                                                          const uint32_t* seg_len, const uint32_t* seg_nb,
                                                          uint32_t NBmax, uint32_t OS, uint64_t level_seed,
-                                                         uint64_t* spl) {
+                                                         uint64_t* spl, const tup_t* const* seg_src) {
   using Sorter = BlockSort<NT, IPT, 4>;
   __shared__ uint64_t buf[Sorter::BUF_WORDS];
   __shared__ uint32_t wsum[Sorter::WSUM_WORDS];
@@ -195,6 +210,7 @@ __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict
   const uint32_t s = blockIdx.x, tid = threadIdx.x;
   const uint32_t len = seg_len[s], start = seg_start[s], nb = seg_nb[s];
   if (len == 0 || nb < 2) return;
+  if (seg_src) src = seg_src[s] - start;   // segment read in place from its own array
   const uint32_t M = nb * OS;
   uint64_t* out = spl + (uint64_t)s * (NBmax - 1);
   const uint64_t seed = splitmix_at(level_seed, s);
@@ -234,13 +250,14 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
                                                          const uint32_t* seg_len, const uint32_t* seg_tile0,
                                                          const uint32_t* seg_cnt0, const uint32_t* seg_nb,
                                                          uint32_t nseg, const uint64_t* spl, uint32_t NBmax,
-                                                         uint32_t TILE, uint32_t* cnt) {
+                                                         uint32_t TILE, uint32_t* cnt, const tup_t* const* seg_src) {
   __shared__ uint64_t sp[MAX_NB];
   __shared__ uint32_t h[MAX_NB];
   __shared__ SplitDir<SPLIT_DIR> dir;
   const uint32_t g = blockIdx.x;
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
+  if (seg_src) src = seg_src[s] - seg_start[s];   // segment read in place from its own array
   const uint32_t t = g - seg_tile0[s], ntiles = seg_tile0[s + 1] - seg_tile0[s];
   const uint32_t segend = seg_start[s] + seg_len[s];
   const uint32_t a = seg_start[s] + t * TILE;
@@ -273,7 +290,8 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
                                                             const uint32_t* seg_start, const uint32_t* seg_len,
                                                             const uint32_t* seg_tile0, const uint32_t* seg_cnt0,
                                                             const uint32_t* seg_nb, uint32_t nseg, const uint64_t* spl,
-                                                            uint32_t NBmax, uint32_t TILE, const uint32_t* pos) {
+                                                            uint32_t NBmax, uint32_t TILE, const uint32_t* pos,
+                                                            const tup_t* const* seg_src) {
   __shared__ uint64_t sp[MAX_NB];
   __shared__ uint32_t cursor[MAX_NB], lcnt[MAX_NB], lofs[MAX_NB];
   __shared__ tup_t stage[SCAT_CH];
@@ -283,6 +301,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   const uint32_t g = blockIdx.x, tid = threadIdx.x;
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
+  if (seg_src) src = seg_src[s] - seg_start[s];   // segment read in place from its own array
   const uint32_t t = g - seg_tile0[s], ntiles = seg_tile0[s + 1] - seg_tile0[s];
   const uint32_t segend = seg_start[s] + seg_len[s];
   const uint32_t a = seg_start[s] + t * TILE;
@@ -927,6 +946,25 @@ __device__ __forceinline__ uint32_t interp_search(const tup_t* run, uint32_t n, 
 // +-eps slots around the prediction, bisects that window (or, when the check
 // fails, the whole index), then the run window.  All modes return the same
 // lower bound.
+// Lower bound of key in a sorted run of n tuples by BINARY, INTERP or INDEX
+// (bisection of the run's equi-height index idx of nidx keys, every
+// idx_stride-th key, then of the idx_stride-wide window).
+__device__ __forceinline__ uint32_t run_lower_bound(int mode, const tup_t* run, uint32_t n, uint64_t key,
+                                                    const uint64_t* idx, uint32_t idx_stride, uint32_t* probes) {
+  if (mode == SEARCH_BINARY) return lb_keys(run, 0, n, key, probes);
+  if (mode == SEARCH_INTERP) return interp_search(run, n, key, probes);
+  const uint32_t nidx = (n + idx_stride - 1) / idx_stride;
+  uint32_t lo = 0, hi = nidx;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    (*probes)++;
+    if (idx[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  const uint32_t a = lo ? (lo - 1) * idx_stride + 1 : 0;
+  const uint32_t b = lo < nidx ? lo * idx_stride : n;
+  return lb_keys(run, a, b, key, probes);
+}
+
 __global__ void __launch_bounds__(256) k_search(const tup_t* __restrict__ U, const uint32_t* run_start,
                                                 const uint32_t* run_len, uint32_t Q, const uint64_t* run_idx,
                                                 uint32_t idx_stride, uint32_t idx_per_run, const uint32_t* Pcount,
@@ -1038,6 +1076,9 @@ struct JoinArgs {
   uint64_t pairs_cap;
   uint32_t* item_cnt;       // per-item pair counts (count pass) / offsets (write pass)
   int swapped;              // internal R is the caller's S
+  // batch: per-join table and the join of every partition
+  BatchJoin* J;
+  const uint32_t* pjoin;
 };
 
 __device__ __forceinline__ uint32_t item_partition(const uint32_t* item_pre, uint32_t np2, uint32_t item) {
@@ -1061,7 +1102,7 @@ __device__ __forceinline__ uint32_t item_partition(const uint32_t* item_pre, uin
 // pairs.  VM: what the LDS holds next to each R key.
 constexpr int JOIN_U = 4;     // S tuples per thread per batch (two batches in flight)
 
-template <int MODE, int VM>
+template <int MODE, int VM, bool BATCH = false>
 __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
   __shared__ uint64_t rk[JOIN_CAP];
   __shared__ uint64_t rv[JOIN_CAP];
@@ -1073,7 +1114,6 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
   __shared__ unsigned long long item_acc;
   __shared__ uint64_t jlo, jhi, jC;
   const uint32_t tid = threadIdx.x;
-  const uint32_t Q = A.Q;
   const uint32_t np2 = A.Pmax + 2;
   const uint32_t total = A.item_pre[np2 - 1];
   unsigned long long cnt = 0, sum = 0, mx = 0;
@@ -1085,7 +1125,16 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
     const uint32_t p = item_partition(A.item_pre, np2, item);
     const uint32_t k = item - A.item_pre[p];
     const uint32_t rs = A.pstart[p], rn = A.plen[p];
+    // the partition's rows of start offsets and its runs (in a batch: those of its join)
+    uint32_t Q = A.Q, r0 = 0, jb = 0;
     const uint32_t* oa = A.o + (uint64_t)p * Q;
+    if (BATCH) {
+      jb = A.pjoin[p];
+      Q = A.J[jb].Q;
+      r0 = A.J[jb].r0;
+      oa = A.o + A.J[jb].obase + (uint64_t)(p - A.J[jb].p0) * Q;
+      if (tid == 0) atomicMin(&A.J[jb].t_first, (unsigned long long)wall_clock64());
+    }
     const uint32_t* ob = oa + Q;
     __syncthreads();   // LDS of the previous item is free
     // prefix of slice lengths over the runs; sbase[j] + x = S position of
@@ -1097,7 +1146,7 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
       const uint32_t len = j < Q ? ob[j] - oj : 0;
       uint32_t tot;
       const uint32_t ex = block_excl_scan<JOIN_NT>(len, wsum, &tot);
-      if (j < Q) { cum[j] = carry + ex; sbase[j] = A.run_start[j] + oj - (carry + ex); }
+      if (j < Q) { cum[j] = carry + ex; sbase[j] = A.run_start[r0 + j] + oj - (carry + ex); }
       carry += tot;
       __syncthreads();
     }
@@ -1237,8 +1286,21 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
       if (tid == 0) A.item_cnt[item] = (uint32_t)c;
       cnt = 0;
     }
+    if (BATCH && MODE == 0) {
+      // a batch flushes every item into its join, and the join's last item
+      // stamps the finishing time
+      const uint64_t c = block_sum64<JOIN_NT>(cnt, red);
+      const uint64_t sm = block_sum64<JOIN_NT>(sum, red);
+      if (tid == 0) {
+        if (c) { atomicAdd(&A.J[jb].count, (unsigned long long)c); atomicAdd(&A.J[jb].checksum, (unsigned long long)sm); }
+        __threadfence();
+        if (atomicAdd(&A.J[jb].done, 1u) + 1 == A.J[jb].items) A.J[jb].t_done = wall_clock64();
+      }
+      cnt = 0;
+      sum = 0;
+    }
   }
-  if (MODE == 0) {
+  if (MODE == 0 && !BATCH) {
     const uint64_t c = block_sum64<JOIN_NT>(cnt, red);
     const uint64_t sm = block_sum64<JOIN_NT>(sum, red);
     if (tid == 0) {

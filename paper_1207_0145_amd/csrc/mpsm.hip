@@ -5,6 +5,13 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <string>
+#include <vector>
+
+#include "batch.h"
 #include "kernels.h"
 #include "mpsm.h"
 
@@ -275,7 +282,7 @@ Level make_level(char* ws, uint64_t seg_off, uint32_t nseg, uint32_t NBmax, uint
 // One bucket pass over segments: splitters, histogram, scan, scatter, table.
 // Markers mk0 .. mk0+3 follow splitters, histogram, scan and scatter.
 mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L, uint32_t* bsum, hipStream_t st,
-                        Marker& mk, uint32_t mk0) {
+                        Marker& mk, uint32_t mk0, const tup_t* const* seg_src = nullptr) {
   const Seg& sg = L.seg;
   k_seg_plan<<<1, 1024, 0, st>>>(L.nseg, L.NBmax, L.BT, HIST_TILE, sg.len, sg.tile0, sg.cnt0, sg.nb, sg.b0);
   LAUNCH_CHECK();
@@ -285,23 +292,23 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
   } else if (L.NBmax > 1) {
     if (L.NBmax * L.OS <= (uint32_t)(SMP_NT_S * SMP_IPT_S))
       k_sample_splitters<SMP_NT_S, SMP_IPT_S><<<L.nseg, SMP_NT_S, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax,
-                                                                           L.OS, L.level_seed, L.spl);
+                                                                           L.OS, L.level_seed, L.spl, seg_src);
     else
       k_sample_splitters<SMP_NT, SMP_IPT><<<L.nseg, SMP_NT, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax, L.OS,
-                                                                     L.level_seed, L.spl);
+                                                                     L.level_seed, L.spl, seg_src);
     LAUNCH_CHECK();
   }
   mk.mark(mk0);
   if (L.max_tiles) {
     k_bucket_hist<<<L.max_tiles, HIST_NT, 0, st>>>(src, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb, L.nseg, L.spl,
-                                                   L.NBmax, HIST_TILE, L.cnt);
+                                                   L.NBmax, HIST_TILE, L.cnt, seg_src);
     LAUNCH_CHECK();
     mk.mark(mk0 + 1);
     mpsm_status rc = scan_u32(L.cnt, L.cnt, L.ncnt, bsum, st);
     if (rc != MPSM_OK) return rc;
     mk.mark(mk0 + 2);
     k_bucket_scatter<<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb, L.nseg,
-                                                      L.spl, L.NBmax, HIST_TILE, L.cnt);
+                                                      L.spl, L.NBmax, HIST_TILE, L.cnt, seg_src);
     LAUNCH_CHECK();
   } else {
     mk.mark_range(mk0 + 1, mk0 + 2);
@@ -598,6 +605,8 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     A.Pmax = P.Pmax;
     A.JCH = P.JCH;
     A.res = res;
+    A.J = nullptr;
+    A.pjoin = nullptr;
     A.pairs = reinterpret_cast<uint64_t*>(d_pairs);
     A.pairs_cap = d_pairs ? pairs_capacity : 0;
     A.item_cnt = reinterpret_cast<uint32_t*>(ws + P.item_cnt);
@@ -700,5 +709,529 @@ mpsm_status mpsm_events_elapsed(void* start, void* stop, float* ms) {
   if (!start || !stop || !ms) return MPSM_EINVAL;
   return hipEventElapsedTime(ms, (hipEvent_t)start, (hipEvent_t)stop) == hipSuccess ? MPSM_OK : MPSM_EHIP;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct mpsm_batch {
+  std::vector<mpsm_join_desc> d;
+  mpsm_config cfg;
+  uint32_t L = 0, BT = 0, JCH = 0;       // current tuning
+  uint64_t ws_max = 0;                   // workspace serving every candidate tuning
+  // tables of the current tuning, staged in pinned host memory
+  void* host = nullptr;
+  uint64_t host_bytes = 0;
+  void* uploaded_to = nullptr;           // workspace that holds them
+  hipGraphExec_t graph = nullptr;
+  void* graph_ws = nullptr;
+  hipStream_t capture = nullptr;         // private stream the graph is captured on
+};
+
+namespace {
+
+constexpr uint32_t kBatchL[] = {1u << 16, 1u << 18, 1u << 20};
+constexpr uint32_t kBatchBT[] = {2048u, 4096u};
+constexpr uint32_t kBatchJCH[] = {16384u, 65536u};
+
+struct BatchPlan {
+  uint32_t n, L, BT, JCH;
+  uint32_t NBs, OSs, OSr, Qtot, Gs, Gr, nact;
+  uint64_t nS, nR;
+  uint32_t tilesS, tilesR, Pmax;
+  uint64_t cntS, cntR, ocap, item_cap;
+  // workspace offsets
+  uint64_t T, U, Rp, Rs, cS, cR, bsum, segS, segR, srcS, srcR, splS, splR, bstS, bstR, bndS, bndR;
+  uint64_t bigS, midS, redoS, redoR, bigR, ctr, bkey, Pc, pstart, plen, pkey, pjoin, ridx, o, items, item_pre;
+  uint64_t J, tstart, ototal;
+  uint64_t tab_off, tab_bytes;           // host-written tables: one contiguous range
+  uint64_t total;
+};
+
+bool batch_tuning_valid(uint32_t L, uint32_t BT, uint32_t JCH) {
+  return L >= (1u << 16) && L <= (1u << 22) && (L & (L - 1)) == 0 && BT >= 1024 && BT <= 4096 && JCH >= 4096 &&
+         JCH <= (1u << 18);
+}
+
+uint32_t batch_nb(uint64_t len, uint32_t BT) {   // k_seg_plan's bucket count of one segment
+  uint64_t nb = cdiv(len, BT);
+  if (nb < 1) nb = 1;
+  if (nb > MAX_NB) nb = MAX_NB;
+  return (uint32_t)nb;
+}
+
+bool make_batch_plan(const mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH, BatchPlan* P) {
+  memset(P, 0, sizeof(*P));
+  P->n = (uint32_t)b->d.size();
+  P->L = L; P->BT = BT; P->JCH = JCH;
+  if (!batch_tuning_valid(L, BT, JCH)) return false;
+  const uint32_t BTs = BT < 2048u ? BT : 2048u;
+  P->NBs = next_pow2(cdiv(L, BTs));
+  if (P->NBs > (uint32_t)MAX_NB) P->NBs = MAX_NB;
+  const uint32_t OSreq = b->cfg.oversample ? b->cfg.oversample : 32u;
+  auto os_for = [&](uint32_t NB) { return NB > 1 ? (SMP_CAP / NB < OSreq ? SMP_CAP / NB : OSreq) : 1u; };
+  P->OSs = os_for(P->NBs);
+  P->OSr = os_for(MAX_NB);
+  uint64_t tilesS = 0, tilesR = 0, cntR = 0, ocap = 0;
+  for (const mpsm_join_desc& j : b->d) {
+    if (!j.nR || !j.nS) continue;
+    const uint64_t Q = cdiv(j.nS, L);
+    if (Q > (uint64_t)JOIN_QMAX) return false;
+    const uint32_t nb = batch_nb(j.nR, BT);
+    P->nact++;
+    P->nS += j.nS; P->nR += j.nR; P->Qtot += (uint32_t)Q; P->Gr += nb;
+    for (uint64_t q = 0; q < Q; q++) tilesS += cdiv(q + 1 < Q ? L : j.nS - q * L, HIST_TILE);
+    const uint64_t tr = cdiv(j.nR, HIST_TILE);
+    tilesR += tr;
+    cntR += tr * nb;
+    ocap += (uint64_t)(nb + 1) * Q;
+  }
+  if (P->nS >= (1ull << 32) || P->nR >= (1ull << 32)) return false;
+  P->Gs = P->Qtot * P->NBs;
+  P->tilesS = (uint32_t)tilesS; P->tilesR = (uint32_t)tilesR;
+  P->cntS = tilesS * P->NBs; P->cntR = cntR ? cntR : 1;
+  P->Pmax = P->Gr;
+  P->ocap = ocap;
+  P->item_cap = P->nS / JCH + P->Pmax + 2;
+  const uint32_t ipr = (uint32_t)cdiv(L, IDX_STRIDE);
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) { uint64_t o = off; off += (bytes + 255) & ~255ull; return o; };
+  const uint64_t ts = sizeof(tup_t);
+  P->T = take(P->nS * ts);
+  P->U = take(P->nS * ts);
+  P->Rp = take(P->nR * ts);
+  P->Rs = take(P->nR * ts);
+  P->cS = take(P->cntS * 4 + 4);
+  P->cR = take(P->cntR * 4);
+  uint64_t maxscan = P->cntS > P->cntR ? P->cntS : P->cntR;
+  if (P->item_cap > maxscan) maxscan = P->item_cap;
+  P->bsum = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);
+  // host-written tables, contiguous: S and R segment start/len (inside the
+  // 6-array segment tables), source pointers, join table
+  P->tab_off = off;
+  P->segS = take(6ull * (P->Qtot + 1) * 4);
+  P->segR = take(6ull * (P->nact + 1) * 4);
+  P->srcS = take((uint64_t)P->Qtot * 8);
+  P->srcR = take((uint64_t)P->nact * 8);
+  P->J = take((uint64_t)P->n * sizeof(BatchJoin));
+  P->tab_bytes = off - P->tab_off;
+  P->splS = take((uint64_t)P->Qtot * P->NBs * 8);
+  P->splR = take((uint64_t)P->nact * MAX_NB * 8);
+  P->bstS = take(((uint64_t)P->Gs + 1) * 4);
+  P->bstR = take(((uint64_t)P->Gr + 1) * 4);
+  P->bndS = take((uint64_t)P->Gs * 16);
+  P->bndR = take((uint64_t)P->Gr * 16);
+  P->bigS = take((uint64_t)P->Gs * 4);
+  P->midS = take((uint64_t)P->Gs * 4);
+  P->redoS = take((uint64_t)P->Gs * 4);
+  P->redoR = take((uint64_t)P->Gr * 4);
+  P->bigR = take((uint64_t)P->Gr * 4);
+  P->ctr = take(8 * 8);
+  P->bkey = take((uint64_t)P->Gr * 8);
+  P->Pc = take(4);
+  P->pstart = take((uint64_t)P->Pmax * 4);
+  P->plen = take((uint64_t)P->Pmax * 4);
+  P->pkey = take((uint64_t)P->Pmax * 8);
+  P->pjoin = take((uint64_t)P->Pmax * 4);
+  P->ridx = take((uint64_t)P->Qtot * ipr * 8);
+  P->o = take(P->ocap * 4);
+  P->items = take(((uint64_t)P->Pmax + 2) * 4);
+  P->item_pre = take(((uint64_t)P->Pmax + 2) * 4);
+  P->tstart = take(8);
+  P->ototal = take(8);
+  P->total = off;
+  return true;
+}
+
+// Host image of the tables of plan P (written at workspace offset P.tab_off).
+void batch_tables(const mpsm_batch* b, const BatchPlan& P, char* img) {
+  memset(img, 0, P.tab_bytes);
+  uint32_t* sS = reinterpret_cast<uint32_t*>(img + (P.segS - P.tab_off));
+  uint32_t* sR = reinterpret_cast<uint32_t*>(img + (P.segR - P.tab_off));
+  const tup_t** pS = reinterpret_cast<const tup_t**>(img + (P.srcS - P.tab_off));
+  const tup_t** pR = reinterpret_cast<const tup_t**>(img + (P.srcR - P.tab_off));
+  BatchJoin* J = reinterpret_cast<BatchJoin*>(img + (P.J - P.tab_off));
+  uint32_t q = 0, a = 0, posS = 0, posR = 0, g0 = 0;
+  for (uint32_t i = 0; i < P.n; i++) {
+    const mpsm_join_desc& j = b->d[i];
+    BatchJoin& x = J[i];
+    memset(&x, 0, sizeof(x));
+    x.out_count = j.d_out_count;
+    x.out_checksum = j.d_out_checksum;
+    x.out_times = j.d_out_times;
+    x.r0 = q; x.g0 = g0;
+    if (!j.nR || !j.nS) continue;
+    const uint32_t Q = (uint32_t)cdiv(j.nS, P.L);
+    for (uint32_t r = 0; r < Q; r++) {
+      const uint64_t len = r + 1 < Q ? P.L : j.nS - (uint64_t)r * P.L;
+      sS[q + r] = posS + r * P.L;                         // start
+      sS[(P.Qtot + 1) + q + r] = (uint32_t)len;          // len
+      pS[q + r] = reinterpret_cast<const tup_t*>(j.d_S) + (uint64_t)r * P.L;
+    }
+    sR[a] = posR;
+    sR[(P.nact + 1) + a] = (uint32_t)j.nR;
+    pR[a] = reinterpret_cast<const tup_t*>(j.d_R);
+    x.Q = Q;
+    x.G = batch_nb(j.nR, P.BT);
+    q += Q; a++; g0 += x.G;
+    posS += (uint32_t)j.nS; posR += (uint32_t)j.nR;
+  }
+}
+
+void batch_drop_graph(mpsm_batch* b) {
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  b->graph_ws = nullptr;
+}
+
+mpsm_status batch_set(mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH) {
+  BatchPlan P;
+  if (!make_batch_plan(b, L, BT, JCH, &P)) return MPSM_EUNSUPPORTED;
+  b->L = L; b->BT = BT; b->JCH = JCH;
+  b->uploaded_to = nullptr;
+  batch_drop_graph(b);
+  return MPSM_OK;
+}
+
+mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hipStream_t st) {
+  tup_t* T = reinterpret_cast<tup_t*>(ws + P.T);
+  tup_t* U = reinterpret_cast<tup_t*>(ws + P.U);
+  tup_t* Rp = reinterpret_cast<tup_t*>(ws + P.Rp);
+  tup_t* Rs = reinterpret_cast<tup_t*>(ws + P.Rs);
+  uint32_t* bsum = reinterpret_cast<uint32_t*>(ws + P.bsum);
+  unsigned long long* ctr = reinterpret_cast<unsigned long long*>(ws + P.ctr);
+  BatchJoin* J = reinterpret_cast<BatchJoin*>(ws + P.J);
+  unsigned long long* tstart = reinterpret_cast<unsigned long long*>(ws + P.tstart);
+  unsigned long long* ototal = reinterpret_cast<unsigned long long*>(ws + P.ototal);
+  const uint64_t seed = b->cfg.seed;
+  Marker mk{nullptr, 0, st};
+  k_batch_init<<<(uint32_t)cdiv(P.n, 256) + 1, 256, 0, st>>>(J, P.n, tstart, reinterpret_cast<uint32_t*>(ctr), 16);
+  LAUNCH_CHECK();
+  if (P.nact) {
+    // phase 1: S runs of every join
+    Level LS = make_level(ws, P.segS, P.Qtot, P.NBs, 0, P.OSs, P.tilesS, seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
+                          P.bndS, P.Gs);
+    mpsm_status rc = bucket_pass(nullptr, T, (uint32_t)P.nS, LS, bsum, st, mk, 0,
+                                 reinterpret_cast<const tup_t* const*>(ws + P.srcS));
+    if (rc != MPSM_OK) return rc;
+    SortOut soS;
+    soS.run_idx = reinterpret_cast<uint64_t*>(ws + P.ridx);
+    soS.run_start = LS.seg.start;
+    soS.idx_stride = IDX_STRIDE;
+    soS.idx_shift = __builtin_ctz(IDX_STRIDE);
+    soS.idx_per_run = (uint32_t)cdiv(P.L, IDX_STRIDE);
+    soS.NB = P.NBs;
+    soS.bkey = nullptr;
+    uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
+    uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
+    uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+                                                                 nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
+    LAUNCH_CHECK();
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+                                                                      midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
+                                                                      soS);
+    LAUNCH_CHECK();
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, redoS, ctr + 3, bigS, ctr + 0, soS);
+    LAUNCH_CHECK();
+    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, bigS, ctr + 0, soS);
+    LAUNCH_CHECK();
+    // phases 2 and 3: one R segment per join, bucket counts from its size
+    Level LR = make_level(ws, P.segR, P.nact, MAX_NB, P.BT, P.OSr, P.tilesR, seed ^ TAG_R1, P.splR, P.cR, P.cntR,
+                          P.bstR, P.bndR, P.Gr);
+    rc = bucket_pass(nullptr, Rp, (uint32_t)P.nR, LR, bsum, st, mk, 0,
+                     reinterpret_cast<const tup_t* const*>(ws + P.srcR));
+    if (rc != MPSM_OK) return rc;
+    SortOut soR;
+    soR.run_idx = nullptr;
+    soR.run_start = nullptr;
+    soR.idx_stride = 1;
+    soR.idx_shift = 0;
+    soR.idx_per_run = 0;
+    soR.NB = 1;
+    soR.bkey = reinterpret_cast<uint64_t*>(ws + P.bkey);
+    uint32_t* redoR = reinterpret_cast<uint32_t*>(ws + P.redoR);
+    uint32_t* bigR = reinterpret_cast<uint32_t*>(ws + P.bigR);
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1><<<P.Gr, BL_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(),
+                                                                 nullptr, nullptr, bigR, ctr + 1, redoR, ctr + 4, soR);
+    LAUNCH_CHECK();
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(Rp, Rs, LR.bstart, redoR, ctr + 4, bigR, ctr + 1, soR);
+    LAUNCH_CHECK();
+    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(Rp, Rs, LR.bstart, bigR, ctr + 1, soR);
+    LAUNCH_CHECK();
+    uint32_t* Pc = reinterpret_cast<uint32_t*>(ws + P.Pc);
+    uint32_t* pstart = reinterpret_cast<uint32_t*>(ws + P.pstart);
+    uint32_t* plen = reinterpret_cast<uint32_t*>(ws + P.plen);
+    uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + P.pkey);
+    uint32_t* pjoin = reinterpret_cast<uint32_t*>(ws + P.pjoin);
+    k_partitions_batch<<<1, 1024, 0, st>>>(LR.bstart, soR.bkey, LR.Gcount(), J, P.n, Pc, pstart, plen, pkey, pjoin);
+    LAUNCH_CHECK();
+    k_batch_blocks<<<1, 64, 0, st>>>(J, P.n, ototal);
+    LAUNCH_CHECK();
+    // phase 4
+    uint32_t* o = reinterpret_cast<uint32_t*>(ws + P.o);
+    const int mode = b->cfg.search == MPSM_SEARCH_BINARY ? SEARCH_BINARY
+                   : b->cfg.search == MPSM_SEARCH_INTERP ? SEARCH_INTERP : SEARCH_INDEX;
+    if (P.ocap) {
+      k_search_batch<<<(uint32_t)cdiv(P.ocap, 256), 256, 0, st>>>(U, LS.seg.start, LS.seg.len,
+                                                                 reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
+                                                                 soS.idx_per_run, J, P.n, pkey, o, ototal, mode);
+      LAUNCH_CHECK();
+    }
+    uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
+    uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
+    k_join_items_batch<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, pjoin, J, o, P.Pmax, P.JCH, items);
+    LAUNCH_CHECK();
+    rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
+    if (rc != MPSM_OK) return rc;
+    JoinArgs A;
+    memset(&A, 0, sizeof(A));
+    A.Rs = Rs;
+    A.U = U;
+    A.run_start = LS.seg.start;
+    A.Q = 0;
+    A.Pcount = Pc;
+    A.pstart = pstart;
+    A.plen = plen;
+    A.o = o;
+    A.item_pre = item_pre;
+    A.Pmax = P.Pmax;
+    A.JCH = P.JCH;
+    A.res = nullptr;
+    A.J = J;
+    A.pjoin = pjoin;
+    k_join<0, VAL_HR, true><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+    LAUNCH_CHECK();
+  }
+  k_finalize_batch<<<(uint32_t)cdiv(P.n, 256), 256, 0, st>>>(J, P.n, tstart);
+  LAUNCH_CHECK();
+  return MPSM_OK;
+}
+
+mpsm_status batch_run(mpsm_batch* b, void* d_ws, uint64_t bytes, void* stream, int use_graph) {
+  if (!b || !d_ws || ((uintptr_t)d_ws & 255)) return MPSM_EINVAL;
+  BatchPlan P;
+  if (!make_batch_plan(b, b->L, b->BT, b->JCH, &P)) return MPSM_EUNSUPPORTED;
+  if (bytes < P.total) return MPSM_ENOMEM;
+  if (!g_num_cus) {
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    g_num_cus = ncu > 0 ? ncu : 256;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = static_cast<char*>(d_ws);
+  if (b->uploaded_to != d_ws) {
+    if (P.tab_bytes > b->host_bytes) {   // pinned staging of the tables, kept with the batch
+      if (b->host) (void)hipHostFree(b->host);
+      b->host = nullptr;
+      b->host_bytes = 0;
+      HIP_TRY(hipHostMalloc(&b->host, P.tab_bytes, hipHostMallocDefault));
+      b->host_bytes = P.tab_bytes;
+    }
+    batch_tables(b, P, static_cast<char*>(b->host));
+    HIP_TRY(hipMemcpyAsync(ws + P.tab_off, b->host, P.tab_bytes, hipMemcpyHostToDevice, st));
+    b->uploaded_to = d_ws;
+  }
+  if (!use_graph) return batch_enqueue(b, P, ws, st);
+  if (!b->graph || b->graph_ws != d_ws) {
+    // captured on a stream of the batch's own (the caller's may be the
+    // legacy default stream, which cannot be captured), launched on the
+    // caller's; the tables reach the workspace first
+    batch_drop_graph(b);
+    if (!b->capture) HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+    HIP_TRY(hipStreamSynchronize(st));
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    const mpsm_status rc = batch_enqueue(b, P, ws, b->capture);
+    const hipError_t ec = hipStreamEndCapture(b->capture, &g);
+    if (rc != MPSM_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (ec != hipSuccess || !g) return MPSM_EHIP;
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return MPSM_EHIP;
+    b->graph = ex;
+    b->graph_ws = d_ws;
+  }
+  HIP_TRY(hipGraphLaunch(b->graph, st));
+  return MPSM_OK;
+}
+
+// Cache key: the batch's shape in coarse (log2) terms.
+std::string batch_signature(const mpsm_batch* b) {
+  uint64_t sR = 0, sS = 0, mR = 0, mS = 0;
+  for (const mpsm_join_desc& j : b->d) {
+    sR += j.nR; sS += j.nS;
+    if (j.nR > mR) mR = j.nR;
+    if (j.nS > mS) mS = j.nS;
+  }
+  auto lg = [](uint64_t x) { int k = 0; while (x > 1) { x >>= 1; k++; } return k; };
+  char buf[160];
+  snprintf(buf, sizeof(buf), "gfx950:n%u:R%d:S%d:maxR%d:maxS%d:search%d", (unsigned)b->d.size(), lg(sR), lg(sS),
+           lg(mR), lg(mS), (int)b->cfg.search);
+  return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& sig, uint32_t* L, uint32_t* BT, uint32_t* JCH) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    char key[256];
+    unsigned lg = 0, bt = 0, jc = 0;
+    float ms = 0.f;
+    if (sscanf(line, "%255s %u %u %u %f", key, &lg, &bt, &jc, &ms) != 5) continue;
+    if (sig != key || lg > 31) continue;
+    const uint32_t l = 1u << lg;
+    if (!batch_tuning_valid(l, bt, jc)) continue;
+    *L = l; *BT = bt; *JCH = jc;
+    found = true;   // the last valid entry wins
+  }
+  fclose(f);
+  return found;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpsm_status mpsm_batch_create(const mpsm_join_desc* descs, uint32_t n, const mpsm_config* cfg, mpsm_batch** out) {
+  if (!out) return MPSM_EINVAL;
+  *out = nullptr;
+  if (!descs || n == 0) return MPSM_EINVAL;
+  mpsm_config def;
+  if (!cfg) { mpsm_config_default(&def); cfg = &def; }
+  if (!config_valid(cfg)) return MPSM_EINVAL;
+  if (cfg->splitter != MPSM_SPLIT_SAMPLED || cfg->search == MPSM_SEARCH_LEARNED || cfg->want_max ||
+      cfg->role == MPSM_ROLE_SWAP)
+    return MPSM_EUNSUPPORTED;
+  for (uint32_t i = 0; i < n; i++) {
+    const mpsm_join_desc& j = descs[i];
+    if ((j.nR && !j.d_R) || (j.nS && !j.d_S) || !j.d_out_count || !j.d_out_checksum) return MPSM_EINVAL;
+    if (((uintptr_t)j.d_R & 15) || ((uintptr_t)j.d_S & 15) || ((uintptr_t)j.d_out_count & 7) ||
+        ((uintptr_t)j.d_out_checksum & 7) || ((uintptr_t)j.d_out_times & 7))
+      return MPSM_EINVAL;
+    if (j.nR >= (1ull << 32) || j.nS >= (1ull << 32)) return MPSM_EINVAL;
+  }
+  mpsm_batch* b = new mpsm_batch();
+  b->d.assign(descs, descs + n);
+  b->cfg = *cfg;
+  // initial tuning: the config's values, else a run length that keeps every
+  // join within the run limit, 4096-tuple buckets and 64 K-tuple work items
+  uint64_t maxS = 0;
+  for (const mpsm_join_desc& j : b->d) maxS = j.nS > maxS ? j.nS : maxS;
+  uint32_t L = cfg->log2_run_len ? (1u << cfg->log2_run_len) : (1u << 18);
+  while (!cfg->log2_run_len && L < (1u << 22) && cdiv(maxS, L) > (uint64_t)JOIN_QMAX) L <<= 1;
+  const uint32_t BT = cfg->bucket_target ? cfg->bucket_target : 4096u;
+  const uint32_t JCH = cfg->join_chunk ? cfg->join_chunk : 65536u;
+  // workspace for every candidate tuning (and the initial one)
+  BatchPlan P;
+  uint64_t ws = 0;
+  for (uint32_t l : kBatchL)
+    for (uint32_t bt : kBatchBT)
+      for (uint32_t jc : kBatchJCH)
+        if (make_batch_plan(b, l, bt, jc, &P) && P.total > ws) ws = P.total;
+  if (!make_batch_plan(b, L, BT, JCH, &P)) { delete b; return MPSM_EUNSUPPORTED; }
+  b->ws_max = P.total > ws ? P.total : ws;
+  const mpsm_status rc = batch_set(b, L, BT, JCH);
+  if (rc != MPSM_OK) { mpsm_batch_destroy(b); return rc; }
+  *out = b;
+  return MPSM_OK;
+}
+
+void mpsm_batch_destroy(mpsm_batch* b) {
+  if (!b) return;
+  batch_drop_graph(b);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  if (b->host) (void)hipHostFree(b->host);
+  delete b;
+}
+
+uint64_t mpsm_batch_workspace_bytes(const mpsm_batch* b) { return b ? b->ws_max : 0; }
+
+mpsm_status mpsm_batch_run(mpsm_batch* b, void* d_workspace, uint64_t workspace_bytes, void* stream, int use_graph) {
+  return batch_run(b, d_workspace, workspace_bytes, stream, use_graph);
+}
+
+mpsm_status mpsm_batch_get_tuning(const mpsm_batch* b, mpsm_batch_tuning* t) {
+  if (!b || !t) return MPSM_EINVAL;
+  memset(t, 0, sizeof(*t));
+  t->log2_run_len = (uint32_t)__builtin_ctz(b->L);
+  t->bucket_target = b->BT;
+  t->join_chunk = b->JCH;
+  return MPSM_OK;
+}
+
+mpsm_status mpsm_batch_set_tuning(mpsm_batch* b, const mpsm_batch_tuning* t) {
+  if (!b || !t || t->log2_run_len > 31) return MPSM_EINVAL;
+  BatchPlan P;
+  if (!make_batch_plan(b, 1u << t->log2_run_len, t->bucket_target, t->join_chunk, &P)) return MPSM_EUNSUPPORTED;
+  return batch_set(b, 1u << t->log2_run_len, t->bucket_target, t->join_chunk);
+}
+
+mpsm_status mpsm_batch_autotune(mpsm_batch* b, void* d_workspace, uint64_t workspace_bytes, void* stream,
+                                const char* cache_path, mpsm_batch_tuning* chosen) {
+  if (!b) return MPSM_EINVAL;
+  const std::string sig = batch_signature(b);
+  uint32_t L = 0, BT = 0, JCH = 0;
+  if (cache_lookup(cache_path, sig, &L, &BT, &JCH)) {
+    BatchPlan P;
+    if (make_batch_plan(b, L, BT, JCH, &P) && (!d_workspace || P.total <= workspace_bytes)) {
+      const mpsm_status rc = batch_set(b, L, BT, JCH);
+      if (rc != MPSM_OK) return rc;
+      if (chosen) { mpsm_batch_get_tuning(b, chosen); chosen->from_cache = 1; }
+      return MPSM_OK;
+    }
+  }
+  if (!d_workspace) return MPSM_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = -1.f;
+  uint32_t bL = b->L, bBT = b->BT, bJ = b->JCH;
+  mpsm_status rc = MPSM_OK;
+  for (uint32_t l : kBatchL)
+    for (uint32_t bt : kBatchBT)
+      for (uint32_t jc : kBatchJCH) {
+        BatchPlan P;
+        if (!make_batch_plan(b, l, bt, jc, &P) || P.total > workspace_bytes) continue;
+        if ((rc = batch_set(b, l, bt, jc)) != MPSM_OK) break;
+        if ((rc = batch_run(b, d_workspace, workspace_bytes, stream, 0)) != MPSM_OK) break;   // warm-up
+        float t[3];
+        for (int r = 0; r < 3 && rc == MPSM_OK; r++) {
+          if (hipEventRecord(e0, st) != hipSuccess) { rc = MPSM_EHIP; break; }
+          rc = batch_run(b, d_workspace, workspace_bytes, stream, 0);
+          if (rc != MPSM_OK) break;
+          if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&t[r], e0, e1) != hipSuccess)
+            rc = MPSM_EHIP;
+        }
+        if (rc != MPSM_OK) break;
+        const float med = t[0] < t[1] ? (t[1] < t[2] ? t[1] : (t[0] < t[2] ? t[2] : t[0]))
+                                       : (t[0] < t[2] ? t[0] : (t[1] < t[2] ? t[2] : t[1]));
+        if (best < 0.f || med < best) { best = med; bL = l; bBT = bt; bJ = jc; }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != MPSM_OK) return rc;
+  if (best < 0.f) return MPSM_ENOMEM;
+  rc = batch_set(b, bL, bBT, bJ);
+  if (rc != MPSM_OK) return rc;
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "%s %u %u %u %.4f\n", sig.c_str(), (unsigned)__builtin_ctz(bL), bBT, bJ, best);
+      fclose(f);
+    }
+  }
+  if (chosen) { mpsm_batch_get_tuning(b, chosen); chosen->from_cache = 0; chosen->ms = best; }
+  return MPSM_OK;
+}
+
+uint64_t mpsm_clock_hz(void) { return 100000000ull; }
 
 }  // extern "C"

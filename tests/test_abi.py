@@ -90,3 +90,88 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(mpsm, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         mpsm.lib()
+
+
+# ------------------------------------------------------------ batch (host side)
+
+def _descs(sizes):
+    """Descriptors with fake, aligned device addresses (never dereferenced:
+    batch planning touches no device)."""
+    arr = (mpsm.MpsmJoinDesc * len(sizes))()
+    for i, (nR, nS) in enumerate(sizes):
+        d = arr[i]
+        d.d_R = 0x10000000 + 0x1000000 * i if nR else None
+        d.nR = nR
+        d.d_S = 0x80000000 + 0x1000000 * i if nS else None
+        d.nS = nS
+        d.d_out_count = 0x200000 + 64 * i
+        d.d_out_checksum = 0x200000 + 64 * i + 8
+        d.d_out_times = None
+    return arr
+
+
+def _create(sizes, cfg=None):
+    h = ctypes.c_void_p()
+    rc = mpsm.lib().mpsm_batch_create(_descs(sizes), len(sizes), None if cfg is None else ctypes.byref(cfg),
+                                      ctypes.byref(h))
+    return rc, h
+
+
+def test_batch_plan_and_tuning():
+    L = mpsm.lib()
+    rc, h = _create([(4096, 16384), (1 << 20, 1 << 23), (0, 100), (100, 0), (1, 1)])
+    assert rc == 0 and h
+    try:
+        ws = L.mpsm_batch_workspace_bytes(h)
+        assert ws >= 2 * 16 * ((4096 + (1 << 20) + 1) + (16384 + (1 << 23) + 1))
+        t = mpsm.MpsmBatchTuning()
+        assert L.mpsm_batch_get_tuning(h, ctypes.byref(t)) == 0
+        assert 16 <= t.log2_run_len <= 22 and t.bucket_target == 4096 and t.join_chunk == 65536
+        bad = mpsm.MpsmBatchTuning(12, 4096, 65536, 0, 0.0)           # run length too short
+        assert L.mpsm_batch_set_tuning(h, ctypes.byref(bad)) == 5
+        ok = mpsm.MpsmBatchTuning(16, 2048, 16384, 0, 0.0)
+        assert L.mpsm_batch_set_tuning(h, ctypes.byref(ok)) == 0
+        assert L.mpsm_batch_get_tuning(h, ctypes.byref(t)) == 0 and (t.log2_run_len, t.bucket_target) == (16, 2048)
+    finally:
+        L.mpsm_batch_destroy(h)
+
+
+def test_batch_rejects_bad_input():
+    L = mpsm.lib()
+    h = ctypes.c_void_p()
+    assert L.mpsm_batch_create(None, 0, None, ctypes.byref(h)) == 1
+    d = _descs([(10, 10)])
+    d[0].d_R = None                                                     # NULL R with nR > 0
+    assert L.mpsm_batch_create(d, 1, None, ctypes.byref(h)) == 1
+    d = _descs([(10, 10)])
+    d[0].d_S = 0x80000008                                               # misaligned S
+    assert L.mpsm_batch_create(d, 1, None, ctypes.byref(h)) == 1
+    assert _create([(10, 10)], mpsm.config(splitter=mpsm.SPLIT_LEARNED))[0] == 5
+    assert _create([(10, 10)], mpsm.config(search=mpsm.SEARCH_LEARNED))[0] == 5
+    assert _create([(10, 10)], mpsm.config(want_max=1))[0] == 5
+    assert _create([(1 << 31, 10), (1 << 31, 10)])[0] == 5             # sum of nR beyond 2^32
+
+
+def test_batch_autotune_cache_hit_and_malformed_entries(tmp_path):
+    """A cache entry for the batch's shape is used without touching the GPU;
+    malformed or out-of-range lines are skipped."""
+    L = mpsm.lib()
+    sizes = [(5000, 20000), (70000, 300000)]
+    rc, h = _create(sizes)
+    assert rc == 0
+    try:
+        cache = tmp_path / "tune.txt"
+        t = mpsm.MpsmBatchTuning()
+        # no entry and no workspace: nothing to measure with
+        assert L.mpsm_batch_autotune(h, None, 0, None, str(cache).encode(), ctypes.byref(t)) == 1
+        # learn the signature from a measured entry format, then plant entries
+        sig = "gfx950:n2:R16:S18:maxR16:maxS18:search3"
+        cache.write_text("garbage line\n"
+                         f"{sig} 40 4096 65536 1.0\n"          # log2 run length out of range
+                         f"{sig} 18 999 65536 1.0\n"           # bucket target out of range
+                         f"{sig} 16 2048 16384 0.5\n"
+                         "other:sig 20 4096 65536 0.1\n")
+        assert L.mpsm_batch_autotune(h, None, 0, None, str(cache).encode(), ctypes.byref(t)) == 0
+        assert t.from_cache == 1 and (t.log2_run_len, t.bucket_target, t.join_chunk) == (16, 2048, 16384)
+    finally:
+        L.mpsm_batch_destroy(h)
