@@ -185,12 +185,80 @@ def run_variant(mpsm, torch, R, S, out, cfg, args, names, nR, nS, label):
             "stats": variant_stats(mpsm, torch, R, S, cfg, dev)}
 
 
+def batch_bench(args):
+    """The 256-join batch: one graph-captured launch sequence per step, the
+    autotuned tuning, per-join latency percentiles from the GPU wall clock,
+    and the same joins run one mpsm_join call at a time for comparison."""
+    import numpy as np
+    import torch
+    import paper_1207_0145_amd as mpsm
+    import workloads
+    log("generating batch (256 joins)")
+    ws = workloads.make("batch")
+    joins = [(torch.from_numpy(w.R.view(np.int64)).cuda(), torch.from_numpy(w.S.view(np.int64)).cuda()) for w in ws]
+    nR = sum(len(w.R) for w in ws)
+    nS = sum(len(w.S) for w in ws)
+    del ws
+    b = mpsm.Batch(joins)
+    cache = os.path.join(ROOT, "gpurun_out", "batch_autotune.txt") if args.autotune_cache is None else args.autotune_cache
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    tun = b.autotune(cache)
+    log(f"tuning {tun}")
+    for _ in range(args.warmup):
+        b.run(use_graph=True)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        b.run(use_graph=True)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    tm = b.times.cpu().numpy().view(np.uint64).astype(np.float64) / mpsm.clock_hz() * 1e6   # us
+    total_us = tm[:, 2] - tm[:, 0]
+    work_us = tm[:, 2] - tm[:, 1]
+    res = b.results()
+    # the same joins, one call each, on one stream
+    out = torch.zeros(2, dtype=torch.int64, device="cuda")
+    wsz = max(mpsm.workspace_bytes(R.shape[0], S.shape[0]) for R, S in joins)
+    wbuf = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    for R, S in joins[:8]:
+        mpsm.join_into(R, S, out, wbuf)
+    torch.cuda.synchronize()
+    t0.record()
+    for R, S in joins:
+        mpsm.join_into(R, S, out, wbuf)
+    t1.record()
+    torch.cuda.synchronize()
+    seq_ms = t0.elapsed_time(t1)
+    path_bytes = 48 * nS + 64 * nR
+    line = {
+        "metric": METRIC, "value": round((nR + nS) / (ms * 1e-3) / 1e6, 2), "unit": "M tuples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"batch: 256 joins, |R_b| log-uniform in [2^12, 2^22], |S_b| = k_b |R_b| (k_b in 1..8), "
+                               f"half uniform, half Zipf(0.5..1.2) foreign keys; sum |R| = {nR}, sum |S| = {nS}",
+                   "launch": "one hipGraph replay per step", "tuning": tun},
+        "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_bytes / (ms * 1e-3) / 1e9, 1),
+                          "unit": "GB/s", "frac": round(path_bytes / (ms * 1e-3) / 8e12, 4)},
+        "per_join_us": {"done_since_batch_start": {"p50": round(float(np.percentile(total_us, 50)), 1),
+                                                   "p99": round(float(np.percentile(total_us, 99)), 1)},
+                        "done_since_first_item": {"p50": round(float(np.percentile(work_us, 50)), 1),
+                                                  "p99": round(float(np.percentile(work_us, 99)), 1)}},
+        "one_call_per_join": {"ms": round(seq_ms, 3), "value": round((nR + nS) / (seq_ms * 1e-3) / 1e6, 2)},
+        "result": {"pairs": int(sum(c for c, _ in res))},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fk_uniform", choices=["fk_uniform", "fk_small", "skewed"])
+    ap.add_argument("--workload", default="fk_uniform", choices=["fk_uniform", "fk_small", "skewed", "batch"])
+    ap.add_argument("--autotune-cache", default=None, help="batch workload: autotuner cache file")
     ap.add_argument("--cpu-sample-shift", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-CDF variant")
@@ -215,6 +283,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "batch":
+        batch_bench(args)
+        return
     import numpy as np
     import torch
     import paper_1207_0145_amd as mpsm
