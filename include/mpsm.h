@@ -62,9 +62,13 @@ enum { MPSM_ROLE_AUTO = 0, MPSM_ROLE_AS_GIVEN = 1, MPSM_ROLE_SWAP = 2 };
 /* Splitters of the range partitioning of R:
  *   SAMPLED  equi-depth quantiles of a seeded sample, per segment;
  *   LEARNED  first level from the inverse of a learned CDF of R (a
- *            piecewise-linear CDF over sample quantiles plus a small residual
- *            network, trained on the GPU from 2^16 keys the call draws); the
- *            second level, when R needs one, stays sampled. */
+ *            piecewise-linear CDF over 4096 sample quantiles plus a small
+ *            residual network, trained on the GPU from 2^16 keys the call
+ *            draws); a second level, when R needs one, stays sampled (its
+ *            buckets are finer than the model's knots).
+ * The learned CDFs are built on a stream of the library's own (one per
+ * calling thread) while S is sorted, and joined before R is partitioned.
+ * S runs are always split by sampled splitters. */
 enum { MPSM_SPLIT_SAMPLED = 0, MPSM_SPLIT_LEARNED = 1 };
 /* Start search of every R partition in every S run (Section 3.2.2):
  *   BINARY   bisection of the run;  INTERP  the paper's interpolation search;

@@ -17,7 +17,6 @@
 // (Section 3.2.2) and joins each R partition, held in LDS, with its slices.
 #pragma once
 #include "block_sort.h"
-#include "learned.h"
 
 // ------------------------------------------------------------------ config
 // bucket sort instances: small tiles for S buckets, large tiles (= the join's
@@ -38,7 +37,7 @@ constexpr int SMP_IPT_S = 8;
 using SampleSorterS = BlockSort<SMP_NT_S, SMP_IPT_S, 4>;
 
 constexpr int HIST_NT = 256;
-constexpr int SCAT_NT = 512;
+constexpr int SCAT_NT = 1024;
 constexpr int SCAT_IPT = 4;
 constexpr int SCAT_CH = SCAT_NT * SCAT_IPT;  // tuples staged in LDS per chunk
 constexpr int MAX_NB = 1024;                 // buckets per segment
@@ -52,6 +51,8 @@ constexpr int JOIN_DIR = 4096;               // cells of the R-partition directo
 constexpr int SCAN_NT = 256;
 constexpr int SCAN_IPT = 16;
 constexpr int SCAN_BLOCK = SCAN_NT * SCAN_IPT;
+
+#include "learned.h"
 
 // ------------------------------------------------------------ small kernels
 
@@ -970,14 +971,8 @@ __global__ void __launch_bounds__(256) k_search(const tup_t* __restrict__ U, con
                                                 uint32_t idx_stride, uint32_t idx_per_run, const uint32_t* Pcount,
                                                 const uint64_t* pkey, uint32_t Pmax, uint32_t* o, int mode,
                                                 const CdfModel* model, Result* res) {
-  __shared__ CdfModel m;
   const bool learned = mode == SEARCH_LEARNED;
-  if (learned) {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(model);
-    uint32_t* dst = reinterpret_cast<uint32_t*>(&m);
-    for (uint32_t i = threadIdx.x; i < sizeof(CdfModel) / 4; i += blockDim.x) dst[i] = src[i];
-    __syncthreads();
-  }
+  const CdfModel& m = *model;   // read through the caches: its knots are shared by all threads
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t P = *Pcount;
   uint32_t probes = 0, fallbacks = 0;
@@ -999,11 +994,11 @@ __global__ void __launch_bounds__(256) k_search(const tup_t* __restrict__ U, con
         const uint32_t nidx = (n + idx_stride - 1) / idx_stride;
         uint32_t lo = 0, hi = nidx;
         if (learned && m.valid) {
-          // window: the model's error on its sample, plus the sampling error of
+          // window: the model's error on its sample near the prediction, plus the sampling error of
           // a 2^16-key sample and of this run (two standard deviations each)
           const float q = cdf_eval(m, key);
           const float sd = sqrtf(q * (1.f - q) + 1e-4f);
-          const float err = m.eps + 2.f * sd * (1.f / 256.f + rsqrtf((float)n + 1.f));
+          const float err = cdf_local_eps(m, q) + 2.f * sd * (1.f / 256.f + rsqrtf((float)n + 1.f));
           const int64_t t = (int64_t)(q * (float)nidx);
           const int64_t w = (int64_t)(err * (float)nidx) + 2;
           const uint32_t a = (uint32_t)(t - w < 0 ? 0 : (t - w > (int64_t)nidx ? (int64_t)nidx : t - w));

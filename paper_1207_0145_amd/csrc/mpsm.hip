@@ -179,8 +179,8 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->items = take(((uint64_t)P->Pmax + 2) * 4);
   P->item_pre = take(((uint64_t)P->Pmax + 2) * 4);
   P->item_cnt = take((P->item_cap + 1) * 4);
-  P->cdf_chunks = take((uint64_t)CDF_M * 8);
-  P->cdf_sorted = take((uint64_t)CDF_M * 8);
+  P->cdf_chunks = take(2ull * CDF_M * 8);
+  P->cdf_sorted = take(2ull * CDF_M * 8);
   P->modelR = take(sizeof(CdfModel));
   P->modelS = take(sizeof(CdfModel));
   P->res = take(sizeof(Result));
@@ -256,7 +256,7 @@ struct Level {
   uint64_t *blo, *bhi;
   const uint64_t* outer;     // splitters of the previous level (NULL at the first level)
   uint32_t outer_nspl;
-  const CdfModel* model;     // learned splitters from this model (one segment only), or NULL
+  const CdfModel* model;     // learned splitters from this model, or NULL
   const uint32_t* Gcount() const { return seg.b0 + nseg; }
 };
 
@@ -287,7 +287,7 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
   k_seg_plan<<<1, 1024, 0, st>>>(L.nseg, L.NBmax, L.BT, HIST_TILE, sg.len, sg.tile0, sg.cnt0, sg.nb, sg.b0);
   LAUNCH_CHECK();
   if (L.NBmax > 1 && L.model) {
-    k_learned_splitters<<<1, 256, 0, st>>>(L.model, L.NBmax, L.spl);
+    k_learned_splitters<<<L.nseg, 256, 0, st>>>(L.model, L.NBmax, sg.nb, L.outer, L.outer_nspl, L.spl);
     LAUNCH_CHECK();
   } else if (L.NBmax > 1) {
     if (L.NBmax * L.OS <= (uint32_t)(SMP_NT_S * SMP_IPT_S))
@@ -321,16 +321,36 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
   return MPSM_OK;
 }
 
-// Sample CDF_M keys of a relation, sort them, fit the learned CDF.
-mpsm_status train_cdf(const tup_t* src, uint32_t n, uint64_t seed, uint64_t* chunks, uint64_t* sorted,
-                      CdfModel* model, hipStream_t st) {
-  k_cdf_sample<<<CDF_M / 256, 256, 0, st>>>(src, n, seed, chunks);
+// A stream of the calling thread's own for the learned-CDF kernels, so that
+// the models are built while phase 1 runs, and the events that order it
+// against the caller's stream (created once per thread, default priority).
+struct SideStream {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, done = nullptr;
+};
+thread_local SideStream t_side;
+
+mpsm_status side_stream(SideStream** out) {
+  SideStream& s = t_side;
+  if (!s.st) {
+    HIP_TRY(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&s.fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+  }
+  *out = &s;
+  return MPSM_OK;
+}
+
+// Sample CDF_M keys of each relation of the job, sort them, fit the learned
+// CDFs (nmodel = 1 or 2 models built side by side).
+mpsm_status train_cdf(const CdfJob& job, uint32_t nmodel, uint64_t* chunks, uint64_t* sorted, hipStream_t st) {
+  k_cdf_sample<<<dim3(CDF_M / 256, nmodel), 256, 0, st>>>(job, chunks);
   LAUNCH_CHECK();
-  k_cdf_sort_chunks<<<CDF_M / CDF_CHUNK, 1024, 0, st>>>(chunks);
+  k_cdf_sort_chunks<<<dim3(CDF_M / CDF_CHUNK, nmodel), 1024, 0, st>>>(chunks);
   LAUNCH_CHECK();
-  k_cdf_merge<<<CDF_M / 256, 256, 0, st>>>(chunks, sorted);
+  k_cdf_merge<<<dim3(CDF_M / 256, nmodel), 256, 0, st>>>(chunks, sorted);
   LAUNCH_CHECK();
-  k_cdf_train<<<1, 1024, 0, st>>>(sorted, n, model);
+  k_cdf_train<<<dim3(1, nmodel), 1024, 0, st>>>(sorted, job);
   LAUNCH_CHECK();
   return MPSM_OK;
 }
@@ -462,17 +482,25 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
   mk.mark(MK_INIT);
   CdfModel* modelR = reinterpret_cast<CdfModel*>(ws + P.modelR);
   CdfModel* modelS = reinterpret_cast<CdfModel*>(ws + P.modelS);
+  // learned splitters use R's model, the learned search S's; both are built
+  // on a side stream while phase 1 runs and joined before R's partitioning
   const bool learn_r = P.splitter == MPSM_SPLIT_LEARNED && P.nR && P.nS;
   const bool learn_s = P.search == MPSM_SEARCH_LEARNED && P.nR && P.nS;
-  if (learn_r) {
-    mpsm_status rc = train_cdf(Rin, (uint32_t)P.nR, P.seed ^ TAG_CR, reinterpret_cast<uint64_t*>(ws + P.cdf_chunks),
-                               reinterpret_cast<uint64_t*>(ws + P.cdf_sorted), modelR, st);
+  SideStream* side = nullptr;
+  if (learn_r || learn_s) {
+    mpsm_status rs = side_stream(&side);
+    if (rs != MPSM_OK) return rs;
+    HIP_TRY(hipEventRecord(side->fork, st));
+    HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0));
+    CdfJob job;
+    memset(&job, 0, sizeof(job));
+    uint32_t nm = 0;
+    if (learn_r) { job.src[nm] = Rin; job.n[nm] = (uint32_t)P.nR; job.seed[nm] = P.seed ^ TAG_CR; job.model[nm] = modelR; nm++; }
+    if (learn_s) { job.src[nm] = Sin; job.n[nm] = (uint32_t)P.nS; job.seed[nm] = P.seed ^ TAG_CS; job.model[nm] = modelS; nm++; }
+    mpsm_status rc = train_cdf(job, nm, reinterpret_cast<uint64_t*>(ws + P.cdf_chunks),
+                               reinterpret_cast<uint64_t*>(ws + P.cdf_sorted), side->st);
     if (rc != MPSM_OK) return rc;
-  }
-  if (learn_s) {
-    mpsm_status rc = train_cdf(Sin, (uint32_t)P.nS, P.seed ^ TAG_CS, reinterpret_cast<uint64_t*>(ws + P.cdf_chunks),
-                               reinterpret_cast<uint64_t*>(ws + P.cdf_sorted), modelS, st);
-    if (rc != MPSM_OK) return rc;
+    HIP_TRY(hipEventRecord(side->done, side->st));
   }
   mk.mark(MK_CDF);
   if (P.nR == 0 || P.nS == 0) {
@@ -518,6 +546,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     Level LR1 = make_level(ws, P.segR1, 1, P.NB1, 0, P.OS1, P.tilesR1, P.seed ^ TAG_R1, P.splR1, P.cR1, P.cntR1,
                            P.bstR1, P.bndR1, P.NB1);
     if (learn_r) LR1.model = modelR;
+    if (side) HIP_TRY(hipStreamWaitEvent(st, side->done, 0));   // the models are needed from here on
     k_seg_uniform<<<1, 64, 0, st>>>((uint32_t)P.nR, (uint32_t)P.nR, 1, LR1.seg.start, LR1.seg.len);
     LAUNCH_CHECK();
     rc = bucket_pass(Rin, R1, (uint32_t)P.nR, LR1, bsum, st, mk, MK_R1_SPL);
@@ -542,6 +571,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
                        P.bstR2, P.bndR2, P.Gr);
       LR2.outer = LR1.spl;
       LR2.outer_nspl = P.NB1 - 1;
+      // the second level stays sampled: its buckets are finer than the model's knots
       k_seg_from_buckets<<<(uint32_t)cdiv(P.NB1, 256), 256, 0, st>>>(LR1.bstart, P.NB1, LR2.seg.start,
                                                                      LR2.seg.len);
       LAUNCH_CHECK();
@@ -652,13 +682,11 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     stats->search_probes = r.search_probes;
     stats->search_fallbacks = r.fallbacks;
     stats->max_partition = r.spare;
-    CdfModel mdl_r, mdl_s;
-    memset(&mdl_r, 0, sizeof(mdl_r));
-    memset(&mdl_s, 0, sizeof(mdl_s));
-    if (learn_r) HIP_TRY(hipMemcpy(&mdl_r, modelR, sizeof(mdl_r), hipMemcpyDeviceToHost));
-    if (learn_s) HIP_TRY(hipMemcpy(&mdl_s, modelS, sizeof(mdl_s), hipMemcpyDeviceToHost));
-    stats->cdf_eps_r = learn_r ? mdl_r.eps : -1.0;
-    stats->cdf_eps_s = learn_s ? mdl_s.eps : -1.0;
+    float eps_r = -1.f, eps_s = -1.f;
+    if (learn_r) HIP_TRY(hipMemcpy(&eps_r, &modelR->eps, sizeof(float), hipMemcpyDeviceToHost));
+    if (learn_s) HIP_TRY(hipMemcpy(&eps_s, &modelS->eps, sizeof(float), hipMemcpyDeviceToHost));
+    stats->cdf_eps_r = eps_r;
+    stats->cdf_eps_s = eps_s;
     stats->swapped = (uint64_t)P.swapped;
     stats->ms_total = ms;
     if (d_pairs && r.count > pairs_capacity) return MPSM_ECAPACITY;

@@ -382,3 +382,59 @@ def test_fk_uniform_full_size_sampled():
 
 def _ws_view_range(ws, off, a, b):
     return ws[off + 16 * a: off + 16 * b].cpu().numpy().view(np.uint64).reshape(-1, 2)
+
+
+# ------------------------------------- large configurations (opt-in: MPSM_LARGE=1)
+
+large = pytest.mark.skipif(not __import__("os").environ.get("MPSM_LARGE"),
+                           reason="large configuration: set MPSM_LARGE=1 (minutes of host time)")
+
+
+@large
+def test_lognormal_eighth_scale_against_oracle():
+    """|R| = 2^25 log-normal keys with duplicates, |S| = 2^27 (1..16 copies
+    per key): count and checksum against the CPU oracle."""
+    w = workloads.make("lognormal", scale_shift=3)
+    _say("lognormal 1/8: generated")
+    got = gpu_join(w.R, w.S)
+    assert got["count"] == w.expected_count
+    _say("lognormal 1/8: GPU count matches the generator; running the oracle")
+    want = oracle.join(w.R, w.S)
+    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+
+
+@large
+def test_lognormal_full_size():
+    """|R| = 2^28, |S| = 2^30: the count from the generator (exact by
+    construction), the same checksum from every start-search mode and from
+    the learned form, and sampled runs and start offsets against the oracle."""
+    w = workloads.make("lognormal")
+    nR, nS = len(w.R), len(w.S)
+    _say(f"lognormal full: generated |R|={nR} |S|={nS}, expected pairs {w.expected_count}")
+    R, S = _dev(w.R), _dev(w.S)
+    cfg = mpsm.config()
+    lay = mpsm.layout(nR, nS, cfg)
+    ws = mpsm.alloc_workspace(nR, nS, cfg)
+    got = mpsm.join(R, S, cfg, workspace=ws)
+    assert got["count"] == w.expected_count
+    torch.cuda.synchronize()
+    Q, L = lay["runs"], lay["run_len"]
+    rng = np.random.default_rng(3)
+    P = int(_ws_view(ws, lay["off_partitions"], 1, np.uint32)[0])
+    pkey = _ws_view(ws, lay["off_part_key"], P, np.uint64)
+    o = _ws_view(ws, lay["off_offsets"], (P + 1) * Q, np.uint32).reshape(P + 1, Q)
+    for j in sorted(set([0, Q - 1] + rng.integers(0, Q, 2).tolist())):
+        a, b = j * L, min((j + 1) * L, nS)
+        x = _ws_view_range(ws, lay["off_s_sorted"], a, b)
+        ref = oracle.sort_by_key(w.S[a:b])
+        assert np.array_equal(x[:, 0], ref[:, 0])
+        assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], ref[np.lexsort((ref[:, 1], ref[:, 0]))])
+        ps = rng.integers(0, P, 64)
+        assert np.array_equal(o[ps, j], np.searchsorted(ref[:, 0], pkey[ps], side="left"))
+        _say(f"lognormal full: run {j} checked")
+    del ws
+    torch.cuda.empty_cache()
+    for kw in (dict(search=mpsm.SEARCH_BINARY), dict(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED)):
+        other = mpsm.join(R, S, mpsm.config(**kw))
+        assert (other["count"], other["checksum"]) == (got["count"], got["checksum"]), kw
+        _say(f"lognormal full: {kw} agrees")
