@@ -470,7 +470,7 @@ __device__ __forceinline__ uint32_t cs_group_rank(const uint64_t* sk, uint32_t g
   return r;
 }
 
-template <int NT, int IPT, int M, int MINB>
+template <int NT, int IPT, int M, int MINB, bool STAGE>
 __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
                                                        const uint32_t* bstart, const uint64_t* blo,
                                                        const uint64_t* bhi, const uint32_t* Gcount,
@@ -482,11 +482,23 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
   constexpr int PER = M / NT;
   static_assert(M % NT == 0, "sub-buckets per thread");
   static_assert(CAP < (1 << 16), "positions fit 16 bits");
-  __shared__ uint64_t sk[CAP];               // keys grouped by (sub-)group
-  __shared__ uint32_t cnt[M + 1];            // first-level counters, then group starts
-  __shared__ uint32_t cnt2[CAP + 1];         // second-level counters, indexed by bucket position
-  __shared__ uint16_t slot1[M];              // slot of a large first-level group
-  __shared__ uint16_t slot2[CAP];            // slot of a large second-level cell, by its first position
+  // One LDS area holds the working arrays while ranks are computed and
+  // then (STAGE), once every rank is known, the whole bucket in sorted order,
+  // so the output leaves in fully coalesced stores; without STAGE every tuple
+  // is stored straight from registers to its rank (fewer live registers).
+  constexpr uint32_t OFF_CNT2 = CAP * 8;
+  constexpr uint32_t OFF_SLOT2 = OFF_CNT2 + ((CAP + 1) * 4 + 15) / 16 * 16;
+  constexpr uint32_t OFF_CNT = OFF_SLOT2 + CAP * 2;
+  constexpr uint32_t OFF_SLOT1 = OFF_CNT + ((M + 1) * 4 + 15) / 16 * 16;
+  constexpr uint32_t WORK_BYTES = OFF_SLOT1 + M * 2;
+  constexpr uint32_t AREA = WORK_BYTES > CAP * 16 ? WORK_BYTES : CAP * 16;
+  __shared__ __align__(16) unsigned char area[AREA];
+  uint64_t* const sk = reinterpret_cast<uint64_t*>(area);                 // keys grouped by (sub-)group
+  uint32_t* const cnt2 = reinterpret_cast<uint32_t*>(area + OFF_CNT2);    // second-level counters, by position
+  uint16_t* const slot2 = reinterpret_cast<uint16_t*>(area + OFF_SLOT2);  // slot of a large cell, by its first position
+  uint32_t* const cnt = reinterpret_cast<uint32_t*>(area + OFF_CNT);      // first-level counters, then group starts
+  uint16_t* const slot1 = reinterpret_cast<uint16_t*>(area + OFF_SLOT1);  // slot of a large first-level group
+  tup_t* const stage = reinterpret_cast<tup_t*>(area);                    // the sorted bucket
   __shared__ uint64_t smin[CS_SLOTS], smax[CS_SLOTS], sC[CS_SLOTS];
   __shared__ uint32_t sgs[CS_SLOTS];
   __shared__ uint64_t spiv[CS_SLOTS];
@@ -750,12 +762,33 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
       if (tid == 0) redo_list[atomicAdd(redo_count, 1ull)] = g;
       continue;
     }
+    if (STAGE) {
+      // every rank is known and the working arrays are free: stage, then copy
 #pragma unroll
-    for (int k = 0; k < IPT; k++) {
-      if (k * NT + tid < n) {
-        tup_t v; v.key = key[k]; v.pay = val[k];
-        store_tup(dst + a + fin[k], v);
-        emit_sorted(so, g, a, fin[k], key[k]);
+      for (int k = 0; k < IPT; k++) {
+        if (k * NT + tid < n) {
+          tup_t v; v.key = key[k]; v.pay = val[k];
+          stage[fin[k]] = v;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < IPT; k++) {
+        const uint32_t i = k * NT + tid;
+        if (i < n) {
+          const tup_t v = stage[i];
+          store_tup(dst + a + i, v);
+          emit_sorted(so, g, a, i, v.key);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < IPT; k++) {
+        if (k * NT + tid < n) {
+          tup_t v; v.key = key[k]; v.pay = val[k];
+          store_tup(dst + a + fin[k], v);
+          emit_sorted(so, g, a, fin[k], key[k]);
+        }
       }
     }
   }

@@ -528,10 +528,10 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
     uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
     uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
-    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
                                                                  nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
     LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
                                                                       midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
                                                                       soS);
     LAUNCH_CHECK();
@@ -583,7 +583,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     } else {
       mk.mark_range(MK_R2_SPL, MK_R2_SCAT);
     }
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1><<<LRf->Gmax, BL_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true><<<LRf->Gmax, BL_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
                                                                       LRf->Gcount(), nullptr, nullptr, bigR, ctr + 1,
                                                                       redoR, ctr + 4, soR);
     LAUNCH_CHECK();
@@ -953,10 +953,10 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
     uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
     uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
-    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
                                                                  nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
     LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
                                                                       midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
                                                                       soS);
     LAUNCH_CHECK();
@@ -980,7 +980,7 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     soR.bkey = reinterpret_cast<uint64_t*>(ws + P.bkey);
     uint32_t* redoR = reinterpret_cast<uint32_t*>(ws + P.redoR);
     uint32_t* bigR = reinterpret_cast<uint32_t*>(ws + P.bigR);
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1><<<P.Gr, BL_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(),
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true><<<P.Gr, BL_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(),
                                                                  nullptr, nullptr, bigR, ctr + 1, redoR, ctr + 4, soR);
     LAUNCH_CHECK();
     k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(Rp, Rs, LR.bstart, redoR, ctr + 4, bigR, ctr + 1, soR);
