@@ -95,21 +95,28 @@ __global__ void __launch_bounds__(256) k_search_batch(const tup_t* __restrict__ 
 }
 
 // Work items of every partition (as k_join_items) and their count per join.
-__global__ void k_join_items_batch(const uint32_t* Pcount, const uint32_t* pjoin, BatchJoin* J, const uint32_t* o,
-                                   uint32_t Pmax, uint32_t JCH, uint32_t* items) {
+// Join units and work items of every partition (as k_join_items; a unit
+// never spans two joins) and the item count per join.
+__global__ void k_join_items_batch(const uint32_t* Pcount, const uint32_t* plen, const uint32_t* pjoin,
+                                   BatchJoin* J, const uint32_t* o, uint32_t Pmax, uint32_t JCH, uint8_t* span,
+                                   uint32_t* items) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > Pmax + 1) return;
   const uint32_t P = *Pcount;
   uint32_t it = 0;
   if (p < P) {
     const uint32_t jb = pjoin[p];
-    const uint32_t Q = J[jb].Q;
-    const uint32_t* a = o + J[jb].obase + (uint64_t)(p - J[jb].p0) * Q;
-    const uint32_t* b = a + Q;
-    uint64_t np = 0;
-    for (uint32_t q = 0; q < Q; q++) np += b[q] - a[q];
-    it = (uint32_t)((np + JCH - 1) / JCH);
-    if (it) atomicAdd(&J[jb].items, it);
+    const uint32_t sp = join_span(plen, P, p, [&](uint32_t q) { return pjoin[q] == pjoin[q + 1]; });
+    span[p] = (uint8_t)sp;
+    if (sp) {
+      const uint32_t Q = J[jb].Q;
+      const uint32_t* a = o + J[jb].obase + (uint64_t)(p - J[jb].p0) * Q;
+      const uint32_t* b = a + (uint64_t)sp * Q;
+      uint64_t np = 0;
+      for (uint32_t q = 0; q < Q; q++) np += b[q] - a[q];
+      it = (uint32_t)((np + JCH - 1) / JCH);
+      if (it) atomicAdd(&J[jb].items, it);
+    }
   }
   items[p] = it;
 }

@@ -1066,20 +1066,36 @@ __global__ void __launch_bounds__(256) k_search(const tup_t* __restrict__ U, con
 
 // ------------------------------------------------------------------- join
 
-// Work items: partition p contributes ceil(n_p / JCH) items, n_p = S tuples
+// Join units: partitions 2i and 2i+1 are joined as one unit when together
+// they fit the LDS tile (they are adjacent in key order and in the sorted
+// R, and their slices of every run are adjacent too), which halves the
+// per-item setup of the join for small partitions.  span[p] = partitions in
+// the unit starting at p (2 or 1), 0 for the second partition of a unit.
+// same(p) says whether partitions p and p + 1 may share a unit.
+template <typename F>
+__device__ __forceinline__ uint32_t join_span(const uint32_t* plen, uint32_t P, uint32_t p, F same) {
+  if (p & 1) return (plen[p - 1] + plen[p] <= (uint32_t)JOIN_CAP && same(p - 1)) ? 0u : 1u;
+  return (p + 1 < P && plen[p] + plen[p + 1] <= (uint32_t)JOIN_CAP && same(p)) ? 2u : 1u;
+}
+
+// Work items: join unit u contributes ceil(n_u / JCH) items, n_u = S tuples
 // in its slices (0 when nothing can match).  items has Pmax + 2 entries.
-__global__ void k_join_items(const uint32_t* Pcount, const uint32_t* o, uint32_t Q, uint32_t Pmax, uint32_t JCH,
-                             uint32_t* items) {
+__global__ void k_join_items(const uint32_t* Pcount, const uint32_t* plen, const uint32_t* o, uint32_t Q,
+                             uint32_t Pmax, uint32_t JCH, uint8_t* span, uint32_t* items) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > Pmax + 1) return;
   const uint32_t P = *Pcount;
   uint32_t it = 0;
   if (p < P) {
-    uint64_t np = 0;
-    const uint32_t* a = o + (uint64_t)p * Q;
-    const uint32_t* b = a + Q;
-    for (uint32_t j = 0; j < Q; j++) np += b[j] - a[j];
-    it = (uint32_t)((np + JCH - 1) / JCH);
+    const uint32_t sp = join_span(plen, P, p, [](uint32_t) { return true; });
+    span[p] = (uint8_t)sp;
+    if (sp) {
+      uint64_t np = 0;
+      const uint32_t* a = o + (uint64_t)p * Q;
+      const uint32_t* b = a + (uint64_t)sp * Q;
+      for (uint32_t j = 0; j < Q; j++) np += b[j] - a[j];
+      it = (uint32_t)((np + JCH - 1) / JCH);
+    }
   }
   items[p] = it;
 }
@@ -1107,6 +1123,7 @@ struct JoinArgs {
   // batch: per-join table and the join of every partition
   BatchJoin* J;
   const uint32_t* pjoin;
+  const uint8_t* span;      // partitions per join unit (see join_span)
 };
 
 __device__ __forceinline__ uint32_t item_partition(const uint32_t* item_pre, uint32_t np2, uint32_t item) {
@@ -1152,8 +1169,9 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
   for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
     const uint32_t p = item_partition(A.item_pre, np2, item);
     const uint32_t k = item - A.item_pre[p];
-    const uint32_t rs = A.pstart[p], rn = A.plen[p];
-    // the partition's rows of start offsets and its runs (in a batch: those of its join)
+    const uint32_t pe = p + A.span[p];   // the item's join unit: partitions [p, pe)
+    const uint32_t rs = A.pstart[p], rn = A.pstart[pe - 1] + A.plen[pe - 1] - rs;
+    // the unit's rows of start offsets and its runs (in a batch: those of its join)
     uint32_t Q = A.Q, r0 = 0, jb = 0;
     const uint32_t* oa = A.o + (uint64_t)p * Q;
     if (BATCH) {
@@ -1163,7 +1181,7 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
       oa = A.o + A.J[jb].obase + (uint64_t)(p - A.J[jb].p0) * Q;
       if (tid == 0) atomicMin(&A.J[jb].t_first, (unsigned long long)wall_clock64());
     }
-    const uint32_t* ob = oa + Q;
+    const uint32_t* ob = oa + (uint64_t)(pe - p) * Q;
     __syncthreads();   // LDS of the previous item is free
     // prefix of slice lengths over the runs; sbase[j] + x = S position of
     // concatenated index x when x falls in run j
@@ -1197,7 +1215,8 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
       const uint32_t nxt = item + gridDim.x;
       if (nxt < total) {
         const uint32_t p2 = item_partition(A.item_pre, np2, nxt);
-        const uint32_t rs2 = A.pstart[p2], rn2 = A.plen[p2];
+        const uint32_t pe2 = p2 + A.span[p2];
+        const uint32_t rs2 = A.pstart[p2], rn2 = A.pstart[pe2 - 1] + A.plen[pe2 - 1] - rs2;
         if (rn2 <= (uint32_t)JOIN_CAP) {
 #pragma unroll
           for (int r = 0; r < JPF; r++) {

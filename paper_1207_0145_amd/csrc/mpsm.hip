@@ -52,7 +52,7 @@ struct Plan {
   uint64_t bndS, bndR1, bndR2;             // per-bucket key bounds (lo array, then hi array)
   uint64_t bigS, midS, redoS, redoR, bigR, ctr;
   uint64_t bkey, Pc, pstart, plen, pkey;
-  uint64_t ridx, o, items, item_pre, item_cnt, res;
+  uint64_t ridx, o, items, item_pre, item_cnt, res, span;
   uint64_t cdf_chunks, cdf_sorted, modelR, modelS;  // learned CDF samples and models
   uint64_t total;
 };
@@ -179,6 +179,7 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->items = take(((uint64_t)P->Pmax + 2) * 4);
   P->item_pre = take(((uint64_t)P->Pmax + 2) * 4);
   P->item_cnt = take((P->item_cap + 1) * 4);
+  P->span = take((uint64_t)P->Pmax + 2);
   P->cdf_chunks = take(2ull * CDF_M * 8);
   P->cdf_sorted = take(2ull * CDF_M * 8);
   P->modelR = take(sizeof(CdfModel));
@@ -616,7 +617,8 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     mk.mark(MK_SEARCH);
     uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
     uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
-    k_join_items<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, o, P.Q, P.Pmax, P.JCH, items);
+    uint8_t* span = reinterpret_cast<uint8_t*>(ws + P.span);
+    k_join_items<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, plen, o, P.Q, P.Pmax, P.JCH, span, items);
     LAUNCH_CHECK();
     rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
     if (rc != MPSM_OK) return rc;
@@ -637,6 +639,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     A.res = res;
     A.J = nullptr;
     A.pjoin = nullptr;
+    A.span = span;
     A.pairs = reinterpret_cast<uint64_t*>(d_pairs);
     A.pairs_cap = d_pairs ? pairs_capacity : 0;
     A.item_cnt = reinterpret_cast<uint32_t*>(ws + P.item_cnt);
@@ -771,7 +774,7 @@ struct BatchPlan {
   // workspace offsets
   uint64_t T, U, Rp, Rs, cS, cR, bsum, segS, segR, srcS, srcR, splS, splR, bstS, bstR, bndS, bndR;
   uint64_t bigS, midS, redoS, redoR, bigR, ctr, bkey, Pc, pstart, plen, pkey, pjoin, ridx, o, items, item_pre;
-  uint64_t J, tstart, ototal;
+  uint64_t J, tstart, ototal, span;
   uint64_t tab_off, tab_bytes;           // host-written tables: one contiguous range
   uint64_t total;
 };
@@ -867,6 +870,7 @@ bool make_batch_plan(const mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH,
   P->item_pre = take(((uint64_t)P->Pmax + 2) * 4);
   P->tstart = take(8);
   P->ototal = take(8);
+  P->span = take((uint64_t)P->Pmax + 2);
   P->total = off;
   return true;
 }
@@ -1008,7 +1012,9 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     }
     uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
     uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
-    k_join_items_batch<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, pjoin, J, o, P.Pmax, P.JCH, items);
+    uint8_t* span = reinterpret_cast<uint8_t*>(ws + P.span);
+    k_join_items_batch<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, plen, pjoin, J, o, P.Pmax, P.JCH, span,
+                                                                       items);
     LAUNCH_CHECK();
     rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
     if (rc != MPSM_OK) return rc;
@@ -1028,6 +1034,7 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     A.res = nullptr;
     A.J = J;
     A.pjoin = pjoin;
+    A.span = span;
     k_join<0, VAL_HR, true><<<g_num_cus, JOIN_NT, 0, st>>>(A);
     LAUNCH_CHECK();
   }
