@@ -173,12 +173,15 @@ typedef struct mpsm_layout {
   uint64_t off_part_start;   /* P u32 */
   uint64_t off_part_len;     /* P u32 */
   uint64_t off_part_key;     /* P u64: first key of each partition */
-  uint64_t off_offsets;      /* (P_max+1) x runs u32: start of partition p in run j */
+  uint64_t off_offsets;      /* (P_max+1) x runs u32: start of partition p in run j; written for the
+                                partitions that start a join unit (span > 0) and for row P */
   uint32_t p_max;            /* capacity of the partition arrays */
   uint32_t idx_stride;       /* equi-height index: every idx_stride-th key of a run */
   uint64_t off_run_index;    /* runs * idx_per_run u64 */
   uint32_t idx_per_run;
   uint32_t reserved;
+  uint64_t off_join_span;    /* P u8: partitions joined together starting at p (2: p and p+1 share an LDS
+                                tile; 1: p alone; 0: p is the second of a pair) */
 } mpsm_layout;
 
 mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* cfg, mpsm_layout* out);

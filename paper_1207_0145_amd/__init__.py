@@ -58,7 +58,8 @@ class MpsmLayout(ctypes.Structure):
                 ("off_part_start", ctypes.c_uint64), ("off_part_len", ctypes.c_uint64),
                 ("off_part_key", ctypes.c_uint64), ("off_offsets", ctypes.c_uint64), ("p_max", ctypes.c_uint32),
                 ("idx_stride", ctypes.c_uint32), ("off_run_index", ctypes.c_uint64),
-                ("idx_per_run", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("idx_per_run", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("off_join_span", ctypes.c_uint64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -79,13 +79,15 @@ __global__ void __launch_bounds__(256) k_search_batch(const tup_t* __restrict__ 
                                                       const uint32_t* run_len, const uint64_t* run_idx,
                                                       uint32_t idx_stride, uint32_t idx_per_run, const BatchJoin* J,
                                                       uint32_t n, const uint64_t* pkey, uint32_t* o,
-                                                      const unsigned long long* o_total, int mode) {
+                                                      const unsigned long long* o_total, int mode,
+                                                      const uint8_t* span) {
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= *o_total) return;
   const uint32_t jb = batch_join_of(n, gid, [&](uint32_t i) { return (uint64_t)J[i].obase; });
   const BatchJoin& j = J[jb];
   const uint64_t local = gid - j.obase;
   const uint32_t row = (uint32_t)(local / j.Q), q = (uint32_t)(local % j.Q);
+  if (row < j.P && !span[j.p0 + row]) return;   // inside a join unit: never read
   const uint32_t run = j.r0 + q;
   const uint32_t len = run_len[run];
   uint32_t probes = 0;
@@ -95,19 +97,25 @@ __global__ void __launch_bounds__(256) k_search_batch(const tup_t* __restrict__ 
 }
 
 // Work items of every partition (as k_join_items) and their count per join.
-// Join units and work items of every partition (as k_join_items; a unit
-// never spans two joins) and the item count per join.
-__global__ void k_join_items_batch(const uint32_t* Pcount, const uint32_t* plen, const uint32_t* pjoin,
-                                   BatchJoin* J, const uint32_t* o, uint32_t Pmax, uint32_t JCH, uint8_t* span,
-                                   uint32_t* items) {
+// Join units of every partition (as k_join_units; a unit never spans two joins).
+__global__ void k_join_units_batch(const uint32_t* Pcount, const uint32_t* plen, const uint32_t* pjoin,
+                                   uint32_t Pmax, uint8_t* span) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t P = *Pcount;
+  if (p < P && p < Pmax)
+    span[p] = (uint8_t)join_span(plen, P, p, [&](uint32_t q) { return pjoin[q] == pjoin[q + 1]; });
+}
+
+// Work items of every join unit (as k_join_items) and the item count per join.
+__global__ void k_join_items_batch(const uint32_t* Pcount, const uint32_t* pjoin, BatchJoin* J, const uint32_t* o,
+                                   uint32_t Pmax, uint32_t JCH, const uint8_t* span, uint32_t* items) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > Pmax + 1) return;
   const uint32_t P = *Pcount;
   uint32_t it = 0;
   if (p < P) {
     const uint32_t jb = pjoin[p];
-    const uint32_t sp = join_span(plen, P, p, [&](uint32_t q) { return pjoin[q] == pjoin[q + 1]; });
-    span[p] = (uint8_t)sp;
+    const uint32_t sp = span[p];
     if (sp) {
       const uint32_t Q = J[jb].Q;
       const uint32_t* a = o + J[jb].obase + (uint64_t)(p - J[jb].p0) * Q;

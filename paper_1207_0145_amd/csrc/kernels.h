@@ -38,7 +38,7 @@ using SampleSorterS = BlockSort<SMP_NT_S, SMP_IPT_S, 4>;
 
 constexpr int HIST_NT = 256;
 constexpr int SCAT_NT = 1024;
-constexpr int SCAT_IPT = 4;
+constexpr int SCAT_IPT = 8;
 constexpr int SCAT_CH = SCAT_NT * SCAT_IPT;  // tuples staged in LDS per chunk
 constexpr int MAX_NB = 1024;                 // buckets per segment
 constexpr int SPLIT_DIR = 2048;              // cells of the splitter directory
@@ -296,7 +296,6 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   __shared__ uint64_t sp[MAX_NB];
   __shared__ uint32_t cursor[MAX_NB], lcnt[MAX_NB], lofs[MAX_NB];
   __shared__ tup_t stage[SCAT_CH];
-  __shared__ uint16_t sid[SCAT_CH];
   __shared__ uint32_t wsum[SCAT_NT / 64 + 2];
   __shared__ SplitDir<SPLIT_DIR> dir;
   const uint32_t g = blockIdx.x, tid = threadIdx.x;
@@ -361,14 +360,16 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
       if (i < b) {
         const uint32_t q = lofs[bk[k]] + lr[k];
         stage[q] = v[k];
-        sid[q] = (uint16_t)bk[k];
       }
     }
     __syncthreads();
     const uint32_t m = min((uint32_t)SCAT_CH, b - c0);
     for (uint32_t q = tid; q < m; q += SCAT_NT) {
-      const uint32_t bb = sid[q];
-      store_tup(dst + cursor[bb] + (q - lofs[bb]), stage[q]);
+      // the bucket is looked up again rather than staged: LDS holds 8 K
+      // tuples per chunk, so that every bucket gets a run of several tuples
+      const tup_t tq = stage[q];
+      const uint32_t bb = dir.bucket(sp, nspl, tq.key);
+      store_tup(dst + cursor[bb] + (q - lofs[bb]), tq);
     }
     __syncthreads();
     for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] += lcnt[i]; lcnt[i] = 0; }
@@ -1003,13 +1004,14 @@ __global__ void __launch_bounds__(256) k_search(const tup_t* __restrict__ U, con
                                                 const uint32_t* run_len, uint32_t Q, const uint64_t* run_idx,
                                                 uint32_t idx_stride, uint32_t idx_per_run, const uint32_t* Pcount,
                                                 const uint64_t* pkey, uint32_t Pmax, uint32_t* o, int mode,
-                                                const CdfModel* model, Result* res) {
+                                                const CdfModel* model, Result* res, const uint8_t* span) {
   const bool learned = mode == SEARCH_LEARNED;
   const CdfModel& m = *model;   // read through the caches: its knots are shared by all threads
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t P = *Pcount;
   uint32_t probes = 0, fallbacks = 0;
-  if (gid < (uint64_t)(P + 1) * Q) {
+  // rows of partitions that do not start a join unit are never read
+  if (gid < (uint64_t)(P + 1) * Q && (gid / Q == P || span[gid / Q])) {
     const uint32_t p = (uint32_t)(gid / Q), j = (uint32_t)(gid % Q);
     const uint32_t n = run_len[j];
     const tup_t* run = U + run_start[j];
@@ -1078,17 +1080,24 @@ __device__ __forceinline__ uint32_t join_span(const uint32_t* plen, uint32_t P, 
   return (p + 1 < P && plen[p] + plen[p + 1] <= (uint32_t)JOIN_CAP && same(p)) ? 2u : 1u;
 }
 
+// The join units of all partitions (before the start search, which only
+// needs the rows of partitions that start a unit).
+__global__ void k_join_units(const uint32_t* Pcount, const uint32_t* plen, uint32_t Pmax, uint8_t* span) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t P = *Pcount;
+  if (p < P && p < Pmax) span[p] = (uint8_t)join_span(plen, P, p, [](uint32_t) { return true; });
+}
+
 // Work items: join unit u contributes ceil(n_u / JCH) items, n_u = S tuples
 // in its slices (0 when nothing can match).  items has Pmax + 2 entries.
-__global__ void k_join_items(const uint32_t* Pcount, const uint32_t* plen, const uint32_t* o, uint32_t Q,
-                             uint32_t Pmax, uint32_t JCH, uint8_t* span, uint32_t* items) {
+__global__ void k_join_items(const uint32_t* Pcount, const uint32_t* o, uint32_t Q, uint32_t Pmax, uint32_t JCH,
+                             const uint8_t* span, uint32_t* items) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > Pmax + 1) return;
   const uint32_t P = *Pcount;
   uint32_t it = 0;
   if (p < P) {
-    const uint32_t sp = join_span(plen, P, p, [](uint32_t) { return true; });
-    span[p] = (uint8_t)sp;
+    const uint32_t sp = span[p];
     if (sp) {
       uint64_t np = 0;
       const uint32_t* a = o + (uint64_t)p * Q;

@@ -430,6 +430,7 @@ mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* c
   out->idx_stride = IDX_STRIDE;
   out->off_run_index = P.ridx;
   out->idx_per_run = P.idx_per_run;
+  out->off_join_span = P.span;
   return MPSM_OK;
 }
 
@@ -601,6 +602,9 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     k_partitions<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), Pc, pstart, plen, pkey,
                                      stats ? res : nullptr);
     LAUNCH_CHECK();
+    uint8_t* span = reinterpret_cast<uint8_t*>(ws + P.span);
+    k_join_units<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, st>>>(Pc, plen, P.Pmax, span);
+    LAUNCH_CHECK();
     mk.mark(MK_PART);
 
     // ---- phase 4: merge starts of every partition in every run, then the join
@@ -612,13 +616,12 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
                                                           learn_s ? MPSM_SEARCH_LEARNED
                                                                   : (P.search == MPSM_SEARCH_LEARNED ? MPSM_SEARCH_INDEX
                                                                                                      : P.search),
-                                                          modelS, stats ? res : nullptr);
+                                                          modelS, stats ? res : nullptr, span);
     LAUNCH_CHECK();
     mk.mark(MK_SEARCH);
     uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
     uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
-    uint8_t* span = reinterpret_cast<uint8_t*>(ws + P.span);
-    k_join_items<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, plen, o, P.Q, P.Pmax, P.JCH, span, items);
+    k_join_items<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, o, P.Q, P.Pmax, P.JCH, span, items);
     LAUNCH_CHECK();
     rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
     if (rc != MPSM_OK) return rc;
@@ -1000,6 +1003,9 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     LAUNCH_CHECK();
     k_batch_blocks<<<1, 64, 0, st>>>(J, P.n, ototal);
     LAUNCH_CHECK();
+    uint8_t* span = reinterpret_cast<uint8_t*>(ws + P.span);
+    k_join_units_batch<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, st>>>(Pc, plen, pjoin, P.Pmax, span);
+    LAUNCH_CHECK();
     // phase 4
     uint32_t* o = reinterpret_cast<uint32_t*>(ws + P.o);
     const int mode = b->cfg.search == MPSM_SEARCH_BINARY ? SEARCH_BINARY
@@ -1007,14 +1013,13 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     if (P.ocap) {
       k_search_batch<<<(uint32_t)cdiv(P.ocap, 256), 256, 0, st>>>(U, LS.seg.start, LS.seg.len,
                                                                  reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
-                                                                 soS.idx_per_run, J, P.n, pkey, o, ototal, mode);
+                                                                 soS.idx_per_run, J, P.n, pkey, o, ototal, mode,
+                                                                 span);
       LAUNCH_CHECK();
     }
     uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
     uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
-    uint8_t* span = reinterpret_cast<uint8_t*>(ws + P.span);
-    k_join_items_batch<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, plen, pjoin, J, o, P.Pmax, P.JCH, span,
-                                                                       items);
+    k_join_items_batch<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, pjoin, J, o, P.Pmax, P.JCH, span, items);
     LAUNCH_CHECK();
     rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
     if (rc != MPSM_OK) return rc;

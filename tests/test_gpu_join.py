@@ -333,12 +333,19 @@ def test_intermediate_results(nR, nS, bt):
     assert pstart[0] == 0 and np.all(pstart[1:] == pstart[:-1] + plen[:-1]) and pstart[-1] + plen[-1] == nR
     assert np.array_equal(pkey, Rsorted[pstart, 0])
     assert np.all(Rsorted[pstart[1:] - 1, 0] < pkey[1:])          # key-disjoint partitions
-    # phase 4: start offsets are lower bounds of the first key of every partition
+    # join units: pairs (2i, 2i+1) that fit one LDS tile together, else singles
+    span = _ws_view(ws, lay["off_join_span"], P, np.uint8).astype(np.int64)
+    for p in range(P):
+        pair = p % 2 == 0 and p + 1 < P and plen[p] + plen[p + 1] <= 8192
+        second = p % 2 == 1 and plen[p - 1] + plen[p] <= 8192
+        assert span[p] == (2 if pair else (0 if second else 1)), p
+    heads = np.nonzero(span > 0)[0]
+    # phase 4: start offsets are lower bounds of the first key of every unit's first partition
     o = _ws_view(ws, lay["off_offsets"], (P + 1) * Q, np.uint32).reshape(P + 1, Q)
     for j in range(Q):
         a, b = j * L, min((j + 1) * L, nS)
-        ref = np.searchsorted(ref_runs[a:b, 0], pkey, side="left")
-        assert np.array_equal(o[:P, j], ref)
+        ref = np.searchsorted(ref_runs[a:b, 0], pkey[heads], side="left")
+        assert np.array_equal(o[heads, j], ref)
         assert o[P, j] == b - a
     # equi-height index: every idx_stride-th key of each run
     st, ipr = lay["idx_stride"], lay["idx_per_run"]
@@ -375,7 +382,8 @@ def test_fk_uniform_full_size_sampled():
         assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], ref[np.lexsort((ref[:, 1], ref[:, 0]))])
         P = int(_ws_view(ws, lay["off_partitions"], 1, np.uint32)[0])
         pkey = _ws_view(ws, lay["off_part_key"], P, np.uint64)
-        ps = rng.integers(0, P, 64)
+        heads = np.nonzero(_ws_view(ws, lay["off_join_span"], P, np.uint8))[0]
+        ps = heads[rng.integers(0, len(heads), 64)]
         o = _ws_view(ws, lay["off_offsets"], (P + 1) * Q, np.uint32).reshape(P + 1, Q)
         assert np.array_equal(o[ps, j], np.searchsorted(ref[:, 0], pkey[ps], side="left"))
 
@@ -422,6 +430,7 @@ def test_lognormal_full_size():
     rng = np.random.default_rng(3)
     P = int(_ws_view(ws, lay["off_partitions"], 1, np.uint32)[0])
     pkey = _ws_view(ws, lay["off_part_key"], P, np.uint64)
+    heads = np.nonzero(_ws_view(ws, lay["off_join_span"], P, np.uint8))[0]
     o = _ws_view(ws, lay["off_offsets"], (P + 1) * Q, np.uint32).reshape(P + 1, Q)
     for j in sorted(set([0, Q - 1] + rng.integers(0, Q, 2).tolist())):
         a, b = j * L, min((j + 1) * L, nS)
@@ -429,7 +438,7 @@ def test_lognormal_full_size():
         ref = oracle.sort_by_key(w.S[a:b])
         assert np.array_equal(x[:, 0], ref[:, 0])
         assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], ref[np.lexsort((ref[:, 1], ref[:, 0]))])
-        ps = rng.integers(0, P, 64)
+        ps = heads[rng.integers(0, len(heads), 64)]
         assert np.array_equal(o[ps, j], np.searchsorted(ref[:, 0], pkey[ps], side="left"))
         _say(f"lognormal full: run {j} checked")
     del ws
