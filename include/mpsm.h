@@ -68,8 +68,14 @@ enum { MPSM_ROLE_AUTO = 0, MPSM_ROLE_AS_GIVEN = 1, MPSM_ROLE_SWAP = 2 };
  *            buckets are finer than the model's knots).
  * The learned CDFs are built on a stream of the library's own (one per
  * calling thread) while S is sorted, and joined before R is partitioned.
- * S runs are always split by sampled splitters. */
-enum { MPSM_SPLIT_SAMPLED = 0, MPSM_SPLIT_LEARNED = 1 };
+ * S runs are always split by sampled splitters.
+ *   COST     first level balanced by the paper's cost model (Section 4.3):
+ *            the largest partition cost |R_i| log2 |R_i| + Q |R_i| + |S_i|
+ *            (Q = S runs; |S_i| from the S runs' equi-height bounds merged
+ *            into a global S distribution, Section 4.1; |R_i| from a sorted
+ *            R sample) is minimised over contiguous groups of sample cells.
+ *            A second level, when R needs one, stays sampled. */
+enum { MPSM_SPLIT_SAMPLED = 0, MPSM_SPLIT_LEARNED = 1, MPSM_SPLIT_COST = 2 };
 /* Start search of every R partition in every S run (Section 3.2.2):
  *   BINARY   bisection of the run;  INTERP  the paper's interpolation search;
  *   INDEX    bisection of the run's equi-height index, then of one window;
@@ -182,6 +188,12 @@ typedef struct mpsm_layout {
   uint32_t reserved;
   uint64_t off_join_span;    /* P u8: partitions joined together starting at p (2: p and p+1 share an LDS
                                 tile; 1: p alone; 0: p is the second of a pair) */
+  /* splitter COST only: */
+  uint64_t off_cost_sample;  /* cost_cells u64: the sorted R sample (cell i starts at its key i) */
+  uint64_t off_cost_s_below; /* cost_cells+1 u64: estimated S tuples below each sample key; last = |S| */
+  uint64_t off_cost_best;    /* f64: the largest group cost of the chosen split */
+  uint32_t cost_cells;
+  uint32_t reserved2;
 } mpsm_layout;
 
 mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* cfg, mpsm_layout* out);

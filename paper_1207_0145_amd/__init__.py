@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpsm.so")
 
 ROLE_AUTO, ROLE_AS_GIVEN, ROLE_SWAP = 0, 1, 2
-SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
+SPLIT_SAMPLED, SPLIT_LEARNED, SPLIT_COST = 0, 1, 2
 SEARCH_BINARY, SEARCH_INTERP, SEARCH_LEARNED, SEARCH_INDEX = 0, 1, 2, 3
 STATUS = {0: "MPSM_OK", 1: "MPSM_EINVAL", 2: "MPSM_ECAPACITY", 3: "MPSM_ENOMEM", 4: "MPSM_EHIP",
           5: "MPSM_EUNSUPPORTED"}
@@ -59,7 +59,9 @@ class MpsmLayout(ctypes.Structure):
                 ("off_part_key", ctypes.c_uint64), ("off_offsets", ctypes.c_uint64), ("p_max", ctypes.c_uint32),
                 ("idx_stride", ctypes.c_uint32), ("off_run_index", ctypes.c_uint64),
                 ("idx_per_run", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("off_join_span", ctypes.c_uint64)]
+                ("off_join_span", ctypes.c_uint64), ("off_cost_sample", ctypes.c_uint64),
+                ("off_cost_s_below", ctypes.c_uint64), ("off_cost_best", ctypes.c_uint64),
+                ("cost_cells", ctypes.c_uint32), ("reserved2", ctypes.c_uint32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

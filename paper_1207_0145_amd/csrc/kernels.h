@@ -203,7 +203,8 @@ template <int NT, int IPT>
 __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict__ src, const uint32_t* seg_start,
                                                          const uint32_t* seg_len, const uint32_t* seg_nb,
                                                          uint32_t NBmax, uint32_t OS, uint64_t level_seed,
-                                                         uint64_t* spl, const tup_t* const* seg_src) {
+                                                         uint64_t* spl, const tup_t* const* seg_src,
+                                                         uint64_t* full) {
   using Sorter = BlockSort<NT, IPT, 4>;
   __shared__ uint64_t buf[Sorter::BUF_WORDS];
   __shared__ uint32_t wsum[Sorter::WSUM_WORDS];
@@ -232,6 +233,123 @@ __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict
   for (int k = 0; k < IPT; k++) {
     const uint32_t r = k * NT + tid;
     if (r > 0 && r < M && r % OS == 0) out[r / OS - 1] = key[k];
+    if (full && r < M) full[r] = key[k];   // the whole sorted sample (one segment)
+  }
+}
+
+// ------------------------------------------------- cost-balanced splitters
+
+// The global S distribution (Section 4.1): the runs' equi-height bounds
+// (every stride-th key of each sorted run) merged by counting, for each
+// sorted sample key x of R, the S tuples below x: in run j about
+// lb * stride - stride / 2, lb = number of bounds below x.  s_below[i] for
+// sample key i; s_below[M] = all S tuples.
+__global__ void k_cost_s_cdf(const uint64_t* sample, uint32_t M, const uint64_t* run_idx, const uint32_t* run_len,
+                             uint32_t Q, uint32_t idx_per_run, uint32_t stride, uint64_t nS, uint64_t* s_below) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > M) return;
+  if (i == M) { s_below[M] = nS; return; }
+  const uint64_t x = sample[i];
+  uint64_t tot = 0;
+  for (uint32_t j = 0; j < Q; j++) {
+    const uint64_t* idx = run_idx + (uint64_t)j * idx_per_run;
+    const uint32_t n = run_len[j], nidx = (n + stride - 1) / stride;
+    uint32_t lo = 0, hi = nidx;
+    while (lo < hi) { const uint32_t m = (lo + hi) >> 1; if (idx[m] < x) lo = m + 1; else hi = m; }
+    const uint64_t est = lo ? (uint64_t)lo * stride - stride / 2 : 0;
+    tot += est < n ? est : n;
+  }
+  s_below[i] = tot;
+}
+
+// Cost of a partition of r R tuples and s S tuples (Section 4.3): sorting
+// it, r log2 r, plus joining it, T r + s (T = S runs).
+__device__ __forceinline__ double cost_of(double r, double s, double T) {
+  return (r > 1.0 ? r * log2(r) : 0.0) + T * r + s;
+}
+
+constexpr int COST_NT = 1024;
+constexpr int COST_MAX = SMP_CAP;  // sample keys (cells) held in LDS
+
+// Cells: sample key i starts cell i, which holds about RC(i+1) - RC(i) R
+// tuples, RC(i) = floor(i nR / M), and s_below[i+1] - s_below[i] S tuples
+// (cell 0 also takes the S tuples below the first sample key).  Group g of
+// consecutive cells [c_g, c_{g+1}) becomes bucket g, split at the first key
+// of cell c_{g+1}.  The groups minimise the largest group cost: the smallest
+// threshold C whose greedy partition (each group as long as its cost stays
+// <= C; optimal for contiguous min-max partitions) needs at most NB groups
+// is searched on a geometric grid of COST_NT thresholds at a time (each
+// thread checks one), twice (the second grid between the last infeasible
+// and the first feasible threshold); the result is the greedy partition of
+// the smallest feasible threshold.  Unused splitters repeat the largest key.
+__global__ void __launch_bounds__(COST_NT) k_cost_splitters(const uint64_t* sample, const uint64_t* s_below,
+                                                           uint32_t M, uint64_t nR, uint32_t NB, uint32_t T,
+                                                           uint64_t* spl, double* best_cost) {
+  __shared__ uint64_t sc[COST_MAX + 1];
+  __shared__ double lohi[2];
+  __shared__ uint32_t first_ok;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i <= M; i += COST_NT) sc[i] = i == 0 ? 0 : s_below[i];
+  __syncthreads();
+  const double dT = (double)T;
+  auto rc = [&](uint32_t i) -> double { return (double)((uint64_t)i * nR / M); };
+  auto cost = [&](uint32_t a, uint32_t b) -> double {
+    return cost_of(rc(b) - rc(a), (double)(sc[b] - sc[a]), dT);
+  };
+  // number of groups the greedy needs for threshold C (M + 1 if a cell alone exceeds it)
+  auto groups = [&](double C) -> uint32_t {
+    uint32_t a = 0, g = 0;
+    while (a < M) {
+      if (cost(a, a + 1) > C || g > NB) return M + 1;
+      uint32_t lo = a + 1, hi = M;   // largest b with cost(a, b) <= C
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (cost(a, mid) <= C) lo = mid; else hi = mid - 1;
+      }
+      a = lo;
+      g++;
+    }
+    return g;
+  };
+  if (tid == 0) {
+    double mx = 0.0;
+    for (uint32_t i = 0; i < M; i++) { const double c = cost(i, i + 1); mx = c > mx ? c : mx; }
+    lohi[0] = mx > 0.0 ? mx : 1.0;
+    lohi[1] = cost(0, M) > lohi[0] ? cost(0, M) : lohi[0];
+  }
+  __syncthreads();
+  for (int round = 0; round < 2; round++) {
+    const double lo = lohi[0], hi = lohi[1];
+    if (tid == 0) first_ok = COST_NT;
+    __syncthreads();
+    const double C = tid == COST_NT - 1 ? hi : lo * pow(hi / lo, (double)tid / (double)(COST_NT - 1));
+    if (groups(C) <= NB) atomicMin(&first_ok, tid);
+    __syncthreads();
+    const uint32_t f = first_ok;
+    const double Cf = f == COST_NT - 1 ? hi : lo * pow(hi / lo, (double)f / (double)(COST_NT - 1));
+    const double Cp = f == 0 ? lo : lo * pow(hi / lo, (double)(f - 1) / (double)(COST_NT - 1));
+    __syncthreads();
+    if (tid == 0) { lohi[0] = Cp; lohi[1] = Cf; }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double C = lohi[1];
+    uint32_t a = 0, g = 0;
+    double worst = 0.0;
+    while (a < M) {
+      uint32_t lo = a + 1, hi = M;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (cost(a, mid) <= C) lo = mid; else hi = mid - 1;
+      }
+      const double c = cost(a, lo);
+      worst = c > worst ? c : worst;
+      if (lo < M && g + 1 < NB) spl[g] = sample[lo];
+      a = lo;
+      g++;
+    }
+    for (uint32_t k = g > 0 ? g - 1 : 0; k + 1 < NB; k++) spl[k] = ~0ull;
+    if (best_cost) *best_cost = worst;
   }
 }
 

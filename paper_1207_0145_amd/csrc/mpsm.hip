@@ -54,6 +54,7 @@ struct Plan {
   uint64_t bkey, Pc, pstart, plen, pkey;
   uint64_t ridx, o, items, item_pre, item_cnt, res, span;
   uint64_t cdf_chunks, cdf_sorted, modelR, modelS;  // learned CDF samples and models
+  uint64_t cost_sample, cost_s_below, cost_best;   // cost-balanced splitters
   uint64_t total;
 };
 
@@ -64,7 +65,8 @@ struct Seg {  // device pointers of one segment table (nseg + 1 entries each)
 bool config_valid(const mpsm_config* c) {
   if (c->struct_size != sizeof(mpsm_config)) return false;
   if (c->role < 0 || c->role > 2) return false;
-  if (c->splitter != MPSM_SPLIT_SAMPLED && c->splitter != MPSM_SPLIT_LEARNED) return false;
+  if (c->splitter != MPSM_SPLIT_SAMPLED && c->splitter != MPSM_SPLIT_LEARNED && c->splitter != MPSM_SPLIT_COST)
+    return false;
   if (c->search < 0 || c->search > 3) return false;
   if (c->log2_run_len && (c->log2_run_len < 12 || c->log2_run_len > 24)) return false;
   if (c->bucket_target && (c->bucket_target < 256 || c->bucket_target > 4096)) return false;
@@ -184,6 +186,9 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->cdf_sorted = take(2ull * CDF_M * 8);
   P->modelR = take(sizeof(CdfModel));
   P->modelS = take(sizeof(CdfModel));
+  P->cost_sample = take((uint64_t)COST_MAX * 8);
+  P->cost_s_below = take(((uint64_t)COST_MAX + 1) * 8);
+  P->cost_best = take(8);
   P->res = take(sizeof(Result));
   P->total = off;
   return true;
@@ -258,6 +263,7 @@ struct Level {
   const uint64_t* outer;     // splitters of the previous level (NULL at the first level)
   uint32_t outer_nspl;
   const CdfModel* model;     // learned splitters from this model, or NULL
+  const struct CostArgs* cost;  // cost-balanced splitters (one segment), or NULL
   const uint32_t* Gcount() const { return seg.b0 + nseg; }
 };
 
@@ -277,8 +283,21 @@ Level make_level(char* ws, uint64_t seg_off, uint32_t nseg, uint32_t NBmax, uint
   L.outer = nullptr;
   L.outer_nspl = 0;
   L.model = nullptr;
+  L.cost = nullptr;
   return L;
 }
+
+// Inputs of the cost-balanced splitters: the sorted S runs' equi-height
+// bounds and room for the sorted R sample, the S counts and the result.
+struct CostArgs {
+  uint64_t* sample;
+  uint64_t* s_below;
+  double* best;
+  const uint64_t* run_idx;
+  const uint32_t* run_len;
+  uint32_t Q, idx_per_run, stride;
+  uint64_t nS, nR;
+};
 
 // One bucket pass over segments: splitters, histogram, scan, scatter, table.
 // Markers mk0 .. mk0+3 follow splitters, histogram, scan and scatter.
@@ -287,16 +306,33 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
   const Seg& sg = L.seg;
   k_seg_plan<<<1, 1024, 0, st>>>(L.nseg, L.NBmax, L.BT, HIST_TILE, sg.len, sg.tile0, sg.cnt0, sg.nb, sg.b0);
   LAUNCH_CHECK();
-  if (L.NBmax > 1 && L.model) {
+  if (L.NBmax > 1 && L.cost) {
+    // the whole sorted sample, the S distribution at its keys, the min-max split
+    const CostArgs& c = *L.cost;
+    const uint32_t M = L.NBmax * L.OS;
+    if (M <= (uint32_t)(SMP_NT_S * SMP_IPT_S))
+      k_sample_splitters<SMP_NT_S, SMP_IPT_S><<<1, SMP_NT_S, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax, L.OS,
+                                                                      L.level_seed, L.spl, seg_src, c.sample);
+    else
+      k_sample_splitters<SMP_NT, SMP_IPT><<<1, SMP_NT, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax, L.OS,
+                                                                L.level_seed, L.spl, seg_src, c.sample);
+    LAUNCH_CHECK();
+    k_cost_s_cdf<<<(uint32_t)cdiv((uint64_t)M + 1, 256), 256, 0, st>>>(c.sample, M, c.run_idx, c.run_len, c.Q,
+                                                                      c.idx_per_run, c.stride, c.nS, c.s_below);
+    LAUNCH_CHECK();
+    k_cost_splitters<<<1, COST_NT, 0, st>>>(c.sample, c.s_below, M, c.nR, L.NBmax, c.Q, L.spl, c.best);
+    LAUNCH_CHECK();
+  } else if (L.NBmax > 1 && L.model) {
     k_learned_splitters<<<L.nseg, 256, 0, st>>>(L.model, L.NBmax, sg.nb, L.outer, L.outer_nspl, L.spl);
     LAUNCH_CHECK();
   } else if (L.NBmax > 1) {
     if (L.NBmax * L.OS <= (uint32_t)(SMP_NT_S * SMP_IPT_S))
       k_sample_splitters<SMP_NT_S, SMP_IPT_S><<<L.nseg, SMP_NT_S, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax,
-                                                                           L.OS, L.level_seed, L.spl, seg_src);
+                                                                           L.OS, L.level_seed, L.spl, seg_src,
+                                                                           nullptr);
     else
       k_sample_splitters<SMP_NT, SMP_IPT><<<L.nseg, SMP_NT, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax, L.OS,
-                                                                     L.level_seed, L.spl, seg_src);
+                                                                     L.level_seed, L.spl, seg_src, nullptr);
     LAUNCH_CHECK();
   }
   mk.mark(mk0);
@@ -431,6 +467,10 @@ mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* c
   out->off_run_index = P.ridx;
   out->idx_per_run = P.idx_per_run;
   out->off_join_span = P.span;
+  out->off_cost_sample = P.cost_sample;
+  out->off_cost_s_below = P.cost_s_below;
+  out->off_cost_best = P.cost_best;
+  out->cost_cells = P.NB1 * P.OS1;
   return MPSM_OK;
 }
 
@@ -548,6 +588,20 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     Level LR1 = make_level(ws, P.segR1, 1, P.NB1, 0, P.OS1, P.tilesR1, P.seed ^ TAG_R1, P.splR1, P.cR1, P.cntR1,
                            P.bstR1, P.bndR1, P.NB1);
     if (learn_r) LR1.model = modelR;
+    CostArgs cost_args;
+    if (P.splitter == MPSM_SPLIT_COST) {
+      cost_args.sample = reinterpret_cast<uint64_t*>(ws + P.cost_sample);
+      cost_args.s_below = reinterpret_cast<uint64_t*>(ws + P.cost_s_below);
+      cost_args.best = reinterpret_cast<double*>(ws + P.cost_best);
+      cost_args.run_idx = soS.run_idx;
+      cost_args.run_len = LS.seg.len;
+      cost_args.Q = P.Q;
+      cost_args.idx_per_run = P.idx_per_run;
+      cost_args.stride = IDX_STRIDE;
+      cost_args.nS = P.nS;
+      cost_args.nR = P.nR;
+      LR1.cost = &cost_args;
+    }
     if (side) HIP_TRY(hipStreamWaitEvent(st, side->done, 0));   // the models are needed from here on
     k_seg_uniform<<<1, 64, 0, st>>>((uint32_t)P.nR, (uint32_t)P.nR, 1, LR1.seg.start, LR1.seg.len);
     LAUNCH_CHECK();

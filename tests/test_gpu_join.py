@@ -112,6 +112,7 @@ CONFIGS = [
     dict(bucket_target=1024, join_chunk=1024), dict(seed=12345), dict(want_max=1),
     dict(splitter=mpsm.SPLIT_LEARNED), dict(search=mpsm.SEARCH_LEARNED),
     dict(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED, bucket_target=1024),
+    dict(splitter=mpsm.SPLIT_COST), dict(splitter=mpsm.SPLIT_COST, bucket_target=1024, search=mpsm.SEARCH_INTERP),
 ]
 
 
@@ -447,3 +448,54 @@ def test_lognormal_full_size():
         other = mpsm.join(R, S, mpsm.config(**kw))
         assert (other["count"], other["checksum"]) == (got["count"], got["checksum"]), kw
         _say(f"lognormal full: {kw} agrees")
+
+
+def test_cost_balanced_splitters_negatively_correlated():
+    """The paper's hardest skew case (Section 4.3): 80% of R keys in the top
+    20% of the key domain, 80% of S tuples in the bottom 20%.  Exact join;
+    the GPU's S distribution at the sample keys equals the merge of the runs'
+    equi-height bounds; its split reaches the optimum of the oracle's exact
+    min-max dynamic program on the same cells (and beats equi-depth)."""
+    rng = np.random.default_rng(0x8020)
+    nR, nS, D = 1 << 15, 1 << 18, 1 << 32
+    top = rng.random(nR) < 0.8
+    rk = np.where(top, rng.integers(int(0.8 * D), D, nR), rng.integers(0, int(0.8 * D), nR)).astype(np.uint64)
+    rk = np.unique(rk)
+    rng.shuffle(rk)
+    low = rk[rk < np.uint64(int(0.2 * D))]
+    sk = np.where(rng.random(nS) < 0.8, low[rng.integers(0, len(low), nS)], rk[rng.integers(0, len(rk), nS)])
+    R = np.stack([rk, rng.integers(0, U64, len(rk), dtype=np.uint64, endpoint=True)], 1)
+    S = np.stack([sk.astype(np.uint64), rng.integers(0, U64, nS, dtype=np.uint64, endpoint=True)], 1)
+    cfg = mpsm.config(splitter=mpsm.SPLIT_COST, log2_run_len=16)
+    lay = mpsm.layout(len(R), nS, cfg)
+    assert lay["levels"] == 1
+    ws = mpsm.alloc_workspace(len(R), nS, cfg)
+    got = gpu_join(R, S, cfg, workspace=ws)
+    want = oracle.join(R, S)
+    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+    torch.cuda.synchronize()
+    M, Q, L, NB = lay["cost_cells"], lay["runs"], lay["run_len"], lay["r_buckets1"]
+    sample = _ws_view(ws, lay["off_cost_sample"], M, np.uint64)
+    s_below = _ws_view(ws, lay["off_cost_s_below"], M + 1, np.uint64).astype(np.int64)
+    best = float(_ws_view(ws, lay["off_cost_best"], 1, np.float64)[0])
+    assert np.all(np.diff(sample.astype(np.float64)) >= 0)
+    # the merged equi-height bounds: every 256th key of each sorted run
+    runs = oracle.sort_runs(S, L)
+    est = np.zeros(M, np.int64)
+    for j in range(Q):
+        a, b = j * L, min((j + 1) * L, nS)
+        lb = np.searchsorted(runs[a:b:256, 0], sample, side="left").astype(np.int64)
+        est += np.minimum(np.where(lb > 0, lb * 256 - 128, 0), b - a)
+    assert np.array_equal(s_below[:M], est) and s_below[M] == nS
+    # cells and the oracle's exact optimum
+    RC = (np.arange(M + 1, dtype=np.uint64) * np.uint64(len(R))) // np.uint64(M)
+    SC = np.concatenate([[0], s_below[1:]]).astype(np.uint64)
+    h, s = np.diff(RC), np.diff(SC)
+    opt, _ = oracle.cost_splitters_dp(h, s, P=NB, T=Q)
+    assert opt * (1 - 1e-9) <= best <= opt * 1.001, (best, opt)
+    # equi-depth over the same cells (what sampled splitters do) is no better
+    OS = M // NB
+    equi = max(oracle.split_cost(int(h[g * OS:(g + 1) * OS].sum()), Q, int(s[g * OS:(g + 1) * OS].sum()))
+               for g in range(NB))
+    assert best <= equi * (1 + 1e-9)
+    _say(f"cost split: best {best:.0f}, optimum {opt:.0f}, equi-depth {equi:.0f}")
