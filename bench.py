@@ -61,6 +61,13 @@ def measured_traffic(step: str, workload: str):
     return t.get("steps", {}).get(step, {}).get("hbm_bytes_per_launch")
 
 
+WORKLOAD_KEYS = {
+    "fk_uniform": "R keys a 64-bit bijective mix of a permutation, S uniform foreign keys",
+    "fk_small": "R keys a permutation of [0, 2^20), S uniform foreign keys",
+    "skewed": "R keys from 64 Gaussian blobs, S Zipf(1.0) foreign keys",
+    "lognormal": "R keys floor(exp(2Z) 2^28) with duplicates, S 1..16 copies of every distinct R key",
+}
+
 # launch steps -> (kernel name prefix, occurrence of that kernel inside one join)
 STEP_DISPATCH = {
     "s_histogram": ("k_bucket_hist", 0), "s_scatter": ("k_bucket_scatter", 0),
@@ -257,7 +264,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fk_uniform", choices=["fk_uniform", "fk_small", "skewed", "batch"])
+    ap.add_argument("--workload", default="fk_uniform", choices=["fk_uniform", "fk_small", "skewed", "lognormal", "batch"])
     ap.add_argument("--autotune-cache", default=None, help="batch workload: autotuner cache file")
     ap.add_argument("--cpu-sample-shift", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -270,7 +277,8 @@ def main():
     ap.add_argument("--profile-command", default="", help="command line recorded in the summary")
     args = ap.parse_args()
     if args.summarize_profiles:
-        sizes = {"fk_uniform": (1 << 26, 1 << 28), "skewed": (1 << 26, 1 << 28), "fk_small": (1 << 20, 1 << 22)}
+        sizes = {"fk_uniform": (1 << 26, 1 << 28), "skewed": (1 << 26, 1 << 28), "fk_small": (1 << 20, 1 << 22),
+                 "lognormal": (1 << 28, 1 << 30)}
         nR, nS = sizes[args.workload]
         t = summarize_profiles(*args.summarize_profiles, args.workload, nR, nS, args.profile_command)
         out = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
@@ -356,7 +364,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: |R|=2^{nR.bit_length() - 1}, |S|=2^{nS.bit_length() - 1}, "
-                               "uniform foreign keys, 16-byte tuples (u64 key, u64 payload)",
+                               f"{WORKLOAD_KEYS[args.workload]}, 16-byte tuples (u64 key, u64 payload)",
                    "nR": nR, "nS": nS, "variant": "plain (sampled splitters, " + args.search + " start search)",
                    "runs": lay["runs"], "run_len": lay["run_len"], "r_levels": lay["levels"]},
         "result": {"count": count, "checksum": f"{checksum:#018x}"},
