@@ -91,9 +91,9 @@ typedef struct mpsm_config {
   int32_t role;            /* MPSM_ROLE_*: which input is private (R) */
   int32_t splitter;        /* MPSM_SPLIT_*: how R's range partitions are chosen */
   int32_t search;          /* MPSM_SEARCH_*: how merge starts in S runs are found */
-  uint32_t log2_run_len;   /* S run length 2^k, 16 <= k <= 24 */
+  uint32_t log2_run_len;   /* S run length 2^k, 12 <= k <= 24 */
   uint32_t bucket_target;  /* mean tuples per sort bucket / R partition, 256..4096 */
-  uint32_t join_chunk;     /* S tuples per join work item, >= 1024 */
+  uint32_t join_chunk;     /* S tuples per join work item, 1024..261888 */
   uint32_t want_max;       /* 1: also compute max(R.payload + S.payload) (Section 5.1 query) */
   uint32_t oversample;     /* sample keys drawn per bucket for the splitters, 1..64 */
   uint32_t reserved;       /* must be 0 */
@@ -254,7 +254,7 @@ typedef struct mpsm_batch mpsm_batch;
 typedef struct mpsm_batch_tuning {
   uint32_t log2_run_len;   /* 16..22 */
   uint32_t bucket_target;  /* 1024..4096 */
-  uint32_t join_chunk;     /* 4096..262144 */
+  uint32_t join_chunk;     /* 4096..261888 */
   uint32_t from_cache;     /* set by mpsm_batch_autotune: 1 if read from the cache file */
   float ms;                /* set by mpsm_batch_autotune: measured batch time of the choice (0 if cached) */
 } mpsm_batch_tuning;

@@ -47,6 +47,8 @@ constexpr int JOIN_NT = 1024;
 constexpr int JOIN_CAP = 8192;               // R partition held in LDS
 constexpr int JOIN_QMAX = 2048;              // S runs
 constexpr int JOIN_DIR = 4096;               // cells of the R-partition directory
+constexpr int JOIN_RDIR = 1024;              // run directory of a work item (one entry per 256 positions)
+constexpr int JOIN_CHUNK_MAX = 256 * (JOIN_RDIR - 1);
 
 constexpr int SCAN_NT = 256;
 constexpr int SCAN_IPT = 16;
@@ -1281,6 +1283,7 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
   __shared__ uint32_t cum[JOIN_QMAX + 1];
   __shared__ uint32_t sbase[JOIN_QMAX];
   __shared__ uint16_t jdir[JOIN_DIR + 1];
+  __shared__ uint16_t rdir[JOIN_RDIR];
   __shared__ uint32_t wsum[JOIN_NT / 64 + 2];
   __shared__ uint64_t red[JOIN_NT / 64 + 1];
   __shared__ unsigned long long item_acc;
@@ -1386,6 +1389,16 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
     const uint32_t lo_item = k * A.JCH;
     const uint32_t hi_item = min(lo_item + A.JCH, cum[Q]);
     const tup_t* Rg = A.Rs + rs;
+    // run directory of the item: rdir[d] = run of position lo_item + 256 d,
+    // so that a position's run is found between two neighbouring entries
+    const uint32_t nd = (hi_item - lo_item + 255) >> 8;
+    for (uint32_t d = tid; d < nd; d += JOIN_NT) {
+      const uint32_t x = lo_item + (d << 8);
+      uint32_t a0 = 0, b0 = Q;
+      while (b0 - a0 > 1) { const uint32_t m = (a0 + b0) >> 1; if (cum[m] <= x) a0 = m; else b0 = m; }
+      rdir[d] = (uint16_t)a0;
+    }
+    __syncthreads();
     // S tuples of the item, JOIN_U per thread per batch; the next batch is
     // loaded while the current one is matched
     auto load_batch = [&](uint32_t base, tup_t (&sv)[JOIN_U]) {
@@ -1393,7 +1406,8 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
       for (int u = 0; u < JOIN_U; u++) {
         const uint32_t x = base + u * JOIN_NT + tid;
         if (x < hi_item) {
-          uint32_t a0 = 0, b0 = Q;   // run j: cum[j] <= x < cum[j+1]
+          const uint32_t d = (x - lo_item) >> 8;   // run j: cum[j] <= x < cum[j+1]
+          uint32_t a0 = rdir[d], b0 = d + 1 < nd ? rdir[d + 1] + 1u : Q;
           while (b0 - a0 > 1) { const uint32_t m = (a0 + b0) >> 1; if (cum[m] <= x) a0 = m; else b0 = m; }
           sv[u] = load_tup(A.U + sbase[a0] + x);
         }

@@ -70,7 +70,7 @@ bool config_valid(const mpsm_config* c) {
   if (c->search < 0 || c->search > 3) return false;
   if (c->log2_run_len && (c->log2_run_len < 12 || c->log2_run_len > 24)) return false;
   if (c->bucket_target && (c->bucket_target < 256 || c->bucket_target > 4096)) return false;
-  if (c->join_chunk && c->join_chunk < 1024) return false;
+  if (c->join_chunk && (c->join_chunk < 1024 || c->join_chunk > (uint32_t)JOIN_CHUNK_MAX)) return false;
   if (c->oversample > 64 || c->reserved) return false;
   return true;
 }
@@ -838,7 +838,7 @@ struct BatchPlan {
 
 bool batch_tuning_valid(uint32_t L, uint32_t BT, uint32_t JCH) {
   return L >= (1u << 16) && L <= (1u << 22) && (L & (L - 1)) == 0 && BT >= 1024 && BT <= 4096 && JCH >= 4096 &&
-         JCH <= (1u << 18);
+         JCH <= (uint32_t)JOIN_CHUNK_MAX;
 }
 
 uint32_t batch_nb(uint64_t len, uint32_t BT) {   // k_seg_plan's bucket count of one segment

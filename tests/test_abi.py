@@ -60,6 +60,8 @@ def test_unsupported_sizes():
     assert mpsm.workspace_bytes(10, 10, mpsm.config(search=7)) == 0
     assert mpsm.workspace_bytes(10, 10, mpsm.config(log2_run_len=30)) == 0
     assert mpsm.workspace_bytes(10, 10, mpsm.config(reserved=1)) == 0
+    assert mpsm.workspace_bytes(10, 10, mpsm.config(join_chunk=1 << 20)) == 0
+    assert mpsm.workspace_bytes(10, 10, mpsm.config(join_chunk=261888)) > 0
     bad = mpsm.config()
     bad.struct_size = 4
     assert mpsm.workspace_bytes(10, 10, bad) == 0
