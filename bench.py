@@ -136,6 +136,25 @@ def summarize_profiles(kt_csv, fetch_csv, write_csv, workload, nR, nS, command):
             "command": command, "steps": steps}
 
 
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
+    """Read+write bandwidth of a plain device-to-device copy (the runtime's
+    copy kernel) on this GPU: the practical ceiling next to the 8 TB/s peak."""
+    x = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del x, y
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -358,6 +377,8 @@ def main():
     path_bytes = 48 * nS + 64 * nR
     path_gbs = path_bytes / (ms * 1e-3) / 1e9
     value = (nR + nS) / (ms * 1e-3) / 1e6
+    copy_gbs = copy_bandwidth(torch, dev)
+    log(f"device copy: {copy_gbs:.0f} GB/s")
 
     res = {
         "metric": METRIC, "value": round(value, 2), "unit": "M tuples/s", "n_gpus": 1, "steps": args.steps,
@@ -372,9 +393,12 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes": step_bytes(dom),
-                     "avg_launch_ms": round(steps_ms[dom], 4)},
+                     "avg_launch_ms": round(steps_ms[dom], 4),
+                     "frac_of_measured_copy": round(achieved / copy_gbs, 4)},
         "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_gbs, 1), "unit": "GB/s",
-                          "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
+                          "frac": round(path_gbs / HBM_PEAK_GBS, 4),
+                          "frac_of_measured_copy": round(path_gbs / copy_gbs, 4)},
+        "measured_copy_GBps": round(copy_gbs, 1),
         "steps_ms": {k: round(v, 4) for k, v in steps_ms.items()},
     }
     if not args.no_learned:
