@@ -634,7 +634,12 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
     if (n == 0) continue;
     const uint64_t lo = blo[g], span = bhi[g] - lo;
     if (span == 0) {   // one key: input order is sorted order
+      // The lane index is passed through an empty asm so that the lane's
+      // addresses are formed here, per bucket: hoisted out of the bucket
+      // loop they would be spilled to scratch at every workgroup's start,
+      // and those dead scratch lines are later written back to HBM.
       uint32_t i = tid;
+      asm volatile("" : "+v"(i));
       for (; i + 3 * NT < n; i += 4 * NT) {   // four loads in flight
         tup_t t[4];
 #pragma unroll
