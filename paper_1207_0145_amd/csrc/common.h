@@ -92,6 +92,28 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, 
   return r;
 }
 
+// Workgroup-wide OR of v through one LDS word that is zero on entry and is
+// not written again until every thread has returned (the caller clears it
+// behind a later barrier).  Ends with a barrier.  Uses only threadIdx.x, so
+// no other work-item id stays live in the caller's loops.
+__device__ __forceinline__ bool block_any(bool v, uint32_t* flag) {
+  if (__any(v) && (threadIdx.x & 63) == 0) *flag = 1u;
+  __syncthreads();
+  return *flag != 0u;
+}
+
+// block_any of two values behind one barrier; returns the first, *b2 the second.
+__device__ __forceinline__ bool block_any2(bool v1, bool v2, uint32_t* f1, uint32_t* f2, bool* b2) {
+  const bool w1 = __any(v1), w2 = __any(v2);
+  if ((threadIdx.x & 63) == 0) {
+    if (w1) *f1 = 1u;
+    if (w2) *f2 = 1u;
+  }
+  __syncthreads();
+  *b2 = *f2 != 0u;
+  return *f1 != 0u;
+}
+
 template <int NT>
 __device__ __forceinline__ uint64_t block_sum64(uint64_t v, uint64_t* wsum) {
   constexpr int NW = NT / 64;
@@ -138,15 +160,17 @@ __device__ __forceinline__ uint32_t bucket_of(const uint64_t* spl, uint32_t nspl
   return b;
 }
 
-// A multiplier C with C <= M * 2^64 / (span + 1) (M a power of two, span >= M),
-// so that x -> mulhi(x, C) maps [0, span] monotonically into [0, M).  Taken
-// from a double-precision quotient scaled down by 2^-40, which keeps it
-// below the exact value (relative error of the quotient is ~2^-52); a wide
-// integer division is far slower on the GPU.
+// A multiplier C with C <= M * 2^64 / (span + 1) (span >= M), so that
+// x -> mulhi(x, C) maps [0, span] monotonically into [0, M).  Taken from a
+// single-precision reciprocal scaled down by 2^-18: the reciprocal (1 ulp)
+// and the four roundings around it stay below 3 * 2^-23 relative, so C never
+// exceeds the exact value, and its coarser resolution only moves cell
+// borders a little.  A wide integer or double division needs several times
+// the registers, which the kernels that call this do not have to spare.
 __device__ __forceinline__ uint64_t interp_scale(uint32_t M, uint64_t span) {
-  const double q = ldexp((double)M, 64) / ((double)span + 1.0);
-  const double c = q * (1.0 - 0x1p-40);
-  return c >= 18446744073709551615.0 ? ~0ull : (uint64_t)c;
+  const float r = __builtin_amdgcn_rcpf((float)span + 1.0f);
+  const float q = (float)M * r * 0x1p64f * (1.0f - 0x1p-18f);
+  return q >= 0x1p64f ? ~0ull : (uint64_t)q;
 }
 
 // Directory over sorted splitters for fast bucket_of: the span [spl[0],

@@ -553,24 +553,30 @@ __device__ __forceinline__ void emit_sorted(const SortOut& so, uint32_t g, uint3
 // through LDS).  Inside a group a tuple's rank is the number of smaller
 // keys plus the number of equal keys placed before it, so ranks form a
 // permutation.  By group size:
-//   * at most GMAX keys: ranked by comparing with every key of the group;
+//   * at most PIVMIN keys: ranked by comparing with every key of the group;
+//   * at most GMAX keys: split three ways around the key at the group's first
+//     position (a random member, so most often the group's most frequent
+//     key): its copies count themselves, and only the other keys are ranked
+//     by comparison;
 //   * all keys equal (found from the group's min and max): positions stand;
 //   * otherwise the group is sorted by a second counting pass that
 //     interpolates over the group's own [min, max] into as many cells as it
 //     has keys (keys clustered inside the bucket, duplicates of several
-//     keys).  A second-level cell of more than GMAX keys is split three ways
-//     around a pivot key taken from the cell: the copies of the pivot take
-//     the middle, the at most SIDE other keys are ranked by comparison.
+//     keys).  Second-level cells are ranked like first-level groups, and a
+//     cell of more than GMAX keys is split three ways around a pivot key
+//     taken from the cell: the copies of the pivot take the middle, the at
+//     most SIDE other keys are ranked by comparison.
 // A bucket that still has an unresolved cell, or more large groups than
 // there are slots, goes to redo_list for the LSD radix sort
 // (k_bucket_sort_lsd).  A bucket whose bounds admit one key is copied as is,
 // whatever its size; other buckets larger than CAP go to over_list.  With
 // in_list the kernel walks a list of bucket ids instead of all G buckets.
+constexpr int CS_PIVMIN = 8;
 constexpr int CS_GMAX = 32;
 constexpr int CS_SIDE = 64;
 constexpr int CS_SLOTS = 128;
 
-enum : uint8_t { CS_DONE = 0, CS_BIG = 1, CS_SMALL2 = 2, CS_PIVOT = 3, CS_OTHER = 4 };
+enum : uint8_t { CS_DONE = 0, CS_BIG = 1, CS_SMALL2 = 2, CS_SMALL = 3 };
 
 // Rank of key (at group position p) among the gs keys sk[gl, gl+gs).
 __device__ __forceinline__ uint32_t cs_group_rank(const uint64_t* sk, uint32_t gl, uint32_t gs, uint32_t p,
@@ -607,25 +613,41 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
   // then (STAGE), once every rank is known, the whole bucket in sorted order,
   // so the output leaves in fully coalesced stores; without STAGE every tuple
   // is stored straight from registers to its rank (fewer live registers).
-  constexpr uint32_t OFF_CNT2 = CAP * 8;
-  constexpr uint32_t OFF_SLOT2 = OFF_CNT2 + ((CAP + 1) * 4 + 15) / 16 * 16;
-  constexpr uint32_t OFF_CNT = OFF_SLOT2 + CAP * 2;
-  constexpr uint32_t OFF_SLOT1 = OFF_CNT + ((M + 1) * 4 + 15) / 16 * 16;
-  constexpr uint32_t WORK_BYTES = OFF_SLOT1 + M * 2;
+  constexpr uint32_t OFF_SLOT1 = ((M + 1) * 4 + 15) / 16 * 16;
+  constexpr uint32_t OFF_CNT2 = OFF_SLOT1 + (M * 2 + 15) / 16 * 16;
+  constexpr uint32_t OFF_SK = OFF_CNT2 + ((CAP + 1) * 4 + 15) / 16 * 16;
+  constexpr uint32_t WORK_BYTES = OFF_SK + CAP * 8;
   constexpr uint32_t AREA = WORK_BYTES > CAP * 16 ? WORK_BYTES : CAP * 16;
-  __shared__ __align__(16) unsigned char area[AREA];
-  uint64_t* const sk = reinterpret_cast<uint64_t*>(area);                 // keys grouped by (sub-)group
-  uint32_t* const cnt2 = reinterpret_cast<uint32_t*>(area + OFF_CNT2);    // second-level counters, by position
-  uint16_t* const slot2 = reinterpret_cast<uint16_t*>(area + OFF_SLOT2);  // slot of a large cell, by its first position
-  uint32_t* const cnt = reinterpret_cast<uint32_t*>(area + OFF_CNT);      // first-level counters, then group starts
+  // One LDS block in a fixed order: the small per-slot arrays first and the
+  // counters at the front of the work area, so that the lane-indexed
+  // accesses all fall within the 64 KiB an LDS instruction's immediate
+  // offset reaches from one lane-scaled base register.
+  struct __align__(16) Lds {
+    uint64_t smin[CS_SLOTS], smax[CS_SLOTS], sC[CS_SLOTS];
+    uint32_t sgs[CS_SLOTS];
+    // per group in the pivot pass, at index (first position)/4: copies of
+    // its pivot (bits 0..15) and other keys (bits 16..31) counted so far
+    uint32_t gcnt[CAP / 4];
+    uint32_t wsum[NT / 64 + 2];
+    uint32_t nslot[2];   // large first-level groups (one spare word)
+    uint32_t anyf[8];    // block_any flags, one per test below
+    __align__(16) unsigned char area[AREA];
+  };
+  __shared__ Lds lds;
+  unsigned char* const area = lds.area;
+  uint32_t* const cnt = reinterpret_cast<uint32_t*>(area);                // first-level counters, then group starts
   uint16_t* const slot1 = reinterpret_cast<uint16_t*>(area + OFF_SLOT1);  // slot of a large first-level group
+  uint32_t* const cnt2 = reinterpret_cast<uint32_t*>(area + OFF_CNT2);    // second-level counters, by position
+  uint64_t* const sk = reinterpret_cast<uint64_t*>(area + OFF_SK);        // keys grouped by (sub-)group
   tup_t* const stage = reinterpret_cast<tup_t*>(area);                    // the sorted bucket
-  __shared__ uint64_t smin[CS_SLOTS], smax[CS_SLOTS], sC[CS_SLOTS];
-  __shared__ uint32_t sgs[CS_SLOTS];
-  __shared__ uint64_t spiv[CS_SLOTS];
-  __shared__ uint32_t sE[CS_SLOTS], sL[CS_SLOTS], sN[CS_SLOTS];
-  __shared__ uint32_t nslot[2];
-  __shared__ uint32_t wsum[NT / 64 + 2];
+  uint64_t* const smin = lds.smin;
+  uint64_t* const smax = lds.smax;
+  uint64_t* const sC = lds.sC;
+  uint32_t* const sgs = lds.sgs;
+  uint32_t* const gcnt = lds.gcnt;
+  uint32_t* const wsum = lds.wsum;
+  uint32_t* const nslot = lds.nslot;
+  uint32_t* const anyf = lds.anyf;
   const uint32_t tid = threadIdx.x;
   const uint32_t nitems = in_list ? (uint32_t)*in_count : *Gcount;
   for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -634,9 +656,9 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
     if (n == 0) continue;
     const uint64_t lo = blo[g], span = bhi[g] - lo;
     if (span == 0) {   // one key: input order is sorted order
-      // The lane index is passed through an empty asm so that the lane's
-      // addresses are formed here, per bucket: hoisted out of the bucket
-      // loop they would be spilled to scratch at every workgroup's start,
+      // Lane indexes pass through an empty asm where the lane's addresses
+      // would otherwise be hoisted out of the bucket loop: live across the
+      // whole loop they are spilled to scratch at every workgroup's start,
       // and those dead scratch lines are later written back to HBM.
       uint32_t i = tid;
       asm volatile("" : "+v"(i));
@@ -682,7 +704,9 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
     bool bad = false;
     __syncthreads();   // LDS of the previous bucket is free
     for (uint32_t b = tid; b <= (uint32_t)M; b += NT) cnt[b] = 0;
+    for (uint32_t b = tid; b < (uint32_t)(CAP / 4); b += NT) gcnt[b] = 0;
     if (tid < 2) nslot[tid] = 0;
+    if (tid < 8) anyf[tid] = 0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
@@ -710,11 +734,102 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
         if (!exact) sk[fin[k]] = key[k];
       }
     }
+    bool any_bad;
     if (!exact) {
       // gs_[k]: start of the item's current group (bits 0..27) and its state
-      // (bits 28..31); aux[k]: arrival index inside the current cell
+      // (bits 28..31).  aux[k], in the pivot pass: the group's size (bits
+      // 0..13), the item's arrival index (bits 14..27) and whether its key
+      // differs from the pivot (bit 28); in a second-level cell: the item's
+      // arrival index, then for a small cell the cell's size.
       uint32_t gs_[IPT], aux[IPT];
-      bool big = false;
+      bool big = false, piv = false;
+#define GL(k) (gs_[k] & 0x0FFFFFFFu)
+#define ST(k) (gs_[k] >> 28)
+#define SET(k, v) (gs_[k] = GL(k) | ((uint32_t)(v) << 28))
+      // the group's pivot: the key found at two of three spread positions,
+      // else the middle one
+      auto pivot_of = [&](uint32_t gl, uint32_t gs) -> uint64_t {
+        const uint64_t a0 = sk[gl], a1 = sk[gl + (gs >> 1)], a2 = sk[gl + gs - 1];
+        return (a0 == a1 || a0 == a2) ? a0 : a1;
+      };
+      // whether two of the three agree in their low halves (a false match
+      // only sends a group through the pivot pass, which counts exactly)
+      auto may_agree = [&](uint32_t gl, uint32_t gs) -> bool {
+        const uint32_t* lo32 = reinterpret_cast<const uint32_t*>(sk);
+        const uint32_t a0 = lo32[2 * gl], a1 = lo32[2 * (gl + (gs >> 1))], a2 = lo32[2 * (gl + gs - 1)];
+        return a0 == a1 || a0 == a2 || a1 == a2;
+      };
+      // a large first-level group's slot, opened by the item at its first position
+      auto open_slot = [&](int k, uint32_t gl, uint32_t gs) {
+        if (fin[k] == gl) {
+          const uint32_t s = atomicAdd(&nslot[0], 1u);
+          if (s < (uint32_t)CS_SLOTS) {
+            slot1[sub(key[k])] = (uint16_t)s; smin[s] = key[k]; smax[s] = key[k]; sgs[s] = gs;
+          }
+        }
+      };
+      // Three-way split of the groups in state SMALL (keys at sk[gl, gl + gs))
+      // around their pivots: the copies of the pivot count themselves and
+      // follow the other keys that are smaller, and the at most SIDE other
+      // keys are ranked by comparison among themselves.  A group with more
+      // other keys goes, at the first level, to the second-level counting;
+      // at the second level it makes the bucket a redo.
+      auto pivot_pass = [&](bool first_level) {
+#pragma unroll
+        for (int k = 0; k < IPT; k++)
+          if (ST(k) == CS_SMALL) {
+            const uint32_t gl = GL(k);
+            const bool other = key[k] != pivot_of(gl, aux[k] & 0x3FFFu);
+            const uint32_t old = atomicAdd(&gcnt[gl >> 2], other ? 0x10000u : 1u);
+            aux[k] |= ((other ? old >> 16 : old & 0xFFFFu) << 14) | ((uint32_t)other << 28);
+          }
+        __syncthreads();
+        // the other keys move to the group's end, in arrival order from the
+        // last position; the first copy of the pivot writes it at the start
+#pragma unroll
+        for (int k = 0; k < IPT; k++)
+          if (ST(k) == CS_SMALL) {
+            const uint32_t gl = GL(k), gs = aux[k] & 0x3FFFu, q = (aux[k] >> 14) & 0x3FFFu;
+            if ((gcnt[gl >> 2] >> 16) <= (uint32_t)CS_SIDE) {
+              if (aux[k] >> 28) sk[gl + gs - 1 - q] = key[k];
+              else if (q == 0) sk[gl] = key[k];
+            }
+          }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < IPT; k++)
+          if (ST(k) == CS_SMALL) {
+            const uint32_t gl = GL(k), gs = aux[k] & 0x3FFFu, q = (aux[k] >> 14) & 0x3FFFu;
+            const uint32_t c = gcnt[gl >> 2], no = c >> 16;
+            if (no > (uint32_t)CS_SIDE) {
+              if (first_level) {
+                SET(k, CS_BIG);
+                big = true;
+                aux[k] = 0;
+                open_slot(k, gl, gs);
+              } else {
+                bad = true;
+              }
+              continue;
+            }
+            const uint32_t ob = gl + gs - no;   // the other keys, at [ob, gl + gs)
+            uint32_t r;
+            if (aux[k] >> 28) {   // smaller other keys, then the pivot's copies if it is larger
+              r = gl + (key[k] > sk[gl] ? (c & 0xFFFFu) : 0u);
+#pragma unroll 2
+              for (uint32_t t = 0; t < no; t++) {
+                const uint64_t kq = sk[ob + t];
+                r += (kq < key[k]) || (kq == key[k] && no - 1 - t < q);
+              }
+            } else {              // a copy of the pivot: after the other keys that are smaller
+              r = gl + q;
+#pragma unroll 2
+              for (uint32_t t = 0; t < no; t++) r += sk[ob + t] < key[k];
+            }
+            fin[k] = r;
+            SET(k, CS_DONE);
+          }
+      };
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < IPT; k++) {
@@ -725,35 +840,43 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
           const uint32_t l = cnt[dd], gs = cnt[dd + 1] - l;
           cnt2[fin[k]] = 0;
           gs_[k] = l;
-          if (gs > (uint32_t)CS_GMAX) {
-            gs_[k] = l | ((uint32_t)CS_BIG << 28);
-            big = true;
-            if (fin[k] == l) {   // the item at the group's first position opens its slot
-              const uint32_t s = atomicAdd(&nslot[0], 1u);
-              if (s < (uint32_t)CS_SLOTS) {
-                slot1[dd] = (uint16_t)s; smin[s] = key[k]; smax[s] = key[k]; sgs[s] = gs;
-              }
+          if (gs > (uint32_t)CS_PIVMIN) {
+            // a large group whose three sampled keys all differ holds many
+            // keys: straight to the second level
+            if (gs > (uint32_t)CS_GMAX && !may_agree(l, gs)) {
+              gs_[k] = l | ((uint32_t)CS_BIG << 28);
+              big = true;
+              open_slot(k, l, gs);
+            } else {
+              gs_[k] = l | ((uint32_t)CS_SMALL << 28);
+              aux[k] = gs;
+              piv = true;
             }
           } else if (gs > 1) {
             fin[k] = cs_group_rank(sk, l, gs, fin[k], key[k]);
           }
         }
       }
-#define GL(k) (gs_[k] & 0x0FFFFFFFu)
-#define ST(k) (gs_[k] >> 28)
-#define SET(k, v) (gs_[k] = GL(k) | ((uint32_t)(v) << 28))
-      if (__syncthreads_or(big)) {
+      bool any_big;
+      if (block_any2(piv, big, &anyf[0], &anyf[1], &any_big)) {
+        pivot_pass(true);
+        any_big = block_any(big, &anyf[2]);
+      }
+      bool piv2 = false;
+      if (any_big) {
         const uint32_t nbig = nslot[0];
         if (nbig > (uint32_t)CS_SLOTS) {
           bad = true;
         } else {
-          // group bounds
+          // group bounds; a group's first item also clears the pivot-pass
+          // counter at its start for the cells that may start there
 #pragma unroll
           for (int k = 0; k < IPT; k++)
             if (ST(k) == CS_BIG) {
               const uint32_t s = slot1[sub(key[k])];
               atomicMin(reinterpret_cast<unsigned long long*>(&smin[s]), (unsigned long long)key[k]);
               atomicMax(reinterpret_cast<unsigned long long*>(&smax[s]), (unsigned long long)key[k]);
+              if (fin[k] == GL(k)) gcnt[GL(k) >> 2] = 0;
             }
           __syncthreads();
           // second-level cells, as many as the group has keys; C = 0 marks a
@@ -765,7 +888,7 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
             sC[s] = sp2 < (uint64_t)sgs[s] ? 0ull : interp_scale(sgs[s], sp2);
           }
           // when every large group holds one key, their positions stand
-          if (__syncthreads_or(mixed)) {
+          if (block_any(mixed, &anyf[3])) {
           auto cell = [&](uint32_t s, uint64_t k) -> uint32_t {
             const uint64_t x = k - smin[s], c = sC[s];
             const uint32_t c2 = c ? (uint32_t)__umul64hi(x, c) : (uint32_t)x;
@@ -785,10 +908,12 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
           __syncthreads();
           // exclusive scan of the second-level counters over the bucket
           {
+            uint32_t t = tid;   // the lane's addresses are formed here, not hoisted
+            asm volatile("" : "+v"(t));
             uint32_t loc[IPT], run = 0;
 #pragma unroll
             for (int q = 0; q < IPT; q++) {
-              const uint32_t i = tid * IPT + q;
+              const uint32_t i = t * IPT + q;
               loc[q] = run;
               run += i < n ? cnt2[i] : 0u;
             }
@@ -796,13 +921,12 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
             const uint32_t ex = block_excl_scan<NT>(run, wsum, &tot);
 #pragma unroll
             for (int q = 0; q < IPT; q++) {
-              const uint32_t i = tid * IPT + q;
+              const uint32_t i = t * IPT + q;
               if (i < n) cnt2[i] = loc[q] + ex;
             }
             if (tid == 0) cnt2[n] = tot;
           }
           __syncthreads();
-          bool three = false;
 #pragma unroll
           for (int k = 0; k < IPT; k++)
             if (ST(k) == CS_BIG) {
@@ -814,18 +938,13 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
               sk[fin[k]] = key[k];
               if (gs2 <= 1) {
                 SET(k, CS_DONE);
-              } else if (gs2 <= (uint32_t)CS_GMAX) {
+              } else if (gs2 <= (uint32_t)CS_PIVMIN) {
                 gs_[k] = g2 | ((uint32_t)CS_SMALL2 << 28);
                 aux[k] = gs2;
               } else {
-                gs_[k] = g2 | ((uint32_t)CS_PIVOT << 28);
-                three = true;
-                if (aux[k] == 0) {   // first arrival opens the cell's slot; its key is the pivot
-                  const uint32_t s2 = atomicAdd(&nslot[1], 1u);
-                  if (s2 < (uint32_t)CS_SLOTS) {
-                    slot2[g2] = (uint16_t)s2; spiv[s2] = key[k]; sE[s2] = 0; sL[s2] = 0; sN[s2] = 0;
-                  }
-                }
+                gs_[k] = g2 | ((uint32_t)CS_SMALL << 28);
+                aux[k] = gs2;
+                piv2 = true;
               }
             }
           __syncthreads();
@@ -835,60 +954,24 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
               fin[k] = cs_group_rank(sk, GL(k), aux[k], fin[k], key[k]);
               SET(k, CS_DONE);
             }
-          if (__syncthreads_or(three)) {
-            if (nslot[1] > (uint32_t)CS_SLOTS) {
-              bad = true;
-            } else {
-              // three-way split: copies of the pivot count themselves, the
-              // other keys are packed at the front of the cell
-#pragma unroll
-              for (int k = 0; k < IPT; k++) {
-                const bool piv = ST(k) == CS_PIVOT;
-                const uint32_t s2 = piv ? slot2[GL(k)] : 0u;
-                const uint64_t pv = piv ? spiv[s2] : 0ull;
-                if (piv) {
-                  if (key[k] == pv) {
-                    aux[k] = atomicAdd(&sE[s2], 1u);
-                  } else {
-                    if (key[k] < pv) atomicAdd(&sL[s2], 1u);
-                    const uint32_t q = atomicAdd(&sN[s2], 1u);
-                    aux[k] = q;
-                    SET(k, CS_OTHER);
-                    if (q < (uint32_t)CS_SIDE) sk[GL(k) + q] = key[k];
-                  }
-                }
-              }
-              __syncthreads();
-#pragma unroll
-              for (int k = 0; k < IPT; k++) {
-                if (ST(k) == CS_PIVOT) {
-                  fin[k] = GL(k) + sL[slot2[GL(k)]] + aux[k];
-                } else if (ST(k) == CS_OTHER) {
-                  const uint32_t s2 = slot2[GL(k)];
-                  const uint32_t no = sN[s2];
-                  if (no > (uint32_t)CS_SIDE) { bad = true; continue; }
-                  uint32_t r = GL(k) + (key[k] > spiv[s2] ? sE[s2] : 0u);
-                  for (uint32_t q = 0; q < no; q++) {
-                    const uint64_t kq = sk[GL(k) + q];
-                    r += (kq < key[k]) || (kq == key[k] && q < aux[k]);
-                  }
-                  fin[k] = r;
-                }
-              }
-            }
-          }
           }
         }
+      }
+      if (block_any2(piv2, bad, &anyf[4], &anyf[5], &any_bad)) {
+        pivot_pass(false);
+        any_bad = block_any(bad, &anyf[6]);
       }
 #undef GL
 #undef ST
 #undef SET
+    } else {
+      any_bad = block_any(bad, &anyf[5]);
     }
-    if (__syncthreads_or(bad)) {
+    if (any_bad) {
       if (tid == 0) redo_list[atomicAdd(redo_count, 1ull)] = g;
       continue;
     }
-    if (STAGE) {
+    if constexpr (STAGE) {
       // every rank is known and the working arrays are free: stage, then copy
 #pragma unroll
       for (int k = 0; k < IPT; k++) {
@@ -898,9 +981,11 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
         }
       }
       __syncthreads();
+      uint32_t t = tid;   // the staged addresses are formed here, not hoisted
+      asm volatile("" : "+v"(t));
 #pragma unroll
       for (int k = 0; k < IPT; k++) {
-        const uint32_t i = k * NT + tid;
+        const uint32_t i = k * NT + t;
         if (i < n) {
           const tup_t v = stage[i];
           store_tup(dst + a + i, v);

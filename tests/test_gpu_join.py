@@ -204,6 +204,24 @@ def _dup_pattern(name, rng, n):
         return k
     if name == "geometric":            # distinct-ish keys packed towards zero
         return np.floor(np.exp2(rng.random(n) * 60.0)).astype(np.uint64)
+    if name in ("mid_groups", "mid_cells"):
+        # run by run (runs of 2^17): keys with 9 to 32 copies, some copies
+        # moved a little above their key, so that an interpolation cell
+        # holds one frequent key and a few strays; mid_cells puts three such
+        # keys next to each other, so that they share a first-level cell and
+        # part in second-level cells
+        out = []
+        for _ in range((n + (1 << 17) - 1) >> 17):
+            m = 1 << 17
+            h = rng.integers(1 << 20, 1 << 62, m // 12, dtype=np.uint64)
+            if name == "mid_cells":
+                h = (h[:, None] + np.arange(3, dtype=np.uint64) * np.uint64(4096)).ravel()
+            k = np.repeat(h, rng.integers(9, 33, len(h)))[:m]
+            k = np.concatenate([k, rng.integers(0, U64, m - len(k), dtype=np.uint64)])
+            stray = rng.random(m) < 0.06
+            k[stray] += rng.integers(1, 256, int(stray.sum()), dtype=np.uint64)
+            out.append(k[rng.permutation(m)])
+        return np.concatenate(out)[:n]
     if name == "heavy_pairs":          # adjacent heavy keys share every cell: fallback path
         h = rng.integers(1 << 20, 1 << 60, 256, dtype=np.uint64)
         k = h[rng.integers(0, len(h), n)]
@@ -213,7 +231,7 @@ def _dup_pattern(name, rng, n):
 
 
 @pytest.mark.parametrize("pattern", ["zipf_copies", "two_clusters", "heavy_with_neighbours", "geometric",
-                                     "heavy_pairs"])
+                                     "mid_groups", "mid_cells", "heavy_pairs"])
 def test_bucket_sort_duplicates_and_clusters(pattern):
     rng = np.random.default_rng(zlib.crc32(pattern.encode()))
     nS = 1 << 20
