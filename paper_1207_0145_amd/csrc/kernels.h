@@ -597,7 +597,7 @@ __device__ __forceinline__ uint32_t cs_group_rank(const uint64_t* sk, uint32_t g
   return r;
 }
 
-template <int NT, int IPT, int M, int MINB, bool STAGE>
+template <int NT, int IPT, int M, int MINB, bool STAGE, bool TIGHT>
 __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
                                                        const uint32_t* bstart, const uint64_t* blo,
                                                        const uint64_t* bhi, const uint32_t* Gcount,
@@ -631,6 +631,7 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
     uint32_t wsum[NT / 64 + 2];
     uint32_t nslot[2];   // large first-level groups (one spare word)
     uint32_t anyf[8];    // block_any flags, one per test below
+    uint64_t wmin[NT / 64], wmax[NT / 64];   // per-wave key range (TIGHT)
     __align__(16) unsigned char area[AREA];
   };
   __shared__ Lds lds;
@@ -654,7 +655,7 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
     const uint32_t g = in_list ? in_list[it] : it;
     const uint32_t a = bstart[g], n = bstart[g + 1] - a;
     if (n == 0) continue;
-    const uint64_t lo = blo[g], span = bhi[g] - lo;
+    uint64_t lo = blo[g], span = bhi[g] - lo;
     if (span == 0) {   // one key: input order is sorted order
       // Lane indexes pass through an empty asm where the lane's addresses
       // would otherwise be hoisted out of the bucket loop: live across the
@@ -693,6 +694,39 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
         key[k] = ~0ull; val[k] = 0;
       }
     }
+    __syncthreads();   // LDS of the previous bucket is free
+    for (uint32_t b = tid; b <= (uint32_t)M; b += NT) cnt[b] = 0;
+    for (uint32_t b = tid; b < (uint32_t)(CAP / 4); b += NT) gcnt[b] = 0;
+    if (tid < 2) nslot[tid] = 0;
+    if (tid < 8) anyf[tid] = 0;
+    __syncthreads();
+    if constexpr (TIGHT) {
+      // per-wave key range; the keys are first used here, two barriers
+      // after their loads were issued, so that the loads overlap
+      uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+      for (int k = 0; k < IPT; k++)
+        if (k * NT + tid < n) { mn = key[k] < mn ? key[k] : mn; mx = key[k] > mx ? key[k] : mx; }
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        const uint64_t x = __shfl_xor(mn, d, 64), y = __shfl_xor(mx, d, 64);
+        mn = x < mn ? x : mn;
+        mx = y > mx ? y : mx;
+      }
+      if ((tid & 63) == 0) { lds.wmin[tid >> 6] = mn; lds.wmax[tid >> 6] = mx; }
+      __syncthreads();
+      // interpolate over the keys' own range: the splitter bounds may enclose
+      // empty key space (a segment's outer buckets, or a splitter that falls
+      // in a gap between clusters), which would crowd the keys into few cells
+      uint64_t bmn = lds.wmin[0], bmx = lds.wmax[0];
+#pragma unroll
+      for (int w = 1; w < NT / 64; w++) {
+        bmn = lds.wmin[w] < bmn ? lds.wmin[w] : bmn;
+        bmx = lds.wmax[w] > bmx ? lds.wmax[w] : bmx;
+      }
+      lo = bmn;
+      span = bmx - bmn;
+    }
     const bool exact = span < (uint64_t)M;   // one key per sub-bucket
     const uint64_t C = exact ? 0ull : interp_scale(M, span);
     auto sub = [&](uint64_t k) -> uint32_t {
@@ -702,12 +736,6 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
     };
     uint32_t fin[IPT];
     bool bad = false;
-    __syncthreads();   // LDS of the previous bucket is free
-    for (uint32_t b = tid; b <= (uint32_t)M; b += NT) cnt[b] = 0;
-    for (uint32_t b = tid; b < (uint32_t)(CAP / 4); b += NT) gcnt[b] = 0;
-    if (tid < 2) nslot[tid] = 0;
-    if (tid < 8) anyf[tid] = 0;
-    __syncthreads();
 #pragma unroll
     for (int k = 0; k < IPT; k++) {
       if (k * NT + tid < n) {

@@ -50,7 +50,7 @@ struct Plan {
   uint64_t splS, splR1, splR2;
   uint64_t bstS, bstR1, bstR2;
   uint64_t bndS, bndR1, bndR2;             // per-bucket key bounds (lo array, then hi array)
-  uint64_t bigS, midS, redoS, redoR, bigR, ctr;
+  uint64_t bigS, midS, redoS, redoR, redoR2, bigR, ctr;
   uint64_t bkey, Pc, pstart, plen, pkey;
   uint64_t ridx, o, items, item_pre, item_cnt, res, span;
   uint64_t cdf_chunks, cdf_sorted, modelR, modelS;  // learned CDF samples and models
@@ -169,6 +169,7 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->midS = take((uint64_t)P->Gs * 4);
   P->redoS = take((uint64_t)P->Gs * 4);
   P->redoR = take((uint64_t)P->Gr * 4);
+  P->redoR2 = take((uint64_t)P->Gr * 4);
   P->bigR = take((uint64_t)P->Gr * 4);
   P->ctr = take(8 * 8);
   P->bkey = take((uint64_t)P->Gr * 8);
@@ -570,10 +571,10 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
     uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
     uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
-    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
                                                                  nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
     LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
                                                                       midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
                                                                       soS);
     LAUNCH_CHECK();
@@ -639,11 +640,19 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     } else {
       mk.mark_range(MK_R2_SPL, MK_R2_SCAT);
     }
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true><<<LRf->Gmax, BL_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<LRf->Gmax, BL_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
                                                                       LRf->Gcount(), nullptr, nullptr, bigR, ctr + 1,
                                                                       redoR, ctr + 4, soR);
     LAUNCH_CHECK();
-    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, redoR, ctr + 4, bigR, ctr + 1, soR);
+    // buckets the sort gave up on get a second pass over their own key range
+    // (splitter bounds can enclose a gap between key clusters); the rest go
+    // to the LSD radix sort
+    uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
+                                                                      LRf->Gcount(), redoR, ctr + 4, bigR, ctr + 1,
+                                                                      redoR2, ctr + 5, soR);
+    LAUNCH_CHECK();
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, redoR2, ctr + 5, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
     mk.mark(MK_R_SORT);
     k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, bigR, ctr + 1, soR);
@@ -728,7 +737,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     (void)hipEventDestroy(ev1);
     Result r;
     HIP_TRY(hipMemcpy(&r, res, sizeof(r), hipMemcpyDeviceToHost));
-    unsigned long long c[5];
+    unsigned long long c[6];
     HIP_TRY(hipMemcpy(c, ctr, sizeof(c), hipMemcpyDeviceToHost));
     uint32_t pc = 0;
     if (P.nR && P.nS) HIP_TRY(hipMemcpy(&pc, ws + P.Pc, 4, hipMemcpyDeviceToHost));
@@ -738,7 +747,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     stats->partitions = pc;
     stats->runs = P.Q;
     stats->oversize_buckets = c[0] + c[1];
-    stats->resorted_buckets = c[3] + c[4];
+    stats->resorted_buckets = c[3] + c[5];
     stats->search_probes = r.search_probes;
     stats->search_fallbacks = r.fallbacks;
     stats->max_partition = r.spare;
@@ -830,7 +839,7 @@ struct BatchPlan {
   uint64_t cntS, cntR, ocap, item_cap;
   // workspace offsets
   uint64_t T, U, Rp, Rs, cS, cR, bsum, segS, segR, srcS, srcR, splS, splR, bstS, bstR, bndS, bndR;
-  uint64_t bigS, midS, redoS, redoR, bigR, ctr, bkey, Pc, pstart, plen, pkey, pjoin, ridx, o, items, item_pre;
+  uint64_t bigS, midS, redoS, redoR, redoR2, bigR, ctr, bkey, Pc, pstart, plen, pkey, pjoin, ridx, o, items, item_pre;
   uint64_t J, tstart, ototal, span;
   uint64_t tab_off, tab_bytes;           // host-written tables: one contiguous range
   uint64_t total;
@@ -913,6 +922,7 @@ bool make_batch_plan(const mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH,
   P->midS = take((uint64_t)P->Gs * 4);
   P->redoS = take((uint64_t)P->Gs * 4);
   P->redoR = take((uint64_t)P->Gr * 4);
+  P->redoR2 = take((uint64_t)P->Gr * 4);
   P->bigR = take((uint64_t)P->Gr * 4);
   P->ctr = take(8 * 8);
   P->bkey = take((uint64_t)P->Gr * 8);
@@ -1014,10 +1024,10 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
     uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
     uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
-    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
                                                                  nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
     LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
                                                                       midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
                                                                       soS);
     LAUNCH_CHECK();
@@ -1040,11 +1050,15 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     soR.NB = 1;
     soR.bkey = reinterpret_cast<uint64_t*>(ws + P.bkey);
     uint32_t* redoR = reinterpret_cast<uint32_t*>(ws + P.redoR);
+    uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
     uint32_t* bigR = reinterpret_cast<uint32_t*>(ws + P.bigR);
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true><<<P.Gr, BL_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(),
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<P.Gr, BL_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(),
                                                                  nullptr, nullptr, bigR, ctr + 1, redoR, ctr + 4, soR);
     LAUNCH_CHECK();
-    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(Rp, Rs, LR.bstart, redoR, ctr + 4, bigR, ctr + 1, soR);
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(),
+                                                                 redoR, ctr + 4, bigR, ctr + 1, redoR2, ctr + 5, soR);
+    LAUNCH_CHECK();
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(Rp, Rs, LR.bstart, redoR2, ctr + 5, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
     k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(Rp, Rs, LR.bstart, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
