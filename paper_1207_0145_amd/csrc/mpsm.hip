@@ -526,7 +526,10 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
   CdfModel* modelR = reinterpret_cast<CdfModel*>(ws + P.modelR);
   CdfModel* modelS = reinterpret_cast<CdfModel*>(ws + P.modelS);
   // learned splitters use R's model, the learned search S's; both are built
-  // on a side stream while phase 1 runs and joined before R's partitioning
+  // on a side stream while phase 1 runs and joined before R's partitioning.
+  // The side stream may start from here (fork); its kernels are enqueued
+  // once phase 1's first long kernels are, so that the host time their
+  // launches take never leaves the GPU waiting.
   const bool learn_r = P.splitter == MPSM_SPLIT_LEARNED && P.nR && P.nS;
   const bool learn_s = P.search == MPSM_SEARCH_LEARNED && P.nR && P.nS;
   SideStream* side = nullptr;
@@ -534,6 +537,9 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     mpsm_status rs = side_stream(&side);
     if (rs != MPSM_OK) return rs;
     HIP_TRY(hipEventRecord(side->fork, st));
+  }
+  auto start_models = [&]() -> mpsm_status {
+    if (!side) return MPSM_OK;
     HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0));
     CdfJob job;
     memset(&job, 0, sizeof(job));
@@ -544,7 +550,8 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
                                reinterpret_cast<uint64_t*>(ws + P.cdf_sorted), side->st);
     if (rc != MPSM_OK) return rc;
     HIP_TRY(hipEventRecord(side->done, side->st));
-  }
+    return MPSM_OK;
+  };
   mk.mark(MK_CDF);
   if (P.nR == 0 || P.nS == 0) {
     mk.mark_range(MK_S_SPL, MK_JOIN);  // MK_CDF was recorded above
@@ -559,6 +566,8 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     k_seg_uniform<<<(uint32_t)cdiv(P.Q, 256), 256, 0, st>>>((uint32_t)P.nS, P.L, P.Q, LS.seg.start, LS.seg.len);
     LAUNCH_CHECK();
     rc = bucket_pass(Sin, T, (uint32_t)P.nS, LS, bsum, st, mk, MK_S_SPL);
+    if (rc != MPSM_OK) return rc;
+    rc = start_models();
     if (rc != MPSM_OK) return rc;
     SortOut soS;
     soS.run_idx = reinterpret_cast<uint64_t*>(ws + P.ridx);
