@@ -121,8 +121,9 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
     // average need (level-1 buckets are sampled, so their sizes vary)
     P->NB2 = 2 * next_pow2(cdiv(F, P->NB1));
     if (P->NB2 > (uint32_t)MAX_NB) P->NB2 = MAX_NB;
-    P->OS2 = SMP_NT_S * SMP_IPT_S / P->NB2 < 16u ? SMP_NT_S * SMP_IPT_S / P->NB2 : 16u;
-    if (P->OS2 < 4) P->OS2 = os_for(P->NB2);
+    // 16 samples per level-2 bucket (the larger sample sort when NB2 > 128):
+    // with 4, bucket sizes spread so far that about 1% exceed the LDS tile
+    P->OS2 = SMP_CAP / P->NB2 < 16u ? SMP_CAP / P->NB2 : 16u;
   }
   P->Gs = P->Q * P->NBs;
   P->Gr = P->NB1 * P->NB2;
