@@ -58,8 +58,8 @@ __device__ __forceinline__ float cdf_pwl(const CdfModel& m, uint64_t key) {
     if (m.kkey[mid] <= key) lo = mid; else hi = mid;
   }
   const uint64_t a = m.kkey[lo], b = m.kkey[hi];
-  const float t = (float)((double)(key - a) / (double)(b - a));
-  return ((float)lo + t) * (1.f / (float)(CDF_K - 1));
+  const float t = (float)(key - a) / (float)(b - a);   // in [0, 1); single precision is ample
+  return ((float)lo + (t < 1.f ? t : 1.f)) * (1.f / (float)(CDF_K - 1));
 }
 
 __device__ __forceinline__ float cdf_residual(const CdfModel& m, float q) {
@@ -156,12 +156,15 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 // of the 1024-thread block call; the result is in every thread).  With
 // seg != NULL also the largest per quantile segment (seg: CDF_SEG floats of
 // LDS, zeroed by the caller).
+// (NET false: the piecewise-linear part alone, the model before training
+// and after a network that did not help.)
+template <bool NET>
 __device__ float cdf_sample_error(const CdfModel& m, const uint64_t* sorted, float* emax, float* seg) {
   const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   float e = 0.f;
   for (uint32_t j = tid * 4; j < (uint32_t)CDF_M; j += 4096) {
     const float y = ((float)j + 0.5f) / (float)CDF_M;
-    const float d = fabsf(cdf_eval(m, sorted[j]) - y);
+    const float d = fabsf((NET ? cdf_eval(m, sorted[j]) : cdf_pwl(m, sorted[j])) - y);
     e = d > e ? d : e;
     // non-negative floats order like their bit patterns
     if (seg) atomicMax(reinterpret_cast<unsigned int*>(&seg[j / (CDF_M / CDF_SEG)]), __float_as_uint(d));
@@ -204,7 +207,7 @@ __global__ void __launch_bounds__(1024) k_cdf_train(const uint64_t* sorted_all, 
   if (tid == 0) { m.b2 = 0.f; m.valid = job.n[blockIdx.y] ? 1u : 0u; m.pad = 0; }
   if (tid < (uint32_t)NP) { mom1[tid] = 0.f; mom2[tid] = 0.f; }
   __syncthreads();
-  const float e_pwl = cdf_sample_error(m, sorted, emax, nullptr);
+  const float e_pwl = cdf_sample_error<false>(m, sorted, emax, nullptr);
   // two training points per thread
   float xq[2], yv[2];
 #pragma unroll
@@ -259,16 +262,18 @@ __global__ void __launch_bounds__(1024) k_cdf_train(const uint64_t* sorted_all, 
     }
     __syncthreads();
   }
-  float e = cdf_sample_error(m, sorted, emax, nullptr);
+  // error bounds of the trained model, overall and per quantile segment
+  if (tid < (uint32_t)CDF_SEG) eseg[tid] = 0.f;
+  __syncthreads();
+  float e = cdf_sample_error<true>(m, sorted, emax, eseg);
   if (!(e < e_pwl)) {   // the network did not help (or diverged): drop it
     __syncthreads();
     if (tid < (uint32_t)CDF_H) m.w2[tid] = 0.f;
     if (tid == 0) m.b2 = 0.f;
+    if (tid < (uint32_t)CDF_SEG) eseg[tid] = 0.f;
+    __syncthreads();
+    e = cdf_sample_error<false>(m, sorted, emax, eseg);
   }
-  // error bounds of the final model, overall and per quantile segment
-  if (tid < (uint32_t)CDF_SEG) eseg[tid] = 0.f;
-  __syncthreads();
-  e = cdf_sample_error(m, sorted, emax, eseg);
   __syncthreads();
   if (tid < (uint32_t)CDF_SEG) m.eps_seg[tid] = eseg[tid];
   if (tid == 0) m.eps = e;
