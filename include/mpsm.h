@@ -115,6 +115,7 @@ typedef struct mpsm_stats {
   double cdf_eps_r;           /* learned CDF of R: largest error on its sample (-1 if not trained) */
   double cdf_eps_s;           /* learned CDF of S: same */
   uint64_t resorted_buckets;  /* buckets whose one-pass sort gave up, re-sorted by LSD radix passes */
+  uint64_t retried_buckets;   /* R buckets the one-pass sort gave up on and sorted again over their own key range */
 } mpsm_stats;
 
 /* Fill *cfg with defaults (all automatic, role AUTO, sampled splitters,

@@ -41,7 +41,7 @@ class MpsmStats(ctypes.Structure):
                 ("search_probes", ctypes.c_uint64), ("swapped", ctypes.c_uint64), ("ms_total", ctypes.c_double),
                 ("search_fallbacks", ctypes.c_uint64), ("max_partition", ctypes.c_uint64),
                 ("cdf_eps_r", ctypes.c_double), ("cdf_eps_s", ctypes.c_double),
-                ("resorted_buckets", ctypes.c_uint64)]
+                ("resorted_buckets", ctypes.c_uint64), ("retried_buckets", ctypes.c_uint64)]
 
 
 class MpsmLayout(ctypes.Structure):

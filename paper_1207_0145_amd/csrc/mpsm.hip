@@ -758,6 +758,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     stats->runs = P.Q;
     stats->oversize_buckets = c[0] + c[1];
     stats->resorted_buckets = c[3] + c[5];
+    stats->retried_buckets = c[4];
     stats->search_probes = r.search_probes;
     stats->search_fallbacks = r.fallbacks;
     stats->max_partition = r.spare;

@@ -177,3 +177,13 @@ def test_batch_autotune_cache_hit_and_malformed_entries(tmp_path):
         assert t.from_cache == 1 and (t.log2_run_len, t.bucket_target, t.join_chunk) == (16, 2048, 16384)
     finally:
         L.mpsm_batch_destroy(h)
+
+
+def test_stats_binding_matches_header():
+    """The ctypes MpsmStats mirrors include/mpsm.h field by field."""
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "mpsm.h")).read()
+    body = hdr[hdr.index("typedef struct mpsm_stats {"):hdr.index("} mpsm_stats;")]
+    fields = re.findall(r"^\s*(uint64_t|double)\s+(\w+);", body, re.M)
+    ct = {"uint64_t": ctypes.c_uint64, "double": ctypes.c_double}
+    assert [(n, ct[t]) for t, n in fields] == list(mpsm.MpsmStats._fields_)

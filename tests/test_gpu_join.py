@@ -264,6 +264,41 @@ def test_bucket_sort_duplicates_and_clusters(pattern):
         assert st["resorted_buckets"] > 0
 
 
+def test_r_bucket_retry_over_own_range():
+    """R made of blocks of 1500 consecutive keys plus 1500 keys spread over
+    the next 2^20, far from both ends of the key space.  The first and last
+    R buckets take their outer bounds from the key space itself (0 and
+    2^64 - 1); interpolated over those, their keys fall into one cell whose
+    second-level cells still hold hundreds of distinct keys, so the one-pass
+    sort gives up on them and they are sorted again over their own key
+    range (what is still left would go to the LSD sort)."""
+    rng = np.random.default_rng(0x7E7)
+    blocks = []
+    for k in range(88):
+        base = np.uint64((1 << 40) + (k << 20))
+        tail = rng.choice((1 << 20) - 1500, 1500, replace=False).astype(np.uint64) + np.uint64(1500)
+        blocks.append(base + np.concatenate([np.arange(1500, dtype=np.uint64), tail]))
+    rk = np.concatenate(blocks)
+    assert len(np.unique(rk)) == len(rk)
+    R = np.stack([rk, rng.integers(0, U64, len(rk), dtype=np.uint64, endpoint=True)], 1)
+    R = R[rng.permutation(len(R))]
+    nS = 1 << 19
+    S = np.stack([rk[rng.integers(0, len(rk), nS)], rng.integers(0, U64, nS, dtype=np.uint64, endpoint=True)], 1)
+    cfg = mpsm.config()
+    lay = mpsm.layout(len(R), nS, cfg)
+    ws = mpsm.alloc_workspace(len(R), nS, cfg)
+    got = gpu_join(R, S, cfg, workspace=ws, stats=True)
+    want = oracle.join(R, S)
+    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+    torch.cuda.synchronize()
+    Rsorted = _ws_view(ws, lay["off_r_sorted"], 2 * len(R), np.uint64).reshape(-1, 2)
+    assert np.array_equal(Rsorted[:, 0], np.sort(R[:, 0]))
+    assert np.array_equal(Rsorted[np.lexsort((Rsorted[:, 1], Rsorted[:, 0]))], R[np.lexsort((R[:, 1], R[:, 0]))])
+    st = got["stats"]
+    _say(f"retried R buckets {st['retried_buckets']}, LSD re-sorts {st['resorted_buckets']}")
+    assert st["retried_buckets"] >= 1
+
+
 # ------------------------------------------------------- named workloads
 
 def test_fk_small_full_size():
