@@ -73,7 +73,7 @@ STEP_DISPATCH = {
     "s_histogram": ("k_bucket_hist", 0), "s_scatter": ("k_bucket_scatter", 0),
     "r1_histogram": ("k_bucket_hist", 1), "r1_scatter": ("k_bucket_scatter", 1),
     "r2_histogram": ("k_bucket_hist", 2), "r2_scatter": ("k_bucket_scatter", 2),
-    "s_bucket_sort": ("void k_bucket_sort_cs<1024, 4", 0), "r_bucket_sort": ("void k_bucket_sort_cs<1024, 8", 1),
+    "s_bucket_sort": ("void k_bucket_sort_cs<1024, 4", 0), "r_bucket_sort": ("void k_bucket_sort_cs<1024, 4", 1),
     "search": ("k_search", 0), "join": ("void k_join<0", 0),
 }
 

@@ -50,7 +50,7 @@ struct Plan {
   uint64_t splS, splR1, splR2;
   uint64_t bstS, bstR1, bstR2;
   uint64_t bndS, bndR1, bndR2;             // per-bucket key bounds (lo array, then hi array)
-  uint64_t bigS, midS, redoS, redoR, redoR2, bigR, ctr;
+  uint64_t bigS, midS, redoS, midR, redoR, redoR2, bigR, ctr;
   uint64_t bkey, Pc, pstart, plen, pkey;
   uint64_t ridx, o, items, item_pre, item_cnt, res, span;
   uint64_t cdf_chunks, cdf_sorted, modelR, modelS;  // learned CDF samples and models
@@ -169,6 +169,7 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->bigS = take((uint64_t)P->Gs * 4);
   P->midS = take((uint64_t)P->Gs * 4);
   P->redoS = take((uint64_t)P->Gs * 4);
+  P->midR = take((uint64_t)P->Gr * 4);
   P->redoR = take((uint64_t)P->Gr * 4);
   P->redoR2 = take((uint64_t)P->Gr * 4);
   P->bigR = take((uint64_t)P->Gr * 4);
@@ -650,9 +651,16 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     } else {
       mk.mark_range(MK_R2_SPL, MK_R2_SCAT);
     }
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<LRf->Gmax, BL_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
-                                                                      LRf->Gcount(), nullptr, nullptr, bigR, ctr + 1,
-                                                                      redoR, ctr + 4, soR);
+    // as for S runs: the 2-per-CU sort takes the buckets up to its tile, the
+    // larger ones go to the 1-per-CU sort
+    uint32_t* midR = reinterpret_cast<uint32_t*>(ws + P.midR);
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<LRf->Gmax, BS_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
+                                                                      LRf->bhi, LRf->Gcount(), nullptr, nullptr, midR,
+                                                                      ctr + 6, redoR, ctr + 4, soR);
+    LAUNCH_CHECK();
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
+                                                                      LRf->bhi, LRf->Gcount(), midR, ctr + 6, bigR,
+                                                                      ctr + 1, redoR, ctr + 4, soR);
     LAUNCH_CHECK();
     // buckets the sort gave up on get a second pass over their own key range
     // (splitter bounds can enclose a gap between key clusters); the rest go
@@ -850,7 +858,7 @@ struct BatchPlan {
   uint64_t cntS, cntR, ocap, item_cap;
   // workspace offsets
   uint64_t T, U, Rp, Rs, cS, cR, bsum, segS, segR, srcS, srcR, splS, splR, bstS, bstR, bndS, bndR;
-  uint64_t bigS, midS, redoS, redoR, redoR2, bigR, ctr, bkey, Pc, pstart, plen, pkey, pjoin, ridx, o, items, item_pre;
+  uint64_t bigS, midS, redoS, midR, redoR, redoR2, bigR, ctr, bkey, Pc, pstart, plen, pkey, pjoin, ridx, o, items, item_pre;
   uint64_t J, tstart, ototal, span;
   uint64_t tab_off, tab_bytes;           // host-written tables: one contiguous range
   uint64_t total;
@@ -932,6 +940,7 @@ bool make_batch_plan(const mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH,
   P->bigS = take((uint64_t)P->Gs * 4);
   P->midS = take((uint64_t)P->Gs * 4);
   P->redoS = take((uint64_t)P->Gs * 4);
+  P->midR = take((uint64_t)P->Gr * 4);
   P->redoR = take((uint64_t)P->Gr * 4);
   P->redoR2 = take((uint64_t)P->Gr * 4);
   P->bigR = take((uint64_t)P->Gr * 4);
@@ -1060,11 +1069,17 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     soR.idx_per_run = 0;
     soR.NB = 1;
     soR.bkey = reinterpret_cast<uint64_t*>(ws + P.bkey);
+    uint32_t* midR = reinterpret_cast<uint32_t*>(ws + P.midR);
     uint32_t* redoR = reinterpret_cast<uint32_t*>(ws + P.redoR);
     uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
     uint32_t* bigR = reinterpret_cast<uint32_t*>(ws + P.bigR);
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<P.Gr, BL_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(),
-                                                                 nullptr, nullptr, bigR, ctr + 1, redoR, ctr + 4, soR);
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gr, BS_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi,
+                                                                 LR.Gcount(), nullptr, nullptr, midR, ctr + 6, redoR,
+                                                                 ctr + 4, soR);
+    LAUNCH_CHECK();
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi,
+                                                                 LR.Gcount(), midR, ctr + 6, bigR, ctr + 1, redoR,
+                                                                 ctr + 4, soR);
     LAUNCH_CHECK();
     k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(),
                                                                  redoR, ctr + 4, bigR, ctr + 1, redoR2, ctr + 5, soR);
