@@ -41,6 +41,7 @@ constexpr int SCAT_NT = 1024;
 constexpr int SCAT_IPT = 8;
 constexpr int SCAT_CH = SCAT_NT * SCAT_IPT;  // tuples staged in LDS per chunk
 constexpr int MAX_NB = 1024;                 // buckets per segment
+constexpr uint32_t S_BUCKET_MEAN = 2400;   // mean tuples per S-run bucket
 constexpr int SPLIT_DIR = 2048;              // cells of the splitter directory
 
 constexpr int JOIN_NT = 1024;

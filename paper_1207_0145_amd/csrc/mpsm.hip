@@ -86,7 +86,13 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->want_max = cfg->want_max ? 1 : 0;
   P->seed = cfg->seed;
   const uint32_t BT = cfg->bucket_target ? cfg->bucket_target : 4096u;   // R partitions
-  const uint32_t BTs = BT < 2048u ? BT : 2048u;                           // S buckets
+  // S buckets: a mean of 2400 tuples (any count works: buckets are cut by
+  // splitters, not by key bits).  Buckets up to 1.7x the mean fit the
+  // two-per-CU sort's 4096-tuple tile.  A key that matches one splitter only
+  // (under two buckets' worth of copies) stays in its bucket, which can then
+  // hold about three means: 3 x 2400 leaves room below the 8192-tuple tile,
+  // where 3 x 2730 already let Zipf-distributed keys overflow it.
+  const uint32_t BTs = BT < S_BUCKET_MEAN ? BT : S_BUCKET_MEAN;
   // S runs
   uint64_t L;
   if (cfg->log2_run_len) L = 1ull << cfg->log2_run_len;
@@ -98,7 +104,7 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->L = (uint32_t)L;
   P->Q = P->nS ? (uint32_t)cdiv(P->nS, L) : 1;
   if (P->Q > (uint32_t)JOIN_QMAX) return false;
-  P->NBs = next_pow2(cdiv(L, BTs));
+  P->NBs = (uint32_t)cdiv(L, BTs);
   if (P->NBs > (uint32_t)MAX_NB) P->NBs = MAX_NB;
   const uint32_t OSreq = cfg->oversample ? cfg->oversample : 32u;
   auto os_for = [&](uint32_t NB) { return NB > 1 ? (SMP_CAP / NB < OSreq ? SMP_CAP / NB : OSreq) : 1u; };
@@ -881,8 +887,8 @@ bool make_batch_plan(const mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH,
   P->n = (uint32_t)b->d.size();
   P->L = L; P->BT = BT; P->JCH = JCH;
   if (!batch_tuning_valid(L, BT, JCH)) return false;
-  const uint32_t BTs = BT < 2048u ? BT : 2048u;
-  P->NBs = next_pow2(cdiv(L, BTs));
+  const uint32_t BTs = BT < S_BUCKET_MEAN ? BT : S_BUCKET_MEAN;
+  P->NBs = (uint32_t)cdiv(L, BTs);
   if (P->NBs > (uint32_t)MAX_NB) P->NBs = MAX_NB;
   const uint32_t OSreq = b->cfg.oversample ? b->cfg.oversample : 32u;
   auto os_for = [&](uint32_t NB) { return NB > 1 ? (SMP_CAP / NB < OSreq ? SMP_CAP / NB : OSreq) : 1u; };
