@@ -73,7 +73,9 @@ STEP_DISPATCH = {
     "s_histogram": ("k_bucket_hist", 0), "s_scatter": ("k_bucket_scatter", 0),
     "r1_histogram": ("k_bucket_hist", 1), "r1_scatter": ("k_bucket_scatter", 1),
     "r2_histogram": ("k_bucket_hist", 2), "r2_scatter": ("k_bucket_scatter", 2),
-    "s_bucket_sort": ("void k_bucket_sort_cs<1024, 4", 0), "r_bucket_sort": ("void k_bucket_sort_cs<1024, 4", 1),
+    # the sorts: the two-per-CU kernel, then the one-per-CU kernel over the larger buckets
+    "s_bucket_sort": [("void k_bucket_sort_cs<1024, 4", 0), ("void k_bucket_sort_cs<1024, 8", 0)],
+    "r_bucket_sort": [("void k_bucket_sort_cs<1024, 4", 1), ("void k_bucket_sort_cs<1024, 8", 1)],
     "search": ("k_search", 0), "join": ("void k_join<0", 0),
 }
 
@@ -115,18 +117,24 @@ def summarize_profiles(kt_csv, fetch_csv, write_csv, workload, nR, nS, command):
         cal[label] = {"copy_kib": float(big["Counter_Value"]), "factor": (1 << 30) / (1024.0 * float(big["Counter_Value"]))}
         cal[label]["joins"] = _per_join(rows, "Kernel_Name", "Start_Timestamp")
     steps = {}
-    for step, (prefix, k) in STEP_DISPATCH.items():
-        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
-                for j in kt for r in [_nth(j, prefix, k)] if r is not None]
-        f = _nth(cal["fetch"]["joins"][0], prefix, k)
-        w = _nth(cal["write"]["joins"][0], prefix, k)
-        if not durs or f is None or w is None:
+    for step, spec in STEP_DISPATCH.items():
+        picks = spec if isinstance(spec, list) else [spec]   # a step may span several dispatches
+        durs = []
+        for j in kt:
+            rows = [_nth(j, prefix, k) for prefix, k in picks]
+            if all(r is not None for r in rows):
+                durs.append(sum((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in rows))
+        fs = [_nth(cal["fetch"]["joins"][0], prefix, k) for prefix, k in picks]
+        ws = [_nth(cal["write"]["joins"][0], prefix, k) for prefix, k in picks]
+        if not durs or any(r is None for r in fs + ws):
             continue
-        fb = float(f["Counter_Value"]) * 1024 * cal["fetch"]["factor"]
-        wb = float(w["Counter_Value"]) * 1024 * cal["write"]["factor"]
+        fb = sum(float(f["Counter_Value"]) for f in fs) * 1024 * cal["fetch"]["factor"]
+        wb = sum(float(w["Counter_Value"]) for w in ws) * 1024 * cal["write"]["factor"]
         rel, per = STEP_BYTES.get(step, ("RS", 0))
         alg = per * {"S": nS, "R": nR, "RS": nR + nS}[rel]
-        steps[step] = {"kernel": f["Kernel_Name"][:80], "avg_launch_ms": round(sum(durs) / len(durs), 4),
+        f = fs[0]
+        steps[step] = {"kernel": " + ".join(r["Kernel_Name"].split("(")[0][:60] for r in fs),
+                       "avg_launch_ms": round(sum(durs) / len(durs), 4),
                        "launches": len(durs), "fetch_bytes": round(fb), "write_bytes": round(wb),
                        "hbm_bytes_per_launch": round(fb + wb), "algorithmic_bytes": alg or None,
                        "traffic_over_algorithmic": round((fb + wb) / alg, 3) if alg else None}
