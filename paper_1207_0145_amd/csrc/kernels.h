@@ -95,37 +95,38 @@ __global__ void k_finalize(const Result* res, uint64_t* out_count, uint64_t* out
   }
 }
 
-// Runs of equal length L over [0, n): segment tables.
-__global__ void k_seg_uniform(uint32_t n, uint32_t L, uint32_t nseg, uint32_t* seg_start, uint32_t* seg_len) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
-  const uint64_t a = (uint64_t)s * L;
-  seg_start[s] = (uint32_t)a;
-  seg_len[s] = (uint32_t)((a + L <= n) ? L : (n > a ? n - a : 0));
-}
-
-// Segments = the buckets of a previous pass (bstart has nseg+1 entries).
-__global__ void k_seg_from_buckets(const uint32_t* bstart, uint32_t nseg, uint32_t* seg_start, uint32_t* seg_len) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nseg) return;
-  seg_start[s] = bstart[s];
-  seg_len[s] = bstart[s + 1] - bstart[s];
-}
-
-// Per-segment plan: tiles, bucket count and their prefixes.
+// Per-segment plan: tiles, bucket count and their prefixes.  The segments
+// are runs of run_len tuples over [0, n) (run_len != 0), or the buckets of
+// a previous pass (src_bstart, nseg + 1 entries), both written here, or
+// already in seg_start / seg_len.
 //   seg_nb[s]    buckets of segment s: NBmax, or (BT != 0) ceil(len/BT)
 //                clamped to [1, NBmax], so buckets average at most BT tuples
 //   seg_tile0    prefix of tile counts (nseg + 1 entries)
 //   seg_cnt0     prefix of seg_nb * tiles (count-matrix offsets)
 //   seg_b0       prefix of seg_nb (global bucket ids)
 __global__ void __launch_bounds__(1024) k_seg_plan(uint32_t nseg, uint32_t NBmax, uint32_t BT, uint32_t TILE,
-                                                   const uint32_t* seg_len, uint32_t* seg_tile0, uint32_t* seg_cnt0,
-                                                   uint32_t* seg_nb, uint32_t* seg_b0) {
+                                                   uint32_t n, uint32_t run_len, const uint32_t* src_bstart,
+                                                   uint32_t* seg_start, uint32_t* seg_len, uint32_t* seg_tile0,
+                                                   uint32_t* seg_cnt0, uint32_t* seg_nb, uint32_t* seg_b0) {
   __shared__ uint32_t wsum[3][1024 / 64 + 2];
   uint32_t c1 = 0, c2 = 0, c3 = 0;
   for (uint32_t b = 0; b < nseg; b += 1024) {
     const uint32_t s = b + threadIdx.x;
-    const uint32_t len = s < nseg ? seg_len[s] : 0;
+    uint32_t len = 0;
+    if (s < nseg) {
+      if (run_len) {
+        const uint64_t a = (uint64_t)s * run_len;
+        len = (uint32_t)(a + run_len <= n ? run_len : (n > a ? n - a : 0));
+        seg_start[s] = (uint32_t)a;
+        seg_len[s] = len;
+      } else if (src_bstart) {
+        len = src_bstart[s + 1] - src_bstart[s];
+        seg_start[s] = src_bstart[s];
+        seg_len[s] = len;
+      } else {
+        len = seg_len[s];
+      }
+    }
     const uint32_t nt = (len + TILE - 1) / TILE;
     uint32_t nb = 0;
     if (s < nseg) {
@@ -158,24 +159,17 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_reduce(const uint32_t* in, uin
   if (threadIdx.x == 0) bsum[blockIdx.x] = (uint32_t)s;
 }
 
-__global__ void __launch_bounds__(1024) k_scan_bsums(uint32_t* bsum, uint32_t nb) {
-  __shared__ uint32_t wsum[1024 / 64 + 2];
-  uint32_t carry = 0;
-  for (uint32_t b = 0; b < nb; b += 1024) {
-    const uint32_t i = b + threadIdx.x;
-    const uint32_t v = i < nb ? bsum[i] : 0;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<1024>(v, wsum, &tot);
-    if (i < nb) bsum[i] = carry + ex;
-    carry += tot;
-    __syncthreads();
-  }
-}
-
-// Exclusive scan of one SCAN_BLOCK-sized block, offset by the block prefix.
+// Exclusive scan of one SCAN_BLOCK-sized block, offset by the block prefix:
+// the sum of the totals (from k_scan_reduce) of the blocks before it, which
+// every block adds up itself (a few thousand blocks at most, so this costs
+// less than a launch that scans the totals).
 __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const uint32_t* in, uint32_t* out, uint32_t n,
                                                         const uint32_t* bsum) {
   __shared__ uint32_t wsum[SCAN_NT / 64 + 2];
+  __shared__ uint64_t red[SCAN_NT / 64 + 1];
+  uint64_t pre = 0;
+  for (uint32_t i = threadIdx.x; i < blockIdx.x; i += SCAN_NT) pre += bsum[i];
+  pre = block_sum64<SCAN_NT>(pre, red);
   const uint32_t base = blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_IPT;
   uint32_t v[SCAN_IPT];
   uint32_t run = 0;
@@ -188,7 +182,7 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const uint32_t* in, uint
     run += x;
   }
   uint32_t tot;
-  const uint32_t ex = block_excl_scan<SCAN_NT>(run, wsum, &tot) + bsum[blockIdx.x];
+  const uint32_t ex = block_excl_scan<SCAN_NT>(run, wsum, &tot) + (uint32_t)pre;
 #pragma unroll
   for (int k = 0; k < SCAN_IPT; k++) {
     const uint32_t i = base + k;

@@ -226,8 +226,6 @@ mpsm_status scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* bs
   const uint32_t nb = (uint32_t)cdiv(n, SCAN_BLOCK);
   k_scan_reduce<<<nb, SCAN_NT, 0, st>>>(in, (uint32_t)n, bsum);
   LAUNCH_CHECK();
-  k_scan_bsums<<<1, 1024, 0, st>>>(bsum, nb);
-  LAUNCH_CHECK();
   k_scan_apply<<<nb, SCAN_NT, 0, st>>>(in, out, (uint32_t)n, bsum);
   LAUNCH_CHECK();
   return MPSM_OK;
@@ -273,6 +271,10 @@ struct Level {
   uint32_t outer_nspl;
   const CdfModel* model;     // learned splitters from this model, or NULL
   const struct CostArgs* cost;  // cost-balanced splitters (one segment), or NULL
+  // where the segment table comes from (see k_seg_plan): runs of run_len
+  // tuples, the buckets of a previous level, or filled in beforehand
+  uint32_t run_len = 0;
+  const uint32_t* src_bstart = nullptr;
   const uint32_t* Gcount() const { return seg.b0 + nseg; }
 };
 
@@ -313,7 +315,8 @@ struct CostArgs {
 mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L, uint32_t* bsum, hipStream_t st,
                         Marker& mk, uint32_t mk0, const tup_t* const* seg_src = nullptr) {
   const Seg& sg = L.seg;
-  k_seg_plan<<<1, 1024, 0, st>>>(L.nseg, L.NBmax, L.BT, HIST_TILE, sg.len, sg.tile0, sg.cnt0, sg.nb, sg.b0);
+  k_seg_plan<<<1, 1024, 0, st>>>(L.nseg, L.NBmax, L.BT, HIST_TILE, n, L.run_len, L.src_bstart, sg.start, sg.len,
+                                 sg.tile0, sg.cnt0, sg.nb, sg.b0);
   LAUNCH_CHECK();
   if (L.NBmax > 1 && L.cost) {
     // the whole sorted sample, the S distribution at its keys, the min-max split
@@ -571,8 +574,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     // ---- phase 1: sort S into Q runs of L tuples
     Level LS = make_level(ws, P.segS, P.Q, P.NBs, 0, P.OSs, P.tilesS, P.seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
                           P.bndS, P.Gs);
-    k_seg_uniform<<<(uint32_t)cdiv(P.Q, 256), 256, 0, st>>>((uint32_t)P.nS, P.L, P.Q, LS.seg.start, LS.seg.len);
-    LAUNCH_CHECK();
+    LS.run_len = P.L;
     rc = bucket_pass(Sin, T, (uint32_t)P.nS, LS, bsum, st, mk, MK_S_SPL);
     if (rc != MPSM_OK) return rc;
     rc = start_models();
@@ -621,8 +623,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       LR1.cost = &cost_args;
     }
     if (side) HIP_TRY(hipStreamWaitEvent(st, side->done, 0));   // the models are needed from here on
-    k_seg_uniform<<<1, 64, 0, st>>>((uint32_t)P.nR, (uint32_t)P.nR, 1, LR1.seg.start, LR1.seg.len);
-    LAUNCH_CHECK();
+    LR1.run_len = (uint32_t)P.nR;   // one segment: all of R
     rc = bucket_pass(Rin, R1, (uint32_t)P.nR, LR1, bsum, st, mk, MK_R1_SPL);
     if (rc != MPSM_OK) return rc;
     SortOut soR;
@@ -646,9 +647,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       LR2.outer = LR1.spl;
       LR2.outer_nspl = P.NB1 - 1;
       // the second level stays sampled: its buckets are finer than the model's knots
-      k_seg_from_buckets<<<(uint32_t)cdiv(P.NB1, 256), 256, 0, st>>>(LR1.bstart, P.NB1, LR2.seg.start,
-                                                                     LR2.seg.len);
-      LAUNCH_CHECK();
+      LR2.src_bstart = LR1.bstart;   // segments: the level-1 buckets
       rc = bucket_pass(R1, R2, (uint32_t)P.nR, LR2, bsum, st, mk, MK_R2_SPL);
       if (rc != MPSM_OK) return rc;
       LRf = &LR2;
