@@ -51,6 +51,7 @@ def lib():
             "orc_sort_runs": ([p, u64, u64, p], i32),
             "orc_radix_partition": ([p, u64, u64, i32, i32, p, u32, p, p, p, p], i32),
             "orc_sample_splitters": ([p, u64, u32, u32, u64, p], i32),
+            "orc_splitters_from_sample": ([p, u64, u32, u32, p], None),
             "orc_bucket_of": ([p, u32, u64], u32),
             "orc_bucket_partition": ([p, u64, p, u32, p, p], i32),
             "orc_lower_bound": ([p, u64, u64], u64),
@@ -180,6 +181,17 @@ def sample_splitters(T, nbucket: int, oversample: int, seed: int) -> np.ndarray:
     T = _tuples(T)
     spl = np.zeros(max(nbucket - 1, 1), np.uint64)
     _check(lib().orc_sample_splitters(_p(T), len(T), nbucket, oversample, seed, _p(spl)), "sample_splitters")
+    return spl[: max(nbucket - 1, 0)]
+
+
+def splitters_from_sample(sorted_sample, nbucket: int, oversample: int) -> np.ndarray:
+    """Splitters from a sorted sample of nbucket * oversample keys (the rule
+    of orc_splitters_from_sample: every oversample-th key, with frequent keys
+    of a single splitter given a bucket of their own)."""
+    smp = np.ascontiguousarray(sorted_sample, dtype=np.uint64)
+    assert len(smp) == nbucket * oversample
+    spl = np.zeros(max(nbucket - 1, 1), np.uint64)
+    lib().orc_splitters_from_sample(_p(smp), len(smp), nbucket, oversample, _p(spl))
     return spl[: max(nbucket - 1, 0)]
 
 

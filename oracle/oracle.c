@@ -276,19 +276,51 @@ int orc_radix_partition(const uint64_t* C, uint64_t n, uint64_t chunk_len, int B
  * SplitMix64 stream `seed`: pos_t = floor(x_t * len / 2^64); the sampled keys
  * are sorted and splitter m' (m' = 1..nbucket-1) is sorted[m' * oversample].
  * Writes nbucket-1 splitters to spl (non-decreasing). */
+/* Splitters from a sorted sample of m = nbucket * oversample keys: splitter
+ * j (0 <= j < nbucket-1) is the sample key at rank (j+1)*oversample, except
+ * that a key which is the only splitter equal to it and which also fills the
+ * sample oversample/2 ranks before or after that rank (so about half a
+ * bucket's worth of the input or more) gets a bucket of its own: the next
+ * splitter becomes key + 1, provided that is below it.  A moved splitter no
+ * longer carries its own key, so along a run of such splitters every other
+ * one moves (the first, the third, ...).  With the bucket function below,
+ * keys of at least two splitters were isolated already; this isolates the
+ * keys of one, so that no bucket holds a frequent key plus a full bucket of
+ * other keys. */
+void orc_splitters_from_sample(const uint64_t* smp, uint64_t m, uint32_t nbucket, uint32_t oversample,
+                               uint64_t* spl) {
+  const uint64_t h = oversample / 2;
+  int moved_prev = 0;   /* splitter j-1 moved splitter j */
+  for (uint32_t j = 0; j + 1 < nbucket; j++) {
+    const uint64_t pos = (uint64_t)(j + 1) * oversample, c = smp[pos];
+    spl[j] = moved_prev ? smp[pos - oversample] + 1 : c;
+    int moves = 0;
+    if (h && !moved_prev && j + 2 < nbucket) {
+      const uint64_t next = smp[pos + oversample];
+      const int prev_same = j > 0 && smp[pos - oversample] == c;
+      if (!prev_same && next - c > 1)   /* next >= c: no wrap-around */
+        moves = (pos >= h && smp[pos - h] == c) || (pos + h < m && smp[pos + h] == c);
+    }
+    moved_prev = moves;
+  }
+}
+
 int orc_sample_splitters(const uint64_t* T, uint64_t len, uint32_t nbucket, uint32_t oversample, uint64_t seed,
                          uint64_t* spl) {
   if (nbucket < 2) return 0;
   uint64_t m = (uint64_t)nbucket * oversample;
   uint64_t* smp = (uint64_t*)malloc(2 * m * sizeof(uint64_t));
-  if (!smp) return -1;
+  uint64_t* keys = (uint64_t*)malloc(m * sizeof(uint64_t));
+  if (!smp || !keys) { free(smp); free(keys); return -1; }
   for (uint64_t t = 0; t < m; t++) {
     uint64_t pos = (uint64_t)(((unsigned __int128)orc_splitmix_at(seed, t) * len) >> 64);
     smp[2 * t] = T[2 * pos]; smp[2 * t + 1] = 0;
   }
   orc_sort_by_key(smp, m);
-  for (uint32_t b = 1; b < nbucket; b++) spl[b - 1] = smp[2 * ((uint64_t)b * oversample)];
+  for (uint64_t t = 0; t < m; t++) keys[t] = smp[2 * t];
+  orc_splitters_from_sample(keys, m, nbucket, oversample, spl);
   free(smp);
+  free(keys);
   return 0;
 }
 

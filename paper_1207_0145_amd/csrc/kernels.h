@@ -195,7 +195,11 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const uint32_t* in, uint
 // One workgroup per segment: draw nb*OS keys at uniform positions of the
 // segment (SplitMix64 stream seg_seed = splitmix_at(level_seed, s)), sort
 // them, and keep every OS-th as the nb-1 splitters of the segment
-// (nb = seg_nb[s]; splitters of segment s start at s*(NBmax-1)).
+// (nb = seg_nb[s]; splitters of segment s start at s*(NBmax-1)).  A key that
+// is the only splitter equal to it but also fills the sample OS/2 ranks
+// before or after its rank gets a bucket of its own: the next splitter
+// becomes key + 1 when that is below it; along a run of such splitters
+// every other one moves (a moved splitter no longer carries its key).
 template <int NT, int IPT>
 __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict__ src, const uint32_t* seg_start,
                                                          const uint32_t* seg_len, const uint32_t* seg_nb,
@@ -226,11 +230,31 @@ __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict
     dummy[k] = 0;
   }
   Sorter::template sort<false>(key, dummy, (int)M, buf, wsum, red);
+  __syncthreads();   // the sort's exchange buffer now holds the sorted sample
 #pragma unroll
   for (int k = 0; k < IPT; k++) {
     const uint32_t r = k * NT + tid;
-    if (r > 0 && r < M && r % OS == 0) out[r / OS - 1] = key[k];
+    if (r < M) buf[r] = key[k];
     if (full && r < M) full[r] = key[k];   // the whole sorted sample (one segment)
+  }
+  uint8_t* const moves = reinterpret_cast<uint8_t*>(buf + Sorter::CAP);   // nb - 1 flags
+  __syncthreads();
+  const uint32_t h = OS / 2;
+  for (uint32_t j = tid; j + 1 < nb; j += NT) {
+    const uint32_t pos = (j + 1) * OS;
+    const uint64_t c = buf[pos];
+    bool f = false;
+    if (h && j + 2 < nb && !(j > 0 && buf[pos - OS] == c) && buf[pos + OS] - c > 1)
+      f = (pos >= h && buf[pos - h] == c) || (pos + h < M && buf[pos + h] == c);
+    moves[j] = f;
+  }
+  __syncthreads();
+  for (uint32_t j = tid; j + 1 < nb; j += NT) {
+    // splitter j-1 moved this one if it starts a run of candidates of odd length
+    uint32_t t = 0;
+    while (t < j && moves[j - 1 - t]) t++;
+    const uint32_t pos = (j + 1) * OS;
+    out[j] = (t & 1) ? buf[pos - OS] + 1 : buf[pos];
   }
 }
 

@@ -337,11 +337,15 @@ def _ws_view(ws, off, n, dtype):
     return b.view(dtype)
 
 
-@pytest.mark.parametrize("nR,nS,bt", [(1 << 17, 1 << 19, 1024), (1 << 19, 1 << 20, 256)])
-def test_intermediate_results(nR, nS, bt):
+@pytest.mark.parametrize("nR,nS,bt,skew", [(1 << 17, 1 << 19, 1024, False), (1 << 19, 1 << 20, 256, False),
+                                          (1 << 17, 1 << 19, 4096, True)])
+def test_intermediate_results(nR, nS, bt, skew):
     rng = np.random.default_rng(nR + bt)
     R = rel(rng, nR, 1 << 24)
     S = rel(rng, nS, 1 << 24)
+    if skew:   # S keys with a heavy head: frequent keys of one splitter get their own bucket
+        base = np.unique(R[:, 0])
+        S[:, 0] = base[(len(base) * rng.random(nS) ** 4).astype(np.int64)]
     cfg = mpsm.config(bucket_target=bt, log2_run_len=17)
     lay = mpsm.layout(nR, nS, cfg)
     ws = mpsm.alloc_workspace(nR, nS, cfg)
@@ -365,6 +369,8 @@ def test_intermediate_results(nR, nS, bt):
         seed = oracle.splitmix_at(lay["s_level_seed"], j)
         a, b = j * L, min((j + 1) * L, nS)
         assert np.array_equal(spl[j], oracle.sample_splitters(S[a:b], NB, lay["s_oversample"], seed))
+    if skew:   # the rule has fired: some splitter is its predecessor + 1
+        assert np.count_nonzero(spl[:, 1:] == spl[:, :-1] + np.uint64(1)) > 0
     # S bucket boundaries = a stable bucket partition of each run under those splitters
     bst = _ws_view(ws, lay["off_s_bucket_start"], Q * NB + 1, np.uint32)
     for j in range(Q):

@@ -243,6 +243,53 @@ def test_sample_splitters_against_numpy():
     assert spl.tolist() == [int(smp[b * os_]) for b in range(1, nb)]
 
 
+def test_splitters_from_sample_isolate_frequent_single_splitter_keys():
+    # oversample 4: splitters at ranks 4, 8, 12, 16 of 20 sorted keys
+    smp = [1, 2, 3, 4, 5, 5, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18]
+    # 5 sits at rank 4 and again at rank 4 + 2: the next splitter 7 becomes 6
+    assert oracle.splitters_from_sample(smp, 5, 4).tolist() == [5, 6, 11, 15]
+    # no key repeated: every fourth key
+    plain = list(range(1, 21))
+    assert oracle.splitters_from_sample(plain, 5, 4).tolist() == [5, 9, 13, 17]
+    # 5 also at rank 8: two splitters equal, already isolated by bucket_of, unchanged
+    two = [1, 2, 3, 4, 5, 5, 5, 5, 5, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18]
+    assert oracle.splitters_from_sample(two, 5, 4).tolist() == [5, 5, 11, 15]
+    # the next splitter already key + 1: nothing to move
+    adj = [1, 2, 3, 4, 5, 5, 5, 6, 6, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18]
+    assert oracle.splitters_from_sample(adj, 5, 4).tolist() == [5, 6, 11, 15]
+    # a run of frequent single-splitter keys (5, 7, 9 at ranks 4, 8, 12): the
+    # first and third move their successor; 7 loses its splitter to 5 + 1
+    run = [1, 2, 3, 4, 5, 5, 5, 6, 7, 7, 7, 8, 9, 9, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18]
+    assert oracle.splitters_from_sample(run, 6, 4).tolist() == [5, 6, 9, 10, 15]
+    # the largest key: no key + 1 above it
+    top = [1, 2, 3, 4, 5, 6, 7, 8, 2**64 - 1, 2**64 - 1, 2**64 - 1, 2**64 - 1] + [2**64 - 1] * 8
+    assert oracle.splitters_from_sample(top, 5, 4).tolist() == [5, 2**64 - 1, 2**64 - 1, 2**64 - 1]
+    # the last splitter has no successor to move
+    last = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 17, 17, 18]
+    assert oracle.splitters_from_sample(last, 5, 4).tolist() == [5, 9, 13, 17]
+
+
+def test_splitters_from_sample_bound_bucket_sizes():
+    # every bucket of the sample holds a frequent key alone or at most about
+    # two oversample stretches of keys (brute force over random skewed samples)
+    rng = np.random.default_rng(21)
+    for trial in range(200):
+        nb, os_ = int(rng.integers(2, 40)), int(rng.integers(2, 24))
+        heavy = rng.integers(0, 1000, 5)
+        keys = np.where(rng.random(nb * os_) < 0.5, rng.choice(heavy, nb * os_),
+                        rng.integers(0, 1000, nb * os_)).astype(np.uint64)
+        smp = np.sort(keys)
+        spl = oracle.splitters_from_sample(smp, nb, os_)
+        assert np.all(spl[1:] >= spl[:-1])
+        b = np.array([oracle.bucket_of(spl, nb, int(k)) for k in smp])
+        assert np.all(b[1:] >= b[:-1])
+        for q in range(nb):
+            ks = smp[b == q]
+            if len(ks) and ks.min() != ks.max():
+                # a bucket of mixed keys: at most two stretches plus a trailing run
+                assert len(ks) <= 2 * os_ + os_ // 2 + 1, (trial, q, len(ks), os_)
+
+
 def test_bucket_of_monotone_and_isolates_frequent_keys():
     spl = np.array([10, 20, 20, 20, 30, 40, 40], np.uint64)
     nb = len(spl) + 1
