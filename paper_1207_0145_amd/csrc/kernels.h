@@ -1093,17 +1093,22 @@ __global__ void __launch_bounds__(LSD_NT) k_bucket_sort_lsd(const tup_t* __restr
 }
 
 // Oversize buckets: one workgroup sorts a whole bucket through global memory
-// with stable 4-bit LSD passes, ping-ponging between src and dst ranges.
-constexpr int BIG_NT = 256;
+// with stable 4-bit LSD passes (only over the nibbles in which the bucket's
+// keys differ), ping-ponging between src and dst ranges.  Each pass counts
+// the digits of the whole bucket, then ranks chunks of 8192 tuples in LDS
+// (each thread holds 8 consecutive tuples, which keeps the ranks stable)
+// and writes every tuple to its digit's cursor.
+constexpr int BIG_NT = 1024, BIG_IPT = 8;
 __global__ void __launch_bounds__(BIG_NT) k_big_sort(tup_t* __restrict__ src, tup_t* __restrict__ dst,
                                                      const uint32_t* bstart, const uint32_t* big_list,
                                                      const unsigned long long* big_count, SortOut so) {
-  using R1 = BlockSort<BIG_NT, 1, 4>;
-  __shared__ uint64_t buf[R1::BUF_WORDS];
-  __shared__ uint32_t wsum[R1::WSUM_WORDS];
+  using RS = BlockSort<BIG_NT, BIG_IPT, 4>;
+  constexpr uint32_t CH = BIG_NT * BIG_IPT;
+  __shared__ uint64_t buf[RS::BUF_WORDS];
+  __shared__ uint32_t wsum[RS::WSUM_WORDS];
   __shared__ uint64_t red[BIG_NT / 64 + 1];
-  __shared__ uint32_t cur[16], ccnt[16], cpre[16];
-  const uint32_t tid = threadIdx.x;
+  __shared__ uint32_t cur[16], ccnt[16], cpre[17];
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t nbig = (uint32_t)*big_count;
   for (uint32_t e = blockIdx.x; e < nbig; e += gridDim.x) {
     const uint32_t g = big_list[e];
@@ -1111,41 +1116,55 @@ __global__ void __launch_bounds__(BIG_NT) k_big_sort(tup_t* __restrict__ src, tu
     const uint64_t k0 = src[a].key;
     uint64_t vary = 0;
     for (uint32_t i = tid; i < n; i += BIG_NT) vary |= src[a + i].key ^ k0;
-    vary = R1::block_or(vary, red);
+    vary = RS::block_or(vary, red);
     tup_t* from = src + a;
     tup_t* to = dst + a;
     for (int sh = 0; sh < 64; sh += 4) {
       if (((vary >> sh) & 15ull) == 0) continue;
-      // global digit histogram
+      // digit counts of the whole bucket: 16-bit fields per thread, then wave sums
+      uint64_t hw[4] = {0, 0, 0, 0};
+      for (uint32_t i = tid; i < n; i += BIG_NT) {
+        const uint32_t d = (uint32_t)(from[i].key >> sh) & 15u;
+        const uint64_t inc = 1ull << (16 * (d & 3));
+#pragma unroll
+        for (int q = 0; q < 4; q++) hw[q] += (d >> 2) == (uint32_t)q ? inc : 0ull;
+      }
       if (tid < 16) ccnt[tid] = 0;
       __syncthreads();
-      for (uint32_t i = tid; i < n; i += BIG_NT) atomicAdd(&ccnt[(uint32_t)(from[i].key >> sh) & 15u], 1u);
+#pragma unroll
+      for (int d = 0; d < 16; d++) {
+        uint32_t c = (uint32_t)(hw[d >> 2] >> (16 * (d & 3))) & 0xFFFFu;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, 64);
+        if (lane == 0 && c) atomicAdd(&ccnt[d], c);
+      }
       __syncthreads();
       if (tid == 0) {
         uint32_t run = 0;
         for (int d = 0; d < 16; d++) { cur[d] = run; run += ccnt[d]; }
       }
       __syncthreads();
-      for (uint32_t c0 = 0; c0 < n; c0 += BIG_NT) {
-        const uint32_t i = c0 + tid;
-        const bool ok = i < n;
-        tup_t v;
-        v.key = ~0ull; v.pay = 0;
-        if (ok) v = from[i];
-        uint32_t d[1], r[1];
-        d[0] = ok ? (uint32_t)(v.key >> sh) & 15u : 15u;
-        if (tid < 16) ccnt[tid] = 0;
-        __syncthreads();
-        if (ok) atomicAdd(&ccnt[d[0]], 1u);
-        R1::rank(d, r, buf, wsum);   // stable rank of this chunk, digit-major
-        if (tid == 0) {
-          uint32_t run = 0;
-          for (int q = 0; q < 16; q++) { cpre[q] = run; run += ccnt[q]; }
+      for (uint32_t c0 = 0; c0 < n; c0 += CH) {
+        const uint32_t nv = n - c0 < CH ? n - c0 : CH;   // tuples of this chunk
+        tup_t v[BIG_IPT];
+        uint32_t d[BIG_IPT], r[BIG_IPT];
+#pragma unroll
+        for (int k = 0; k < BIG_IPT; k++) {
+          const uint32_t i = tid * BIG_IPT + k;
+          v[k].key = ~0ull; v[k].pay = 0;
+          if (i < nv) v[k] = from[c0 + i];
+          d[k] = i < nv ? (uint32_t)(v[k].key >> sh) & 15u : 15u;   // past the end: last, after the valid 15s
         }
+        RS::rank(d, r, buf, wsum);   // stable rank in the chunk, digit-major
+        // the chunk's digit starts are the rank counters of thread 0
+        if (tid < 16) cpre[tid] = reinterpret_cast<const uint16_t*>(buf)[tid * BIG_NT];
+        if (tid == 0) cpre[16] = nv;
         __syncthreads();
-        if (ok) to[cur[d[0]] + (r[0] - cpre[d[0]])] = v;
+#pragma unroll
+        for (int k = 0; k < BIG_IPT; k++)
+          if (tid * BIG_IPT + k < nv) to[cur[d[k]] + (r[k] - cpre[d[k]])] = v[k];
         __syncthreads();
-        if (tid < 16) cur[tid] += ccnt[tid];
+        if (tid < 16) cur[tid] += cpre[tid + 1] - cpre[tid];
         __syncthreads();
       }
       tup_t* t = from; from = to; to = t;

@@ -171,9 +171,23 @@ def test_oversize_bucket_fallback():
     S[: len(S) // 2, 0] = R[rng.integers(0, len(R), len(S) // 2), 0]
     cfg = mpsm.config(oversample=1, bucket_target=4096)
     want = oracle.join(R, S)
-    got = gpu_join(R, S, cfg, stats=True)
+    lay = mpsm.layout(len(R), len(S), cfg)
+    ws = mpsm.alloc_workspace(len(R), len(S), cfg)
+    got = gpu_join(R, S, cfg, workspace=ws, stats=True)
     assert (got["count"], got["checksum"]) == (want.count, want.checksum)
     assert got["stats"]["oversize_buckets"] > 0
+    torch.cuda.synchronize()
+    # the buckets sorted by the multi-pass sort are sorted like the rest
+    L = lay["run_len"]
+    Ssorted = _ws_view(ws, lay["off_s_sorted"], 2 * len(S), np.uint64).reshape(-1, 2)
+    ref = oracle.sort_runs(S, L)
+    assert np.array_equal(Ssorted[:, 0], ref[:, 0])
+    for j in range(lay["runs"]):
+        x, y = Ssorted[j * L:(j + 1) * L], ref[j * L:(j + 1) * L]
+        assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], y[np.lexsort((y[:, 1], y[:, 0]))])
+    Rsorted = _ws_view(ws, lay["off_r_sorted"], 2 * len(R), np.uint64).reshape(-1, 2)
+    assert np.array_equal(Rsorted[np.lexsort((Rsorted[:, 1], Rsorted[:, 0]))], R[np.lexsort((R[:, 1], R[:, 0]))])
+    assert np.array_equal(Rsorted[:, 0], np.sort(R[:, 0]))
 
 
 def test_few_distinct_keys_oversize_equal_buckets():
