@@ -104,6 +104,25 @@ def _nth(join, prefix, k):
     return hits[k] if k < len(hits) else None
 
 
+def step_times(names, evsets, steps):
+    """Average device time of every launch step from the join's markers.
+    R's partitioning and sort may run on a second stream beside S's run
+    generation: its first step then counts from the fork (cdf_models), and
+    the partition step from the later of the two phases' ends."""
+    ix = {n: i for i, n in enumerate(names)}
+
+    def el(a, b):
+        return sum(e.elapsed(ix[a], ix[b]) for e in evsets) / steps
+
+    out = {names[i]: el(names[i - 1], names[i]) for i in range(1, len(names))}
+    overlapped = el("s_oversize_sort", "r1_splitters") < 0
+    if overlapped:
+        out["r1_splitters"] = el("cdf_models", "r1_splitters")
+        last = "r_oversize_sort" if el("s_oversize_sort", "r_oversize_sort") > 0 else "s_oversize_sort"
+        out["partitions"] = el(last, "partitions")
+    return out, overlapped
+
+
 def summarize_profiles(kt_csv, fetch_csv, write_csv, workload, nR, nS, command):
     """HBM bytes and durations per launch step from a rocprofv3 kernel trace
     and two counter runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), scaled
@@ -207,7 +226,7 @@ def run_variant(mpsm, torch, R, S, out, cfg, args, names, nR, nS, label):
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / args.steps
-    steps_ms = {names[i]: sum(e.elapsed(i - 1, i) for e in evsets) / args.steps for i in range(1, len(names))}
+    steps_ms, _ = step_times(names, evsets, args.steps)
     for e in evsets:
         e.close()
     count, checksum = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
@@ -368,9 +387,7 @@ def main():
     log(f"timed {args.steps} steps: {ms:.3f} ms/step")
     count, checksum = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
 
-    steps_ms = {}
-    for i in range(1, len(names)):
-        steps_ms[names[i]] = sum(e.elapsed(i - 1, i) for e in evsets) / args.steps
+    steps_ms, overlapped = step_times(names, evsets, args.steps)
     for e in evsets:
         e.close()
 
@@ -402,7 +419,10 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes": step_bytes(dom),
                      "avg_launch_ms": round(steps_ms[dom], 4),
-                     "frac_of_measured_copy": round(achieved / copy_gbs, 4)},
+                     "frac_of_measured_copy": round(achieved / copy_gbs, 4),
+                     # the kernel's launch time includes sharing the GPU with
+                     # R's phase when that runs on the second stream
+                     "concurrent_with": "R partitioning and sort (second stream)" if overlapped and dom.startswith("s_") else None},
         "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_gbs, 1), "unit": "GB/s",
                           "frac": round(path_gbs / HBM_PEAK_GBS, 4),
                           "frac_of_measured_copy": round(path_gbs / copy_gbs, 4)},

@@ -45,7 +45,7 @@ struct Plan {
   uint64_t item_cap;                       // upper bound of join work items
   // workspace offsets (bytes)
   uint64_t T, U, R1, R2;
-  uint64_t cS, cR1, cR2, bsum;
+  uint64_t cS, cR1, cR2, bsum, bsumR;
   uint64_t segS, segR1, segR2;             // 4 arrays each: start, len, tile0, cnt0
   uint64_t splS, splR1, splR2;
   uint64_t bstS, bstR1, bstR2;
@@ -160,6 +160,7 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   if (P->cntR2 > maxscan) maxscan = P->cntR2;
   if (P->item_cap > maxscan) maxscan = P->item_cap;
   P->bsum = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);
+  P->bsumR = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);   // R's scans, which may run beside S's
   P->segS = take(6ull * (P->Q + 1) * 4);
   P->segR1 = take(6ull * 2 * 4);
   P->segR2 = take(6ull * (P->NB1 + 1) * 4);
@@ -543,8 +544,12 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
   // launches take never leaves the GPU waiting.
   const bool learn_r = P.splitter == MPSM_SPLIT_LEARNED && P.nR && P.nS;
   const bool learn_s = P.search == MPSM_SEARCH_LEARNED && P.nR && P.nS;
+  // R's partitioning and sort run on the side stream too, beside S's run
+  // generation (they are independent until the search), except with
+  // cost-balanced splitters, which need S's runs
+  const bool r_side = P.splitter != MPSM_SPLIT_COST && P.nR && P.nS;
   SideStream* side = nullptr;
-  if (learn_r || learn_s) {
+  if (learn_r || learn_s || r_side) {
     mpsm_status rs = side_stream(&side);
     if (rs != MPSM_OK) return rs;
     HIP_TRY(hipEventRecord(side->fork, st));
@@ -552,6 +557,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
   auto start_models = [&]() -> mpsm_status {
     if (!side) return MPSM_OK;
     HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0));
+    if (!learn_r && !learn_s) return MPSM_OK;
     CdfJob job;
     memset(&job, 0, sizeof(job));
     uint32_t nm = 0;
@@ -560,7 +566,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     mpsm_status rc = train_cdf(job, nm, reinterpret_cast<uint64_t*>(ws + P.cdf_chunks),
                                reinterpret_cast<uint64_t*>(ws + P.cdf_sorted), side->st);
     if (rc != MPSM_OK) return rc;
-    HIP_TRY(hipEventRecord(side->done, side->st));
+    if (!r_side) HIP_TRY(hipEventRecord(side->done, side->st));
     return MPSM_OK;
   };
   mk.mark(MK_CDF);
@@ -622,9 +628,14 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       cost_args.nR = P.nR;
       LR1.cost = &cost_args;
     }
-    if (side) HIP_TRY(hipStreamWaitEvent(st, side->done, 0));   // the models are needed from here on
+    // the models are needed from here on; R's phase runs on the side stream
+    // after them, or on this stream after S's
+    if (side && !r_side) HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
+    const hipStream_t rst = r_side ? side->st : st;
+    uint32_t* const rbsum = r_side ? reinterpret_cast<uint32_t*>(ws + P.bsumR) : bsum;
+    Marker mkR{events, n_events, rst};
     LR1.run_len = (uint32_t)P.nR;   // one segment: all of R
-    rc = bucket_pass(Rin, R1, (uint32_t)P.nR, LR1, bsum, st, mk, MK_R1_SPL);
+    rc = bucket_pass(Rin, R1, (uint32_t)P.nR, LR1, rbsum, rst, mkR, MK_R1_SPL);
     if (rc != MPSM_OK) return rc;
     SortOut soR;
     soR.run_idx = nullptr;
@@ -648,22 +659,22 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       LR2.outer_nspl = P.NB1 - 1;
       // the second level stays sampled: its buckets are finer than the model's knots
       LR2.src_bstart = LR1.bstart;   // segments: the level-1 buckets
-      rc = bucket_pass(R1, R2, (uint32_t)P.nR, LR2, bsum, st, mk, MK_R2_SPL);
+      rc = bucket_pass(R1, R2, (uint32_t)P.nR, LR2, rbsum, rst, mkR, MK_R2_SPL);
       if (rc != MPSM_OK) return rc;
       LRf = &LR2;
       Rsrc = R2;
       Rsorted = R1;
     } else {
-      mk.mark_range(MK_R2_SPL, MK_R2_SCAT);
+      mkR.mark_range(MK_R2_SPL, MK_R2_SCAT);
     }
     // as for S runs: the 2-per-CU sort takes the buckets up to its tile, the
     // larger ones go to the 1-per-CU sort
     uint32_t* midR = reinterpret_cast<uint32_t*>(ws + P.midR);
-    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<LRf->Gmax, BS_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<LRf->Gmax, BS_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
                                                                       LRf->bhi, LRf->Gcount(), nullptr, nullptr, midR,
                                                                       ctr + 6, redoR, ctr + 4, soR);
     LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
                                                                       LRf->bhi, LRf->Gcount(), midR, ctr + 6, bigR,
                                                                       ctr + 1, redoR, ctr + 4, soR);
     LAUNCH_CHECK();
@@ -671,16 +682,20 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     // (splitter bounds can enclose a gap between key clusters); the rest go
     // to the LSD radix sort
     uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
                                                                       LRf->Gcount(), redoR, ctr + 4, bigR, ctr + 1,
                                                                       redoR2, ctr + 5, soR);
     LAUNCH_CHECK();
-    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, redoR2, ctr + 5, bigR, ctr + 1, soR);
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, redoR2, ctr + 5, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
-    mk.mark(MK_R_SORT);
-    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(Rsrc, Rsorted, LRf->bstart, bigR, ctr + 1, soR);
+    mkR.mark(MK_R_SORT);
+    k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
-    mk.mark(MK_R_BIG);
+    mkR.mark(MK_R_BIG);
+    if (r_side) {   // the rest needs R's partitions
+      HIP_TRY(hipEventRecord(side->done, rst));
+      HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
+    }
     uint32_t* Pc = reinterpret_cast<uint32_t*>(ws + P.Pc);
     uint32_t* pstart = reinterpret_cast<uint32_t*>(ws + P.pstart);
     uint32_t* plen = reinterpret_cast<uint32_t*>(ws + P.plen);
