@@ -371,9 +371,10 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
   return MPSM_OK;
 }
 
-// A stream of the calling thread's own for the learned-CDF kernels, so that
-// the models are built while phase 1 runs, and the events that order it
-// against the caller's stream (created once per thread, default priority).
+// A stream of the calling thread's own for the work that runs beside phase 1
+// (the learned-CDF kernels, R's partitioning and sort), and the events that
+// order it against the caller's stream (created once per thread, default
+// priority).
 struct SideStream {
   hipStream_t st = nullptr;
   hipEvent_t fork = nullptr, done = nullptr;
@@ -877,7 +878,7 @@ struct BatchPlan {
   uint32_t tilesS, tilesR, Pmax;
   uint64_t cntS, cntR, ocap, item_cap;
   // workspace offsets
-  uint64_t T, U, Rp, Rs, cS, cR, bsum, segS, segR, srcS, srcR, splS, splR, bstS, bstR, bndS, bndR;
+  uint64_t T, U, Rp, Rs, cS, cR, bsum, bsumR, segS, segR, srcS, srcR, splS, splR, bstS, bstR, bndS, bndR;
   uint64_t bigS, midS, redoS, midR, redoR, redoR2, bigR, ctr, bkey, Pc, pstart, plen, pkey, pjoin, ridx, o, items, item_pre;
   uint64_t J, tstart, ototal, span;
   uint64_t tab_off, tab_bytes;           // host-written tables: one contiguous range
@@ -942,6 +943,7 @@ bool make_batch_plan(const mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH,
   uint64_t maxscan = P->cntS > P->cntR ? P->cntS : P->cntR;
   if (P->item_cap > maxscan) maxscan = P->item_cap;
   P->bsum = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);
+  P->bsumR = take((cdiv(P->cntR, SCAN_BLOCK) + 1) * 4);   // R's scan, beside S's phase
   // host-written tables, contiguous: S and R segment start/len (inside the
   // 6-array segment tables), source pointers, join table
   P->tab_off = off;
@@ -1047,11 +1049,19 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
   k_batch_init<<<(uint32_t)cdiv(P.n, 256) + 1, 256, 0, st>>>(J, P.n, tstart, reinterpret_cast<uint32_t*>(ctr), 16);
   LAUNCH_CHECK();
   if (P.nact) {
+    // R's phase runs on the side stream beside S's run generation (the two
+    // are independent until the search); under capture the fork and join
+    // make them two branches of the graph
+    SideStream* side = nullptr;
+    mpsm_status rc = side_stream(&side);
+    if (rc != MPSM_OK) return rc;
+    HIP_TRY(hipEventRecord(side->fork, st));
+    HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0));
     // phase 1: S runs of every join
     Level LS = make_level(ws, P.segS, P.Qtot, P.NBs, 0, P.OSs, P.tilesS, seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
                           P.bndS, P.Gs);
-    mpsm_status rc = bucket_pass(nullptr, T, (uint32_t)P.nS, LS, bsum, st, mk, 0,
-                                 reinterpret_cast<const tup_t* const*>(ws + P.srcS));
+    rc = bucket_pass(nullptr, T, (uint32_t)P.nS, LS, bsum, st, mk, 0,
+                     reinterpret_cast<const tup_t* const*>(ws + P.srcS));
     if (rc != MPSM_OK) return rc;
     SortOut soS;
     soS.run_idx = reinterpret_cast<uint64_t*>(ws + P.ridx);
@@ -1078,7 +1088,9 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     // phases 2 and 3: one R segment per join, bucket counts from its size
     Level LR = make_level(ws, P.segR, P.nact, MAX_NB, P.BT, P.OSr, P.tilesR, seed ^ TAG_R1, P.splR, P.cR, P.cntR,
                           P.bstR, P.bndR, P.Gr);
-    rc = bucket_pass(nullptr, Rp, (uint32_t)P.nR, LR, bsum, st, mk, 0,
+    const hipStream_t rst = side->st;
+    Marker mkR{nullptr, 0, rst};
+    rc = bucket_pass(nullptr, Rp, (uint32_t)P.nR, LR, reinterpret_cast<uint32_t*>(ws + P.bsumR), rst, mkR, 0,
                      reinterpret_cast<const tup_t* const*>(ws + P.srcR));
     if (rc != MPSM_OK) return rc;
     SortOut soR;
@@ -1093,21 +1105,24 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     uint32_t* redoR = reinterpret_cast<uint32_t*>(ws + P.redoR);
     uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
     uint32_t* bigR = reinterpret_cast<uint32_t*>(ws + P.bigR);
-    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gr, BS_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi,
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gr, BS_NT, 0, rst>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi,
                                                                  LR.Gcount(), nullptr, nullptr, midR, ctr + 6, redoR,
                                                                  ctr + 4, soR);
     LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi,
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi,
                                                                  LR.Gcount(), midR, ctr + 6, bigR, ctr + 1, redoR,
                                                                  ctr + 4, soR);
     LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, st>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(),
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(),
                                                                  redoR, ctr + 4, bigR, ctr + 1, redoR2, ctr + 5, soR);
     LAUNCH_CHECK();
-    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(Rp, Rs, LR.bstart, redoR2, ctr + 5, bigR, ctr + 1, soR);
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rp, Rs, LR.bstart, redoR2, ctr + 5, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
-    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(Rp, Rs, LR.bstart, bigR, ctr + 1, soR);
+    k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rp, Rs, LR.bstart, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
+    // the rest needs R's partitions
+    HIP_TRY(hipEventRecord(side->done, rst));
+    HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
     uint32_t* Pc = reinterpret_cast<uint32_t*>(ws + P.Pc);
     uint32_t* pstart = reinterpret_cast<uint32_t*>(ws + P.pstart);
     uint32_t* plen = reinterpret_cast<uint32_t*>(ws + P.plen);
