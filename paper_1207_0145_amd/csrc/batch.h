@@ -74,7 +74,10 @@ __global__ void k_batch_blocks(BatchJoin* J, uint32_t n, unsigned long long* o_t
 }
 
 // o[obase_b + row * Q_b + j] = lower bound of the first key of the join's
-// partition `row` in run j of the join (row P_b: the run's length).
+// partition `row` in run j of the join (row P_b: the run's length).  Threads
+// walk a join's block run by run, consecutive threads taking consecutive
+// partitions of one run, so that a wave's bisections share their first
+// index entries and end in neighbouring lines.
 __global__ void __launch_bounds__(256) k_search_batch(const tup_t* __restrict__ U, const uint32_t* run_start,
                                                       const uint32_t* run_len, const uint64_t* run_idx,
                                                       uint32_t idx_stride, uint32_t idx_per_run, const BatchJoin* J,
@@ -86,12 +89,13 @@ __global__ void __launch_bounds__(256) k_search_batch(const tup_t* __restrict__ 
   const uint32_t jb = batch_join_of(n, gid, [&](uint32_t i) { return (uint64_t)J[i].obase; });
   const BatchJoin& j = J[jb];
   const uint64_t local = gid - j.obase;
-  const uint32_t row = (uint32_t)(local / j.Q), q = (uint32_t)(local % j.Q);
+  const uint32_t rows = j.P + 1;
+  const uint32_t row = (uint32_t)(local % rows), q = (uint32_t)(local / rows);
   if (row < j.P && !span[j.p0 + row]) return;   // inside a join unit: never read
   const uint32_t run = j.r0 + q;
   const uint32_t len = run_len[run];
   uint32_t probes = 0;
-  o[gid] = row == j.P ? len
+  o[j.obase + (uint64_t)row * j.Q + q] = row == j.P ? len
                       : run_lower_bound(mode, U + run_start[run], len, pkey[j.p0 + row],
                                         run_idx + (uint64_t)run * idx_per_run, idx_stride, &probes);
 }

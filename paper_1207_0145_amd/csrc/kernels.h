@@ -1276,19 +1276,28 @@ __device__ __forceinline__ uint32_t run_lower_bound(int mode, const tup_t* run, 
   return lb_keys(run, a, b, key, probes);
 }
 
-__global__ void __launch_bounds__(256) k_search(const tup_t* __restrict__ U, const uint32_t* run_start,
+// Launch shape: a wave takes 64 consecutive partitions of one run, so the
+// first levels of its lanes' bisections read the same index entries and the
+// last ones neighbouring lines; a workgroup takes 16 runs, so that each row
+// o[p][.] is written in 64-byte pieces.  Blocks: cdiv(Pmax + 1, 64) *
+// cdiv(Q, SEARCH_RUNS), runs fastest.
+constexpr int SEARCH_NT = 1024;
+constexpr int SEARCH_RUNS = SEARCH_NT / 64;
+
+__global__ void __launch_bounds__(SEARCH_NT) k_search(const tup_t* __restrict__ U, const uint32_t* run_start,
                                                 const uint32_t* run_len, uint32_t Q, const uint64_t* run_idx,
                                                 uint32_t idx_stride, uint32_t idx_per_run, const uint32_t* Pcount,
                                                 const uint64_t* pkey, uint32_t Pmax, uint32_t* o, int mode,
                                                 const CdfModel* model, Result* res, const uint8_t* span) {
   const bool learned = mode == SEARCH_LEARNED;
   const CdfModel& m = *model;   // read through the caches: its knots are shared by all threads
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t njt = (Q + SEARCH_RUNS - 1) / SEARCH_RUNS;
+  const uint32_t p = (blockIdx.x / njt) * 64 + (threadIdx.x & 63);
+  const uint32_t j = (blockIdx.x % njt) * SEARCH_RUNS + (threadIdx.x >> 6);
   const uint32_t P = *Pcount;
   uint32_t probes = 0, fallbacks = 0;
   // rows of partitions that do not start a join unit are never read
-  if (gid < (uint64_t)(P + 1) * Q && (gid / Q == P || span[gid / Q])) {
-    const uint32_t p = (uint32_t)(gid / Q), j = (uint32_t)(gid % Q);
+  if (p <= P && p <= Pmax && j < Q && (p == P || span[p])) {
     const uint32_t n = run_len[j];
     const tup_t* run = U + run_start[j];
     uint32_t r;
@@ -1443,7 +1452,8 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
   __shared__ uint32_t wsum[JOIN_NT / 64 + 2];
   __shared__ uint64_t red[JOIN_NT / 64 + 1];
   __shared__ unsigned long long item_acc;
-  __shared__ uint64_t jlo, jhi, jC;
+  __shared__ uint64_t jlo, jhi;
+  __shared__ uint32_t jsh, jC;
   const uint32_t tid = threadIdx.x;
   const uint32_t np2 = A.Pmax + 2;
   const uint32_t total = A.item_pre[np2 - 1];
@@ -1519,17 +1529,25 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
     // bound in [jdir[c], jdir[c+1]].  Built in one pass over the keys.
     if (in_lds) {
       if (tid == 0) {
+        // cell(key) = hi32(((key - lo) >> sh) * C): the shift brings the
+        // range under 2^32 (one 32-bit multiply per probe), C spreads it
+        // over the directory; a range narrower than the directory gets
+        // about one key value per cell
         jlo = rk[0]; jhi = rk[rn - 1];
         const uint64_t width = jhi - jlo;
-        jC = width < (uint64_t)JOIN_DIR ? 0ull : interp_scale(JOIN_DIR, width);
+        const uint32_t sh = (width >> 32) ? 32u - (uint32_t)__builtin_clzll(width) : 0u;
+        const uint64_t c = ((uint64_t)JOIN_DIR << 32) / ((width >> sh) + 1);
+        jsh = sh;
+        jC = c > 0xffffffffull ? 0xffffffffu : (uint32_t)c;
       }
       __syncthreads();
-      const uint64_t l = jlo, c = jC;
+      const uint64_t l = jlo;
+      const uint32_t sh = jsh, c = jC;
       // cells are clamped to the directory, so the fill stays bounded even
       // if the partition were not sorted
       auto cell_of = [&](uint64_t key) -> int {
-        const uint64_t x = __umul64hi(key - l, c);
-        return x < (uint64_t)JOIN_DIR ? (int)x : JOIN_DIR - 1;
+        const uint32_t x = __umulhi((uint32_t)((key - l) >> sh), c);
+        return x < (uint32_t)JOIN_DIR ? (int)x : JOIN_DIR - 1;
       };
       for (uint32_t i = tid; i < rn; i += JOIN_NT) {
         const int ci = cell_of(rk[i]);
@@ -1541,7 +1559,8 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
         if (cc > clast) jdir[cc] = (uint16_t)rn;
       __syncthreads();
     }
-    const uint64_t dlo = jlo, dhi = jhi, dC = jC;
+    const uint64_t dlo = jlo, dhi = jhi;
+    const uint32_t dsh = jsh, dC = jC;
     const uint32_t lo_item = k * A.JCH;
     const uint32_t hi_item = min(lo_item + A.JCH, cum[Q]);
     const tup_t* Rg = A.Rs + rs;
@@ -1588,7 +1607,8 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
           } else if (s.key > dhi) {
             lo = rn;
           } else {
-            const uint32_t cell = (uint32_t)__umul64hi(s.key - dlo, dC);
+            // below JOIN_DIR for dlo < key <= dhi (C <= JOIN_DIR 2^32 / (range + 1))
+            const uint32_t cell = __umulhi((uint32_t)((s.key - dlo) >> dsh), dC);
             lo = jdir[cell];
             hi = jdir[cell + 1];
             while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (rk[mid] < s.key) lo = mid + 1; else hi = mid; }

@@ -711,8 +711,8 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
 
     // ---- phase 4: merge starts of every partition in every run, then the join
     uint32_t* o = reinterpret_cast<uint32_t*>(ws + P.o);
-    const uint64_t nsearch = ((uint64_t)P.Pmax + 1) * P.Q;
-    k_search<<<(uint32_t)cdiv(nsearch, 256), 256, 0, st>>>(U, LS.seg.start, LS.seg.len, P.Q,
+    const uint64_t nsearch = cdiv((uint64_t)P.Pmax + 1, 64) * cdiv(P.Q, SEARCH_RUNS);
+    k_search<<<(uint32_t)nsearch, SEARCH_NT, 0, st>>>(U, LS.seg.start, LS.seg.len, P.Q,
                                                           reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
                                                           P.idx_per_run, Pc, pkey, P.Pmax, o,
                                                           learn_s ? MPSM_SEARCH_LEARNED
