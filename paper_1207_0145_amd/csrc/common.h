@@ -37,6 +37,19 @@ __device__ __forceinline__ tup_t load_tup(const tup_t* p) {
   tup_t t; t.key = v.x; t.pay = v.y;
   return t;
 }
+// Tuples known to be in device (global) memory.  A pointer read from a
+// table is generic to the compiler, which then issues flat loads; a flat
+// load also counts in the LDS wait counter, so every later wait for an LDS
+// access would wait for it too (and drain a prefetch).  Reads through this
+// type are global loads.
+typedef __attribute__((address_space(1))) const tup_t gtup_t;
+__device__ __forceinline__ const gtup_t* as_global(const tup_t* p) { return (const gtup_t*)p; }
+__device__ __forceinline__ tup_t load_tup(const gtup_t* p) {
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+  const u64x2 v = *reinterpret_cast<__attribute__((address_space(1))) const u64x2*>(p);
+  tup_t t; t.key = v.x; t.pay = v.y;
+  return t;
+}
 __device__ __forceinline__ void store_tup(tup_t* p, tup_t t) {
   ulonglong2 v; v.x = t.key; v.y = t.pay;
   *reinterpret_cast<ulonglong2*>(p) = v;
@@ -173,32 +186,56 @@ __device__ __forceinline__ uint64_t interp_scale(uint32_t M, uint64_t span) {
   return q >= 0x1p64f ? ~0ull : (uint64_t)q;
 }
 
+// Monotone map of the keys [lo, lo + width] onto cells [0, D):
+// cell(x) = hi32(((x - lo) >> sh) * C).  The shift brings the range under
+// 2^32, so that a lookup costs one 32-bit multiply-high; C is at most
+// D 2^32 / ((width >> sh) + 1) (rounded down with margin, as in
+// interp_scale), so every cell is below D, and a range narrower than D gets
+// about one key value per cell.
+__device__ __forceinline__ uint32_t cell_shift(uint64_t width) {
+  return (width >> 32) ? 32u - (uint32_t)__builtin_clzll(width) : 0u;
+}
+// w1 = (width >> shift) + 1, in [1, 2^32]
+__device__ __forceinline__ uint32_t cell_scale(uint32_t D, uint64_t w1) {
+  const float q = (float)D * 0x1p32f * __builtin_amdgcn_rcpf((float)w1) * (1.0f - 0x1p-18f);
+  return q >= 0x1p32f ? 0xffffffffu : (uint32_t)q;
+}
+struct CellMap {
+  uint64_t lo;
+  uint32_t sh, C;
+  __device__ __forceinline__ void init(uint64_t lo_, uint64_t width, uint32_t D) {
+    lo = lo_;
+    sh = cell_shift(width);
+    C = cell_scale(D, (width >> sh) + 1);
+  }
+  // x in [lo, lo + width]
+  __device__ __forceinline__ uint32_t operator()(uint64_t x) const {
+    return __umulhi((uint32_t)((x - lo) >> sh), C);
+  }
+};
+
 // Directory over sorted splitters for fast bucket_of: the span [spl[0],
-// spl[nspl-1]] is cut into D equal cells by a monotone map (multiply-high by
-// C); first[c] is the first splitter whose cell is >= c.  A key in cell c
+// spl[nspl-1]] is cut into D cells by a CellMap; first[c] is the first
+// splitter whose cell is >= c.  A key in cell c
 // has every splitter below first[c] under it and every splitter from
 // first[c+1] on above it, so only the splitters of its own cell (usually 0
 // or 1) are searched.  Same answer as bucket_of.
 template <int D>
 struct SplitDir {
   uint16_t first[D + 1];
-  uint64_t lo, C;
+  CellMap map;
 
   // All threads of the block call; spl (LDS) holds nspl >= 1 sorted splitters.
   template <int NT>
   __device__ void build(const uint64_t* spl, uint32_t nspl) {
-    if (threadIdx.x == 0) {
-      lo = spl[0];
-      const uint64_t width = spl[nspl - 1] - spl[0];
-      C = width < (uint64_t)D ? 0ull : interp_scale(D, width);   // narrow span: every key in cell 0
-    }
+    if (threadIdx.x == 0) map.init(spl[0], spl[nspl - 1] - spl[0], D);
     __syncthreads();
-    const uint64_t l = lo, c = C;
+    const CellMap mp = map;
     for (uint32_t cell = threadIdx.x; cell <= (uint32_t)D; cell += NT) {
       uint32_t a = 0, b = nspl;  // first m with cell(spl[m]) >= cell
       while (a < b) {
         const uint32_t m = (a + b) >> 1;
-        if ((uint32_t)__umul64hi(spl[m] - l, c) < cell) a = m + 1; else b = m;
+        if (mp(spl[m]) < cell) a = m + 1; else b = m;
       }
       first[cell] = (uint16_t)a;
     }
@@ -206,12 +243,12 @@ struct SplitDir {
   }
 
   __device__ __forceinline__ uint32_t bucket(const uint64_t* spl, uint32_t nspl, uint64_t key) const {
-    if (nspl == 0 || key < lo) return 0;
+    if (nspl == 0 || key < map.lo) return 0;
     uint32_t b;
     if (key >= spl[nspl - 1]) {
       b = nspl;
     } else {
-      const uint32_t cell = (uint32_t)__umul64hi(key - lo, C);
+      const uint32_t cell = map(key);   // spl[0] <= key < spl[nspl - 1]: below D
       uint32_t a = first[cell], e = first[cell + 1];
       while (a < e) {
         const uint32_t m = (a + e) >> 1;

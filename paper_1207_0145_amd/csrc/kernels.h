@@ -213,7 +213,8 @@ __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict
   const uint32_t s = blockIdx.x, tid = threadIdx.x;
   const uint32_t len = seg_len[s], start = seg_start[s], nb = seg_nb[s];
   if (len == 0 || nb < 2) return;
-  if (seg_src) src = seg_src[s] - start;   // segment read in place from its own array
+  // a segment may be read in place from its own array
+  const gtup_t* const gsrc = as_global(seg_src ? seg_src[s] - start : src);
   const uint32_t M = nb * OS;
   uint64_t* out = spl + (uint64_t)s * (NBmax - 1);
   const uint64_t seed = splitmix_at(level_seed, s);
@@ -223,7 +224,7 @@ __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict
     const uint32_t t = k * NT + tid;
     if (t < M) {
       const uint64_t pos = start + draw_below(splitmix_at(seed, t), len);
-      key[k] = src[pos].key;
+      key[k] = gsrc[pos].key;
     } else {
       key[k] = ~0ull;
     }
@@ -397,7 +398,8 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
   const uint32_t g = blockIdx.x;
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
-  if (seg_src) src = seg_src[s] - seg_start[s];   // segment read in place from its own array
+  // a segment may be read in place from its own array
+  const gtup_t* const gsrc = as_global(seg_src ? seg_src[s] - seg_start[s] : src);
   const uint32_t t = g - seg_tile0[s], ntiles = seg_tile0[s + 1] - seg_tile0[s];
   const uint32_t segend = seg_start[s] + seg_len[s];
   const uint32_t a = seg_start[s] + t * TILE;
@@ -413,7 +415,7 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
 #pragma unroll
     for (int u = 0; u < HU; u++) {
       const uint32_t i = base + u * HIST_NT + threadIdx.x;
-      kk[u] = i < b ? src[i].key : 0;
+      kk[u] = i < b ? gsrc[i].key : 0;
     }
 #pragma unroll
     for (int u = 0; u < HU; u++)
@@ -440,7 +442,8 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   const uint32_t g = blockIdx.x, tid = threadIdx.x;
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
-  if (seg_src) src = seg_src[s] - seg_start[s];   // segment read in place from its own array
+  // a segment may be read in place from its own array
+  const gtup_t* const gsrc = as_global(seg_src ? seg_src[s] - seg_start[s] : src);
   const uint32_t t = g - seg_tile0[s], ntiles = seg_tile0[s + 1] - seg_tile0[s];
   const uint32_t segend = seg_start[s] + seg_len[s];
   const uint32_t a = seg_start[s] + t * TILE;
@@ -456,7 +459,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
 #pragma unroll
   for (int k = 0; k < SCAT_IPT; k++) {
     const uint32_t i = a + k * SCAT_NT + tid;
-    if (i < b) nv[k] = load_tup(src + i);
+    if (i < b) nv[k] = load_tup(gsrc + i);
   }
   for (uint32_t c0 = a; c0 < b; c0 += SCAT_CH) {
     tup_t v[SCAT_IPT];
@@ -466,7 +469,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
 #pragma unroll
     for (int k = 0; k < SCAT_IPT; k++) {
       const uint32_t i = c0 + SCAT_CH + k * SCAT_NT + tid;
-      if (i < b) nv[k] = load_tup(src + i);
+      if (i < b) nv[k] = load_tup(gsrc + i);
     }
 #pragma unroll
     for (int k = 0; k < SCAT_IPT; k++) {
@@ -747,10 +750,12 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
       span = bmx - bmn;
     }
     const bool exact = span < (uint64_t)M;   // one key per sub-bucket
-    const uint64_t C = exact ? 0ull : interp_scale(M, span);
+    // sub-bucket: k - lo, or as a CellMap
+    const uint32_t csh = cell_shift(span);
+    const uint32_t C = cell_scale(M, (span >> csh) + 1);
     auto sub = [&](uint64_t k) -> uint32_t {
       const uint64_t x = k - lo;
-      const uint32_t dd = exact ? (uint32_t)x : (uint32_t)__umul64hi(x, C);
+      const uint32_t dd = exact ? (uint32_t)x : __umulhi((uint32_t)(x >> csh), C);
       return dd < (uint32_t)M ? dd : (uint32_t)(M - 1);
     };
     uint32_t fin[IPT];
@@ -1452,8 +1457,8 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
   __shared__ uint32_t wsum[JOIN_NT / 64 + 2];
   __shared__ uint64_t red[JOIN_NT / 64 + 1];
   __shared__ unsigned long long item_acc;
-  __shared__ uint64_t jlo, jhi;
-  __shared__ uint32_t jsh, jC;
+  __shared__ uint64_t jhi;
+  __shared__ CellMap jmap;
   const uint32_t tid = threadIdx.x;
   const uint32_t np2 = A.Pmax + 2;
   const uint32_t total = A.item_pre[np2 - 1];
@@ -1529,24 +1534,15 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
     // bound in [jdir[c], jdir[c+1]].  Built in one pass over the keys.
     if (in_lds) {
       if (tid == 0) {
-        // cell(key) = hi32(((key - lo) >> sh) * C): the shift brings the
-        // range under 2^32 (one 32-bit multiply per probe), C spreads it
-        // over the directory; a range narrower than the directory gets
-        // about one key value per cell
-        jlo = rk[0]; jhi = rk[rn - 1];
-        const uint64_t width = jhi - jlo;
-        const uint32_t sh = (width >> 32) ? 32u - (uint32_t)__builtin_clzll(width) : 0u;
-        const uint64_t c = ((uint64_t)JOIN_DIR << 32) / ((width >> sh) + 1);
-        jsh = sh;
-        jC = c > 0xffffffffull ? 0xffffffffu : (uint32_t)c;
+        jhi = rk[rn - 1];
+        jmap.init(rk[0], rk[rn - 1] - rk[0], JOIN_DIR);
       }
       __syncthreads();
-      const uint64_t l = jlo;
-      const uint32_t sh = jsh, c = jC;
+      const CellMap mp = jmap;
       // cells are clamped to the directory, so the fill stays bounded even
       // if the partition were not sorted
       auto cell_of = [&](uint64_t key) -> int {
-        const uint32_t x = __umulhi((uint32_t)((key - l) >> sh), c);
+        const uint32_t x = mp(key);
         return x < (uint32_t)JOIN_DIR ? (int)x : JOIN_DIR - 1;
       };
       for (uint32_t i = tid; i < rn; i += JOIN_NT) {
@@ -1559,8 +1555,8 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
         if (cc > clast) jdir[cc] = (uint16_t)rn;
       __syncthreads();
     }
-    const uint64_t dlo = jlo, dhi = jhi;
-    const uint32_t dsh = jsh, dC = jC;
+    const CellMap dmap = jmap;
+    const uint64_t dlo = dmap.lo, dhi = jhi;
     const uint32_t lo_item = k * A.JCH;
     const uint32_t hi_item = min(lo_item + A.JCH, cum[Q]);
     const tup_t* Rg = A.Rs + rs;
@@ -1607,8 +1603,7 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
           } else if (s.key > dhi) {
             lo = rn;
           } else {
-            // below JOIN_DIR for dlo < key <= dhi (C <= JOIN_DIR 2^32 / (range + 1))
-            const uint32_t cell = __umulhi((uint32_t)((s.key - dlo) >> dsh), dC);
+            const uint32_t cell = dmap(s.key);   // dlo < key <= dhi: below JOIN_DIR
             lo = jdir[cell];
             hi = jdir[cell + 1];
             while (lo < hi) { const uint32_t mid = (lo + hi) >> 1; if (rk[mid] < s.key) lo = mid + 1; else hi = mid; }
