@@ -125,7 +125,7 @@ __global__ void k_join_items_batch(const uint32_t* Pcount, const uint32_t* pjoin
       const uint32_t* a = o + J[jb].obase + (uint64_t)(p - J[jb].p0) * Q;
       const uint32_t* b = a + (uint64_t)sp * Q;
       uint64_t np = 0;
-      for (uint32_t q = 0; q < Q; q++) np += b[q] - a[q];
+      for (uint32_t q = 0; q < Q; q++) np += b[q] > a[q] ? b[q] - a[q] : 0;   // as in k_join
       it = (uint32_t)((np + JCH - 1) / JCH);
       if (it) atomicAdd(&J[jb].items, it);
     }

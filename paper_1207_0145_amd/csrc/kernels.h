@@ -1392,7 +1392,7 @@ __global__ void k_join_items(const uint32_t* Pcount, const uint32_t* o, uint32_t
       uint64_t np = 0;
       const uint32_t* a = o + (uint64_t)p * Q;
       const uint32_t* b = a + (uint64_t)sp * Q;
-      for (uint32_t j = 0; j < Q; j++) np += b[j] - a[j];
+      for (uint32_t j = 0; j < Q; j++) np += b[j] > a[j] ? b[j] - a[j] : 0;   // as in k_join
       it = (uint32_t)((np + JCH - 1) / JCH);
     }
   }
@@ -1418,6 +1418,7 @@ struct JoinArgs {
   uint64_t* pairs;          // 3 u64 per pair (key, caller-R payload, caller-S payload)
   uint64_t pairs_cap;
   uint32_t* item_cnt;       // per-item pair counts (count pass) / offsets (write pass)
+  uint32_t item_cap;        // entries of item_cnt
   int swapped;              // internal R is the caller's S
   // batch: per-join table and the join of every partition
   BatchJoin* J;
@@ -1461,7 +1462,8 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
   __shared__ CellMap jmap;
   const uint32_t tid = threadIdx.x;
   const uint32_t np2 = A.Pmax + 2;
-  const uint32_t total = A.item_pre[np2 - 1];
+  // the pair passes keep one entry per item
+  const uint32_t total = MODE == 0 ? A.item_pre[np2 - 1] : min(A.item_pre[np2 - 1], A.item_cap);
   unsigned long long cnt = 0, sum = 0, mx = 0;
   bool any = false;
   constexpr int JPF = JOIN_CAP / JOIN_NT;   // R tuples per thread
@@ -1490,7 +1492,9 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
     for (uint32_t j0 = 0; j0 < Q; j0 += JOIN_NT) {
       const uint32_t j = j0 + tid;
       const uint32_t oj = j < Q ? oa[j] : 0;
-      const uint32_t len = j < Q ? ob[j] - oj : 0;
+      // offsets are monotone in the partition for sorted runs; clamped so
+      // that every read stays inside run j whatever the offsets hold
+      const uint32_t len = (j < Q && ob[j] > oj) ? ob[j] - oj : 0;
       uint32_t tot;
       const uint32_t ex = block_excl_scan<JOIN_NT>(len, wsum, &tot);
       if (j < Q) { cum[j] = carry + ex; sbase[j] = A.run_start[r0 + j] + oj - (carry + ex); }

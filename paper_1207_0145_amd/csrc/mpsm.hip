@@ -748,6 +748,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     A.pairs = reinterpret_cast<uint64_t*>(d_pairs);
     A.pairs_cap = d_pairs ? pairs_capacity : 0;
     A.item_cnt = reinterpret_cast<uint32_t*>(ws + P.item_cnt);
+    A.item_cap = (uint32_t)P.item_cap;
     A.swapped = P.swapped;
     const bool raw = P.swapped || P.want_max || d_pairs;
     if (raw) k_join<0, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
