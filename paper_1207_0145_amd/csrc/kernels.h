@@ -557,10 +557,16 @@ struct SortOut {
   uint64_t* bkey;
 };
 
+// Tuple of sorted rank r of bucket g (which starts at a): its key goes to
+// the run index at every idx_stride-th run position, and to bkey at rank 0.
+// The run's start is read through the constant address space (no kernel
+// that sorts writes it), so it is a scalar load: a vector load issued after
+// the bucket's stores would wait for every one of them.
 __device__ __forceinline__ void emit_sorted(const SortOut& so, uint32_t g, uint32_t a, uint32_t r, uint64_t key) {
   if (so.run_idx) {
     const uint32_t s = g / so.NB;
-    const uint32_t rel = a + r - so.run_start[s];
+    const uint32_t rs = *(__attribute__((address_space(4))) const uint32_t*)(so.run_start + s);
+    const uint32_t rel = a + r - rs;
     if ((rel & (so.idx_stride - 1)) == 0) so.run_idx[(uint64_t)s * so.idx_per_run + (rel >> so.idx_shift)] = key;
   }
   if (so.bkey && r == 0) so.bkey[g] = key;
@@ -1045,14 +1051,31 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
         }
       }
     } else {
+      // every byte offset is formed before the first store and the index
+      // entries follow the tuples: a register written between two stores
+      // would be taken from a stored tuple, and writing it waits for that
+      // store to complete
+      tup_t* const out = dst + a;
+#pragma unroll
+      for (int k = 0; k < IPT; k++) {
+        fin[k] *= (uint32_t)sizeof(tup_t);
+        asm volatile("" : "+v"(fin[k]));
+      }
+      // the payloads arrive here, once: a load still pending at a store
+      // that sits behind a branch makes that store wait for every earlier
+      // store as well
+#pragma unroll
+      for (int k = 0; k < IPT; k++) asm volatile("" ::"v"(val[k]));
 #pragma unroll
       for (int k = 0; k < IPT; k++) {
         if (k * NT + tid < n) {
           tup_t v; v.key = key[k]; v.pay = val[k];
-          store_tup(dst + a + fin[k], v);
-          emit_sorted(so, g, a, fin[k], key[k]);
+          store_tup(reinterpret_cast<tup_t*>(reinterpret_cast<char*>(out) + fin[k]), v);
         }
       }
+#pragma unroll
+      for (int k = 0; k < IPT; k++)
+        if (k * NT + tid < n) emit_sorted(so, g, a, fin[k] / (uint32_t)sizeof(tup_t), key[k]);
     }
   }
 }
