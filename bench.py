@@ -106,9 +106,10 @@ def _nth(join, prefix, k):
 
 def step_times(names, evsets, steps):
     """Average device time of every launch step from the join's markers.
-    R's partitioning and sort may run on a second stream beside S's run
-    generation: its first step then counts from the fork (cdf_models), and
-    the partition step from the later of the two phases' ends."""
+    R's partitioning and sort may run on a second stream beside S's bucket
+    sort, starting once S's scatter is done: R's first step then counts from
+    s_scatter, and the partition step from the later of the two phases'
+    ends."""
     ix = {n: i for i, n in enumerate(names)}
 
     def el(a, b):
@@ -117,7 +118,7 @@ def step_times(names, evsets, steps):
     out = {names[i]: el(names[i - 1], names[i]) for i in range(1, len(names))}
     overlapped = el("s_oversize_sort", "r1_splitters") < 0
     if overlapped:
-        out["r1_splitters"] = el("cdf_models", "r1_splitters")
+        out["r1_splitters"] = el("s_scatter", "r1_splitters")
         last = "r_oversize_sort" if el("s_oversize_sort", "r_oversize_sort") > 0 else "s_oversize_sort"
         out["partitions"] = el(last, "partitions")
     return out, overlapped
@@ -421,8 +422,10 @@ def main():
                      "avg_launch_ms": round(steps_ms[dom], 4),
                      "frac_of_measured_copy": round(achieved / copy_gbs, 4),
                      # the kernel's launch time includes sharing the GPU with
-                     # R's phase when that runs on the second stream
-                     "concurrent_with": "R partitioning and sort (second stream)" if overlapped and dom.startswith("s_") else None},
+                     # R's phase when that runs on the second stream (beside
+                     # S's steps after the scatter)
+                     "concurrent_with": "R partitioning and sort (second stream)"
+                     if overlapped and dom in ("s_bucket_sort", "s_oversize_sort") else None},
         "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_gbs, 1), "unit": "GB/s",
                           "frac": round(path_gbs / HBM_PEAK_GBS, 4),
                           "frac_of_measured_copy": round(path_gbs / copy_gbs, 4)},

@@ -206,10 +206,10 @@ mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* c
  * run still record their marker, so the elapsed time between consecutive
  * markers is the device time of that step.  R's partitioning and sort
  * (markers r1_splitters .. r_oversize_sort) run on a second stream of the
- * library, beside S's run generation, unless splitters are cost-balanced;
- * their markers are then recorded on that stream, R's first step counts
- * from cdf_models, and the partition step from the later of
- * s_oversize_sort and r_oversize_sort.  Same arguments, results and errors
+ * library, beside S's bucket sort (from the end of S's scatter on), unless
+ * splitters are cost-balanced; their markers are then recorded on that
+ * stream, R's first step counts from s_scatter, and the partition step from
+ * the later of s_oversize_sort and r_oversize_sort.  Same arguments, results and errors
  * as mpsm_join otherwise. */
 mpsm_status mpsm_join_events(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS,
                              uint64_t* d_out_count, uint64_t* d_out_checksum, mpsm_pair* d_pairs,

@@ -377,7 +377,7 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
 // priority).
 struct SideStream {
   hipStream_t st = nullptr;
-  hipEvent_t fork = nullptr, done = nullptr;
+  hipEvent_t fork = nullptr, gate = nullptr, done = nullptr;
 };
 thread_local SideStream t_side;
 
@@ -386,6 +386,7 @@ mpsm_status side_stream(SideStream** out) {
   if (!s.st) {
     HIP_TRY(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&s.fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&s.gate, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
   }
   *out = &s;
@@ -547,7 +548,10 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
   const bool learn_s = P.search == MPSM_SEARCH_LEARNED && P.nR && P.nS;
   // R's partitioning and sort run on the side stream too, beside S's run
   // generation (they are independent until the search), except with
-  // cost-balanced splitters, which need S's runs
+  // cost-balanced splitters, which need S's runs.  They start once S's
+  // tuples are scattered into runs: beside S's histogram and scatter, both
+  // bound by HBM and on the critical path, R's passes took bandwidth from
+  // them; S's bucket sort, bound by its ALU work, leaves more of it.
   const bool r_side = P.splitter != MPSM_SPLIT_COST && P.nR && P.nS;
   SideStream* side = nullptr;
   if (learn_r || learn_s || r_side) {
@@ -584,6 +588,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     LS.run_len = P.L;
     rc = bucket_pass(Sin, T, (uint32_t)P.nS, LS, bsum, st, mk, MK_S_SPL);
     if (rc != MPSM_OK) return rc;
+    if (r_side) HIP_TRY(hipEventRecord(side->gate, st));
     rc = start_models();
     if (rc != MPSM_OK) return rc;
     SortOut soS;
@@ -633,6 +638,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     // after them, or on this stream after S's
     if (side && !r_side) HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
     const hipStream_t rst = r_side ? side->st : st;
+    if (r_side) HIP_TRY(hipStreamWaitEvent(rst, side->gate, 0));
     uint32_t* const rbsum = r_side ? reinterpret_cast<uint32_t*>(ws + P.bsumR) : bsum;
     Marker mkR{events, n_events, rst};
     LR1.run_len = (uint32_t)P.nR;   // one segment: all of R
@@ -1050,20 +1056,20 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
   k_batch_init<<<(uint32_t)cdiv(P.n, 256) + 1, 256, 0, st>>>(J, P.n, tstart, reinterpret_cast<uint32_t*>(ctr), 16);
   LAUNCH_CHECK();
   if (P.nact) {
-    // R's phase runs on the side stream beside S's run generation (the two
-    // are independent until the search); under capture the fork and join
-    // make them two branches of the graph
+    // R's phase runs on the side stream beside S's run sort, from the
+    // point where S's tuples are scattered (as for a single join); under
+    // capture the fork and join make them two branches of the graph
     SideStream* side = nullptr;
     mpsm_status rc = side_stream(&side);
     if (rc != MPSM_OK) return rc;
-    HIP_TRY(hipEventRecord(side->fork, st));
-    HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0));
     // phase 1: S runs of every join
     Level LS = make_level(ws, P.segS, P.Qtot, P.NBs, 0, P.OSs, P.tilesS, seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
                           P.bndS, P.Gs);
     rc = bucket_pass(nullptr, T, (uint32_t)P.nS, LS, bsum, st, mk, 0,
                      reinterpret_cast<const tup_t* const*>(ws + P.srcS));
     if (rc != MPSM_OK) return rc;
+    HIP_TRY(hipEventRecord(side->fork, st));
+    HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0));
     SortOut soS;
     soS.run_idx = reinterpret_cast<uint64_t*>(ws + P.ridx);
     soS.run_start = LS.seg.start;
