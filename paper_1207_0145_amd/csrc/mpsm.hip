@@ -373,16 +373,20 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
 
 // A stream of the calling thread's own for the work that runs beside phase 1
 // (the learned-CDF kernels, R's partitioning and sort), and the events that
-// order it against the caller's stream (created once per thread, default
-// priority).
+// order it against the caller's stream (created once per thread and device,
+// on the device current at the call, default priority).
 struct SideStream {
   hipStream_t st = nullptr;
   hipEvent_t fork = nullptr, gate = nullptr, done = nullptr;
 };
-thread_local SideStream t_side;
+constexpr int SIDE_MAX_DEVICES = 64;
+thread_local SideStream t_side[SIDE_MAX_DEVICES];
 
 mpsm_status side_stream(SideStream** out) {
-  SideStream& s = t_side;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SIDE_MAX_DEVICES) return MPSM_EUNSUPPORTED;
+  SideStream& s = t_side[dev];
   if (!s.st) {
     HIP_TRY(hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&s.fork, hipEventDisableTiming));
