@@ -106,6 +106,45 @@ def test_ragged_sizes():
     check(rel(rng, 70001, 1 << 20), rel(rng, 300007, 1 << 20))
 
 
+def _spaced_keys(kind, n, rng):
+    """R key sets whose partitions span key ranges around the bounds of the
+    cell maps (splitter directory, sort sub-buckets, join directory): narrower
+    than the directory (a dense range far from 0), a range just over 2^32
+    per partition, ranges of 2^40 and more, the top of the 64-bit range, and
+    dense and sparse partitions side by side."""
+    i = rng.permutation(n).astype(np.uint64)
+    if kind == "dense_high_base":
+        return np.uint64(1 << 40) + i
+    if kind == "step_2p31":
+        return i * np.uint64((1 << 31) + 7)
+    if kind == "step_2p40":
+        return i * np.uint64((1 << 40) + 12345)
+    if kind == "top_of_range":
+        return np.uint64(U64) - i * np.uint64(3)
+    if kind == "dense_and_sparse":
+        half = n // 2
+        sparse = rng.integers(1 << 20, U64, size=n - half, dtype=np.uint64, endpoint=True)
+        return np.concatenate([i[:half] % np.uint64(half), sparse])
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind", ["dense_high_base", "step_2p31", "step_2p40", "top_of_range", "dense_and_sparse"])
+@pytest.mark.parametrize("kw", [dict(), dict(search=mpsm.SEARCH_BINARY), dict(splitter=mpsm.SPLIT_LEARNED)],
+                         ids=["default", "binary", "learned"])
+def test_key_ranges_around_the_cell_maps(kind, kw):
+    rng = np.random.default_rng(zlib.crc32(kind.encode()))
+    nR, nS = 1 << 17, 1 << 19
+    rk = _spaced_keys(kind, nR, rng)
+    R = np.stack([rk, rng.integers(0, U64, nR, dtype=np.uint64, endpoint=True)], 1)
+    # foreign keys, plus keys just beside R's (absent unless R has them)
+    sk = rk[rng.integers(0, nR, nS)]
+    nudge = rng.integers(0, 4, nS) == 0
+    sk[nudge] = sk[nudge] + np.uint64(1)
+    S = np.stack([sk, rng.integers(0, U64, nS, dtype=np.uint64, endpoint=True)], 1)
+    check(R, S, mpsm.config(**kw))
+    check(R[:3000], S[:9000], mpsm.config(**kw), pairs=True)
+
+
 CONFIGS = [
     dict(role=mpsm.ROLE_AS_GIVEN), dict(role=mpsm.ROLE_SWAP), dict(search=mpsm.SEARCH_BINARY),
     dict(search=mpsm.SEARCH_INTERP), dict(log2_run_len=12), dict(log2_run_len=16, bucket_target=256),
