@@ -109,9 +109,9 @@ def test_ragged_sizes():
 def _spaced_keys(kind, n, rng):
     """R key sets whose partitions span key ranges around the bounds of the
     cell maps (splitter directory, sort sub-buckets, join directory): narrower
-    than the directory (a dense range far from 0), a range just over 2^32
-    per partition, ranges of 2^40 and more, the top of the 64-bit range, and
-    dense and sparse partitions side by side."""
+    than the directory (a dense range far from 0), partitions about 2^42 and
+    2^51 wide (keys 2^31 + 7 and 2^40 + 12345 apart), the top of the 64-bit
+    range, and dense and sparse partitions side by side."""
     i = rng.permutation(n).astype(np.uint64)
     if kind == "dense_high_base":
         return np.uint64(1 << 40) + i
