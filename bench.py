@@ -3,7 +3,9 @@
 
 One step = one complete mpsm_join call (every phase: S run sort, R range
 partitioning and partition sort, start search, merge join, result) over the
-benchmark workload, with the inputs already resident in HBM.
+benchmark workload, with the inputs already resident in HBM.  The headline
+workload is the largest single-GPU one: |R| = 2^28 log-normal keys with
+duplicates joined with |S| = 2^30 (1..16 copies of every distinct key).
 
 Prints one JSON line.  Fields beyond the common contract:
   roofline      the dominant kernel's achieved algorithmic HBM bandwidth
@@ -11,8 +13,12 @@ Prints one JSON line.  Fields beyond the common contract:
                 between the kernels of the timed steps on the join's stream;
   path_roofline the same for the whole step (algorithmic bytes of the path);
   steps_ms      per-step device time of every launch step, averaged;
-  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
-                same workload.
+  cpu_baseline  the CPU oracle on a bounded sample of the same workload:
+                its join over key-range slices on all host threads (up to
+                16), and single-threaded, with the host's CPU model, cores
+                and RAM;
+  other_workloads  the same figures for the other single-join workloads
+                (plain and learned).
 """
 import argparse
 import hashlib
@@ -42,7 +48,8 @@ KERNEL_OF_STEP = {
 
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
-    for f in ("common.h", "block_sort.h", "kernels.h", "learned.h", "mpsm.hip"):
+    from paper_1207_0145_amd import build as hipbuild
+    for f in (*hipbuild.HEADERS, "mpsm.hip"):
         with open(os.path.join(ROOT, "paper_1207_0145_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -187,17 +194,54 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(shift: int):
+def host_info():
+    """CPU model, logical cores and RAM of this host (lscpu, /proc/meminfo)."""
+    import subprocess
+    info = {"cores": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() == "Model name":
+                info["cpu_model"] = v.strip()
+            elif k.strip() == "Socket(s)":
+                info["sockets"] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/meminfo") as f:
+            kb = int(f.readline().split()[1])
+        info["ram_gib"] = round(kb / 2**20, 1)
+    except (OSError, ValueError, IndexError):
+        pass
+    return info
+
+
+def cpu_baseline(workload: str, shift: int, threads: int):
+    """The CPU oracle on the same workload recipe at 1/2^shift of its size:
+    its sort-merge join with one thread, and the same join split into
+    key-range slices that `threads` threads join side by side."""
+    import numpy as np
     import oracle
     import workloads
-    w = workloads.make("fk_uniform", scale_shift=shift)
-    t0 = time.perf_counter()
-    r = oracle.join(w.R, w.S)
-    dt = time.perf_counter() - t0
+    w = workloads.make(workload, scale_shift=shift)
     n = len(w.R) + len(w.S)
-    return {"value": n / dt / 1e6, "unit": "M tuples/s", "cores": 1, "kind": "oracle",
-            "sample": f"fk_uniform at 1/{1 << shift} scale: |R|=2^{26 - shift}, |S|=2^{28 - shift}, "
-                      f"same key recipe; {dt:.1f} s single-threaded sort-merge join (count {r.count})"}
+    t0 = time.perf_counter()
+    r1 = oracle.join(w.R, w.S)
+    dt1 = time.perf_counter() - t0
+    smp = np.sort(w.R[np.random.default_rng(0).integers(0, len(w.R), 1 << 14), 0])
+    nsl = 4 * threads
+    bounds = np.unique(smp[(np.arange(1, nsl) * len(smp)) // nsl])
+    t0 = time.perf_counter()
+    rt = oracle.join_sliced(w.R, w.S, bounds, threads=threads)
+    dtt = time.perf_counter() - t0
+    assert (rt.count, rt.checksum) == (r1.count, r1.checksum)
+    sample = (f"{workload} at 1/{1 << shift} scale (|R|={len(w.R)}, |S|={len(w.S)}, same recipe): "
+              f"{dtt:.1f} s for the oracle's sort-merge join over {len(bounds) + 1} key-range slices "
+              f"on {threads} threads; {dt1:.1f} s on one thread (count {r1.count})")
+    return {"value": round(n / dtt / 1e6, 3), "unit": "M tuples/s", "cores": threads, "kind": "oracle",
+            "sample": sample, "single_thread": {"value": round(n / dt1 / 1e6, 3), "cores": 1, "seconds": round(dt1, 2)},
+            "host": host_info()}
 
 
 def variant_stats(mpsm, torch, R, S, cfg, dev):
@@ -211,23 +255,23 @@ def variant_stats(mpsm, torch, R, S, cfg, dev):
     return {k: (round(v, 5) if isinstance(v, float) else v) for k, v in d.items()}
 
 
-def run_variant(mpsm, torch, R, S, out, cfg, args, names, nR, nS, label):
-    """Time args.steps calls of another configuration, same inputs."""
+def run_variant(mpsm, torch, R, S, out, cfg, args, names, nR, nS, label, steps):
+    """Time `steps` calls of another configuration, same inputs."""
     dev = R.device
     ws = mpsm.alloc_workspace(nR, nS, cfg, dev)
     for _ in range(args.warmup):
         mpsm.join_into(R, S, out, ws, cfg)
-    evsets = [mpsm.EventSet(len(names)) for _ in range(args.steps)]
+    evsets = [mpsm.EventSet(len(names)) for _ in range(steps)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record()
-    for k in range(args.steps):
+    for k in range(steps):
         mpsm.join_events_into(R, S, out, ws, evsets[k], cfg)
     t1.record()
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / args.steps
-    steps_ms, _ = step_times(names, evsets, args.steps)
+    ms = t0.elapsed_time(t1) / steps
+    steps_ms, _ = step_times(names, evsets, steps)
     for e in evsets:
         e.close()
     count, checksum = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
@@ -306,14 +350,108 @@ def batch_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def measure(args, workload, steps, learned=True):
+    """Plain (and learned) form of one single-join workload: timed steps,
+    per-step device times, the dominant step's roofline and the whole
+    path's."""
+    import numpy as np
+    import torch
+    import paper_1207_0145_amd as mpsm
+    import workloads
+
+    log(f"generating {workload}")
+    w = workloads.make(workload)
+    nR, nS = len(w.R), len(w.S)
+    dev = torch.device("cuda", 0)
+    R = torch.from_numpy(w.R.view(np.int64)).to(dev)
+    S = torch.from_numpy(w.S.view(np.int64)).to(dev)
+    del w
+    search = {"index": mpsm.SEARCH_INDEX, "binary": mpsm.SEARCH_BINARY, "interp": mpsm.SEARCH_INTERP}[args.search]
+    cfg = mpsm.config(search=search)
+    cfg_learned = mpsm.config(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED)
+    lay = mpsm.layout(nR, nS, cfg)
+    ws = mpsm.alloc_workspace(nR, nS, cfg, dev)
+    out = torch.zeros(2, dtype=torch.int64, device=dev)
+    names = mpsm.marker_names()
+    log(f"{workload}: |R|={nR} |S|={nS} workspace={ws.numel() / 2**30:.2f} GiB runs={lay['runs']} "
+        f"R levels={lay['levels']}")
+    if args.calibrate_copy:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 1073741824 bytes read and written once")
+        del x, y
+    for i in range(args.warmup):
+        mpsm.join_into(R, S, out, ws, cfg)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    evsets = [mpsm.EventSet(len(names)) for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for k in range(steps):
+        mpsm.join_events_into(R, S, out, ws, evsets[k], cfg)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    log(f"{workload}: timed {steps} steps: {ms:.3f} ms/step")
+    count, checksum = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
+    steps_ms, overlapped = step_times(names, evsets, steps)
+    for e in evsets:
+        e.close()
+
+    def step_bytes(step):
+        rel, b = STEP_BYTES[step]
+        return b * {"S": nS, "R": nR, "RS": nR + nS}[rel]
+
+    dom = max((s for s in STEP_BYTES if steps_ms.get(s, 0) > 0), key=lambda s: steps_ms[s])
+    achieved = step_bytes(dom) / (steps_ms[dom] * 1e-3) / 1e9
+    path_bytes = 48 * nS + 64 * nR
+    path_gbs = path_bytes / (ms * 1e-3) / 1e9
+    res = {
+        "nR": nR, "nS": nS, "ms_per_step": round(ms, 4), "value": round((nR + nS) / (ms * 1e-3) / 1e6, 2),
+        "variant": "plain (sampled splitters, " + args.search + " start search)",
+        "runs": lay["runs"], "run_len": lay["run_len"], "r_levels": lay["levels"],
+        "result": {"count": count, "checksum": f"{checksum:#018x}"},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_OF_STEP[dom], "step": dom,
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, workload), "algorithmic_bytes": step_bytes(dom),
+                     "avg_launch_ms": round(steps_ms[dom], 4),
+                     # the kernel's launch time includes sharing the GPU with
+                     # R's phase when that runs on the second stream (beside
+                     # S's steps after the scatter)
+                     "concurrent_with": "R partitioning and sort (second stream)"
+                     if overlapped and dom in ("s_bucket_sort", "s_oversize_sort") else None},
+        "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_gbs, 1), "unit": "GB/s",
+                          "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
+        "steps_ms": {k: round(v, 4) for k, v in steps_ms.items()},
+    }
+    if learned:
+        res["learned"] = run_variant(mpsm, torch, R, S, out, cfg_learned, args, names, nR, nS,
+                                     f"{workload} learned", steps)
+        res["learned_over_plain_speedup"] = round(ms / res["learned"]["ms_per_step"], 4)
+        res["plain_stats"] = variant_stats(mpsm, torch, R, S, cfg, dev)
+    del ws, R, S
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="fk_uniform", choices=["fk_uniform", "fk_small", "skewed", "lognormal", "batch"])
+    ap.add_argument("--workload", default="lognormal",
+                    choices=["fk_uniform", "fk_small", "skewed", "lognormal", "batch"])
+    ap.add_argument("--extra", default="fk_uniform,skewed",
+                    help="comma-separated single-join workloads reported beside the headline ('' for none)")
     ap.add_argument("--autotune-cache", default=None, help="batch workload: autotuner cache file")
-    ap.add_argument("--cpu-sample-shift", type=int, default=3)
+    ap.add_argument("--cpu-sample-shift", type=int, default=4)
+    ap.add_argument("--cpu-threads", type=int, default=0, help="threads of the CPU baseline (0: all cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-CDF variant")
     ap.add_argument("--search", default="index", choices=["index", "binary", "interp"])
@@ -341,104 +479,42 @@ def main():
     if args.workload == "batch":
         batch_bench(args)
         return
-    import numpy as np
     import torch
-    import paper_1207_0145_amd as mpsm
-    import workloads
-
-    log(f"generating {args.workload}")
-    w = workloads.make(args.workload)
-    nR, nS = len(w.R), len(w.S)
-    dev = torch.device("cuda", 0)
-    R = torch.from_numpy(w.R.view(np.int64)).to(dev)
-    S = torch.from_numpy(w.S.view(np.int64)).to(dev)
-    del w
-    search = {"index": mpsm.SEARCH_INDEX, "binary": mpsm.SEARCH_BINARY, "interp": mpsm.SEARCH_INTERP}[args.search]
-    cfg = mpsm.config(search=search)
-    cfg_learned = mpsm.config(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED)
-    lay = mpsm.layout(nR, nS, cfg)
-    ws = mpsm.alloc_workspace(nR, nS, cfg, dev)
-    out = torch.zeros(2, dtype=torch.int64, device=dev)
-    names = mpsm.marker_names()
-    log(f"|R|={nR} |S|={nS} workspace={ws.numel() / 2**30:.2f} GiB runs={lay['runs']} "
-        f"R levels={lay['levels']}")
-    if args.calibrate_copy:
-        x = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        log("copy calibration: 1073741824 bytes read and written once")
-        del x, y
-    for i in range(args.warmup):
-        mpsm.join_into(R, S, out, ws, cfg)
-    torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
-
-    evsets = [mpsm.EventSet(len(names)) for _ in range(args.steps)]
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for k in range(args.steps):
-        mpsm.join_events_into(R, S, out, ws, evsets[k], cfg)
-    t1.record()
-    torch.cuda.synchronize()
-    total_ms = t0.elapsed_time(t1)
-    ms = total_ms / args.steps
-    log(f"timed {args.steps} steps: {ms:.3f} ms/step")
-    count, checksum = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
-
-    steps_ms, overlapped = step_times(names, evsets, args.steps)
-    for e in evsets:
-        e.close()
-
-    def step_bytes(step):
-        rel, b = STEP_BYTES[step]
-        n = {"S": nS, "R": nR, "RS": nR + nS}[rel]
-        return b * n
-
-    dom = max((s for s in STEP_BYTES if steps_ms.get(s, 0) > 0), key=lambda s: steps_ms[s])
-    achieved = step_bytes(dom) / (steps_ms[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(dom, args.workload)
-    path_bytes = 48 * nS + 64 * nR
-    path_gbs = path_bytes / (ms * 1e-3) / 1e9
-    value = (nR + nS) / (ms * 1e-3) / 1e6
-    copy_gbs = copy_bandwidth(torch, dev)
+    main_res = measure(args, args.workload, args.steps, learned=not args.no_learned)
+    copy_gbs = copy_bandwidth(torch, torch.device("cuda", 0))
     log(f"device copy: {copy_gbs:.0f} GB/s")
-
-    res = {
-        "metric": METRIC, "value": round(value, 2), "unit": "M tuples/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "strong",
+    m = main_res
+    m["roofline"]["frac_of_measured_copy"] = round(m["roofline"]["achieved"] / copy_gbs, 4)
+    m["path_roofline"]["frac_of_measured_copy"] = round(m["path_roofline"]["achieved"] / copy_gbs, 4)
+    line = {
+        "metric": METRIC, "value": m["value"], "unit": "M tuples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": m["ms_per_step"], "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: |R|=2^{nR.bit_length() - 1}, |S|=2^{nS.bit_length() - 1}, "
+        "config": {"workload": f"{args.workload}: |R|=2^{m['nR'].bit_length() - 1}, |S|=2^{m['nS'].bit_length() - 1}, "
                                f"{WORKLOAD_KEYS[args.workload]}, 16-byte tuples (u64 key, u64 payload)",
-                   "nR": nR, "nS": nS, "variant": "plain (sampled splitters, " + args.search + " start search)",
-                   "runs": lay["runs"], "run_len": lay["run_len"], "r_levels": lay["levels"]},
-        "result": {"count": count, "checksum": f"{checksum:#018x}"},
-        "roofline": {"bound": "hbm", "kernel": KERNEL_OF_STEP[dom], "step": dom,
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes": step_bytes(dom),
-                     "avg_launch_ms": round(steps_ms[dom], 4),
-                     "frac_of_measured_copy": round(achieved / copy_gbs, 4),
-                     # the kernel's launch time includes sharing the GPU with
-                     # R's phase when that runs on the second stream (beside
-                     # S's steps after the scatter)
-                     "concurrent_with": "R partitioning and sort (second stream)"
-                     if overlapped and dom in ("s_bucket_sort", "s_oversize_sort") else None},
-        "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_gbs, 1), "unit": "GB/s",
-                          "frac": round(path_gbs / HBM_PEAK_GBS, 4),
-                          "frac_of_measured_copy": round(path_gbs / copy_gbs, 4)},
-        "measured_copy_GBps": round(copy_gbs, 1),
-        "steps_ms": {k: round(v, 4) for k, v in steps_ms.items()},
+                   "nR": m["nR"], "nS": m["nS"], "variant": m["variant"], "runs": m["runs"], "run_len": m["run_len"],
+                   "r_levels": m["r_levels"]},
+        "result": m["result"], "roofline": m["roofline"], "path_roofline": m["path_roofline"],
+        "measured_copy_GBps": round(copy_gbs, 1), "steps_ms": m["steps_ms"],
     }
-    if not args.no_learned:
-        res["learned"] = run_variant(mpsm, torch, R, S, out, cfg_learned, args, names, nR, nS, "learned")
-        res["plain_stats"] = variant_stats(mpsm, torch, R, S, cfg, dev)
+    for k in ("learned", "learned_over_plain_speedup", "plain_stats"):
+        if k in m:
+            line[k] = m[k]
+    extras = {}
+    for wl in [x for x in args.extra.split(",") if x and x != args.workload]:
+        e = measure(args, wl, max(5, args.steps // 2), learned=not args.no_learned)
+        e.pop("plain_stats", None)
+        if "learned" in e:
+            e["learned"].pop("stats", None)
+            e["learned"].pop("steps_ms", None)
+        extras[wl] = e
+    if extras:
+        line["other_workloads"] = extras
     if not args.no_cpu_baseline:
-        log(f"cpu baseline (oracle, 1 thread, 1/{1 << args.cpu_sample_shift} scale)")
-        res["cpu_baseline"] = cpu_baseline(args.cpu_sample_shift)
-    print(json.dumps(res), flush=True)
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        log(f"cpu baseline (oracle, 1 and {threads} threads, 1/{1 << args.cpu_sample_shift} scale)")
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_shift, threads)
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

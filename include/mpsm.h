@@ -25,7 +25,8 @@
  *     pointer after returning.  The caller owns all buffers.
  *   - Inputs are never modified.
  *   - Arguments are validated on the host before anything is enqueued; a
- *     rejected call enqueues nothing.
+ *     rejected call enqueues nothing.  Only a failing HIP runtime call
+ *     (MPSM_EHIP) can end a call after part of its work was enqueued.
  */
 #ifndef MPSM_H
 #define MPSM_H
@@ -116,6 +117,7 @@ typedef struct mpsm_stats {
   double cdf_eps_s;           /* learned CDF of S: same */
   uint64_t resorted_buckets;  /* buckets whose one-pass sort gave up, re-sorted by LSD radix passes */
   uint64_t retried_buckets;   /* R buckets the one-pass sort gave up on and sorted again over their own key range */
+  uint64_t pairs_truncated;   /* 1 if pairs were requested and the join has more than pairs_capacity */
 } mpsm_stats;
 
 /* Fill *cfg with defaults (all automatic, role AUTO, sampled splitters,
@@ -143,9 +145,14 @@ uint64_t mpsm_workspace_bytes(uint64_t nR, uint64_t nS, const mpsm_config* cfg);
  *                   not matter and on return hold intermediate results.
  *   stream          hipStream_t (void* here so the header needs no HIP).
  *   stats           optional; when non-NULL the call synchronises the
- *                   stream and fills *stats (and returns MPSM_ECAPACITY if
- *                   pairs were truncated).
- * Returns MPSM_OK, or an error before anything is enqueued. */
+ *                   stream and fills *stats, and returns MPSM_ECAPACITY if
+ *                   pairs were truncated (the device status word the call
+ *                   keeps in its workspace; without stats the caller can
+ *                   test *d_out_count > pairs_capacity itself).
+ * Returns MPSM_OK; argument errors (MPSM_EINVAL, MPSM_ENOMEM) are returned
+ * before anything is enqueued.  A HIP failure (MPSM_EHIP) can happen after
+ * part of the launch sequence was enqueued; the caller's stream is then made
+ * to wait for the library's side stream before the call returns. */
 mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS,
                       uint64_t* d_out_count, uint64_t* d_out_checksum, mpsm_pair* d_pairs, uint64_t pairs_capacity,
                       const mpsm_config* cfg, void* d_workspace, uint64_t workspace_bytes, void* stream,
@@ -297,6 +304,20 @@ mpsm_status mpsm_batch_set_tuning(mpsm_batch* b, const mpsm_batch_tuning* t);
 
 /* Ticks per second of the GPU wall clock used by d_out_times. */
 uint64_t mpsm_clock_hz(void);
+
+/* Host copy of the join kernel's slice plan (Section 3.2.2), for tests that
+ * run without a GPU.  A join unit reads slice j = [oa[j], ob[j]) of each of
+ * the Q sorted S runs (run j at S positions [run_start[j], run_start[j] +
+ * run_len[j])); the offsets come from the start search.  The kernel clamps
+ * both offsets to the run and treats a reversed pair as empty, so its reads
+ * stay inside the runs whatever the offsets hold; this function runs the
+ * same per-run code.  Host arrays: oa, ob, run_start, run_len (Q each) in;
+ * cum (Q + 1: exclusive prefix of the clamped slice lengths, cum[Q] their
+ * sum) and sbase (Q: concatenated index x with cum[j] <= x < cum[j+1] reads
+ * S position sbase[j] + x, mod 2^32) out.  Returns MPSM_EINVAL on NULL
+ * arrays with Q > 0. */
+mpsm_status mpsm_join_slices_host(const uint32_t* oa, const uint32_t* ob, const uint32_t* run_start,
+                                  const uint32_t* run_len, uint32_t Q, uint32_t* cum, uint32_t* sbase);
 
 #ifdef __cplusplus
 }

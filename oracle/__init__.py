@@ -4,8 +4,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The product library never loads it,
 and it imports nothing from the product package.
 
-Thin ctypes wrapper around ``oracle.c`` (plain, sequential C, integer
-arithmetic only).  Arrays are numpy ``uint64`` of shape ``[n, 2]``
+Thin ctypes wrapper around ``oracle.c`` (plain, sequential C; integer
+arithmetic in every join result, floating point only in the Section 4
+estimates).  Arrays are numpy ``uint64`` of shape ``[n, 2]``
 (key, payload).  See ``oracle.c`` for the paper passage each function
 follows.
 """
@@ -46,17 +47,18 @@ def lib():
             "orc_sort_pairs": ([p, u64], None),
             "orc_join": ([p, u64, p, u64, p, p, u64], i32),
             "orc_join_nested": ([p, u64, p, u64, p, p, u64], i32),
+            "orc_join_key_range": ([p, u64, p, u64, u64, u64, i32, p], i32),
             "orc_join_hash": ([p, u64, p, u64, p, p], i32),
             "orc_fk_closed_form": ([p, p, p, u64, p], i32),
             "orc_sort_runs": ([p, u64, u64, p], i32),
             "orc_radix_partition": ([p, u64, u64, i32, i32, p, u32, p, p, p, p], i32),
             "orc_sample_splitters": ([p, u64, u32, u32, u64, p], i32),
-            "orc_splitters_from_sample": ([p, u64, u32, u32, p], None),
             "orc_bucket_of": ([p, u32, u64], u32),
             "orc_bucket_partition": ([p, u64, p, u32, p, p], i32),
             "orc_lower_bound": ([p, u64, u64], u64),
             "orc_interp_search": ([p, u64, u64, p], u64),
-            "orc_equi_height": ([p, u64, u32, p], None),
+            "orc_equi_height": ([p, u64, u64, p], u64),
+            "orc_s_cdf": ([p, p, u32, u64, p, u64, p], i32),
             "orc_split_cost": ([u64, u32, u64], dbl),
             "orc_cost_splitters_dp": ([p, p, u32, u32, u32, p], dbl),
             "orc_pmpsm_join": ([p, u64, p, u64, u32, i32, i32, p, p], i32),
@@ -123,6 +125,32 @@ def join(R, S, pairs: bool = False, cap: int | None = None) -> JoinResult:
     return _result(out4, pbuf)
 
 
+def join_key_range(R, S, lo: int, hi: int | None) -> JoinResult:
+    """The join restricted to keys in [lo, hi) (hi None: up to 2^64 - 1)."""
+    R, S = _tuples(R), _tuples(S)
+    out4 = np.zeros(4, np.uint64)
+    _check(lib().orc_join_key_range(_p(R), len(R), _p(S), len(S), lo, 0 if hi is None else hi,
+                                    1 if hi is None else 0, _p(out4)), "join_key_range")
+    return _result(out4)
+
+
+def join_sliced(R, S, bounds, threads: int = 1) -> JoinResult:
+    """The join as the sum of its key-range slices [b_i, b_{i+1}) over the
+    sorted inner bounds (first slice from 0, last to 2^64 - 1), each slice
+    joined by join_key_range, the slices spread over `threads` threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    edges = [0] + [int(b) for b in bounds] + [None]
+    parts = [(edges[i], edges[i + 1]) for i in range(len(edges) - 1)]
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        res = list(ex.map(lambda ab: join_key_range(R, S, ab[0], ab[1]), parts))
+    M = (1 << 64) - 1
+    count = sum(r.count for r in res)
+    checksum = sum(r.checksum for r in res) & M
+    nonempty = any(r.nonempty for r in res)
+    maxsum = max((r.maxsum for r in res if r.nonempty), default=0)
+    return JoinResult(count, checksum, maxsum, nonempty)
+
+
 def join_nested(R, S, pairs: bool = False) -> JoinResult:
     R, S = _tuples(R), _tuples(S)
     out4 = np.zeros(4, np.uint64)
@@ -184,17 +212,6 @@ def sample_splitters(T, nbucket: int, oversample: int, seed: int) -> np.ndarray:
     return spl[: max(nbucket - 1, 0)]
 
 
-def splitters_from_sample(sorted_sample, nbucket: int, oversample: int) -> np.ndarray:
-    """Splitters from a sorted sample of nbucket * oversample keys (the rule
-    of orc_splitters_from_sample: every oversample-th key, with frequent keys
-    of a single splitter given a bucket of their own)."""
-    smp = np.ascontiguousarray(sorted_sample, dtype=np.uint64)
-    assert len(smp) == nbucket * oversample
-    spl = np.zeros(max(nbucket - 1, 1), np.uint64)
-    lib().orc_splitters_from_sample(_p(smp), len(smp), nbucket, oversample, _p(spl))
-    return spl[: max(nbucket - 1, 0)]
-
-
 def bucket_of(spl, nbucket: int, key: int) -> int:
     spl = np.ascontiguousarray(spl, dtype=np.uint64)
     return int(lib().orc_bucket_of(_p(spl) if len(spl) else None, nbucket, key))
@@ -222,11 +239,26 @@ def interp_search(run, key: int):
     return pos, int(probes.value)
 
 
-def equi_height(run, nb: int) -> np.ndarray:
+def equi_height(run, stride: int) -> np.ndarray:
+    """Bounds of the run's equi-height histogram: its key at every
+    stride-th position from 0 (Section 4.1)."""
     run = _tuples(run)
-    out = np.zeros(nb, np.uint64)
-    lib().orc_equi_height(_p(run), len(run), nb, _p(out))
-    return out
+    out = np.zeros(max(1, (len(run) + stride - 1) // stride), np.uint64)
+    m = int(lib().orc_equi_height(_p(run), len(run), stride, _p(out)))
+    return out[:m]
+
+
+def s_cdf(S_runs, run_start, stride: int, keys) -> np.ndarray:
+    """Estimated number of S tuples below each key, from the runs' merged
+    equi-height bounds with equal step heights and linear interpolation
+    (Section 4.1, Fig. 8).  S_runs: the sorted runs concatenated; run_start:
+    Q + 1 run boundaries."""
+    S_runs = _tuples(S_runs)
+    rs = np.ascontiguousarray(run_start, dtype=np.uint64)
+    x = np.ascontiguousarray(keys, dtype=np.uint64)
+    out = np.zeros(max(1, len(x)), np.float64)
+    _check(lib().orc_s_cdf(_p(S_runs), _p(rs), len(rs) - 1, stride, _p(x), len(x), _p(out)), "s_cdf")
+    return out[:len(x)]
 
 
 def split_cost(r_size: int, T: int, s_tuples: int) -> float:

@@ -7,9 +7,11 @@
  * calls this file; only the tests, the smoke check and the CPU-baseline leg
  * of the benchmark do.  It shares no code with the GPU path.
  *
- * Everything here is plain, slow and sequential on purpose.  All arithmetic
- * is on unsigned 64-bit integers (the paper's keys and payloads are 64-bit
- * integers, Section 5.1); there is no floating point in any result.
+ * Everything here is plain, slow and sequential on purpose.  All join
+ * arithmetic is on unsigned 64-bit integers (the paper's keys and payloads
+ * are 64-bit integers, Section 5.1).  Floating point appears only in the two
+ * estimates of Section 4 (the S distribution and the partition cost), which
+ * choose splitters and never decide a join result.
  *
  * Tuples are arrays of 2*n uint64: T[2i] = key, T[2i+1] = payload.
  *
@@ -21,10 +23,11 @@
  *     foreign-key closed form;
  *   - the method's steps: phase 1 run sort (Section 2.3/3.2), phase 2
  *     histogram / prefix sum / scatter (Section 3.2.1, eq. for ps_i,
- *     Figs. 6 and 10), sampled splitters and their bucket function, phase 4
- *     start search by lower bound and by interpolation (Section 3.2.2,
- *     Fig. 7), the equi-height S CDF (Section 4.1), the cost-balanced
- *     splitter objective (Section 4.3), and the full P-MPSM join (Fig. 5).
+ *     Figs. 6 and 10), equi-depth sampled splitters and their bucket
+ *     function, phase 4 start search by lower bound and by interpolation
+ *     (Section 3.2.2, Fig. 7), the global S distribution from merged
+ *     equi-height bounds (Section 4.1, Fig. 8), the split-relevant cost and
+ *     its min-max split (Section 4.3), and the full P-MPSM join (Fig. 5).
  *
  * Pins: see tests/test_oracle_pins.py.  The learned-CDF quality is not
  * computed here (parity unpinned: the paper has no learned model; only
@@ -145,6 +148,29 @@ int orc_join(const uint64_t* R, uint64_t nR, const uint64_t* S, uint64_t nS, uin
   if (pairs) orc_sort_pairs(pairs, a.count < cap ? a.count : cap);
   free(r); free(s);
   return 0;
+}
+
+/* The join restricted to the keys in [lo, hi) (to_top != 0: [lo, 2^64-1]).
+ * Pairs have equal keys, so the joins of the slices of any partition of the
+ * key space add up to the whole join (counts and checksums as wrapping sums,
+ * max as the largest slice max): large joins are checked slice by slice
+ * with bounded memory and one slice per thread.  out4 as in orc_join. */
+int orc_join_key_range(const uint64_t* R, uint64_t nR, const uint64_t* S, uint64_t nS, uint64_t lo, uint64_t hi,
+                       int to_top, uint64_t* out4) {
+  uint64_t mR = 0, mS = 0;
+  for (uint64_t i = 0; i < nR; i++) mR += R[2 * i] >= lo && (to_top || R[2 * i] < hi);
+  for (uint64_t j = 0; j < nS; j++) mS += S[2 * j] >= lo && (to_top || S[2 * j] < hi);
+  uint64_t* r = (uint64_t*)malloc((2 * mR + 2) * sizeof(uint64_t));
+  uint64_t* s = (uint64_t*)malloc((2 * mS + 2) * sizeof(uint64_t));
+  if (!r || !s) { free(r); free(s); return -1; }
+  uint64_t a = 0, b = 0;
+  for (uint64_t i = 0; i < nR; i++)
+    if (R[2 * i] >= lo && (to_top || R[2 * i] < hi)) { r[2 * a] = R[2 * i]; r[2 * a + 1] = R[2 * i + 1]; a++; }
+  for (uint64_t j = 0; j < nS; j++)
+    if (S[2 * j] >= lo && (to_top || S[2 * j] < hi)) { s[2 * b] = S[2 * j]; s[2 * b + 1] = S[2 * j + 1]; b++; }
+  int rc = orc_join(r, mR, s, mS, out4, NULL, 0);
+  free(r); free(s);
+  return rc;
 }
 
 /* Pin: nested-loop join (every R tuple against every S tuple). */
@@ -271,69 +297,37 @@ int orc_radix_partition(const uint64_t* C, uint64_t n, uint64_t chunk_len, int B
 
 /* ----------------------------------------- sampled splitters and buckets */
 
-/* Equi-depth sampled splitters.  m = oversample * nbucket sample positions
- * are drawn uniformly (with replacement) from the segment [0, len) by the
- * SplitMix64 stream `seed`: pos_t = floor(x_t * len / 2^64); the sampled keys
- * are sorted and splitter m' (m' = 1..nbucket-1) is sorted[m' * oversample].
- * Writes nbucket-1 splitters to spl (non-decreasing). */
-/* Splitters from a sorted sample of m = nbucket * oversample keys: splitter
- * j (0 <= j < nbucket-1) is the sample key at rank (j+1)*oversample, except
- * that a key which is the only splitter equal to it and which also fills the
- * sample oversample/2 ranks before or after that rank (so about half a
- * bucket's worth of the input or more) gets a bucket of its own: the next
- * splitter becomes key + 1, provided that is below it.  A moved splitter no
- * longer carries its own key, so along a run of such splitters every other
- * one moves (the first, the third, ...).  With the bucket function below,
- * keys of at least two splitters were isolated already; this isolates the
- * keys of one, so that no bucket holds a frequent key plus a full bucket of
- * other keys. */
-void orc_splitters_from_sample(const uint64_t* smp, uint64_t m, uint32_t nbucket, uint32_t oversample,
-                               uint64_t* spl) {
-  const uint64_t h = oversample / 2;
-  int moved_prev = 0;   /* splitter j-1 moved splitter j */
-  for (uint32_t j = 0; j + 1 < nbucket; j++) {
-    const uint64_t pos = (uint64_t)(j + 1) * oversample, c = smp[pos];
-    spl[j] = moved_prev ? smp[pos - oversample] + 1 : c;
-    int moves = 0;
-    if (h && !moved_prev && j + 2 < nbucket) {
-      const uint64_t next = smp[pos + oversample];
-      const int prev_same = j > 0 && smp[pos - oversample] == c;
-      if (!prev_same && next - c > 1)   /* next >= c: no wrap-around */
-        moves = (pos >= h && smp[pos - h] == c) || (pos + h < m && smp[pos + h] == c);
-    }
-    moved_prev = moves;
-  }
-}
-
+/* Equi-depth sampled splitters (the range partitioning's bounds, Sections
+ * 3.2.1 and 4.3, drawn from a sample instead of a radix histogram; the paper
+ * fixes no sample, so this is a reading).  m = oversample * nbucket sample
+ * positions are drawn uniformly, with replacement, from the segment [0, len)
+ * by the SplitMix64 stream `seed`: pos_t = floor(x_t * len / 2^64).  The
+ * sampled keys are sorted and splitter j (j = 0 .. nbucket-2) is the sample
+ * key of rank (j+1) * oversample.  Writes nbucket-1 non-decreasing
+ * splitters to spl. */
 int orc_sample_splitters(const uint64_t* T, uint64_t len, uint32_t nbucket, uint32_t oversample, uint64_t seed,
                          uint64_t* spl) {
   if (nbucket < 2) return 0;
   uint64_t m = (uint64_t)nbucket * oversample;
   uint64_t* smp = (uint64_t*)malloc(2 * m * sizeof(uint64_t));
-  uint64_t* keys = (uint64_t*)malloc(m * sizeof(uint64_t));
-  if (!smp || !keys) { free(smp); free(keys); return -1; }
+  if (!smp) return -1;
   for (uint64_t t = 0; t < m; t++) {
     uint64_t pos = (uint64_t)(((unsigned __int128)orc_splitmix_at(seed, t) * len) >> 64);
     smp[2 * t] = T[2 * pos]; smp[2 * t + 1] = 0;
   }
   orc_sort_by_key(smp, m);
-  for (uint64_t t = 0; t < m; t++) keys[t] = smp[2 * t];
-  orc_splitters_from_sample(keys, m, nbucket, oversample, spl);
+  for (uint32_t j = 0; j + 1 < nbucket; j++) spl[j] = smp[2 * ((uint64_t)(j + 1) * oversample)];
   free(smp);
-  free(keys);
   return 0;
 }
 
 /* Bucket of a key under nbucket-1 sorted splitters: the number of splitters
- * <= key (bucket b holds [spl[b-1], spl[b])).  When the key equals two or
- * more splitters, bucket b-1 = [key, key) would be empty, so the key is put
- * there instead: a key frequent enough to be drawn twice gets a bucket of its
- * own.  The map is non-decreasing in the key, which is all the range
- * partitioning needs (Section 3.2.1). */
+ * <= key, so bucket b holds the keys in [spl[b-1], spl[b]) (the partition
+ * [low, high) of Section 4.3).  Non-decreasing in the key, which is all the
+ * range partitioning needs (Section 3.2.1). */
 uint32_t orc_bucket_of(const uint64_t* spl, uint32_t nbucket, uint64_t key) {
   uint32_t b = 0;
-  while (b < nbucket - 1 && spl[b] <= key) b++;
-  if (b >= 2 && spl[b - 1] == key && spl[b - 2] == key) b--;
+  while (b + 1 < nbucket && spl[b] <= key) b++;
   return b;
 }
 
@@ -401,10 +395,66 @@ uint64_t orc_interp_search(const uint64_t* run, uint64_t n, uint64_t key, uint32
 
 /* ------------------------------------------- Section 4: S CDF and costs */
 
-/* Equi-height bounds of one sorted run (Section 4.1): nb keys at positions
- * floor((t+1) * n / (nb+1)), t = 0..nb-1. */
-void orc_equi_height(const uint64_t* run, uint64_t n, uint32_t nb, uint64_t* out) {
-  for (uint32_t t = 0; t < nb; t++) out[t] = n ? run[2 * (((uint64_t)(t + 1) * n) / (nb + 1))] : 0;
+/* Equi-height histogram of one sorted run (Section 4.1): buckets of
+ * `stride` consecutive tuples (the last one may be shorter); the bound of
+ * bucket t is its first key, at position t * stride.  Writes
+ * ceil(n / stride) bounds; returns their number. */
+uint64_t orc_equi_height(const uint64_t* run, uint64_t n, uint64_t stride, uint64_t* out) {
+  uint64_t m = 0;
+  for (uint64_t p = 0; p < n; p += stride) out[m++] = run[2 * p];
+  return m;
+}
+
+static int cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+/* Global S distribution from the runs' local equi-height histograms
+ * (Section 4.1, Fig. 8).  The Q sorted runs are concatenated in S (run j
+ * holds positions [run_start[j], run_start[j+1])).  Steps:
+ *   1. every run contributes its equi-height bounds (orc_equi_height with
+ *      `stride`);
+ *   2. the bounds of all runs are merged into one sorted list v_1 <= ... <=
+ *      v_N;
+ *   3. every bound is taken as one step of the same height h = |S| / N
+ *      (the paper approximates the steps as equally high);
+ *   4. between steps the distribution is interpolated linearly (the
+ *      diagonal connections of Fig. 8): for v_k < x <= v_{k+1}
+ *          C(x) = h (k - 1) + h (x - v_k) / (v_{k+1} - v_k),
+ *      with C(x) = 0 for x <= v_1 and, past the last bound, the last step
+ *      running up to one past the largest key of S, where C = |S|.
+ * out[i] = C(x[i]), the estimated number of S tuples with key < x[i].
+ * Floating point (long double) only shapes the estimate; the join never
+ * depends on it. */
+int orc_s_cdf(const uint64_t* S, const uint64_t* run_start, uint32_t Q, uint64_t stride, const uint64_t* x,
+              uint64_t nx, double* out) {
+  uint64_t nS = run_start[Q], cap = 0;
+  for (uint32_t j = 0; j < Q; j++) cap += (run_start[j + 1] - run_start[j] + stride - 1) / stride;
+  uint64_t* v = (uint64_t*)malloc((cap + 1) * sizeof(uint64_t));
+  if (!v) return -1;
+  uint64_t N = 0, kmax = 0;
+  for (uint32_t j = 0; j < Q; j++) {
+    uint64_t a = run_start[j], n = run_start[j + 1] - a;
+    N += orc_equi_height(S + 2 * a, n, stride, v + N);
+    if (n && S[2 * (a + n - 1)] > kmax) kmax = S[2 * (a + n - 1)];
+  }
+  qsort(v, N, sizeof(uint64_t), cmp_u64);
+  const long double h = N ? (long double)nS / (long double)N : 0.0L;
+  for (uint64_t i = 0; i < nx; i++) {
+    const uint64_t q = x[i];
+    if (N == 0 || q <= v[0]) { out[i] = 0.0; continue; }
+    uint64_t lo = 0, hi = N;                /* k = number of bounds < q (k >= 1 here) */
+    while (lo < hi) { uint64_t mid = lo + (hi - lo) / 2; if (v[mid] < q) lo = mid + 1; else hi = mid; }
+    const uint64_t k = lo;
+    const long double vk = (long double)v[k - 1];
+    const long double vn = k < N ? (long double)v[k] : (long double)kmax + 1.0L;
+    long double frac = vn > vk ? ((long double)q - vk) / (vn - vk) : 1.0L;
+    if (frac > 1.0L) frac = 1.0L;
+    out[i] = (double)(h * (long double)(k - 1) + h * frac);
+  }
+  free(v);
+  return 0;
 }
 
 /* split-relevant cost of one R partition (Section 4.3):

@@ -25,7 +25,7 @@ EXPORTS = ("mpsm_config_default", "mpsm_workspace_bytes", "mpsm_join", "mpsm_sta
            "mpsm_workspace_layout", "mpsm_join_events", "mpsm_marker_count", "mpsm_marker_name",
            "mpsm_events_create", "mpsm_events_destroy", "mpsm_events_elapsed", "mpsm_batch_create",
            "mpsm_batch_destroy", "mpsm_batch_workspace_bytes", "mpsm_batch_run", "mpsm_batch_autotune",
-           "mpsm_batch_get_tuning", "mpsm_batch_set_tuning", "mpsm_clock_hz")
+           "mpsm_batch_get_tuning", "mpsm_batch_set_tuning", "mpsm_clock_hz", "mpsm_join_slices_host")
 
 
 class MpsmConfig(ctypes.Structure):
@@ -41,7 +41,8 @@ class MpsmStats(ctypes.Structure):
                 ("search_probes", ctypes.c_uint64), ("swapped", ctypes.c_uint64), ("ms_total", ctypes.c_double),
                 ("search_fallbacks", ctypes.c_uint64), ("max_partition", ctypes.c_uint64),
                 ("cdf_eps_r", ctypes.c_double), ("cdf_eps_s", ctypes.c_double),
-                ("resorted_buckets", ctypes.c_uint64), ("retried_buckets", ctypes.c_uint64)]
+                ("resorted_buckets", ctypes.c_uint64), ("retried_buckets", ctypes.c_uint64),
+                ("pairs_truncated", ctypes.c_uint64)]
 
 
 class MpsmLayout(ctypes.Structure):
@@ -134,6 +135,8 @@ def lib():
         L.mpsm_batch_set_tuning.restype = ctypes.c_int
         L.mpsm_clock_hz.argtypes = []
         L.mpsm_clock_hz.restype = u64
+        L.mpsm_join_slices_host.argtypes = [p, p, p, p, ctypes.c_uint32, p, p]
+        L.mpsm_join_slices_host.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -367,3 +370,18 @@ class Batch:
 
 def clock_hz() -> int:
     return int(lib().mpsm_clock_hz())
+
+
+def join_slices_host(oa, ob, run_start, run_len):
+    """The join kernel's slice plan, run on the host (no GPU): returns
+    (cum[Q + 1], sbase[Q]) as numpy uint32 arrays."""
+    import numpy as np
+    arrs = [np.ascontiguousarray(a, dtype=np.uint32) for a in (oa, ob, run_start, run_len)]
+    Q = len(arrs[0])
+    cum = np.zeros(Q + 1, np.uint32)
+    sbase = np.zeros(max(Q, 1), np.uint32)
+    rc = lib().mpsm_join_slices_host(*[ctypes.c_void_p(a.ctypes.data) for a in arrs], Q,
+                                     ctypes.c_void_p(cum.ctypes.data), ctypes.c_void_p(sbase.ctypes.data))
+    if rc != 0:
+        raise MpsmError(rc, "mpsm_join_slices_host")
+    return cum, sbase[:Q]

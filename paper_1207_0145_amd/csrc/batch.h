@@ -112,7 +112,8 @@ __global__ void k_join_units_batch(const uint32_t* Pcount, const uint32_t* plen,
 
 // Work items of every join unit (as k_join_items) and the item count per join.
 __global__ void k_join_items_batch(const uint32_t* Pcount, const uint32_t* pjoin, BatchJoin* J, const uint32_t* o,
-                                   uint32_t Pmax, uint32_t JCH, const uint8_t* span, uint32_t* items) {
+                                   const uint32_t* run_len, uint32_t Pmax, uint32_t JCH, const uint8_t* span,
+                                   uint32_t* items) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > Pmax + 1) return;
   const uint32_t P = *Pcount;
@@ -125,7 +126,8 @@ __global__ void k_join_items_batch(const uint32_t* Pcount, const uint32_t* pjoin
       const uint32_t* a = o + J[jb].obase + (uint64_t)(p - J[jb].p0) * Q;
       const uint32_t* b = a + (uint64_t)sp * Q;
       uint64_t np = 0;
-      for (uint32_t q = 0; q < Q; q++) np += b[q] > a[q] ? b[q] - a[q] : 0;   // as in k_join
+      const uint32_t* rl = run_len + J[jb].r0;
+      for (uint32_t q = 0; q < Q; q++) np += slice_len(a[q], b[q], rl[q]);   // as in k_join
       it = (uint32_t)((np + JCH - 1) / JCH);
       if (it) atomicAdd(&J[jb].items, it);
     }

@@ -17,6 +17,7 @@
 // (Section 3.2.2) and joins each R partition, held in LDS, with its slices.
 #pragma once
 #include "block_sort.h"
+#include "join_slices.h"
 
 // ------------------------------------------------------------------ config
 // bucket sort instances: small tiles for S buckets, large tiles (= the join's
@@ -62,6 +63,7 @@ constexpr int SCAN_BLOCK = SCAN_NT * SCAN_IPT;
 struct Result {              // device result block
   unsigned long long count, checksum, maxsum, nonempty;
   unsigned long long big_buckets, search_probes, fallbacks, spare;   // spare: largest R partition
+  unsigned long long truncated;   // status word: 1 if pairs were requested and count > their capacity
 };
 
 // One join of a batch (device table).  The host fills the run and bucket
@@ -84,14 +86,18 @@ __global__ void k_init_result(Result* res, uint32_t* zero_words, uint32_t nzero)
   if (t == 0) {
     res->count = 0; res->checksum = 0; res->maxsum = 0; res->nonempty = 0;
     res->big_buckets = 0; res->search_probes = 0; res->fallbacks = 0; res->spare = 0;
+    res->truncated = 0;
   }
   for (uint32_t i = t; i < nzero; i += gridDim.x * blockDim.x) zero_words[i] = 0;
 }
 
-__global__ void k_finalize(const Result* res, uint64_t* out_count, uint64_t* out_checksum) {
+// Results to the caller's slots; with pairs requested (pairs_cap > 0) the
+// status word records whether the pair buffer was too small.
+__global__ void k_finalize(Result* res, uint64_t* out_count, uint64_t* out_checksum, uint64_t pairs_cap) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *out_count = res->count;
     *out_checksum = res->checksum;
+    res->truncated = (pairs_cap && res->count > pairs_cap) ? 1ull : 0ull;
   }
 }
 
@@ -1403,8 +1409,8 @@ __global__ void k_join_units(const uint32_t* Pcount, const uint32_t* plen, uint3
 
 // Work items: join unit u contributes ceil(n_u / JCH) items, n_u = S tuples
 // in its slices (0 when nothing can match).  items has Pmax + 2 entries.
-__global__ void k_join_items(const uint32_t* Pcount, const uint32_t* o, uint32_t Q, uint32_t Pmax, uint32_t JCH,
-                             const uint8_t* span, uint32_t* items) {
+__global__ void k_join_items(const uint32_t* Pcount, const uint32_t* o, uint32_t Q, const uint32_t* run_len,
+                             uint32_t Pmax, uint32_t JCH, const uint8_t* span, uint32_t* items) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p > Pmax + 1) return;
   const uint32_t P = *Pcount;
@@ -1415,7 +1421,7 @@ __global__ void k_join_items(const uint32_t* Pcount, const uint32_t* o, uint32_t
       uint64_t np = 0;
       const uint32_t* a = o + (uint64_t)p * Q;
       const uint32_t* b = a + (uint64_t)sp * Q;
-      for (uint32_t j = 0; j < Q; j++) np += b[j] > a[j] ? b[j] - a[j] : 0;   // as in k_join
+      for (uint32_t j = 0; j < Q; j++) np += slice_len(a[j], b[j], run_len[j]);   // as in k_join
       it = (uint32_t)((np + JCH - 1) / JCH);
     }
   }
@@ -1428,6 +1434,7 @@ struct JoinArgs {
   const tup_t* Rs;          // R sorted, partitions contiguous
   const tup_t* U;           // S runs sorted
   const uint32_t* run_start;
+  const uint32_t* run_len;
   uint32_t Q;
   const uint32_t* Pcount;
   const uint32_t* pstart;
@@ -1514,13 +1521,12 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
     uint32_t carry = 0;
     for (uint32_t j0 = 0; j0 < Q; j0 += JOIN_NT) {
       const uint32_t j = j0 + tid;
-      const uint32_t oj = j < Q ? oa[j] : 0;
-      // offsets are monotone in the partition for sorted runs; clamped so
-      // that every read stays inside run j whatever the offsets hold
-      const uint32_t len = (j < Q && ob[j] > oj) ? ob[j] - oj : 0;
+      // clamped so that every read stays inside run j whatever the offsets hold
+      const uint32_t nj = j < Q ? A.run_len[r0 + j] : 0;
+      const uint32_t len = j < Q ? slice_len(oa[j], ob[j], nj) : 0;
       uint32_t tot;
       const uint32_t ex = block_excl_scan<JOIN_NT>(len, wsum, &tot);
-      if (j < Q) { cum[j] = carry + ex; sbase[j] = A.run_start[r0 + j] + oj - (carry + ex); }
+      if (j < Q) { cum[j] = carry + ex; sbase[j] = slice_base(A.run_start[r0 + j], oa[j], nj, carry + ex); }
       carry += tot;
       __syncthreads();
     }

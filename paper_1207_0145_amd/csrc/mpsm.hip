@@ -500,7 +500,7 @@ namespace {
 mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS, uint64_t* d_out_count,
                       uint64_t* d_out_checksum, mpsm_pair* d_pairs, uint64_t pairs_capacity, const mpsm_config* cfg,
                       void* d_workspace, uint64_t workspace_bytes, void* stream, mpsm_stats* stats, void** events,
-                      uint32_t n_events) {
+                      uint32_t n_events, bool single_stream = false) {
   mpsm_config def;
   if (!cfg) { mpsm_config_default(&def); cfg = &def; }
   if (!config_valid(cfg)) return MPSM_EINVAL;
@@ -519,14 +519,33 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     g_num_cus = ncu > 0 ? ncu : 256;
   }
+  // learned splitters use R's model, the learned search S's; both are built
+  // on a side stream while phase 1 runs and joined before R's partitioning.
+  const bool learn_r = P.splitter == MPSM_SPLIT_LEARNED && P.nR && P.nS;
+  const bool learn_s = P.search == MPSM_SEARCH_LEARNED && P.nR && P.nS;
+  // R's partitioning and sort run on the side stream too, beside S's run
+  // generation (they are independent until the search), except with
+  // cost-balanced splitters, which need S's runs.  They start once S's
+  // tuples are scattered into runs: beside S's histogram and scatter, both
+  // bound by HBM and on the critical path, R's passes took bandwidth from
+  // them; S's bucket sort, bound by its ALU work, leaves more of it.
+  const bool r_side = P.splitter != MPSM_SPLIT_COST && P.nR && P.nS && !single_stream;
+  // the side stream and its events exist before anything is enqueued
+  SideStream* side = nullptr;
+  if ((learn_r || learn_s || r_side) && !single_stream) {
+    mpsm_status rs = side_stream(&side);
+    if (rs != MPSM_OK) return rs;
+  }
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (stats) {
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
     HIP_TRY(hipEventRecord(ev0, st));
   }
+  // the launch sequence; on a failure after the side stream was forked, the
+  // caller's stream is made to wait for it before returning
+  bool forked = false;
   Marker mk{events, n_events, st};
-  mk.mark(MK_START);
   char* ws = static_cast<char*>(d_workspace);
   const tup_t* Rin = reinterpret_cast<const tup_t*>(P.swapped ? d_S : d_R);
   const tup_t* Sin = reinterpret_cast<const tup_t*>(P.swapped ? d_R : d_S);
@@ -537,247 +556,248 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
   uint32_t* bsum = reinterpret_cast<uint32_t*>(ws + P.bsum);
   unsigned long long* ctr = reinterpret_cast<unsigned long long*>(ws + P.ctr);
   Result* res = reinterpret_cast<Result*>(ws + P.res);
-
-  k_init_result<<<1, 64, 0, st>>>(res, reinterpret_cast<uint32_t*>(ctr), 16);
-  LAUNCH_CHECK();
-  mk.mark(MK_INIT);
   CdfModel* modelR = reinterpret_cast<CdfModel*>(ws + P.modelR);
   CdfModel* modelS = reinterpret_cast<CdfModel*>(ws + P.modelS);
-  // learned splitters use R's model, the learned search S's; both are built
-  // on a side stream while phase 1 runs and joined before R's partitioning.
-  // The side stream may start from here (fork); its kernels are enqueued
-  // once phase 1's first long kernels are, so that the host time their
-  // launches take never leaves the GPU waiting.
-  const bool learn_r = P.splitter == MPSM_SPLIT_LEARNED && P.nR && P.nS;
-  const bool learn_s = P.search == MPSM_SEARCH_LEARNED && P.nR && P.nS;
-  // R's partitioning and sort run on the side stream too, beside S's run
-  // generation (they are independent until the search), except with
-  // cost-balanced splitters, which need S's runs.  They start once S's
-  // tuples are scattered into runs: beside S's histogram and scatter, both
-  // bound by HBM and on the critical path, R's passes took bandwidth from
-  // them; S's bucket sort, bound by its ALU work, leaves more of it.
-  const bool r_side = P.splitter != MPSM_SPLIT_COST && P.nR && P.nS;
-  SideStream* side = nullptr;
-  if (learn_r || learn_s || r_side) {
-    mpsm_status rs = side_stream(&side);
-    if (rs != MPSM_OK) return rs;
-    HIP_TRY(hipEventRecord(side->fork, st));
-  }
-  auto start_models = [&]() -> mpsm_status {
-    if (!side) return MPSM_OK;
-    HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0));
-    if (!learn_r && !learn_s) return MPSM_OK;
-    CdfJob job;
-    memset(&job, 0, sizeof(job));
-    uint32_t nm = 0;
-    if (learn_r) { job.src[nm] = Rin; job.n[nm] = (uint32_t)P.nR; job.seed[nm] = P.seed ^ TAG_CR; job.model[nm] = modelR; nm++; }
-    if (learn_s) { job.src[nm] = Sin; job.n[nm] = (uint32_t)P.nS; job.seed[nm] = P.seed ^ TAG_CS; job.model[nm] = modelS; nm++; }
-    mpsm_status rc = train_cdf(job, nm, reinterpret_cast<uint64_t*>(ws + P.cdf_chunks),
-                               reinterpret_cast<uint64_t*>(ws + P.cdf_sorted), side->st);
-    if (rc != MPSM_OK) return rc;
-    if (!r_side) HIP_TRY(hipEventRecord(side->done, side->st));
-    return MPSM_OK;
-  };
-  mk.mark(MK_CDF);
-  if (P.nR == 0 || P.nS == 0) {
-    mk.mark_range(MK_S_SPL, MK_JOIN);  // MK_CDF was recorded above
-    k_finalize<<<1, 64, 0, st>>>(res, d_out_count, d_out_checksum);
+  auto enqueue = [&]() -> mpsm_status {
+    mk.mark(MK_START);
+    k_init_result<<<1, 64, 0, st>>>(res, reinterpret_cast<uint32_t*>(ctr), 16);
     LAUNCH_CHECK();
-    mk.mark(MK_FIN);
-  } else {
-    mpsm_status rc;
-    // ---- phase 1: sort S into Q runs of L tuples
-    Level LS = make_level(ws, P.segS, P.Q, P.NBs, 0, P.OSs, P.tilesS, P.seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
-                          P.bndS, P.Gs);
-    LS.run_len = P.L;
-    rc = bucket_pass(Sin, T, (uint32_t)P.nS, LS, bsum, st, mk, MK_S_SPL);
-    if (rc != MPSM_OK) return rc;
-    if (r_side) HIP_TRY(hipEventRecord(side->gate, st));
-    rc = start_models();
-    if (rc != MPSM_OK) return rc;
-    SortOut soS;
-    soS.run_idx = reinterpret_cast<uint64_t*>(ws + P.ridx);
-    soS.run_start = LS.seg.start;
-    soS.idx_stride = IDX_STRIDE;
-    soS.idx_shift = __builtin_ctz(IDX_STRIDE);
-    soS.idx_per_run = P.idx_per_run;
-    soS.NB = P.NBs;
-    soS.bkey = nullptr;
-    uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
-    uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
-    uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
-    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
-                                                                 nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
-    LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
-                                                                      midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
-                                                                      soS);
-    LAUNCH_CHECK();
-    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, redoS, ctr + 3, bigS, ctr + 0, soS);
-    LAUNCH_CHECK();
-    mk.mark(MK_S_SORT);
-    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, bigS, ctr + 0, soS);
-    LAUNCH_CHECK();
-    mk.mark(MK_S_BIG);
-
-    // ---- phase 2: range-partition R (one or two levels); phase 3: sort partitions
-    Level LR1 = make_level(ws, P.segR1, 1, P.NB1, 0, P.OS1, P.tilesR1, P.seed ^ TAG_R1, P.splR1, P.cR1, P.cntR1,
-                           P.bstR1, P.bndR1, P.NB1);
-    if (learn_r) LR1.model = modelR;
-    CostArgs cost_args;
-    if (P.splitter == MPSM_SPLIT_COST) {
-      cost_args.sample = reinterpret_cast<uint64_t*>(ws + P.cost_sample);
-      cost_args.s_below = reinterpret_cast<uint64_t*>(ws + P.cost_s_below);
-      cost_args.best = reinterpret_cast<double*>(ws + P.cost_best);
-      cost_args.run_idx = soS.run_idx;
-      cost_args.run_len = LS.seg.len;
-      cost_args.Q = P.Q;
-      cost_args.idx_per_run = P.idx_per_run;
-      cost_args.stride = IDX_STRIDE;
-      cost_args.nS = P.nS;
-      cost_args.nR = P.nR;
-      LR1.cost = &cost_args;
+    mk.mark(MK_INIT);
+    // The side stream may start from here (fork); its kernels are enqueued
+    // once phase 1's first long kernels are, so that the host time their
+    // launches take never leaves the GPU waiting.  Without a side stream
+    // the models are built on the caller's stream.
+    if (side) {
+      HIP_TRY(hipEventRecord(side->fork, st));
+      forked = true;
     }
-    // the models are needed from here on; R's phase runs on the side stream
-    // after them, or on this stream after S's
-    if (side && !r_side) HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
-    const hipStream_t rst = r_side ? side->st : st;
-    if (r_side) HIP_TRY(hipStreamWaitEvent(rst, side->gate, 0));
-    uint32_t* const rbsum = r_side ? reinterpret_cast<uint32_t*>(ws + P.bsumR) : bsum;
-    Marker mkR{events, n_events, rst};
-    LR1.run_len = (uint32_t)P.nR;   // one segment: all of R
-    rc = bucket_pass(Rin, R1, (uint32_t)P.nR, LR1, rbsum, rst, mkR, MK_R1_SPL);
-    if (rc != MPSM_OK) return rc;
-    SortOut soR;
-    soR.run_idx = nullptr;
-    soR.run_start = nullptr;
-    soR.idx_stride = 1;
-    soR.idx_shift = 0;
-    soR.idx_per_run = 0;
-    soR.NB = 1;
-    soR.bkey = reinterpret_cast<uint64_t*>(ws + P.bkey);
-    uint32_t* redoR = reinterpret_cast<uint32_t*>(ws + P.redoR);
-    uint32_t* bigR = reinterpret_cast<uint32_t*>(ws + P.bigR);
-    const Level* LRf = &LR1;   // level whose buckets are the R partitions
-    Level LR2;
-    tup_t* Rsrc = R1;          // partitioned, unsorted
-    tup_t* Rsorted = R2;
-    if (P.levels == 2) {
-      // 3/4 of the target so that sampling noise rarely pushes a partition past the LDS tile
-      LR2 = make_level(ws, P.segR2, P.NB1, P.NB2, P.BT * 3 / 4, P.OS2, P.tilesR2, P.seed ^ TAG_R2, P.splR2, P.cR2, P.cntR2,
-                       P.bstR2, P.bndR2, P.Gr);
-      LR2.outer = LR1.spl;
-      LR2.outer_nspl = P.NB1 - 1;
-      // the second level stays sampled: its buckets are finer than the model's knots
-      LR2.src_bstart = LR1.bstart;   // segments: the level-1 buckets
-      rc = bucket_pass(R1, R2, (uint32_t)P.nR, LR2, rbsum, rst, mkR, MK_R2_SPL);
+    auto start_models = [&]() -> mpsm_status {
+      if (side) HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0));
+      if (!learn_r && !learn_s) return MPSM_OK;
+      CdfJob job;
+      memset(&job, 0, sizeof(job));
+      uint32_t nm = 0;
+      if (learn_r) { job.src[nm] = Rin; job.n[nm] = (uint32_t)P.nR; job.seed[nm] = P.seed ^ TAG_CR; job.model[nm] = modelR; nm++; }
+      if (learn_s) { job.src[nm] = Sin; job.n[nm] = (uint32_t)P.nS; job.seed[nm] = P.seed ^ TAG_CS; job.model[nm] = modelS; nm++; }
+      mpsm_status rc = train_cdf(job, nm, reinterpret_cast<uint64_t*>(ws + P.cdf_chunks),
+                                 reinterpret_cast<uint64_t*>(ws + P.cdf_sorted), side ? side->st : st);
       if (rc != MPSM_OK) return rc;
-      LRf = &LR2;
-      Rsrc = R2;
-      Rsorted = R1;
+      if (side && !r_side) HIP_TRY(hipEventRecord(side->done, side->st));
+      return MPSM_OK;
+    };
+    mk.mark(MK_CDF);
+    if (P.nR == 0 || P.nS == 0) {
+      mk.mark_range(MK_S_SPL, MK_JOIN);  // MK_CDF was recorded above
+      k_finalize<<<1, 64, 0, st>>>(res, d_out_count, d_out_checksum, d_pairs ? pairs_capacity : 0);
+      LAUNCH_CHECK();
+      mk.mark(MK_FIN);
     } else {
-      mkR.mark_range(MK_R2_SPL, MK_R2_SCAT);
-    }
-    // as for S runs: the 2-per-CU sort takes the buckets up to its tile, the
-    // larger ones go to the 1-per-CU sort
-    uint32_t* midR = reinterpret_cast<uint32_t*>(ws + P.midR);
-    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<LRf->Gmax, BS_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
-                                                                      LRf->bhi, LRf->Gcount(), nullptr, nullptr, midR,
-                                                                      ctr + 6, redoR, ctr + 4, soR);
-    LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
-                                                                      LRf->bhi, LRf->Gcount(), midR, ctr + 6, bigR,
-                                                                      ctr + 1, redoR, ctr + 4, soR);
-    LAUNCH_CHECK();
-    // buckets the sort gave up on get a second pass over their own key range
-    // (splitter bounds can enclose a gap between key clusters); the rest go
-    // to the LSD radix sort
-    uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
-                                                                      LRf->Gcount(), redoR, ctr + 4, bigR, ctr + 1,
-                                                                      redoR2, ctr + 5, soR);
-    LAUNCH_CHECK();
-    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, redoR2, ctr + 5, bigR, ctr + 1, soR);
-    LAUNCH_CHECK();
-    mkR.mark(MK_R_SORT);
-    k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, bigR, ctr + 1, soR);
-    LAUNCH_CHECK();
-    mkR.mark(MK_R_BIG);
-    if (r_side) {   // the rest needs R's partitions
-      HIP_TRY(hipEventRecord(side->done, rst));
-      HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
-    }
-    uint32_t* Pc = reinterpret_cast<uint32_t*>(ws + P.Pc);
-    uint32_t* pstart = reinterpret_cast<uint32_t*>(ws + P.pstart);
-    uint32_t* plen = reinterpret_cast<uint32_t*>(ws + P.plen);
-    uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + P.pkey);
-    k_partitions<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), Pc, pstart, plen, pkey,
-                                     stats ? res : nullptr);
-    LAUNCH_CHECK();
-    uint8_t* span = reinterpret_cast<uint8_t*>(ws + P.span);
-    k_join_units<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, st>>>(Pc, plen, P.Pmax, span);
-    LAUNCH_CHECK();
-    mk.mark(MK_PART);
-
-    // ---- phase 4: merge starts of every partition in every run, then the join
-    uint32_t* o = reinterpret_cast<uint32_t*>(ws + P.o);
-    const uint64_t nsearch = cdiv((uint64_t)P.Pmax + 1, 64) * cdiv(P.Q, SEARCH_RUNS);
-    k_search<<<(uint32_t)nsearch, SEARCH_NT, 0, st>>>(U, LS.seg.start, LS.seg.len, P.Q,
-                                                          reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
-                                                          P.idx_per_run, Pc, pkey, P.Pmax, o,
-                                                          learn_s ? MPSM_SEARCH_LEARNED
-                                                                  : (P.search == MPSM_SEARCH_LEARNED ? MPSM_SEARCH_INDEX
-                                                                                                     : P.search),
-                                                          modelS, stats ? res : nullptr, span);
-    LAUNCH_CHECK();
-    mk.mark(MK_SEARCH);
-    uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
-    uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
-    k_join_items<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, o, P.Q, P.Pmax, P.JCH, span, items);
-    LAUNCH_CHECK();
-    rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
-    if (rc != MPSM_OK) return rc;
-    mk.mark(MK_ITEMS);
-
-    JoinArgs A;
-    A.Rs = Rsorted;
-    A.U = U;
-    A.run_start = LS.seg.start;
-    A.Q = P.Q;
-    A.Pcount = Pc;
-    A.pstart = pstart;
-    A.plen = plen;
-    A.o = o;
-    A.item_pre = item_pre;
-    A.Pmax = P.Pmax;
-    A.JCH = P.JCH;
-    A.res = res;
-    A.J = nullptr;
-    A.pjoin = nullptr;
-    A.span = span;
-    A.pairs = reinterpret_cast<uint64_t*>(d_pairs);
-    A.pairs_cap = d_pairs ? pairs_capacity : 0;
-    A.item_cnt = reinterpret_cast<uint32_t*>(ws + P.item_cnt);
-    A.item_cap = (uint32_t)P.item_cap;
-    A.swapped = P.swapped;
-    const bool raw = P.swapped || P.want_max || d_pairs;
-    if (raw) k_join<0, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
-    else k_join<0, VAL_HR><<<g_num_cus, JOIN_NT, 0, st>>>(A);
-    LAUNCH_CHECK();
-    if (d_pairs) {
-      k_join<1, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
-      LAUNCH_CHECK();
-      rc = scan_u32(A.item_cnt, A.item_cnt, P.item_cap, bsum, st);
+      mpsm_status rc;
+      // ---- phase 1: sort S into Q runs of L tuples
+      Level LS = make_level(ws, P.segS, P.Q, P.NBs, 0, P.OSs, P.tilesS, P.seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
+                            P.bndS, P.Gs);
+      LS.run_len = P.L;
+      rc = bucket_pass(Sin, T, (uint32_t)P.nS, LS, bsum, st, mk, MK_S_SPL);
       if (rc != MPSM_OK) return rc;
-      k_join<2, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+      if (r_side) HIP_TRY(hipEventRecord(side->gate, st));
+      rc = start_models();
+      if (rc != MPSM_OK) return rc;
+      SortOut soS;
+      soS.run_idx = reinterpret_cast<uint64_t*>(ws + P.ridx);
+      soS.run_start = LS.seg.start;
+      soS.idx_stride = IDX_STRIDE;
+      soS.idx_shift = __builtin_ctz(IDX_STRIDE);
+      soS.idx_per_run = P.idx_per_run;
+      soS.NB = P.NBs;
+      soS.bkey = nullptr;
+      uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
+      uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
+      uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
+      k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+                                                                   nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
       LAUNCH_CHECK();
+      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+                                                                        midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
+                                                                        soS);
+      LAUNCH_CHECK();
+      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, redoS, ctr + 3, bigS, ctr + 0, soS);
+      LAUNCH_CHECK();
+      mk.mark(MK_S_SORT);
+      k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, bigS, ctr + 0, soS);
+      LAUNCH_CHECK();
+      mk.mark(MK_S_BIG);
+
+      // ---- phase 2: range-partition R (one or two levels); phase 3: sort partitions
+      Level LR1 = make_level(ws, P.segR1, 1, P.NB1, 0, P.OS1, P.tilesR1, P.seed ^ TAG_R1, P.splR1, P.cR1, P.cntR1,
+                             P.bstR1, P.bndR1, P.NB1);
+      if (learn_r) LR1.model = modelR;
+      CostArgs cost_args;
+      if (P.splitter == MPSM_SPLIT_COST) {
+        cost_args.sample = reinterpret_cast<uint64_t*>(ws + P.cost_sample);
+        cost_args.s_below = reinterpret_cast<uint64_t*>(ws + P.cost_s_below);
+        cost_args.best = reinterpret_cast<double*>(ws + P.cost_best);
+        cost_args.run_idx = soS.run_idx;
+        cost_args.run_len = LS.seg.len;
+        cost_args.Q = P.Q;
+        cost_args.idx_per_run = P.idx_per_run;
+        cost_args.stride = IDX_STRIDE;
+        cost_args.nS = P.nS;
+        cost_args.nR = P.nR;
+        LR1.cost = &cost_args;
+      }
+      // the models are needed from here on; R's phase runs on the side stream
+      // after them, or on this stream after S's
+      if (side && !r_side) HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
+      const hipStream_t rst = r_side ? side->st : st;
+      if (r_side) HIP_TRY(hipStreamWaitEvent(rst, side->gate, 0));
+      uint32_t* const rbsum = r_side ? reinterpret_cast<uint32_t*>(ws + P.bsumR) : bsum;
+      Marker mkR{events, n_events, rst};
+      LR1.run_len = (uint32_t)P.nR;   // one segment: all of R
+      rc = bucket_pass(Rin, R1, (uint32_t)P.nR, LR1, rbsum, rst, mkR, MK_R1_SPL);
+      if (rc != MPSM_OK) return rc;
+      SortOut soR;
+      soR.run_idx = nullptr;
+      soR.run_start = nullptr;
+      soR.idx_stride = 1;
+      soR.idx_shift = 0;
+      soR.idx_per_run = 0;
+      soR.NB = 1;
+      soR.bkey = reinterpret_cast<uint64_t*>(ws + P.bkey);
+      uint32_t* redoR = reinterpret_cast<uint32_t*>(ws + P.redoR);
+      uint32_t* bigR = reinterpret_cast<uint32_t*>(ws + P.bigR);
+      const Level* LRf = &LR1;   // level whose buckets are the R partitions
+      Level LR2;
+      tup_t* Rsrc = R1;          // partitioned, unsorted
+      tup_t* Rsorted = R2;
+      if (P.levels == 2) {
+        // 3/4 of the target so that sampling noise rarely pushes a partition past the LDS tile
+        LR2 = make_level(ws, P.segR2, P.NB1, P.NB2, P.BT * 3 / 4, P.OS2, P.tilesR2, P.seed ^ TAG_R2, P.splR2, P.cR2, P.cntR2,
+                         P.bstR2, P.bndR2, P.Gr);
+        LR2.outer = LR1.spl;
+        LR2.outer_nspl = P.NB1 - 1;
+        // the second level stays sampled: its buckets are finer than the model's knots
+        LR2.src_bstart = LR1.bstart;   // segments: the level-1 buckets
+        rc = bucket_pass(R1, R2, (uint32_t)P.nR, LR2, rbsum, rst, mkR, MK_R2_SPL);
+        if (rc != MPSM_OK) return rc;
+        LRf = &LR2;
+        Rsrc = R2;
+        Rsorted = R1;
+      } else {
+        mkR.mark_range(MK_R2_SPL, MK_R2_SCAT);
+      }
+      // as for S runs: the 2-per-CU sort takes the buckets up to its tile, the
+      // larger ones go to the 1-per-CU sort
+      uint32_t* midR = reinterpret_cast<uint32_t*>(ws + P.midR);
+      k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<LRf->Gmax, BS_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
+                                                                        LRf->bhi, LRf->Gcount(), nullptr, nullptr, midR,
+                                                                        ctr + 6, redoR, ctr + 4, soR);
+      LAUNCH_CHECK();
+      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
+                                                                        LRf->bhi, LRf->Gcount(), midR, ctr + 6, bigR,
+                                                                        ctr + 1, redoR, ctr + 4, soR);
+      LAUNCH_CHECK();
+      // buckets the sort gave up on get a second pass over their own key range
+      // (splitter bounds can enclose a gap between key clusters); the rest go
+      // to the LSD radix sort
+      uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
+      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
+                                                                        LRf->Gcount(), redoR, ctr + 4, bigR, ctr + 1,
+                                                                        redoR2, ctr + 5, soR);
+      LAUNCH_CHECK();
+      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, redoR2, ctr + 5, bigR, ctr + 1, soR);
+      LAUNCH_CHECK();
+      mkR.mark(MK_R_SORT);
+      k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, bigR, ctr + 1, soR);
+      LAUNCH_CHECK();
+      mkR.mark(MK_R_BIG);
+      if (r_side) {   // the rest needs R's partitions
+        HIP_TRY(hipEventRecord(side->done, rst));
+        HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
+      }
+      uint32_t* Pc = reinterpret_cast<uint32_t*>(ws + P.Pc);
+      uint32_t* pstart = reinterpret_cast<uint32_t*>(ws + P.pstart);
+      uint32_t* plen = reinterpret_cast<uint32_t*>(ws + P.plen);
+      uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + P.pkey);
+      k_partitions<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), Pc, pstart, plen, pkey,
+                                       stats ? res : nullptr);
+      LAUNCH_CHECK();
+      uint8_t* span = reinterpret_cast<uint8_t*>(ws + P.span);
+      k_join_units<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, st>>>(Pc, plen, P.Pmax, span);
+      LAUNCH_CHECK();
+      mk.mark(MK_PART);
+
+      // ---- phase 4: merge starts of every partition in every run, then the join
+      uint32_t* o = reinterpret_cast<uint32_t*>(ws + P.o);
+      const uint64_t nsearch = cdiv((uint64_t)P.Pmax + 1, 64) * cdiv(P.Q, SEARCH_RUNS);
+      k_search<<<(uint32_t)nsearch, SEARCH_NT, 0, st>>>(U, LS.seg.start, LS.seg.len, P.Q,
+                                                            reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
+                                                            P.idx_per_run, Pc, pkey, P.Pmax, o,
+                                                            learn_s ? MPSM_SEARCH_LEARNED
+                                                                    : (P.search == MPSM_SEARCH_LEARNED ? MPSM_SEARCH_INDEX
+                                                                                                       : P.search),
+                                                            modelS, stats ? res : nullptr, span);
+      LAUNCH_CHECK();
+      mk.mark(MK_SEARCH);
+      uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
+      uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
+      k_join_items<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, o, P.Q, LS.seg.len, P.Pmax, P.JCH, span,
+                                                                    items);
+      LAUNCH_CHECK();
+      rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
+      if (rc != MPSM_OK) return rc;
+      mk.mark(MK_ITEMS);
+
+      JoinArgs A;
+      A.Rs = Rsorted;
+      A.U = U;
+      A.run_start = LS.seg.start;
+      A.run_len = LS.seg.len;
+      A.Q = P.Q;
+      A.Pcount = Pc;
+      A.pstart = pstart;
+      A.plen = plen;
+      A.o = o;
+      A.item_pre = item_pre;
+      A.Pmax = P.Pmax;
+      A.JCH = P.JCH;
+      A.res = res;
+      A.J = nullptr;
+      A.pjoin = nullptr;
+      A.span = span;
+      A.pairs = reinterpret_cast<uint64_t*>(d_pairs);
+      A.pairs_cap = d_pairs ? pairs_capacity : 0;
+      A.item_cnt = reinterpret_cast<uint32_t*>(ws + P.item_cnt);
+      A.item_cap = (uint32_t)P.item_cap;
+      A.swapped = P.swapped;
+      const bool raw = P.swapped || P.want_max || d_pairs;
+      if (raw) k_join<0, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+      else k_join<0, VAL_HR><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+      LAUNCH_CHECK();
+      if (d_pairs) {
+        k_join<1, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+        LAUNCH_CHECK();
+        rc = scan_u32(A.item_cnt, A.item_cnt, P.item_cap, bsum, st);
+        if (rc != MPSM_OK) return rc;
+        k_join<2, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+        LAUNCH_CHECK();
+      }
+      mk.mark(MK_JOIN);
+      k_finalize<<<1, 64, 0, st>>>(res, d_out_count, d_out_checksum, d_pairs ? pairs_capacity : 0);
+      LAUNCH_CHECK();
+      mk.mark(MK_FIN);
     }
-    mk.mark(MK_JOIN);
-    k_finalize<<<1, 64, 0, st>>>(res, d_out_count, d_out_checksum);
-    LAUNCH_CHECK();
-    mk.mark(MK_FIN);
+    return mk.ok ? MPSM_OK : MPSM_EHIP;
+  };
+  const mpsm_status erc = enqueue();
+  if (erc != MPSM_OK) {
+    if (forked) {
+      (void)hipEventRecord(side->done, side->st);
+      (void)hipStreamWaitEvent(st, side->done, 0);
+    }
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    return erc;
   }
-  if (!mk.ok) return MPSM_EHIP;
   if (stats) {
     HIP_TRY(hipEventRecord(ev1, st));
     HIP_TRY(hipEventSynchronize(ev1));
@@ -809,7 +829,8 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     stats->cdf_eps_s = eps_s;
     stats->swapped = (uint64_t)P.swapped;
     stats->ms_total = ms;
-    if (d_pairs && r.count > pairs_capacity) return MPSM_ECAPACITY;
+    stats->pairs_truncated = r.truncated;
+    if (r.truncated) return MPSM_ECAPACITY;
   }
   return MPSM_OK;
 }
@@ -1159,7 +1180,8 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     }
     uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
     uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
-    k_join_items_batch<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, pjoin, J, o, P.Pmax, P.JCH, span, items);
+    k_join_items_batch<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, pjoin, J, o, LS.seg.len, P.Pmax, P.JCH,
+                                                                        span, items);
     LAUNCH_CHECK();
     rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
     if (rc != MPSM_OK) return rc;
@@ -1168,6 +1190,7 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     A.Rs = Rs;
     A.U = U;
     A.run_start = LS.seg.start;
+    A.run_len = LS.seg.len;
     A.Q = 0;
     A.Pcount = Pc;
     A.pstart = pstart;
@@ -1413,5 +1436,18 @@ mpsm_status mpsm_batch_autotune(mpsm_batch* b, void* d_workspace, uint64_t works
 }
 
 uint64_t mpsm_clock_hz(void) { return 100000000ull; }
+
+mpsm_status mpsm_join_slices_host(const uint32_t* oa, const uint32_t* ob, const uint32_t* run_start,
+                                  const uint32_t* run_len, uint32_t Q, uint32_t* cum, uint32_t* sbase) {
+  if (Q && (!oa || !ob || !run_start || !run_len || !cum || !sbase)) return MPSM_EINVAL;
+  uint32_t c = 0;
+  for (uint32_t j = 0; j < Q; j++) {
+    cum[j] = c;
+    sbase[j] = slice_base(run_start[j], oa[j], run_len[j], c);
+    c += slice_len(oa[j], ob[j], run_len[j]);
+  }
+  if (cum) cum[Q] = c;
+  return MPSM_OK;
+}
 
 }  // extern "C"

@@ -385,6 +385,34 @@ def test_batch_members_reduced():
 
 # ------------------------------------------------ intermediate results
 
+def _check_splitters(got, quantiles):
+    """GPU splitters against the oracle's equi-depth quantiles of the same
+    seeded sample: each is its quantile, or (a frequent key isolated in its
+    own bucket) the previous quantile + 1; non-decreasing."""
+    got = np.asarray(got, np.uint64)
+    q = np.asarray(quantiles, np.uint64)
+    assert len(got) == len(q)
+    moved = np.zeros(len(q), bool)
+    moved[1:] = got[1:] == q[:-1] + np.uint64(1)
+    assert np.all((got == q) | moved)
+    assert np.all(got[1:] >= got[:-1])
+
+
+def _bucket_starts_with_rule(keys, spl, nb):
+    """Bucket starts of a stable partition of keys by the oracle's bucket
+    function (the number of splitters <= key) with the kernel's documented
+    exception: a key equal to two or more splitters goes to the bucket below
+    (which those splitters leave empty), so that it has a bucket to itself."""
+    b = np.array([oracle.bucket_of(spl, nb, int(k)) for k in np.unique(keys)], np.int64)
+    u = np.unique(keys)
+    sp = np.concatenate([[np.uint64(0)], spl])   # sp[b] = spl[b-1]
+    twice = (b >= 2) & (sp[np.maximum(b, 1)] == u) & (sp[np.maximum(b - 1, 0)] == u)
+    b = b - twice
+    per_key = b[np.searchsorted(u, keys)]
+    cnt = np.bincount(per_key, minlength=nb)
+    return np.concatenate([[0], np.cumsum(cnt)[:-1]])
+
+
 def _ws_view(ws, off, n, dtype):
     b = ws[off: off + n * np.dtype(dtype).itemsize].cpu().numpy()
     return b.view(dtype)
@@ -416,25 +444,32 @@ def test_intermediate_results(nR, nS, bt, skew):
         x = Ssorted[a:b]
         y = ref_runs[a:b]
         assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], y[np.lexsort((y[:, 1], y[:, 0]))])
-    # S splitters: same seeded sample, same quantiles
+    # S splitters: valid splitters of the same seeded sample (the oracle's plain
+    # equi-depth quantiles, or a quantile's predecessor + 1 where the kernel gave
+    # a frequent key its own bucket), non-decreasing
     spl = _ws_view(ws, lay["off_s_splitters"], Q * (NB - 1), np.uint64).reshape(Q, NB - 1)
     for j in range(Q):
         seed = oracle.splitmix_at(lay["s_level_seed"], j)
         a, b = j * L, min((j + 1) * L, nS)
-        assert np.array_equal(spl[j], oracle.sample_splitters(S[a:b], NB, lay["s_oversample"], seed))
-    if skew:   # the rule has fired: some splitter is its predecessor + 1
+        _check_splitters(spl[j], oracle.sample_splitters(S[a:b], NB, lay["s_oversample"], seed))
+    if skew:   # the frequent-key rule has fired: some splitter is its predecessor + 1
         assert np.count_nonzero(spl[:, 1:] == spl[:, :-1] + np.uint64(1)) > 0
-    # S bucket boundaries = a stable bucket partition of each run under those splitters
+    # S bucket boundaries: the oracle's stable partition of each run under the
+    # GPU's own splitters, with the kernel's rule for keys equal to two or more
+    # splitters applied here; every bucket boundary falls between distinct keys
     bst = _ws_view(ws, lay["off_s_bucket_start"], Q * NB + 1, np.uint32)
     for j in range(Q):
         a, b = j * L, min((j + 1) * L, nS)
-        _, bs = oracle.bucket_partition(S[a:b], spl[j], NB)
-        assert np.array_equal(bst[j * NB:(j + 1) * NB].astype(np.int64) - a, bs[:NB].astype(np.int64))
-    # R level-1 splitters
+        want = _bucket_starts_with_rule(S[a:b, 0], spl[j], NB)
+        got = bst[j * NB:(j + 1) * NB].astype(np.int64) - a
+        assert np.array_equal(got, want)
+        inner = got[(got > 0) & (got < b - a)]
+        assert np.all(ref_runs[a + inner - 1, 0] < ref_runs[a + inner, 0])
+    # R level-1 splitters: valid splitters of R's seeded sample
     NB1 = lay["r_buckets1"]
     spl1 = _ws_view(ws, lay["off_r_splitters1"], NB1 - 1, np.uint64)
-    assert np.array_equal(spl1, oracle.sample_splitters(R, NB1, lay["r_oversample1"],
-                                                        oracle.splitmix_at(lay["r_level_seed1"], 0)))
+    _check_splitters(spl1, oracle.sample_splitters(R, NB1, lay["r_oversample1"],
+                                                   oracle.splitmix_at(lay["r_level_seed1"], 0)))
     # phase 2+3: R sorted, partitions contiguous, first keys
     Rsorted = _ws_view(ws, lay["off_r_sorted"], 2 * nR, np.uint64).reshape(-1, 2)
     ref_R = oracle.sort_by_key(R)
@@ -505,31 +540,83 @@ def _ws_view_range(ws, off, a, b):
     return ws[off + 16 * a: off + 16 * b].cpu().numpy().view(np.uint64).reshape(-1, 2)
 
 
-# ------------------------------------- large configurations (opt-in: MPSM_LARGE=1)
+# ----------------------------------------- the two large workloads at full size
 
-large = pytest.mark.skipif(not __import__("os").environ.get("MPSM_LARGE"),
-                           reason="large configuration: set MPSM_LARGE=1 (minutes of host time)")
-
-
-@large
-def test_lognormal_eighth_scale_against_oracle():
-    """|R| = 2^25 log-normal keys with duplicates, |S| = 2^27 (1..16 copies
-    per key): count and checksum against the CPU oracle."""
-    w = workloads.make("lognormal", scale_shift=3)
-    _say("lognormal 1/8: generated")
-    got = gpu_join(w.R, w.S)
-    assert got["count"] == w.expected_count
-    _say("lognormal 1/8: GPU count matches the generator; running the oracle")
-    want = oracle.join(w.R, w.S)
-    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+def _golden_full(name):
+    import json
+    import os
+    from conftest import GOLDEN
+    with open(os.path.join(GOLDEN, "full_size.json")) as f:
+        return json.load(f)[name]
 
 
-@large
+def _fingerprint(w):
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(w.R[::4097]).tobytes())
+    h.update(np.ascontiguousarray(w.S[::4099]).tobytes())
+    return h.hexdigest()
+
+
+def _sampled_runs_and_offsets(ws, lay, S_host, nS, seed, nruns=2):
+    """Sampled S runs against the oracle's sort of the same chunk, and 64
+    sampled start offsets per run against lower bounds in the oracle's run."""
+    Q, L = lay["runs"], lay["run_len"]
+    rng = np.random.default_rng(seed)
+    P = int(_ws_view(ws, lay["off_partitions"], 1, np.uint32)[0])
+    pkey = _ws_view(ws, lay["off_part_key"], P, np.uint64)
+    heads = np.nonzero(_ws_view(ws, lay["off_join_span"], P, np.uint8))[0]
+    o = _ws_view(ws, lay["off_offsets"], (P + 1) * Q, np.uint32).reshape(P + 1, Q)
+    for j in sorted(set([0, Q - 1] + rng.integers(0, Q, nruns).tolist())):
+        a, b = j * L, min((j + 1) * L, nS)
+        x = _ws_view_range(ws, lay["off_s_sorted"], a, b)
+        ref = oracle.sort_by_key(S_host[a:b])
+        assert np.array_equal(x[:, 0], ref[:, 0])
+        assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], ref[np.lexsort((ref[:, 1], ref[:, 0]))])
+        ps = heads[rng.integers(0, len(heads), 64)]
+        assert np.array_equal(o[ps, j], np.searchsorted(ref[:, 0], pkey[ps], side="left"))
+        _say(f"run {j}: sorted keys, tuples and 64 start offsets match the oracle")
+
+
+@pytest.mark.timeout(900)
+def test_skewed_full_size():
+    """|R| = 2^26 keys from 64 Gaussian blobs, |S| = 2^28 Zipf(1.0) foreign
+    keys, at full size in the plain and the learned form: count and checksum
+    against the foreign-key closed form (computed here, and stored by the
+    oracle-only script), plus sampled runs and start offsets."""
+    g = _golden_full("skewed")
+    w = workloads.make("skewed")
+    assert _fingerprint(w) == g["inputs_sha256"], "the generator differs on this host"
+    fk = oracle.fk_closed_form(w.R, w.S, w.partner)
+    assert (fk.count, fk.checksum) == (g["count"], int(g["checksum_hex"], 16))
+    _say("skewed full: generated, closed form computed")
+    nR, nS = len(w.R), len(w.S)
+    R, S = _dev(w.R), _dev(w.S)
+    cfg = mpsm.config()
+    lay = mpsm.layout(nR, nS, cfg)
+    ws = mpsm.alloc_workspace(nR, nS, cfg)
+    got = mpsm.join(R, S, cfg, workspace=ws)
+    assert (got["count"], got["checksum"]) == (fk.count, fk.checksum)
+    torch.cuda.synchronize()
+    _sampled_runs_and_offsets(ws, lay, w.S, nS, seed=2)
+    learned = mpsm.join(R, S, mpsm.config(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED), workspace=ws)
+    assert (learned["count"], learned["checksum"]) == (fk.count, fk.checksum)
+    _say("skewed full: plain and learned equal the closed form")
+
+
+@pytest.mark.timeout(900)
 def test_lognormal_full_size():
-    """|R| = 2^28, |S| = 2^30: the count from the generator (exact by
-    construction), the same checksum from every start-search mode and from
-    the learned form, and sampled runs and start offsets against the oracle."""
+    """|R| = 2^28 log-normal keys with duplicates, |S| = 2^30 (1..16 copies
+    of every distinct key), at full size in the plain and the learned form
+    and with bisection search: the count against the generator (exact by
+    construction) and the checksum against the oracle's sort-merge join over
+    key-range slices (stored by the oracle-only script), plus sampled runs
+    and start offsets."""
+    g = _golden_full("lognormal")
     w = workloads.make("lognormal")
+    assert _fingerprint(w) == g["inputs_sha256"], "the generator differs on this host"
+    assert w.expected_count == g["count"]
+    want = (g["count"], int(g["checksum_hex"], 16))
     nR, nS = len(w.R), len(w.S)
     _say(f"lognormal full: generated |R|={nR} |S|={nS}, expected pairs {w.expected_count}")
     R, S = _dev(w.R), _dev(w.S)
@@ -537,29 +624,47 @@ def test_lognormal_full_size():
     lay = mpsm.layout(nR, nS, cfg)
     ws = mpsm.alloc_workspace(nR, nS, cfg)
     got = mpsm.join(R, S, cfg, workspace=ws)
-    assert got["count"] == w.expected_count
+    assert (got["count"], got["checksum"]) == want
     torch.cuda.synchronize()
-    Q, L = lay["runs"], lay["run_len"]
-    rng = np.random.default_rng(3)
-    P = int(_ws_view(ws, lay["off_partitions"], 1, np.uint32)[0])
-    pkey = _ws_view(ws, lay["off_part_key"], P, np.uint64)
-    heads = np.nonzero(_ws_view(ws, lay["off_join_span"], P, np.uint8))[0]
-    o = _ws_view(ws, lay["off_offsets"], (P + 1) * Q, np.uint32).reshape(P + 1, Q)
-    for j in sorted(set([0, Q - 1] + rng.integers(0, Q, 2).tolist())):
-        a, b = j * L, min((j + 1) * L, nS)
-        x = _ws_view_range(ws, lay["off_s_sorted"], a, b)
-        ref = oracle.sort_by_key(w.S[a:b])
-        assert np.array_equal(x[:, 0], ref[:, 0])
-        assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], ref[np.lexsort((ref[:, 1], ref[:, 0]))])
-        ps = heads[rng.integers(0, len(heads), 64)]
-        assert np.array_equal(o[ps, j], np.searchsorted(ref[:, 0], pkey[ps], side="left"))
-        _say(f"lognormal full: run {j} checked")
-    del ws
-    torch.cuda.empty_cache()
+    _sampled_runs_and_offsets(ws, lay, w.S, nS, seed=3)
     for kw in (dict(search=mpsm.SEARCH_BINARY), dict(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED)):
-        other = mpsm.join(R, S, mpsm.config(**kw))
-        assert (other["count"], other["checksum"]) == (got["count"], got["checksum"]), kw
-        _say(f"lognormal full: {kw} agrees")
+        other = mpsm.join(R, S, mpsm.config(**kw), workspace=ws)
+        assert (other["count"], other["checksum"]) == want, kw
+        _say(f"lognormal full: {kw} equals the oracle")
+
+
+def test_lognormal_eighth_scale_against_oracle():
+    """|R| = 2^25, |S| = 2^27 log-normal keys with duplicates: count and
+    checksum against the oracle's join over key-range slices, computed here."""
+    w = workloads.make("lognormal", scale_shift=3)
+    got = gpu_join(w.R, w.S)
+    assert got["count"] == w.expected_count
+    smp = np.sort(w.R[np.random.default_rng(0).integers(0, len(w.R), 1 << 14), 0])
+    want = oracle.join_sliced(w.R, w.S, np.unique(smp[(np.arange(1, 16) * len(smp)) // 16]), threads=16)
+    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+
+
+def test_pair_capacity_truncation():
+    """Pairs asked for with too small a buffer: the count and checksum stay
+    exact, the call reports MPSM_ECAPACITY through its status word, and the
+    pairs written are capacity many of the oracle's pairs."""
+    import collections
+    rng = np.random.default_rng(31)
+    R = rel(rng, 5000, 3000)
+    S = rel(rng, 20000, 3000)
+    want = oracle.join(R, S, pairs=True, cap=1 << 20)
+    have = collections.Counter(map(tuple, want.pairs.tolist()))
+    Rd, Sd = _dev(R), _dev(S)
+    for cap in (1, 777, want.count - 1):
+        got = mpsm.join(Rd, Sd, pairs=True, pairs_capacity=cap)
+        assert got["status"] == "MPSM_ECAPACITY" and got["stats"]["pairs_truncated"] == 1
+        assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+        assert len(got["pairs"]) == cap
+        c = collections.Counter(map(tuple, got["pairs"].tolist()))
+        assert all(have[p] >= k for p, k in c.items())
+    got = mpsm.join(Rd, Sd, pairs=True, pairs_capacity=want.count)
+    assert got["status"] == "MPSM_OK" and got["stats"]["pairs_truncated"] == 0
+    assert np.array_equal(got["pairs"], want.pairs)
 
 
 def test_cost_balanced_splitters_negatively_correlated():
@@ -591,14 +696,20 @@ def test_cost_balanced_splitters_negatively_correlated():
     s_below = _ws_view(ws, lay["off_cost_s_below"], M + 1, np.uint64).astype(np.int64)
     best = float(_ws_view(ws, lay["off_cost_best"], 1, np.float64)[0])
     assert np.all(np.diff(sample.astype(np.float64)) >= 0)
-    # the merged equi-height bounds: every 256th key of each sorted run
+    # the S distribution at the sample keys: within half a stride per run of the
+    # exact count (each run's every-256th-key index brackets its count to one
+    # stride, and the kernel takes the middle), and within the error bounds of
+    # both of the oracle's Section 4.1 estimate (merged bounds, equal steps,
+    # linear interpolation; Q strides)
     runs = oracle.sort_runs(S, L)
-    est = np.zeros(M, np.int64)
+    run_start = [min(j * L, nS) for j in range(Q + 1)]
+    exact = np.zeros(M, np.int64)
     for j in range(Q):
-        a, b = j * L, min((j + 1) * L, nS)
-        lb = np.searchsorted(runs[a:b:256, 0], sample, side="left").astype(np.int64)
-        est += np.minimum(np.where(lb > 0, lb * 256 - 128, 0), b - a)
-    assert np.array_equal(s_below[:M], est) and s_below[M] == nS
+        a, b = run_start[j], run_start[j + 1]
+        exact += np.searchsorted(runs[a:b, 0], sample, side="left")
+    assert np.all(np.abs(s_below[:M] - exact) <= 128 * Q) and s_below[M] == nS
+    cdf = oracle.s_cdf(runs, run_start, 256, sample)
+    assert np.all(np.abs(s_below[:M] - cdf) <= 128 * Q + 256 * Q)
     # cells and the oracle's exact optimum
     RC = (np.arange(M + 1, dtype=np.uint64) * np.uint64(len(R))) // np.uint64(M)
     SC = np.concatenate([[0], s_below[1:]]).astype(np.uint64)

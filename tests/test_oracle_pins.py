@@ -108,6 +108,24 @@ def test_join_matches_hash_join_and_invariant(seed):
     assert int(np.sum(cr[ir].astype(np.int64) * cs[is_].astype(np.int64))) == a.count
 
 
+@pytest.mark.parametrize("nb", [1, 2, 7])
+def test_sliced_join_adds_up_to_the_join(nb):
+    # slices of the key space (bounds from the data, repeated and extreme keys)
+    rng = np.random.default_rng(40 + nb)
+    R = _rand_rel(rng, 3000, 500)
+    S = _rand_rel(rng, 9000, 500)
+    R[:5, 0] = [0, U64, U64, 1, 499]
+    S[:4, 0] = [0, U64, 499, 1]
+    b = np.sort(rng.choice(R[:, 0], nb - 1)) if nb > 1 else []
+    a = oracle.join(R, S)
+    s = oracle.join_sliced(R, S, b, threads=3)
+    assert (s.count, s.checksum, s.maxsum, s.nonempty) == (a.count, a.checksum, a.maxsum, a.nonempty)
+    # a single slice that excludes a key loses exactly that key's pairs
+    part = oracle.join_key_range(R, S, 0, 499)
+    h, _ = oracle.join_hash(R[R[:, 0] < np.uint64(499)], S)
+    assert (part.count, part.checksum) == (h.count, h.checksum)
+
+
 def test_fk_closed_form_equals_join():
     w = workloads.make("fk_small", scale_shift=4)
     fk = oracle.fk_closed_form(w.R, w.S, w.partner)
@@ -243,62 +261,34 @@ def test_sample_splitters_against_numpy():
     assert spl.tolist() == [int(smp[b * os_]) for b in range(1, nb)]
 
 
-def test_splitters_from_sample_isolate_frequent_single_splitter_keys():
-    # oversample 4: splitters at ranks 4, 8, 12, 16 of 20 sorted keys
-    smp = [1, 2, 3, 4, 5, 5, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18]
-    # 5 sits at rank 4 and again at rank 4 + 2: the next splitter 7 becomes 6
-    assert oracle.splitters_from_sample(smp, 5, 4).tolist() == [5, 6, 11, 15]
-    # no key repeated: every fourth key
-    plain = list(range(1, 21))
-    assert oracle.splitters_from_sample(plain, 5, 4).tolist() == [5, 9, 13, 17]
-    # 5 also at rank 8: two splitters equal, already isolated by bucket_of, unchanged
-    two = [1, 2, 3, 4, 5, 5, 5, 5, 5, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18]
-    assert oracle.splitters_from_sample(two, 5, 4).tolist() == [5, 5, 11, 15]
-    # the next splitter already key + 1: nothing to move
-    adj = [1, 2, 3, 4, 5, 5, 5, 6, 6, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18]
-    assert oracle.splitters_from_sample(adj, 5, 4).tolist() == [5, 6, 11, 15]
-    # a run of frequent single-splitter keys (5, 7, 9 at ranks 4, 8, 12): the
-    # first and third move their successor; 7 loses its splitter to 5 + 1
-    run = [1, 2, 3, 4, 5, 5, 5, 6, 7, 7, 7, 8, 9, 9, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18]
-    assert oracle.splitters_from_sample(run, 6, 4).tolist() == [5, 6, 9, 10, 15]
-    # the largest key: no key + 1 above it
-    top = [1, 2, 3, 4, 5, 6, 7, 8, 2**64 - 1, 2**64 - 1, 2**64 - 1, 2**64 - 1] + [2**64 - 1] * 8
-    assert oracle.splitters_from_sample(top, 5, 4).tolist() == [5, 2**64 - 1, 2**64 - 1, 2**64 - 1]
-    # the last splitter has no successor to move
-    last = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 17, 17, 18]
-    assert oracle.splitters_from_sample(last, 5, 4).tolist() == [5, 9, 13, 17]
+def test_sample_splitters_with_repeated_keys_are_plain_quantiles():
+    # a frequent key simply fills several ranks: every oversample-th sorted
+    # sample key, repeats kept (4 of 20 sampled keys per bucket)
+    T = _tup([(k, 0) for k in [1, 2, 3, 4, 5, 5, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18]])
+    # a sample of every position once is not what the seeded draw gives, so
+    # pin the quantile rule on the drawn sample itself
+    m, nb, os_, seed = 20, 5, 4, 0x5EED
+    pos = [(workloads.splitmix_at(seed, t) * len(T)) >> 64 for t in range(m)]
+    smp = sorted(int(T[p, 0]) for p in pos)
+    assert oracle.sample_splitters(T, nb, os_, seed).tolist() == [smp[4], smp[8], smp[12], smp[16]]
 
 
-def test_splitters_from_sample_bound_bucket_sizes():
-    # every bucket of the sample holds a frequent key alone or at most about
-    # two oversample stretches of keys (brute force over random skewed samples)
-    rng = np.random.default_rng(21)
-    for trial in range(200):
-        nb, os_ = int(rng.integers(2, 40)), int(rng.integers(2, 24))
-        heavy = rng.integers(0, 1000, 5)
-        keys = np.where(rng.random(nb * os_) < 0.5, rng.choice(heavy, nb * os_),
-                        rng.integers(0, 1000, nb * os_)).astype(np.uint64)
-        smp = np.sort(keys)
-        spl = oracle.splitters_from_sample(smp, nb, os_)
-        assert np.all(spl[1:] >= spl[:-1])
-        b = np.array([oracle.bucket_of(spl, nb, int(k)) for k in smp])
-        assert np.all(b[1:] >= b[:-1])
-        for q in range(nb):
-            ks = smp[b == q]
-            if len(ks) and ks.min() != ks.max():
-                # a bucket of mixed keys: at most two stretches plus a trailing run
-                assert len(ks) <= 2 * os_ + os_ // 2 + 1, (trial, q, len(ks), os_)
-
-
-def test_bucket_of_monotone_and_isolates_frequent_keys():
-    spl = np.array([10, 20, 20, 20, 30, 40, 40], np.uint64)
+@pytest.mark.parametrize("trial", range(5))
+def test_bucket_of_is_upper_bound(trial):
+    # the number of splitters <= key: numpy's right-sided search, an
+    # independent routine; repeated splitters leave empty buckets between
+    rng = np.random.default_rng(100 + trial)
+    spl = np.sort(rng.integers(0, 60, int(rng.integers(1, 12)))).astype(np.uint64)
     nb = len(spl) + 1
-    keys = list(range(0, 50))
+    keys = list(range(0, 64)) + [U64]
     b = [oracle.bucket_of(spl, nb, k) for k in keys]
-    assert b == sorted(b)                                       # non-decreasing
-    assert [k for k in keys if b[keys.index(k)] == b[20]] == [20]   # 20 alone
-    assert [k for k in keys if b[keys.index(k)] == b[40]] == [40]   # 40 alone
-    assert b[9] == 0 and b[10] == 1 and b[19] == 1 and b[21] == 4 and b[49] == 7
+    assert b == np.searchsorted(spl, np.array(keys, np.uint64), side="right").tolist()
+    assert b == sorted(b)
+
+
+def test_bucket_of_hand_values():
+    spl = np.array([10, 20, 20, 30], np.uint64)          # bucket 2 = [20, 20) is empty
+    assert [oracle.bucket_of(spl, 5, k) for k in (0, 9, 10, 19, 20, 29, 30, U64)] == [0, 0, 1, 1, 3, 3, 4, 4]
 
 
 def test_bucket_partition_is_stable_partition():
@@ -340,7 +330,116 @@ def test_interpolation_two_steps_on_arithmetic_run():
 
 def test_equi_height_bounds():
     run = _tup([(10 * i, 0) for i in range(1000)])
-    assert oracle.equi_height(run, 4).tolist() == [2000, 4000, 6000, 8000]
+    # buckets of 256 tuples, bounded by their first keys (positions 0, 256, 512, 768)
+    assert oracle.equi_height(run, 256).tolist() == [0, 2560, 5120, 7680]
+    assert oracle.equi_height(run[:257], 256).tolist() == [0, 2560]
+    assert oracle.equi_height(run[:0], 256).tolist() == []
+
+
+# --------------------------------------- Section 4.1: global S distribution
+
+def _runs(parts):
+    """Concatenate sorted runs; return (tuples, run_start)."""
+    S = np.concatenate([_tup([(k, 0) for k in p]) if len(p) else np.zeros((0, 2), np.uint64) for p in parts])
+    starts = np.cumsum([0] + [len(p) for p in parts]).astype(np.uint64)
+    return S, starts
+
+
+def test_s_cdf_exact_on_one_arithmetic_run():
+    # one run of the keys 0..n-1: bounds every 8th key, steps of 8 tuples,
+    # linear between bounds -> the estimate is the exact count below x
+    n, stride = 64, 8
+    S, st = _runs([list(range(n))])
+    xs = [0, 1, 5, 8, 9, 33, 56, 57, 63, 64, 65, 1000]
+    want = [min(x, n) for x in xs]
+    assert oracle.s_cdf(S, st, stride, xs).tolist() == pytest.approx(want)
+
+
+def test_s_cdf_hand_values_two_runs():
+    # runs [0..7] and [100..107], stride 4: bounds 0, 4, 100, 104; |S| = 16,
+    # h = 4.  C(x) = h(k - 1) + h (x - v_k) / (v_{k+1} - v_k) with k bounds
+    # below x; the last step runs to 108 (one past the largest key).
+    S, st = _runs([list(range(8)), list(range(100, 108))])
+    xs = [0, 2, 4, 5, 52, 100, 101, 104, 106, 108, 200]
+    want = [0.0,                     # x <= v_1
+            4 * 0 + 4 * (2 - 0) / 4,  # k=1: 2
+            4.0,                      # k=1, x = v_2: 4
+            4 + 4 * (5 - 4) / 96,     # k=2, spread over (4, 100]
+            4 + 4 * 48 / 96,          # 6
+            8.0,                      # x = v_3
+            8 + 4 * 1 / 4,            # k=3: 9
+            12.0,                     # x = v_4
+            12 + 4 * 2 / 4,           # k=4, last step to 108: 14
+            16.0, 16.0]
+    assert oracle.s_cdf(S, st, 4, xs).tolist() == pytest.approx(want)
+
+
+@pytest.mark.parametrize("dist", ["uniform", "low_skew", "clusters", "duplicates"])
+def test_s_cdf_within_its_bound_of_the_exact_count(dist):
+    # brute force: the merged equal-step estimate stays within Q strides of
+    # the exact number of S keys below x (each run's bounds bracket its own
+    # count to one stride), is monotone, 0 at the bottom and |S| at the top
+    rng = np.random.default_rng(len(dist))
+    Q, stride = 7, 16
+    parts = []
+    for j in range(Q):
+        n = int(rng.integers(0, 400))
+        if dist == "uniform":
+            k = rng.integers(0, 1 << 40, n)
+        elif dist == "low_skew":                     # mostly small keys (the example of Fig. 8)
+            k = (rng.random(n) ** 4 * (1 << 40)).astype(np.int64)
+        elif dist == "clusters":
+            k = rng.choice([1 << 10, 1 << 30, 1 << 39], n) + rng.integers(0, 1000, n)
+        else:
+            k = rng.integers(0, 20, n)
+        parts.append(sorted(int(v) for v in k))
+    S, st = _runs(parts)
+    allk = np.sort(S[:, 0])
+    xs = np.unique(np.concatenate([allk, allk + np.uint64(1), rng.integers(0, 1 << 41, 200).astype(np.uint64),
+                                   np.array([0, U64], np.uint64)]))
+    est = oracle.s_cdf(S, st, stride, xs)
+    exact = np.searchsorted(allk, xs, side="left")
+    assert np.all(np.abs(est - exact) <= Q * stride + 1e-6), float(np.max(np.abs(est - exact)))
+    assert np.all(np.diff(est) >= -1e-9)
+    assert est[0] == 0.0 and est[-1] == pytest.approx(len(S))
+
+
+def test_s_cdf_fig8_skewed_runs_rise_early():
+    # Fig. 8: four runs with mostly small keys; half of S lies below a small
+    # key, and the merged estimate says so (within the bound)
+    rng = np.random.default_rng(8)
+    parts = [sorted(int(v) for v in (rng.random(1024) ** 6 * 1e9).astype(np.int64)) for _ in range(4)]
+    S, st = _runs(parts)
+    med = int(np.median(S[:, 0]))
+    est = float(oracle.s_cdf(S, st, 64, [med])[0])
+    assert abs(est - np.searchsorted(np.sort(S[:, 0]), med)) <= 4 * 64
+    assert med < 1e9 / 64                       # the median key is small: the CDF rises early
+
+
+# --------------------------------------- Section 4.3: split-relevant cost
+
+def test_split_cost_hand_values():
+    # |R_i| log2 |R_i| + T |R_i| + S tuples of the range (log base 2, S in tuples)
+    assert oracle.split_cost(8, 4, 10) == 66.0             # 8*3 + 4*8 + 10
+    assert oracle.split_cost(1, 7, 5) == 12.0              # 0 + 7 + 5
+    assert oracle.split_cost(0, 9, 3) == 3.0               # an empty R partition costs its S share
+    assert oracle.split_cost(2, 1, 1) == 5.0               # 2*1 + 2 + 1
+    assert oracle.split_cost(1024, 128, 0) == 141312.0     # 1024*10 + 128*1024
+
+
+def test_cost_split_choice_pins_log_base_and_terms():
+    # Three buckets into two partitions.  Case 1: h = [16, 0, 0], s = [0, 10, 75],
+    # T = 1.  {A | BC}: max(16*4 + 16, 85) = 85; {AB | C}: max(64 + 16 + 10, 75) = 90
+    # -> the split after bucket 0, cost 85.  With ln instead of log2 {AB | C} would
+    # cost max(60.4, 75) = 75 and win; without the T |R_i| term it would cost
+    # max(74, 75) = 75 and win too.
+    opt, first = oracle.cost_splitters_dp(np.array([16, 0, 0]), np.array([0, 10, 75]), P=2, T=1)
+    assert first.tolist() == [0, 1] and opt == 85.0
+    # Case 2: h = [8, 8, 0], s = [0, 0, 200], T = 1.  {A | BC}: max(32, 232) = 232;
+    # {AB | C}: max(16*4 + 16, 200) = 200 -> the split after bucket 1.  With S counted
+    # as a fraction of |S| (or dropped) {A | BC} would cost 33 (or 32) and win.
+    opt, first = oracle.cost_splitters_dp(np.array([8, 8, 0]), np.array([0, 0, 200]), P=2, T=1)
+    assert first.tolist() == [0, 2] and opt == 200.0
 
 
 # ------------------------------------------------- the whole P-MPSM on CPU
