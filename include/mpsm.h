@@ -158,6 +158,25 @@ mpsm_status mpsm_join(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
                       const mpsm_config* cfg, void* d_workspace, uint64_t workspace_bytes, void* stream,
                       mpsm_stats* stats);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mpsm_join
+ * with the workspace taken from a fixed array inside the library, one copy
+ * per GPU, MPSM_NOALLOC_SCRATCH_BYTES bytes, held until the process ends.
+ * Same arguments, results and errors as mpsm_join, without the caller's
+ * workspace and without stats; the call uses the caller's stream only (no
+ * second stream) and calls no allocating routine.  Joins whose workspace
+ * (mpsm_workspace_bytes) exceeds MPSM_NOALLOC_SCRATCH_BYTES return
+ * MPSM_ENOMEM before any device call (about 1.5 M tuples in all fit).  The
+ * array's address on a GPU is looked up on the first call with that GPU
+ * current.  Every call on one GPU shares its array and leaves its
+ * intermediate results there; each call initialises what it needs, so the
+ * previous contents never matter, but calls that overlap on one GPU (on
+ * different streams, or from several threads without ordering) race. */
+#define MPSM_NOALLOC_SCRATCH_BYTES (64ull << 20)
+mpsm_status mpsm_join_noalloc(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS,
+                              uint64_t* d_out_count, uint64_t* d_out_checksum, mpsm_pair* d_pairs,
+                              uint64_t pairs_capacity, const mpsm_config* cfg, void* stream);
+
 /* Human-readable name of a status code (static string). */
 const char* mpsm_status_string(mpsm_status s);
 

@@ -25,7 +25,8 @@ EXPORTS = ("mpsm_config_default", "mpsm_workspace_bytes", "mpsm_join", "mpsm_sta
            "mpsm_workspace_layout", "mpsm_join_events", "mpsm_marker_count", "mpsm_marker_name",
            "mpsm_events_create", "mpsm_events_destroy", "mpsm_events_elapsed", "mpsm_batch_create",
            "mpsm_batch_destroy", "mpsm_batch_workspace_bytes", "mpsm_batch_run", "mpsm_batch_autotune",
-           "mpsm_batch_get_tuning", "mpsm_batch_set_tuning", "mpsm_clock_hz", "mpsm_join_slices_host")
+           "mpsm_batch_get_tuning", "mpsm_batch_set_tuning", "mpsm_clock_hz", "mpsm_join_slices_host",
+           "mpsm_join_noalloc")
 
 
 class MpsmConfig(ctypes.Structure):
@@ -137,6 +138,8 @@ def lib():
         L.mpsm_clock_hz.restype = u64
         L.mpsm_join_slices_host.argtypes = [p, p, p, p, ctypes.c_uint32, p, p]
         L.mpsm_join_slices_host.restype = ctypes.c_int
+        L.mpsm_join_noalloc.argtypes = [p, u64, p, u64, p, p, p, u64, ctypes.POINTER(MpsmConfig), p]
+        L.mpsm_join_noalloc.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -211,6 +214,26 @@ def join_into(R, S, out, workspace, cfg: MpsmConfig | None = None, stream=None, 
                          _stream_handle(stream), None if stats is None else ctypes.byref(stats))
     if rc not in (0, 2):
         raise MpsmError(rc, "mpsm_join")
+    return rc
+
+
+# bytes of the library's own per-GPU workspace used by join_noalloc_into
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def join_noalloc_into(R, S, out, cfg: MpsmConfig | None = None, stream=None, pairs=None) -> int:
+    """mpsm_join_noalloc: the join with the library's own fixed workspace
+    (no allocation anywhere in the call); out and pairs as in join_into.
+    Raises MpsmError(MPSM_ENOMEM) for joins too large for that workspace."""
+    _check_tuples(R, "R")
+    _check_tuples(S, "S")
+    pp = ctypes.c_void_p(pairs.data_ptr()) if pairs is not None and pairs.numel() else None
+    cap = pairs.shape[0] if pp is not None else 0
+    rc = lib().mpsm_join_noalloc(ctypes.c_void_p(R.data_ptr()), R.shape[0], ctypes.c_void_p(S.data_ptr()),
+                                 S.shape[0], ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(out.data_ptr() + 8),
+                                 pp, cap, _cfg_ptr(cfg), _stream_handle(stream))
+    if rc != 0:
+        raise MpsmError(rc, "mpsm_join_noalloc")
     return rc
 
 

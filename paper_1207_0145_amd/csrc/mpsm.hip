@@ -8,6 +8,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -853,6 +854,56 @@ mpsm_status mpsm_join_events(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tupl
   if (n_events && !events) return MPSM_EINVAL;
   return join_impl(d_R, nR, d_S, nS, d_out_count, d_out_checksum, d_pairs, pairs_capacity, cfg, d_workspace,
                    workspace_bytes, stream, nullptr, events, n_events);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of mpsm_join_noalloc: a fixed array in the library's own device
+// memory, one copy per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel or a copy (on the host it is only a
+// stand-in for the symbol): the device address of each GPU's copy is looked
+// up once, with that GPU current, and kept here.
+static __device__ __align__(256) unsigned char scratch[MPSM_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SIDE_MAX_DEVICES];
+
+mpsm_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SIDE_MAX_DEVICES) return MPSM_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MPSM_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MPSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpsm_status mpsm_join_noalloc(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS,
+                              uint64_t* d_out_count, uint64_t* d_out_checksum, mpsm_pair* d_pairs,
+                              uint64_t pairs_capacity, const mpsm_config* cfg, void* stream) {
+  mpsm_config def;
+  if (!cfg) { mpsm_config_default(&def); cfg = &def; }
+  if (!config_valid(cfg)) return MPSM_EINVAL;
+  Plan P;
+  if (!make_plan(nR, nS, cfg, &P)) return MPSM_EINVAL;
+  // sizes beyond the array are refused before any device call
+  if (P.total > (uint64_t)MPSM_NOALLOC_SCRATCH_BYTES) return MPSM_ENOMEM;
+  void* ws = nullptr;
+  const mpsm_status rs = scratch_for_current_device(&ws);
+  if (rs != MPSM_OK) return rs;
+  // one stream (no side stream of the library's own) and no statistics
+  // (which would create events): nothing here allocates
+  return join_impl(d_R, nR, d_S, nS, d_out_count, d_out_checksum, d_pairs, pairs_capacity, cfg, ws,
+                   (uint64_t)MPSM_NOALLOC_SCRATCH_BYTES, stream, nullptr, nullptr, 0, true);
 }
 
 uint32_t mpsm_marker_count(void) { return kNumMarkers; }
