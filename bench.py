@@ -171,6 +171,60 @@ def summarize_profiles(kt_csv, fetch_csv, write_csv, workload, nR, nS, command):
             "command": command, "steps": steps}
 
 
+WORKLOAD_TITLE = {
+    "fk_uniform": "|R| = 2^26, |S| = 2^28, uniform foreign keys",
+    "fk_small": "|R| = 2^20, |S| = 2^22, uniform foreign keys",
+    "skewed": "|R| = 2^26 clustered keys, |S| = 2^28 Zipf(1.0) foreign keys",
+    "lognormal": "|R| = 2^28 log-normal keys with duplicates, |S| = 2^30, 1..16 copies per distinct key",
+}
+
+
+def profile_markdown(t, kt_csv, workload):
+    """Text summary of a profile: the per-kernel statistics of the kernel
+    trace, the per-step durations and HBM bytes of `t` (summarize_profiles),
+    and the dispatch sequence of the last join of the trace."""
+    stats_csv = kt_csv.replace("kernel_trace", "kernel_stats")
+    out = [f"# P-MPSM join on {workload} ({WORKLOAD_TITLE.get(workload, '')}), MI355X", "",
+           "Plain join (sampled splitters, index start search).  R's partitioning and sort run on a second "
+           "stream beside S's bucket sort (from the end of S's scatter on): their durations are durations in "
+           "that shared setting.", "",
+           f"Kernel source digest: {t['kernel_source_digest']}.  Commands (run from /tmp, TMPDIR=/tmp):", "",
+           "```", t.get("command", ""), "```", ""]
+    if os.path.exists(stats_csv):
+        out += ["| kernel | calls | avg (us) | total (ms) |", "|---|---|---|---|"]
+        for r in _read_csv(stats_csv)[:18]:
+            name = r["Name"].split("(")[0].replace("void ", "")
+            out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                       f"{float(r['TotalDurationNs']) / 1e6:.2f} |")
+        out.append("")
+    cal = t["calibration"]
+    out += [f"Per launch step: HBM bytes from FETCH_SIZE x {cal['fetch']['bytes_per_counter_byte']} and "
+            f"WRITE_SIZE x {cal['write']['bytes_per_counter_byte']} (the factors that make the counters read "
+            "1 GiB for the 1 GiB device copy in the same runs).", "",
+            "| step | kernel | avg launch (ms) | HBM read (GB) | HBM write (GB) | algorithmic (GB) | "
+            "traffic / algorithmic | achieved alg. GB/s |", "|---|---|---|---|---|---|---|---|"]
+    for step, v in t["steps"].items():
+        alg = v["algorithmic_bytes"]
+        out.append(f"| {step} | `{v['kernel']}` | {v['avg_launch_ms']:.3f} | {v['fetch_bytes'] / 1e9:.2f} | "
+                   f"{v['write_bytes'] / 1e9:.2f} | {alg / 1e9 if alg else 0:.2f} | "
+                   f"{v['traffic_over_algorithmic'] or '-'} | "
+                   f"{alg / (v['avg_launch_ms'] * 1e-3) / 1e9 if alg else 0:.0f} |")
+    joins = _per_join(_read_csv(kt_csv), "Kernel_Name", "Start_Timestamp")
+    if joins:
+        j = sorted(joins[-1], key=lambda r: int(r["Start_Timestamp"]))
+        t0 = int(j[0]["Start_Timestamp"])
+        out += ["", "Dispatches of the last join of the trace (start and duration in ms; queue 1 is the "
+                "join's stream, queue 2 the second stream):", "", "| start | duration | queue | kernel |",
+                "|---|---|---|---|"]
+        for r in j:
+            if "copyBuffer" in r["Kernel_Name"]:
+                continue
+            out.append(f"| {(int(r['Start_Timestamp']) - t0) / 1e6:.3f} | "
+                       f"{(int(r['End_Timestamp']) - int(r['Start_Timestamp'])) / 1e6:.3f} | "
+                       f"{r.get('Queue_Id', '')} | `{r['Kernel_Name'].split('(')[0].replace('void ', '')}` |")
+    return "\n".join(out) + "\n"
+
+
 def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
     """Read+write bandwidth of a plain device-to-device copy (the runtime's
     copy kernel) on this GPU: the practical ceiling next to the 8 TB/s peak."""
@@ -469,6 +523,8 @@ def main():
         out = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
         with open(out, "w") as f:
             json.dump(t, f, indent=1)
+        with open(os.path.join(ROOT, "profiles", f"pmpsm_join_{args.workload}.md"), "w") as f:
+            f.write(profile_markdown(t, args.summarize_profiles[0], args.workload))
         print(json.dumps(t, indent=1))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -215,48 +215,91 @@ struct CellMap {
 };
 
 // Directory over sorted splitters for fast bucket_of: the span [spl[0],
-// spl[nspl-1]] is cut into D cells by a CellMap; first[c] is the first
-// splitter whose cell is >= c.  A key in cell c
-// has every splitter below first[c] under it and every splitter from
-// first[c+1] on above it, so only the splitters of its own cell (usually 0
-// or 1) are searched.  Same answer as bucket_of.
-template <int D>
-struct SplitDir {
-  uint16_t first[D + 1];
-  CellMap map;
+// spl[nspl-1]] is cut into D cells by a CellMap.  Cell c's entry packs the
+// first splitter whose cell is >= c (bits 0..15) and the number of
+// splitters in cell c (bits 16..31).  A key in cell c has every splitter
+// below the first under it and every splitter after the cell's above it, so
+// only its cell's splitters (usually 0 or 1) are compared: one LDS read of
+// the entry, then at most one of a splitter in the common case.  A splitter
+// of an earlier cell is strictly smaller than the key (cells are monotone),
+// so the equal-splitter rule of bucket_of only needs to look at the
+// splitters compared here, and dup[m] (spl[m] == spl[m-1]) answers it.
+// Same answer as bucket_of.  The per-workgroup constants of the map are
+// copied to registers once (SplitView) instead of being re-read from LDS at
+// every lookup.
+struct SplitView {
+  uint64_t lo, last;
+  uint32_t sh, C, nspl;
+};
 
-  // All threads of the block call; spl (LDS) holds nspl >= 1 sorted splitters.
+template <int D, int NSPL>
+struct SplitDir {
+  uint32_t ent[D];
+  uint8_t dup[NSPL];
+  CellMap map;
+  uint64_t last;
+
+  // All threads of the block call; spl (LDS) holds nspl sorted splitters,
+  // 1 <= nspl <= NSPL < 2^16.
   template <int NT>
   __device__ void build(const uint64_t* spl, uint32_t nspl) {
-    if (threadIdx.x == 0) map.init(spl[0], spl[nspl - 1] - spl[0], D);
+    if (threadIdx.x == 0) { map.init(spl[0], spl[nspl - 1] - spl[0], D); last = spl[nspl - 1]; }
     __syncthreads();
     const CellMap mp = map;
-    for (uint32_t cell = threadIdx.x; cell <= (uint32_t)D; cell += NT) {
-      uint32_t a = 0, b = nspl;  // first m with cell(spl[m]) >= cell
+    auto first_at = [&](uint32_t cell) -> uint32_t {   // first m with cell(spl[m]) >= cell
+      uint32_t a = 0, b = nspl;
       while (a < b) {
         const uint32_t m = (a + b) >> 1;
         if (mp(spl[m]) < cell) a = m + 1; else b = m;
       }
-      first[cell] = (uint16_t)a;
+      return a;
+    };
+    for (uint32_t cell = threadIdx.x; cell < (uint32_t)D; cell += NT) {
+      const uint32_t f0 = first_at(cell), f1 = first_at(cell + 1);
+      ent[cell] = f0 | ((f1 - f0) << 16);
     }
+    for (uint32_t m = threadIdx.x; m < nspl; m += NT) dup[m] = m > 0 && spl[m] == spl[m - 1];
     __syncthreads();
   }
 
-  __device__ __forceinline__ uint32_t bucket(const uint64_t* spl, uint32_t nspl, uint64_t key) const {
-    if (nspl == 0 || key < map.lo) return 0;
+  __device__ __forceinline__ SplitView view(uint32_t nspl) const {
+    SplitView v;
+    v.nspl = nspl;
+    if (nspl) { v.lo = map.lo; v.last = last; v.sh = map.sh; v.C = map.C; }
+    else { v.lo = ~0ull; v.last = ~0ull; v.sh = 0; v.C = 0; }
+    return v;
+  }
+
+  __device__ __forceinline__ uint32_t bucket(const SplitView& v, const uint64_t* spl, uint64_t key) const {
+    if (v.nspl == 0 || key < v.lo) return 0;
     uint32_t b;
-    if (key >= spl[nspl - 1]) {
-      b = nspl;
+    bool eq;
+    if (key >= v.last) {
+      b = v.nspl;
+      eq = key == v.last;
     } else {
-      const uint32_t cell = map(key);   // spl[0] <= key < spl[nspl - 1]: below D
-      uint32_t a = first[cell], e = first[cell + 1];
-      while (a < e) {
-        const uint32_t m = (a + e) >> 1;
-        if (spl[m] <= key) a = m + 1; else e = m;
+      const uint32_t cell = __umulhi((uint32_t)((key - v.lo) >> v.sh), v.C);   // below D
+      const uint32_t e = ent[cell];
+      uint32_t a = e & 0xFFFFu;
+      const uint32_t n = e >> 16;
+      if (n == 0) {
+        b = a;
+        eq = false;
+      } else if (n == 1) {
+        const uint64_t s0 = spl[a];
+        b = a + (s0 <= key);
+        eq = s0 == key;
+      } else {
+        uint32_t z = a + n;
+        while (a < z) {
+          const uint32_t m = (a + z) >> 1;
+          if (spl[m] <= key) a = m + 1; else z = m;
+        }
+        b = a;
+        eq = b > 0 && spl[b - 1] == key;
       }
-      b = a;
     }
-    if (b >= 2 && spl[b - 1] == key && spl[b - 2] == key) b--;
+    if (eq && b >= 2 && dup[b - 1]) b--;
     return b;
   }
 };

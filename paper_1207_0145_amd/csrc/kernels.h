@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
                                                          uint32_t TILE, uint32_t* cnt, const tup_t* const* seg_src) {
   __shared__ uint64_t sp[MAX_NB];
   __shared__ uint32_t h[MAX_NB];
-  __shared__ SplitDir<SPLIT_DIR> dir;
+  __shared__ SplitDir<SPLIT_DIR, MAX_NB> dir;
   const uint32_t g = blockIdx.x;
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
@@ -415,6 +415,7 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
   for (uint32_t i = threadIdx.x; i < NB; i += HIST_NT) h[i] = 0;
   __syncthreads();
   if (nspl) dir.build<HIST_NT>(sp, nspl);
+  const SplitView sv = dir.view(nspl);
   constexpr int HU = 8;   // keys per thread in flight
   for (uint32_t base = a; base < b; base += HIST_NT * HU) {
     uint64_t kk[HU];
@@ -425,7 +426,7 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
     }
 #pragma unroll
     for (int u = 0; u < HU; u++)
-      if (base + u * HIST_NT + threadIdx.x < b) atomicAdd(&h[dir.bucket(sp, nspl, kk[u])], 1u);
+      if (base + u * HIST_NT + threadIdx.x < b) atomicAdd(&h[dir.bucket(sv, sp, kk[u])], 1u);
   }
   __syncthreads();
   uint32_t* c = cnt + seg_cnt0[s] + t;
@@ -444,7 +445,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   __shared__ uint32_t cursor[MAX_NB], lcnt[MAX_NB], lofs[MAX_NB];
   __shared__ tup_t stage[SCAT_CH];
   __shared__ uint32_t wsum[SCAT_NT / 64 + 2];
-  __shared__ SplitDir<SPLIT_DIR> dir;
+  __shared__ SplitDir<SPLIT_DIR, MAX_NB> dir;
   const uint32_t g = blockIdx.x, tid = threadIdx.x;
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
@@ -460,6 +461,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] = p[(uint64_t)i * ntiles]; lcnt[i] = 0; }
   __syncthreads();
   if (nspl) dir.build<SCAT_NT>(sp, nspl);
+  const SplitView sv = dir.view(nspl);
   constexpr int PER = (MAX_NB + SCAT_NT - 1) / SCAT_NT;
   tup_t nv[SCAT_IPT];   // next chunk, loaded while the current one is placed
 #pragma unroll
@@ -481,7 +483,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
     for (int k = 0; k < SCAT_IPT; k++) {
       const uint32_t i = c0 + k * SCAT_NT + tid;
       if (i < b) {
-        bk[k] = dir.bucket(sp, nspl, v[k].key);
+        bk[k] = dir.bucket(sv, sp, v[k].key);
         lr[k] = atomicAdd(&lcnt[bk[k]], 1u);
       }
     }
@@ -516,7 +518,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
       // the bucket is looked up again rather than staged: LDS holds 8 K
       // tuples per chunk, so that every bucket gets a run of several tuples
       const tup_t tq = stage[q];
-      const uint32_t bb = dir.bucket(sp, nspl, tq.key);
+      const uint32_t bb = dir.bucket(sv, sp, tq.key);
       store_tup(dst + cursor[bb] + (q - lofs[bb]), tq);
     }
     __syncthreads();

@@ -98,9 +98,12 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   uint64_t L;
   if (cfg->log2_run_len) L = 1ull << cfg->log2_run_len;
   else {
+    // about 128 runs, but no longer than MAX_NB buckets of the mean size:
+    // longer runs get larger buckets, half of which overflow the two-per-CU
+    // sort's tile and go to the slower one-per-CU sort
     L = next_pow2(cdiv(P->nS ? P->nS : 1, 128));
     if (L < (1u << 16)) L = 1u << 16;
-    if (L > (1u << 22)) L = 1u << 22;
+    while (L > (1u << 16) && L > (uint64_t)MAX_NB * S_BUCKET_MEAN) L >>= 1;
   }
   P->L = (uint32_t)L;
   P->Q = P->nS ? (uint32_t)cdiv(P->nS, L) : 1;
