@@ -351,25 +351,36 @@ def batch_bench(args):
     nR = sum(len(w.R) for w in ws)
     nS = sum(len(w.S) for w in ws)
     del ws
-    b = mpsm.Batch(joins)
     cache = os.path.join(ROOT, "gpurun_out", "batch_autotune.txt") if args.autotune_cache is None else args.autotune_cache
     os.makedirs(os.path.dirname(cache), exist_ok=True)
-    tun = b.autotune(cache)
-    log(f"tuning {tun}")
-    for _ in range(args.warmup):
-        b.run(use_graph=True)
-    torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(args.steps):
-        b.run(use_graph=True)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / args.steps
-    tm = b.times.cpu().numpy().view(np.uint64).astype(np.float64) / mpsm.clock_hz() * 1e6   # us
-    total_us = tm[:, 2] - tm[:, 0]
-    work_us = tm[:, 2] - tm[:, 1]
+
+    def timed(waves):
+        """Autotuned batch with the given waves (0: automatic): ms per graph
+        replay and per-join completion times of the last replay."""
+        b = mpsm.Batch(joins, mpsm.config(waves=waves))
+        tun = b.autotune(cache)
+        log(f"waves {waves}: tuning {tun}")
+        for _ in range(args.warmup):
+            b.run(use_graph=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(args.steps):
+            b.run(use_graph=True)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / args.steps
+        tm = b.times.cpu().numpy().view(np.uint64).astype(np.float64) / mpsm.clock_hz() * 1e6   # us
+        return b, tun, ms, tm[:, 2] - tm[:, 0], tm[:, 2] - tm[:, 1]
+
+    def pct(x):
+        return {"p50": round(float(np.percentile(x, 50)), 1), "p99": round(float(np.percentile(x, 99)), 1)}
+
+    b1, tun1, ms1, total1, _ = timed(1)
+    b1.close()
+    b, tun, ms, total_us, work_us = timed(0)
+    log(f"one wave {ms1:.3f} ms, waves {ms:.3f} ms")
     res = b.results()
     # the same joins, one call each, on one stream
     out = torch.zeros(2, dtype=torch.int64, device="cuda")
@@ -391,16 +402,134 @@ def batch_bench(args):
         "scaling": "strong", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"batch: 256 joins, |R_b| log-uniform in [2^12, 2^22], |S_b| = k_b |R_b| (k_b in 1..8), "
                                f"half uniform, half Zipf(0.5..1.2) foreign keys; sum |R| = {nR}, sum |S| = {nS}",
-                   "launch": "one hipGraph replay per step", "tuning": tun},
+                   "launch": "one hipGraph replay per step (mpsm_join_batch over device descriptors, joins "
+                             "taken in 4 waves by size)", "tuning": tun},
         "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_bytes / (ms * 1e-3) / 1e9, 1),
                           "unit": "GB/s", "frac": round(path_bytes / (ms * 1e-3) / 8e12, 4)},
-        "per_join_us": {"done_since_batch_start": {"p50": round(float(np.percentile(total_us, 50)), 1),
-                                                   "p99": round(float(np.percentile(total_us, 99)), 1)},
-                        "done_since_first_item": {"p50": round(float(np.percentile(work_us, 50)), 1),
-                                                  "p99": round(float(np.percentile(work_us, 99)), 1)}},
+        "per_join_us": {"done_since_batch_start": pct(total_us), "done_since_first_item": pct(work_us)},
+        "one_wave": {"ms_per_step": round(ms1, 4), "tuning": tun1,
+                     "per_join_us": {"done_since_batch_start": pct(total1)}},
         "one_call_per_join": {"ms": round(seq_ms, 3), "value": round((nR + nS) / (seq_ms * 1e-3) / 1e6, 2)},
         "result": {"pairs": int(sum(c for c, _ in res))},
     }
+    print(json.dumps(line), flush=True)
+
+
+def unit_costs(mpsm, ws, nR, nS, cfg):
+    """Section 4.3 cost |R_u| log2 |R_u| + Q |R_u| + |S_u| of every join unit
+    of the last join run in workspace ws (R partitions joined together and
+    their S slices in all Q runs): (max, mean) over the units."""
+    import math
+    import numpy as np
+    lay = mpsm.layout(nR, nS, cfg)
+
+    def part(off, nbytes):
+        return ws[off:off + nbytes].cpu().numpy()
+
+    P = int(part(lay["off_partitions"], 4).view(np.uint32)[0])
+    Q = lay["runs"]
+    plen = part(lay["off_part_len"], 4 * P).view(np.uint32).astype(np.int64)
+    span = part(lay["off_join_span"], P)
+    o = part(lay["off_offsets"], 4 * (P + 1) * Q).view(np.uint32).reshape(P + 1, Q).astype(np.int64)
+    costs = []
+    for p in np.nonzero(span)[0]:
+        r = int(plen[p:p + span[p]].sum())
+        sl = int(np.maximum(o[p + span[p]] - o[p], 0).sum())
+        costs.append(r * math.log2(max(r, 1)) + Q * r + sl)
+    return max(costs), sum(costs) / len(costs)
+
+
+def time_join(mpsm, torch, R, S, cfg, args, steps):
+    """ms per call (steps timed calls after the warm-up) and the result."""
+    ws = mpsm.alloc_workspace(R.shape[0], S.shape[0], cfg, R.device)
+    out = torch.zeros(2, dtype=torch.int64, device=R.device)
+    for _ in range(args.warmup):
+        mpsm.join_into(R, S, out, ws, cfg)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        mpsm.join_into(R, S, out, ws, cfg)
+    t1.record()
+    torch.cuda.synchronize()
+    c, k = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
+    return t0.elapsed_time(t1) / steps, (c, f"{k:#018x}"), ws
+
+
+def experiment_bench(args):
+    """The paper's other experiments on one GPU, one JSON line each:
+      negcorr  (Section 5.6) |R| = 2^24, |S| = 2^26 negatively correlated
+               80:20 keys; sampled, learned and cost-balanced splitters: time
+               and the largest / mean Section 4.3 cost of the join units;
+      roles    (Section 5.4) |R| = 2^24 uniform foreign keys, |S| = m |R| for
+               m = 1, 4, 8, 16; R private (as given) against S private;
+      locskew  (Section 5.5) |R| = 2^24, |S| = 2^26 uniform foreign keys, S
+               unordered against S ordered small to large in one cluster per
+               S run."""
+    import numpy as np
+    import torch
+    import paper_1207_0145_amd as mpsm
+    import workloads
+    dev = torch.device("cuda", 0)
+
+    def to_dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
+
+    steps = args.steps
+    base = {"metric": METRIC, "unit": "M tuples/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "strong", "vs_baseline": None, "dtype": "u64", "data": "synthetic"}
+    if args.workload == "negcorr":
+        w = workloads.negcorr(1 << 24, 1 << 26, seed=0x1207014500000701)
+        R, S = to_dev(w.R), to_dev(w.S)
+        forms = {"sampled": mpsm.config(), "learned": mpsm.config(splitter=mpsm.SPLIT_LEARNED,
+                                                                  search=mpsm.SEARCH_LEARNED),
+                 "cost": mpsm.config(splitter=mpsm.SPLIT_COST)}
+        res = {}
+        for name, cfg in forms.items():
+            ms, r, ws = time_join(mpsm, torch, R, S, cfg, args, steps)
+            mx, mean = unit_costs(mpsm, ws, R.shape[0], S.shape[0], cfg)
+            res[name] = {"ms_per_step": round(ms, 4), "value": round((R.shape[0] + S.shape[0]) / (ms * 1e-3) / 1e6, 2),
+                         "result": r, "unit_cost_max": round(mx), "unit_cost_mean": round(mean),
+                         "unit_cost_max_over_mean": round(mx / mean, 3)}
+            log(f"negcorr {name}: {ms:.3f} ms, unit cost max/mean {mx / mean:.3f}")
+            del ws
+        line = {**base, "value": res["sampled"]["value"], "ms_per_step": res["sampled"]["ms_per_step"],
+                "config": {"workload": f"negcorr: |R|=2^24, |S|=2^26, 80% of R keys in the top 20% and 80% of S "
+                                       f"keys in the bottom 20% of [0, {w.meta['domain']})"}, "forms": res}
+    elif args.workload == "roles":
+        res = {}
+        for m in (1, 4, 8, 16):
+            w = workloads.fk_uniform(1 << 24, m << 24, seed=0x1207014500000800 + m, spread=True)
+            R, S = to_dev(w.R), to_dev(w.S)
+            del w
+            row = {}
+            for name, role in (("R_private", mpsm.ROLE_AS_GIVEN), ("S_private", mpsm.ROLE_SWAP)):
+                ms, r, ws = time_join(mpsm, torch, R, S, mpsm.config(role=role), args, steps)
+                del ws
+                row[name] = {"ms_per_step": round(ms, 4), "result": r}
+                log(f"roles m={m} {name}: {ms:.3f} ms")
+            res[f"m{m}"] = row
+            del R, S
+            torch.cuda.empty_cache()
+        line = {**base, "value": round((5 << 24) / (res["m4"]["R_private"]["ms_per_step"] * 1e-3) / 1e6, 2),
+                "ms_per_step": res["m4"]["R_private"]["ms_per_step"],
+                "config": {"workload": "roles: |R|=2^24 uniform foreign keys, |S| = m |R|; value at m = 4, R private"},
+                "multiplicities": res}
+    else:   # locskew
+        w = workloads.fk_uniform(1 << 24, 1 << 26, seed=0x1207014500000901, spread=True)
+        runs = mpsm.layout(len(w.R), len(w.S))["runs"]
+        res = {}
+        for name, ww in (("unordered", w), ("clustered", workloads.location_skew(w, runs, seed=3))):
+            R, S = to_dev(ww.R), to_dev(ww.S)
+            ms, r, ws = time_join(mpsm, torch, R, S, mpsm.config(), args, steps)
+            del ws
+            res[name] = {"ms_per_step": round(ms, 4), "result": r}
+            log(f"locskew {name}: {ms:.3f} ms")
+        line = {**base, "value": round(((1 << 24) + (1 << 26)) / (res["unordered"]["ms_per_step"] * 1e-3) / 1e6, 2),
+                "ms_per_step": res["unordered"]["ms_per_step"],
+                "config": {"workload": f"locskew: |R|=2^24, |S|=2^26 uniform foreign keys; S unordered or ordered "
+                                       f"small to large in {runs} clusters (one per S run)"}, "orders": res}
     print(json.dumps(line), flush=True)
 
 
@@ -500,7 +629,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal",
-                    choices=["fk_uniform", "fk_small", "skewed", "lognormal", "batch"])
+                    choices=["fk_uniform", "fk_small", "skewed", "lognormal", "batch", "negcorr", "roles",
+                             "locskew"])
     ap.add_argument("--extra", default="fk_uniform,skewed",
                     help="comma-separated single-join workloads reported beside the headline ('' for none)")
     ap.add_argument("--autotune-cache", default=None, help="batch workload: autotuner cache file")
@@ -534,6 +664,9 @@ def main():
 
     if args.workload == "batch":
         batch_bench(args)
+        return
+    if args.workload in ("negcorr", "roles", "locskew"):
+        experiment_bench(args)
         return
     import torch
     main_res = measure(args, args.workload, args.steps, learned=not args.no_learned)

@@ -75,8 +75,14 @@ enum { MPSM_ROLE_AUTO = 0, MPSM_ROLE_AS_GIVEN = 1, MPSM_ROLE_SWAP = 2 };
  *            (Q = S runs; |S_i| from the S runs' equi-height bounds merged
  *            into a global S distribution, Section 4.1; |R_i| from a sorted
  *            R sample) is minimised over contiguous groups of sample cells.
- *            A second level, when R needs one, stays sampled. */
-enum { MPSM_SPLIT_SAMPLED = 0, MPSM_SPLIT_LEARNED = 1, MPSM_SPLIT_COST = 2 };
+ *            A second level, when R needs one, stays sampled.
+ *   NONE     B-MPSM (Section 2.1, Fig. 3): no range partitioning.  R is
+ *            sorted into runs of the S run length exactly as S is, and every
+ *            R run is merge-joined with every S run (each partition of an R
+ *            run is one of its sort buckets, a key range inside that run).
+ *            Its join work grows with the number of R runs, and it is
+ *            immune to skew by construction. */
+enum { MPSM_SPLIT_SAMPLED = 0, MPSM_SPLIT_LEARNED = 1, MPSM_SPLIT_COST = 2, MPSM_SPLIT_NONE = 3 };
 /* Start search of every R partition in every S run (Section 3.2.2):
  *   BINARY   bisection of the run;  INTERP  the paper's interpolation search;
  *   INDEX    bisection of the run's equi-height index, then of one window;
@@ -97,7 +103,7 @@ typedef struct mpsm_config {
   uint32_t join_chunk;     /* S tuples per join work item, 1024..261888 */
   uint32_t want_max;       /* 1: also compute max(R.payload + S.payload) (Section 5.1 query) */
   uint32_t oversample;     /* sample keys drawn per bucket for the splitters, 1..64 */
-  uint32_t reserved;       /* must be 0 */
+  uint32_t waves;          /* batches only: waves the joins are taken in, 1..64 (see mpsm_join_batch) */
   uint64_t seed;           /* seed of the splitter samples */
 } mpsm_config;
 
@@ -255,15 +261,15 @@ mpsm_status mpsm_events_elapsed(void* start, void* stop, float* ms);
 
 
 /* ---- Batched joins --------------------------------------------------------
- * Many independent equi-joins of uneven sizes as ONE launch sequence: every
- * phase of the method is a single kernel launch over all joins of the batch
+ * Many independent equi-joins of uneven sizes as one launch sequence: every
+ * phase of the method is a single kernel launch over all joins being joined
  * (segment tables span the joins; each join's inputs are read in place), so
- * the per-launch cost is paid once per batch instead of once per join, and
- * the whole sequence can be captured once into a hipGraph and replayed.
- * Each join's result is the one mpsm_join gives (count and checksum as
- * documented there).  In a batch R is always the private input (no role
- * swap), splitters are sampled and the start search is BINARY, INTERP or
- * INDEX; pairs and the max aggregate are not produced. */
+ * the per-launch cost is paid once per group of joins instead of once per
+ * join, and the whole sequence can be captured once into a hipGraph and
+ * replayed.  Each join's result is the one mpsm_join gives (count and
+ * checksum as documented there).  In a batch R is always the private input
+ * (no role swap), splitters are sampled and the start search is BINARY,
+ * INTERP or INDEX; pairs and the max aggregate are not produced. */
 typedef struct mpsm_join_desc {
   const mpsm_tuple* d_R;   /* device, nR tuples, 16-byte aligned (NULL if nR == 0) */
   uint64_t nR;
@@ -276,8 +282,47 @@ typedef struct mpsm_join_desc {
                               a join without work items reports the batch start three times) */
 } mpsm_join_desc;
 
-/* Host-side plan of a batch (opaque).  Holds a copy of the descriptors, the
- * segment tables, the current tuning and, once used, a captured hipGraph. */
+/* Bounds of a batch's shape class: the sums of nR and of nS over the joins
+ * whose sides are both non-empty, and the largest nS of one join (0: the
+ * sum).  Each sum must stay below 2^32.  A launch sized for a shape serves
+ * every batch of at most that many joins within its bounds. */
+typedef struct mpsm_batch_shape {
+  uint64_t max_sum_nR;
+  uint64_t max_sum_nS;
+  uint64_t max_nS;
+} mpsm_batch_shape;
+
+/* Workspace bytes of mpsm_join_batch for n joins of this shape class and
+ * config (NULL: defaults); 0 if not supported. */
+uint64_t mpsm_join_batch_workspace_bytes(uint32_t n, const mpsm_batch_shape* shape, const mpsm_config* cfg);
+
+/* n independent joins whose descriptors are in DEVICE memory (d_descs: n
+ * mpsm_join_desc, 8-byte aligned), as one stream-ordered launch sequence.
+ * The host reads neither the descriptors nor any size: launches are sized
+ * by n and *shape, and the descriptors are read and checked on the GPU, so
+ * the call can be captured into a hipGraph once and the graph replayed for
+ * any new batch written into the same descriptor array (same n, within the
+ * shape's bounds).  Joins are taken in waves (cfg->waves, 0: 4 for 32 joins
+ * or more, 2 for 8 or more, else 1; one wave beyond 4096 joins): ordered
+ * by nR + nS (ties by index), cut into groups of equal count, smallest
+ * first, so that small joins finish without waiting for the large ones;
+ * a join with an empty side is in the first wave.  cfg's log2_run_len (16..22),
+ * bucket_target (1024..4096) and join_chunk (4096..261888) set the tuning
+ * (0: the shortest run length that keeps every join within 2048 runs,
+ * 4096, 65536).  The workspace (mpsm_join_batch_workspace_bytes, 256-byte
+ * aligned) needs no initialisation; its first 4 bytes receive the batch
+ * status once the stream completes: MPSM_OK, or MPSM_EINVAL when a
+ * descriptor is malformed (NULL or misaligned pointers, a size of 2^32 or
+ * more, nS above max_nS) or the joins exceed the shape's sums; then no
+ * output is written.  Host-side checks (config, shape, alignment, workspace
+ * size) return before anything is enqueued.  Calls on one workspace must
+ * not overlap.  Nothing is allocated. */
+mpsm_status mpsm_join_batch(const mpsm_join_desc* d_descs, uint32_t n, const mpsm_batch_shape* shape,
+                            const mpsm_config* cfg, void* d_workspace, uint64_t workspace_bytes, void* stream);
+
+/* Host-side layer over mpsm_join_batch (opaque): keeps a host copy of the
+ * descriptors, uploads them into its workspace, picks the tuning (autotuner)
+ * and captures the launch into a hipGraph on first use. */
 typedef struct mpsm_batch mpsm_batch;
 
 /* Tuning of a batch: the S run length, the mean bucket / partition size
@@ -301,8 +346,9 @@ void mpsm_batch_destroy(mpsm_batch* b);
 /* Workspace bytes that serve every tuning the autotuner may pick. */
 uint64_t mpsm_batch_workspace_bytes(const mpsm_batch* b);
 
-/* Enqueue the batch on `stream`.  The first call with a workspace (or after
- * a tuning change) copies the batch's tables into it; with use_graph != 0 the
+/* Enqueue the batch on `stream` (mpsm_join_batch with the batch's own sums
+ * as its shape).  The first call with a workspace copies the descriptors
+ * into it (from pinned memory the batch keeps); with use_graph != 0 the
  * launch sequence is captured into a hipGraph on first use (on a stream the
  * batch owns, after synchronising `stream`) and replayed on `stream`
  * afterwards (the graph is bound to that workspace).  Calls on one workspace

@@ -62,6 +62,7 @@ def lib():
             "orc_split_cost": ([u64, u32, u64], dbl),
             "orc_cost_splitters_dp": ([p, p, u32, u32, u32, p], dbl),
             "orc_pmpsm_join": ([p, u64, p, u64, u32, i32, i32, p, p], i32),
+            "orc_bmpsm_join": ([p, u64, p, u64, u32, p], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -271,6 +272,15 @@ def cost_splitters_dp(h, s, P: int, T: int):
     first = np.zeros(P, np.uint32)
     opt = float(lib().orc_cost_splitters_dp(_p(h), _p(s), len(h), P, T, _p(first)))
     return opt, first
+
+
+def bmpsm_join(R, S, T: int) -> JoinResult:
+    """B-MPSM (Section 2.1): T sorted runs of each input, every R run
+    merge-joined with every S run."""
+    R, S = _tuples(R), _tuples(S)
+    out4 = np.zeros(4, np.uint64)
+    _check(lib().orc_bmpsm_join(_p(R), len(R), _p(S), len(S), T, _p(out4)), "bmpsm_join")
+    return _result(out4)
 
 
 def pmpsm_join(R, S, T: int, B: int, shift: int = 0, sp=None) -> JoinResult:

@@ -27,7 +27,8 @@
  *     function, phase 4 start search by lower bound and by interpolation
  *     (Section 3.2.2, Fig. 7), the global S distribution from merged
  *     equi-height bounds (Section 4.1, Fig. 8), the split-relevant cost and
- *     its min-max split (Section 4.3), and the full P-MPSM join (Fig. 5).
+ *     its min-max split (Section 4.3), the basic B-MPSM join (Section 2.1,
+ *     Fig. 3) and the full P-MPSM join (Fig. 5).
  *
  * Pins: see tests/test_oracle_pins.py.  The learned-CDF quality is not
  * computed here (parity unpinned: the paper has no learned model; only
@@ -497,6 +498,48 @@ double orc_cost_splitters_dp(const uint64_t* h, const uint64_t* s, uint32_t nb, 
 #undef ARG
   free(best); free(arg);
   return opt;
+}
+
+/* ------------------------------------------- B-MPSM (the basic variant) */
+
+/* B-MPSM (Section 2.1, Fig. 3) with T workers: both inputs cut into T
+ * chunks, each chunk sorted into a run; worker i merge-joins its private run
+ * R_i with every public run S_j from the start (no range partitioning, so
+ * every pair of runs is merged over its whole length).  out4 as in
+ * orc_join.  Must equal orc_join on any input. */
+int orc_bmpsm_join(const uint64_t* R, uint64_t nR, const uint64_t* S, uint64_t nS, uint32_t T, uint64_t* out4) {
+  if (T == 0) return -2;
+  uint64_t lr = nR ? (nR + T - 1) / T : 1, ls = nS ? (nS + T - 1) / T : 1;
+  uint64_t* Rr = (uint64_t*)malloc((2 * nR + 2) * sizeof(uint64_t));
+  uint64_t* Sr = (uint64_t*)malloc((2 * nS + 2) * sizeof(uint64_t));
+  if (!Rr || !Sr) { free(Rr); free(Sr); return -1; }
+  orc_sort_runs(R, nR, lr, Rr);
+  orc_sort_runs(S, nS, ls, Sr);
+  orc_acc a = {0, 0, 0, 0};
+  for (uint64_t i0 = 0; i0 < nR; i0 += lr) {
+    const uint64_t* Ri = Rr + 2 * i0;
+    uint64_t ni = nR - i0 < lr ? nR - i0 : lr;
+    for (uint64_t j0 = 0; j0 < nS; j0 += ls) {
+      const uint64_t* Sj = Sr + 2 * j0;
+      uint64_t nj = nS - j0 < ls ? nS - j0 : ls;
+      uint64_t x = 0, y = 0;
+      while (x < ni && y < nj) {
+        if (Ri[2 * x] < Sj[2 * y]) x++;
+        else if (Ri[2 * x] > Sj[2 * y]) y++;
+        else {
+          uint64_t k = Ri[2 * x], x2 = x, y2 = y;
+          while (x2 < ni && Ri[2 * x2] == k) x2++;
+          while (y2 < nj && Sj[2 * y2] == k) y2++;
+          for (uint64_t p = x; p < x2; p++)
+            for (uint64_t q = y; q < y2; q++) acc_pair(&a, k, Ri[2 * p + 1], Sj[2 * q + 1], NULL, 0);
+          x = x2; y = y2;
+        }
+      }
+    }
+  }
+  acc_out(&a, out4);
+  free(Rr); free(Sr);
+  return 0;
 }
 
 /* --------------------------------------------- the whole P-MPSM on the CPU */

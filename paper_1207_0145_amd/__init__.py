@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmpsm.so")
 
 ROLE_AUTO, ROLE_AS_GIVEN, ROLE_SWAP = 0, 1, 2
-SPLIT_SAMPLED, SPLIT_LEARNED, SPLIT_COST = 0, 1, 2
+SPLIT_SAMPLED, SPLIT_LEARNED, SPLIT_COST, SPLIT_NONE = 0, 1, 2, 3
 SEARCH_BINARY, SEARCH_INTERP, SEARCH_LEARNED, SEARCH_INDEX = 0, 1, 2, 3
 STATUS = {0: "MPSM_OK", 1: "MPSM_EINVAL", 2: "MPSM_ECAPACITY", 3: "MPSM_ENOMEM", 4: "MPSM_EHIP",
           5: "MPSM_EUNSUPPORTED"}
@@ -26,14 +26,14 @@ EXPORTS = ("mpsm_config_default", "mpsm_workspace_bytes", "mpsm_join", "mpsm_sta
            "mpsm_events_create", "mpsm_events_destroy", "mpsm_events_elapsed", "mpsm_batch_create",
            "mpsm_batch_destroy", "mpsm_batch_workspace_bytes", "mpsm_batch_run", "mpsm_batch_autotune",
            "mpsm_batch_get_tuning", "mpsm_batch_set_tuning", "mpsm_clock_hz", "mpsm_join_slices_host",
-           "mpsm_join_noalloc")
+           "mpsm_join_noalloc", "mpsm_join_batch", "mpsm_join_batch_workspace_bytes")
 
 
 class MpsmConfig(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("role", ctypes.c_int32), ("splitter", ctypes.c_int32),
                 ("search", ctypes.c_int32), ("log2_run_len", ctypes.c_uint32), ("bucket_target", ctypes.c_uint32),
                 ("join_chunk", ctypes.c_uint32), ("want_max", ctypes.c_uint32), ("oversample", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+                ("waves", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
 
 
 class MpsmStats(ctypes.Structure):
@@ -73,6 +73,10 @@ class MpsmJoinDesc(ctypes.Structure):
     _fields_ = [("d_R", ctypes.c_void_p), ("nR", ctypes.c_uint64), ("d_S", ctypes.c_void_p), ("nS", ctypes.c_uint64),
                 ("d_out_count", ctypes.c_void_p), ("d_out_checksum", ctypes.c_void_p),
                 ("d_out_times", ctypes.c_void_p)]
+
+
+class MpsmBatchShape(ctypes.Structure):
+    _fields_ = [("max_sum_nR", ctypes.c_uint64), ("max_sum_nS", ctypes.c_uint64), ("max_nS", ctypes.c_uint64)]
 
 
 class MpsmBatchTuning(ctypes.Structure):
@@ -140,6 +144,12 @@ def lib():
         L.mpsm_join_slices_host.restype = ctypes.c_int
         L.mpsm_join_noalloc.argtypes = [p, u64, p, u64, p, p, p, u64, ctypes.POINTER(MpsmConfig), p]
         L.mpsm_join_noalloc.restype = ctypes.c_int
+        L.mpsm_join_batch_workspace_bytes.argtypes = [ctypes.c_uint32, ctypes.POINTER(MpsmBatchShape),
+                                                      ctypes.POINTER(MpsmConfig)]
+        L.mpsm_join_batch_workspace_bytes.restype = u64
+        L.mpsm_join_batch.argtypes = [p, ctypes.c_uint32, ctypes.POINTER(MpsmBatchShape), ctypes.POINTER(MpsmConfig),
+                                      p, u64, p]
+        L.mpsm_join_batch.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -313,6 +323,39 @@ def join(R, S, cfg: MpsmConfig | None = None, pairs: bool = False, pairs_capacit
     if st is not None:
         res["stats"] = {name: getattr(st, name) for name, _ in st._fields_}
     return res
+
+
+def batch_shape(max_sum_nR: int, max_sum_nS: int, max_nS: int = 0) -> MpsmBatchShape:
+    return MpsmBatchShape(max_sum_nR, max_sum_nS, max_nS)
+
+
+def join_batch_workspace_bytes(n: int, shape: MpsmBatchShape, cfg: MpsmConfig | None = None) -> int:
+    return int(lib().mpsm_join_batch_workspace_bytes(n, ctypes.byref(shape), _cfg_ptr(cfg)))
+
+
+def write_descs(descs, joins, out, times=None):
+    """Fill a GPU int64 [n, 7] tensor with the mpsm_join_desc records of
+    joins (a list of (R, S) tensors): R, nR, S, nS, &out[i, 0], &out[i, 1],
+    &times[i, 0] (or 0).  One host-to-device copy; no join arithmetic."""
+    import torch
+    rows = []
+    for i, (R, S) in enumerate(joins):
+        _check_tuples(R, "R")
+        _check_tuples(S, "S")
+        rows.append([R.data_ptr() if R.shape[0] else 0, R.shape[0], S.data_ptr() if S.shape[0] else 0, S.shape[0],
+                     out.data_ptr() + 16 * i, out.data_ptr() + 16 * i + 8,
+                     times.data_ptr() + 24 * i if times is not None else 0])
+    descs.copy_(torch.tensor(rows, dtype=torch.int64).reshape(descs.shape))
+
+
+def join_batch(descs, n: int, shape: MpsmBatchShape, workspace, cfg: MpsmConfig | None = None, stream=None) -> int:
+    """mpsm_join_batch over the device descriptor array `descs` (a GPU
+    int64 [n, 7] tensor, see write_descs); enqueues only."""
+    rc = lib().mpsm_join_batch(ctypes.c_void_p(descs.data_ptr()), n, ctypes.byref(shape), _cfg_ptr(cfg),
+                               ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_handle(stream))
+    if rc != 0:
+        raise MpsmError(rc, "mpsm_join_batch")
+    return rc
 
 
 class Batch:

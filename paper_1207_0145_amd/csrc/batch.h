@@ -8,17 +8,146 @@
 #pragma once
 #include "kernels.h"
 
-// Fresh join table (all but the host-filled fields) and the batch start time.
-__global__ void k_batch_init(BatchJoin* J, uint32_t n, unsigned long long* t_start, uint32_t* zero_words,
-                             uint32_t nzero) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) *t_start = wall_clock64();
-  for (uint32_t b = t; b < n; b += gridDim.x * blockDim.x) {
-    BatchJoin& j = J[b];
-    j.p0 = 0xFFFFFFFFu; j.P = 0; j.obase = 0; j.items = 0; j.done = 0;
-    j.count = 0; j.checksum = 0; j.t_first = ~0ull; j.t_done = 0;
+#include "mpsm.h"
+
+// The batch reads its joins from a device array of descriptors
+// (mpsm_join_desc); the host knows only their number and bounds on their
+// sizes, so every launch is sized by those bounds and the kernels below
+// build the tables on the device.  Joins are taken in waves: ordered by
+// their tuples (nR + nS, ties by index) and cut into W groups of equal
+// count, the smallest first, so that small joins finish early instead of
+// waiting for the whole batch.
+
+constexpr int BPLAN_NT = 1024;
+constexpr uint32_t BATCH_RANK_MAX = 4096;   // joins that can be ordered into waves
+constexpr uint32_t NO_WAVE = 0xFFFFFFFFu;
+
+// S runs of one join and R buckets of one join (as k_seg_plan counts them).
+__device__ __forceinline__ uint32_t batch_runs_of(uint64_t nS, uint32_t L) { return (uint32_t)((nS + L - 1) / L); }
+__device__ __forceinline__ uint32_t batch_buckets_of(uint64_t nR, uint32_t BT) {
+  const uint64_t nb = (nR + BT - 1) / BT;
+  return nb < 1 ? 1u : (nb > (uint64_t)MAX_NB ? (uint32_t)MAX_NB : (uint32_t)nb);
+}
+
+// Checks the descriptors and assigns every join to a wave (wave[b]).  A
+// join with an empty side is in wave 0, where its result (0, 0) is
+// written.  status[0] = MPSM_OK, or MPSM_EINVAL when a descriptor is
+// malformed (NULL or misaligned pointers, a size of 2^32 or more) or the
+// joins exceed the bounds the launches were sized for: then no join is in
+// any wave and no output is written.  Also stamps the batch start time.
+__global__ void __launch_bounds__(BPLAN_NT) k_batch_check(const mpsm_join_desc* d, uint32_t n, uint32_t W,
+                                                          uint64_t max_sum_nR, uint64_t max_sum_nS, uint64_t max_nS,
+                                                          uint32_t* wave, uint32_t* status,
+                                                          unsigned long long* t_start) {
+  __shared__ unsigned long long sumR, sumS;
+  __shared__ uint32_t bad, nact;
+  __shared__ uint64_t work[BATCH_RANK_MAX];
+  const uint32_t tid = threadIdx.x;
+  if (tid == 0) { sumR = 0; sumS = 0; bad = 0; nact = 0; *t_start = wall_clock64(); }
+  __syncthreads();
+  const bool rank = W > 1 && n <= BATCH_RANK_MAX;
+  for (uint32_t b = tid; b < n; b += BPLAN_NT) {
+    const mpsm_join_desc x = d[b];
+    bool ok = (!x.nR || x.d_R) && (!x.nS || x.d_S) && x.d_out_count && x.d_out_checksum &&
+              !((uintptr_t)x.d_R & 15) && !((uintptr_t)x.d_S & 15) && !((uintptr_t)x.d_out_count & 7) &&
+              !((uintptr_t)x.d_out_checksum & 7) && !((uintptr_t)x.d_out_times & 7) && x.nR < (1ull << 32) &&
+              x.nS < (1ull << 32);
+    const bool act = x.nR && x.nS;
+    if (act) {
+      ok = ok && x.nS <= max_nS;
+      atomicAdd(&sumR, (unsigned long long)x.nR);
+      atomicAdd(&sumS, (unsigned long long)x.nS);
+      atomicAdd(&nact, 1u);
+    }
+    if (!ok) atomicOr(&bad, 1u);
+    if (rank) work[b] = act ? x.nR + x.nS : 0;
   }
-  for (uint32_t i = t; i < nzero; i += gridDim.x * blockDim.x) zero_words[i] = 0;
+  __syncthreads();
+  const bool fail = bad || sumR > max_sum_nR || sumS > max_sum_nS || sumR >= (1ull << 32) || sumS >= (1ull << 32);
+  const uint32_t na = nact;
+  for (uint32_t b = tid; b < n; b += BPLAN_NT) {
+    uint32_t w = 0;
+    if (fail) {
+      w = NO_WAVE;
+    } else if (rank && work[b]) {
+      const uint64_t wb = work[b];
+      uint32_t r = 0;   // rank among the joins with work
+      for (uint32_t q = 0; q < n; q++) {
+        const uint64_t wq = work[q];
+        r += wq && (wq < wb || (wq == wb && q < b));
+      }
+      w = (uint32_t)((uint64_t)r * W / na);
+    }
+    wave[b] = w;
+  }
+  if (tid == 0) status[0] = fail ? (uint32_t)MPSM_EINVAL : (uint32_t)MPSM_OK;
+}
+
+// Tables of wave w: the join table (every join; only the wave's joins get
+// runs and buckets), the S segments (the runs of the wave's joins, in join
+// order, then empty runs up to Qmax) and the R segments (one per joined
+// join, then empty ones up to n), with each segment's source array; zeroes
+// the counter words.
+__global__ void __launch_bounds__(BPLAN_NT) k_batch_plan(const mpsm_join_desc* d, uint32_t n, const uint32_t* wave,
+                                                         uint32_t w, uint32_t L, uint32_t BT, uint32_t Qmax,
+                                                         BatchJoin* J, uint32_t* segS_start, uint32_t* segS_len,
+                                                         const tup_t** srcS, uint32_t* segR_start,
+                                                         uint32_t* segR_len, const tup_t** srcR,
+                                                         uint32_t* zero_words, uint32_t nzero) {
+  __shared__ uint32_t wsum[5][BPLAN_NT / 64 + 2];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < nzero; i += BPLAN_NT) zero_words[i] = 0;
+  uint32_t cQ = 0, cG = 0, cA = 0, cS = 0, cR = 0;
+  for (uint32_t b0 = 0; b0 < n; b0 += BPLAN_NT) {
+    const uint32_t b = b0 + tid;
+    mpsm_join_desc x;
+    bool member = false, act = false;
+    if (b < n) {
+      x = d[b];
+      member = wave[b] == w;
+      act = member && x.nR && x.nS;
+    }
+    const uint32_t Q = act ? batch_runs_of(x.nS, L) : 0, G = act ? batch_buckets_of(x.nR, BT) : 0;
+    const uint32_t nS = act ? (uint32_t)x.nS : 0, nR = act ? (uint32_t)x.nR : 0;
+    uint32_t t[5];
+    const uint32_t eQ = block_excl_scan<BPLAN_NT>(Q, wsum[0], &t[0]);
+    const uint32_t eG = block_excl_scan<BPLAN_NT>(G, wsum[1], &t[1]);
+    const uint32_t eA = block_excl_scan<BPLAN_NT>(act ? 1u : 0u, wsum[2], &t[2]);
+    const uint32_t eS = block_excl_scan<BPLAN_NT>(nS, wsum[3], &t[3]);
+    const uint32_t eR = block_excl_scan<BPLAN_NT>(nR, wsum[4], &t[4]);
+    if (b < n) {
+      BatchJoin& j = J[b];
+      j.r0 = cQ + eQ; j.Q = Q; j.g0 = cG + eG; j.G = G;
+      j.member = member ? 1u : 0u; j.s0 = cS + eS;
+      j.p0 = 0xFFFFFFFFu; j.P = 0; j.obase = 0; j.items = 0; j.done = 0;
+      j.count = 0; j.checksum = 0; j.t_first = ~0ull; j.t_done = 0;
+      j.out_count = x.d_out_count; j.out_checksum = x.d_out_checksum; j.out_times = x.d_out_times;
+      if (act) {
+        const uint32_t a = cA + eA;
+        segR_start[a] = cR + eR;
+        segR_len[a] = nR;
+        srcR[a] = reinterpret_cast<const tup_t*>(x.d_R);
+      }
+    }
+    cQ += t[0]; cG += t[1]; cA += t[2]; cS += t[3]; cR += t[4];
+    __syncthreads();
+  }
+  // empty segments after the joined ones: they start at the end
+  for (uint32_t a = cA + tid; a < n; a += BPLAN_NT) { segR_start[a] = cR; segR_len[a] = 0; srcR[a] = nullptr; }
+  for (uint32_t q = cQ + tid; q < Qmax; q += BPLAN_NT) { segS_start[q] = cS; segS_len[q] = 0; srcS[q] = nullptr; }
+  __syncthreads();   // the join table above is read back below
+  // the runs of every joined join: run q belongs to the last join whose
+  // first run is at or below q (joins without runs share the next start)
+  for (uint32_t q = tid; q < cQ; q += BPLAN_NT) {
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) { const uint32_t m = (lo + hi) >> 1; if (J[m].r0 <= q) lo = m; else hi = m; }
+    const BatchJoin& j = J[lo];
+    const uint32_t r = q - j.r0;
+    const uint64_t nSj = d[lo].nS;
+    segS_start[q] = j.s0 + r * L;
+    segS_len[q] = (uint32_t)((uint64_t)(r + 1) * L <= nSj ? L : nSj - (uint64_t)r * L);
+    srcS[q] = reinterpret_cast<const tup_t*>(d[lo].d_S) + (uint64_t)r * L;
+  }
 }
 
 // Join whose range [x0, x0 + xn) holds position x: the last join with
@@ -135,11 +264,12 @@ __global__ void k_join_items_batch(const uint32_t* Pcount, const uint32_t* pjoin
   items[p] = it;
 }
 
-// Results and times of every join to the caller's slots.
+// Results and times of the wave's joins to the caller's slots.
 __global__ void k_finalize_batch(const BatchJoin* J, uint32_t n, const unsigned long long* t_start) {
   const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= n) return;
   const BatchJoin& j = J[b];
+  if (!j.member) return;
   *j.out_count = j.count;
   *j.out_checksum = j.checksum;
   if (j.out_times) {

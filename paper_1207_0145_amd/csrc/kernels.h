@@ -66,11 +66,14 @@ struct Result {              // device result block
   unsigned long long truncated;   // status word: 1 if pairs were requested and count > their capacity
 };
 
-// One join of a batch (device table).  The host fills the run and bucket
-// ranges and the output pointers; the kernels fill the rest.
+// One join of a batch (device table), rewritten for every wave of the batch
+// by k_batch_plan: the run and bucket ranges (empty unless the join is
+// joined in this wave) and the output pointers; the other kernels fill the
+// rest.
 struct BatchJoin {
   uint32_t r0, Q;                     // S runs [r0, r0 + Q)
   uint32_t g0, G;                     // R buckets [g0, g0 + G)
+  uint32_t member, s0;                // joined in this wave; first position of its S tuples
   uint32_t p0, P;                     // partitions [p0, p0 + P)
   unsigned long long obase;           // first entry of the join's (P + 1) x Q block of start offsets
   uint32_t items, done;               // join work items; items finished
@@ -536,12 +539,14 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
 // [0, 2^64-1] at the first level.
 __global__ void k_bucket_table(uint32_t nseg, uint32_t NBmax, const uint32_t* seg_start, const uint32_t* seg_tile0,
                                const uint32_t* seg_cnt0, const uint32_t* seg_nb, const uint32_t* seg_b0,
-                               const uint32_t* pos, uint32_t n, const uint64_t* spl, const uint64_t* outer,
-                               uint32_t outer_nspl, uint32_t* bstart, uint64_t* blo, uint64_t* bhi) {
+                               const uint32_t* seg_len, const uint32_t* pos, const uint64_t* spl,
+                               const uint64_t* outer, uint32_t outer_nspl, uint32_t* bstart, uint64_t* blo,
+                               uint64_t* bhi) {
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t G = seg_b0[nseg];
   if (g > G) return;
-  if (g == G) { bstart[G] = n; return; }
+  // the segments tile [0, n) in order (trailing empty ones start at n)
+  if (g == G) { bstart[G] = seg_start[nseg - 1] + seg_len[nseg - 1]; return; }
   uint32_t lo = 0, hi = nseg;   // last s with seg_b0[s] <= g
   while (hi - lo > 1) { const uint32_t m = (lo + hi) >> 1; if (seg_b0[m] <= g) lo = m; else hi = m; }
   const uint32_t s = lo, b = g - seg_b0[s], nb = seg_nb[s];
@@ -1241,6 +1246,42 @@ __global__ void __launch_bounds__(1024) k_partitions(const uint32_t* bstart, con
   if (threadIdx.x == 0) *Pcount = carry;
 }
 
+// B-MPSM (Section 2.1, Fig. 3: no range partitioning; every sorted R run
+// meets every sorted S run): the partitions are the non-empty buckets of
+// every sorted R run (key ranges inside that run, in order; NB buckets per
+// run), and every run is closed by an empty terminator partition (pterm)
+// whose start offsets are the S runs' lengths, so that the last partition
+// of a run is joined with the tail of every S run and no join unit spans
+// two R runs.
+__global__ void __launch_bounds__(1024) k_partitions_runs(const uint32_t* bstart, const uint64_t* bkey,
+                                                          const uint32_t* Gcount, uint32_t NB, uint32_t* Pcount,
+                                                          uint32_t* pstart, uint32_t* plen, uint64_t* pkey,
+                                                          uint8_t* pterm, Result* res) {
+  __shared__ uint32_t wsum[1024 / 64 + 2];
+  const uint32_t G = *Gcount;
+  uint32_t carry = 0;
+  for (uint32_t b = 0; b < G; b += 1024) {
+    const uint32_t g = b + threadIdx.x;
+    const uint32_t len = g < G ? bstart[g + 1] - bstart[g] : 0;
+    const bool last = g < G && g % NB == NB - 1;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<1024>((len ? 1u : 0u) + (last ? 1u : 0u), wsum, &tot);
+    if (len) {
+      const uint32_t p = carry + ex;
+      pstart[p] = bstart[g]; plen[p] = len; pkey[p] = bkey[g]; pterm[p] = 0;
+      if (res) atomicMax(&res->spare, (unsigned long long)len);
+    }
+    if (last) {
+      const uint32_t p = carry + ex + (len ? 1u : 0u);
+      pstart[p] = bstart[g + 1]; plen[p] = 0; pkey[p] = ~0ull; pterm[p] = 1;
+    }
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *Pcount = carry;
+}
+
+
 // ------------------------------------------------------------------ search
 
 enum { SEARCH_BINARY = 0, SEARCH_INTERP = 1, SEARCH_LEARNED = 2, SEARCH_INDEX = 3 };
@@ -1324,7 +1365,8 @@ __global__ void __launch_bounds__(SEARCH_NT) k_search(const tup_t* __restrict__ 
                                                 const uint32_t* run_len, uint32_t Q, const uint64_t* run_idx,
                                                 uint32_t idx_stride, uint32_t idx_per_run, const uint32_t* Pcount,
                                                 const uint64_t* pkey, uint32_t Pmax, uint32_t* o, int mode,
-                                                const CdfModel* model, Result* res, const uint8_t* span) {
+                                                const CdfModel* model, Result* res, const uint8_t* span,
+                                                const uint8_t* pterm) {
   const bool learned = mode == SEARCH_LEARNED;
   const CdfModel& m = *model;   // read through the caches: its knots are shared by all threads
   const uint32_t njt = (Q + SEARCH_RUNS - 1) / SEARCH_RUNS;
@@ -1337,7 +1379,7 @@ __global__ void __launch_bounds__(SEARCH_NT) k_search(const tup_t* __restrict__ 
     const uint32_t n = run_len[j];
     const tup_t* run = U + run_start[j];
     uint32_t r;
-    if (p == P) {
+    if (p == P || (pterm && pterm[p])) {   // the end of the runs (B-MPSM: of every R run)
       r = n;
     } else {
       const uint64_t key = pkey[p];
@@ -1402,11 +1444,14 @@ __device__ __forceinline__ uint32_t join_span(const uint32_t* plen, uint32_t P, 
 }
 
 // The join units of all partitions (before the start search, which only
-// needs the rows of partitions that start a unit).
-__global__ void k_join_units(const uint32_t* Pcount, const uint32_t* plen, uint32_t Pmax, uint8_t* span) {
+// needs the rows of partitions that start a unit).  With B-MPSM's
+// terminators (pterm) a terminator never shares a unit.
+__global__ void k_join_units(const uint32_t* Pcount, const uint32_t* plen, uint32_t Pmax, uint8_t* span,
+                             const uint8_t* pterm) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t P = *Pcount;
-  if (p < P && p < Pmax) span[p] = (uint8_t)join_span(plen, P, p, [](uint32_t) { return true; });
+  if (p < P && p < Pmax)
+    span[p] = (uint8_t)join_span(plen, P, p, [&](uint32_t q) { return !pterm || (!pterm[q] && !pterm[q + 1]); });
 }
 
 // Work items: join unit u contributes ceil(n_u / JCH) items, n_u = S tuples

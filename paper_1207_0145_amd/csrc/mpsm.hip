@@ -36,6 +36,7 @@ struct Plan {
   uint64_t nR, nS;           // internal roles
   uint32_t L, Q, NBs, OSs;
   uint32_t levels, NB1, OS1, NB2, OS2;
+  uint32_t QR;                 // B-MPSM (no range partitioning): sorted R runs of L tuples
   uint32_t Gs, Gr, Pmax;
   uint32_t idx_per_run;
   uint32_t JCH, BT;
@@ -53,7 +54,7 @@ struct Plan {
   uint64_t bndS, bndR1, bndR2;             // per-bucket key bounds (lo array, then hi array)
   uint64_t bigS, midS, redoS, midR, redoR, redoR2, bigR, ctr;
   uint64_t bkey, Pc, pstart, plen, pkey;
-  uint64_t ridx, o, items, item_pre, item_cnt, res, span;
+  uint64_t ridx, o, items, item_pre, item_cnt, res, span, pterm;
   uint64_t cdf_chunks, cdf_sorted, modelR, modelS;  // learned CDF samples and models
   uint64_t cost_sample, cost_s_below, cost_best;   // cost-balanced splitters
   uint64_t total;
@@ -66,13 +67,14 @@ struct Seg {  // device pointers of one segment table (nseg + 1 entries each)
 bool config_valid(const mpsm_config* c) {
   if (c->struct_size != sizeof(mpsm_config)) return false;
   if (c->role < 0 || c->role > 2) return false;
-  if (c->splitter != MPSM_SPLIT_SAMPLED && c->splitter != MPSM_SPLIT_LEARNED && c->splitter != MPSM_SPLIT_COST)
+  if (c->splitter != MPSM_SPLIT_SAMPLED && c->splitter != MPSM_SPLIT_LEARNED && c->splitter != MPSM_SPLIT_COST &&
+      c->splitter != MPSM_SPLIT_NONE)
     return false;
   if (c->search < 0 || c->search > 3) return false;
   if (c->log2_run_len && (c->log2_run_len < 12 || c->log2_run_len > 24)) return false;
   if (c->bucket_target && (c->bucket_target < 256 || c->bucket_target > 4096)) return false;
   if (c->join_chunk && (c->join_chunk < 1024 || c->join_chunk > (uint32_t)JOIN_CHUNK_MAX)) return false;
-  if (c->oversample > 64 || c->reserved) return false;
+  if (c->oversample > 64 || c->waves > 64) return false;
   return true;
 }
 
@@ -115,7 +117,18 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->OSs = os_for(P->NBs);
   // R partitioning levels
   const uint64_t F = cdiv(P->nR ? P->nR : 1, BT);
-  if (F <= (uint64_t)MAX_NB) {
+  P->QR = 1;
+  if (P->splitter == MPSM_SPLIT_NONE) {
+    // B-MPSM: R sorted into runs of L tuples exactly as S is (one bucket
+    // pass per run, then the bucket sort); the buckets of a run are its
+    // partitions, and every R run meets every S run
+    P->levels = 1;
+    P->QR = P->nR ? (uint32_t)cdiv(P->nR, L) : 1;
+    P->NB1 = P->NBs;
+    P->OS1 = P->OSs;
+    P->NB2 = 1;
+    P->OS2 = 1;
+  } else if (F <= (uint64_t)MAX_NB) {
     P->levels = 1;
     P->NB1 = next_pow2(F);
     P->OS1 = os_for(P->NB1);
@@ -136,13 +149,13 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
     P->OS2 = SMP_CAP / P->NB2 < 16u ? SMP_CAP / P->NB2 : 16u;
   }
   P->Gs = P->Q * P->NBs;
-  P->Gr = P->NB1 * P->NB2;
-  P->Pmax = P->Gr;
+  P->Gr = P->QR * P->NB1 * P->NB2;
+  P->Pmax = P->Gr + (P->splitter == MPSM_SPLIT_NONE ? P->QR : 0u);   // B-MPSM: one terminator per R run
   P->idx_per_run = (uint32_t)cdiv(L, IDX_STRIDE);
   P->JCH = cfg->join_chunk ? cfg->join_chunk : 32768u;
   P->BT = BT;
   P->tilesS = (uint32_t)(P->nS / HIST_TILE + P->Q);
-  P->tilesR1 = (uint32_t)(P->nR / HIST_TILE + 1);
+  P->tilesR1 = (uint32_t)(P->nR / HIST_TILE + P->QR);
   P->tilesR2 = (uint32_t)(P->nR / HIST_TILE + P->NB1);
   P->cntS = (uint64_t)P->tilesS * P->NBs;
   P->cntR1 = (uint64_t)P->tilesR1 * P->NB1;
@@ -166,16 +179,16 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->bsum = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);
   P->bsumR = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);   // R's scans, which may run beside S's
   P->segS = take(6ull * (P->Q + 1) * 4);
-  P->segR1 = take(6ull * 2 * 4);
+  P->segR1 = take(6ull * (P->QR + 1) * 4);
   P->segR2 = take(6ull * (P->NB1 + 1) * 4);
   P->splS = take((uint64_t)P->Q * P->NBs * 8);
-  P->splR1 = take((uint64_t)P->NB1 * 8);
+  P->splR1 = take((uint64_t)P->QR * P->NB1 * 8);
   P->splR2 = take((uint64_t)P->NB1 * P->NB2 * 8);
   P->bstS = take(((uint64_t)P->Gs + 1) * 4);
-  P->bstR1 = take(((uint64_t)P->NB1 + 1) * 4);
+  P->bstR1 = take(((uint64_t)P->QR * P->NB1 + 1) * 4);
   P->bstR2 = take(((uint64_t)P->Gr + 1) * 4);
   P->bndS = take((uint64_t)P->Gs * 16);
-  P->bndR1 = take((uint64_t)P->NB1 * 16);
+  P->bndR1 = take((uint64_t)P->QR * P->NB1 * 16);
   P->bndR2 = take((uint64_t)P->Gr * 16);
   P->bigS = take((uint64_t)P->Gs * 4);
   P->midS = take((uint64_t)P->Gs * 4);
@@ -196,6 +209,7 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->item_pre = take(((uint64_t)P->Pmax + 2) * 4);
   P->item_cnt = take((P->item_cap + 1) * 4);
   P->span = take((uint64_t)P->Pmax + 2);
+  P->pterm = take((uint64_t)P->Pmax + 2);
   P->cdf_chunks = take(2ull * CDF_M * 8);
   P->cdf_sorted = take(2ull * CDF_M * 8);
   P->modelR = take(sizeof(CdfModel));
@@ -368,8 +382,8 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
     mk.mark_range(mk0 + 1, mk0 + 2);
   }
   k_bucket_table<<<(uint32_t)cdiv((uint64_t)L.Gmax + 1, 256), 256, 0, st>>>(
-      L.nseg, L.NBmax, sg.start, sg.tile0, sg.cnt0, sg.nb, sg.b0, L.cnt, n, L.spl, L.outer, L.outer_nspl, L.bstart,
-      L.blo, L.bhi);
+      L.nseg, L.NBmax, sg.start, sg.tile0, sg.cnt0, sg.nb, sg.b0, sg.len, L.cnt, L.spl, L.outer, L.outer_nspl,
+      L.bstart, L.blo, L.bhi);
   LAUNCH_CHECK();
   mk.mark(mk0 + 3);
   return MPSM_OK;
@@ -632,8 +646,9 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       mk.mark(MK_S_BIG);
 
       // ---- phase 2: range-partition R (one or two levels); phase 3: sort partitions
-      Level LR1 = make_level(ws, P.segR1, 1, P.NB1, 0, P.OS1, P.tilesR1, P.seed ^ TAG_R1, P.splR1, P.cR1, P.cntR1,
-                             P.bstR1, P.bndR1, P.NB1);
+      const bool bmpsm = P.splitter == MPSM_SPLIT_NONE;
+      Level LR1 = make_level(ws, P.segR1, P.QR, P.NB1, 0, P.OS1, P.tilesR1, P.seed ^ TAG_R1, P.splR1, P.cR1, P.cntR1,
+                             P.bstR1, P.bndR1, P.QR * P.NB1);
       if (learn_r) LR1.model = modelR;
       CostArgs cost_args;
       if (P.splitter == MPSM_SPLIT_COST) {
@@ -656,7 +671,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       if (r_side) HIP_TRY(hipStreamWaitEvent(rst, side->gate, 0));
       uint32_t* const rbsum = r_side ? reinterpret_cast<uint32_t*>(ws + P.bsumR) : bsum;
       Marker mkR{events, n_events, rst};
-      LR1.run_len = (uint32_t)P.nR;   // one segment: all of R
+      LR1.run_len = bmpsm ? P.L : (uint32_t)P.nR;   // B-MPSM: R runs; else one segment, all of R
       rc = bucket_pass(Rin, R1, (uint32_t)P.nR, LR1, rbsum, rst, mkR, MK_R1_SPL);
       if (rc != MPSM_OK) return rc;
       SortOut soR;
@@ -722,11 +737,16 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       uint32_t* pstart = reinterpret_cast<uint32_t*>(ws + P.pstart);
       uint32_t* plen = reinterpret_cast<uint32_t*>(ws + P.plen);
       uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + P.pkey);
-      k_partitions<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), Pc, pstart, plen, pkey,
-                                       stats ? res : nullptr);
+      uint8_t* const pterm = bmpsm ? reinterpret_cast<uint8_t*>(ws + P.pterm) : nullptr;
+      if (bmpsm)
+        k_partitions_runs<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), P.NB1, Pc, pstart, plen, pkey,
+                                              pterm, stats ? res : nullptr);
+      else
+        k_partitions<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), Pc, pstart, plen, pkey,
+                                         stats ? res : nullptr);
       LAUNCH_CHECK();
       uint8_t* span = reinterpret_cast<uint8_t*>(ws + P.span);
-      k_join_units<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, st>>>(Pc, plen, P.Pmax, span);
+      k_join_units<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, st>>>(Pc, plen, P.Pmax, span, pterm);
       LAUNCH_CHECK();
       mk.mark(MK_PART);
 
@@ -739,7 +759,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
                                                             learn_s ? MPSM_SEARCH_LEARNED
                                                                     : (P.search == MPSM_SEARCH_LEARNED ? MPSM_SEARCH_INDEX
                                                                                                        : P.search),
-                                                            modelS, stats ? res : nullptr, span);
+                                                            modelS, stats ? res : nullptr, span, pterm);
       LAUNCH_CHECK();
       mk.mark(MK_SEARCH);
       uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
@@ -937,14 +957,15 @@ mpsm_status mpsm_events_elapsed(void* start, void* stop, float* ms) {
 
 // ------------------------------------------------------------------ batches
 
+// Host layer over mpsm_join_batch: a copy of the descriptors (uploaded into
+// the workspace), the current tuning and, once used, a captured hipGraph.
 struct mpsm_batch {
   std::vector<mpsm_join_desc> d;
   mpsm_config cfg;
+  mpsm_batch_shape shape;                // the batch's own sums
   uint32_t L = 0, BT = 0, JCH = 0;       // current tuning
   uint64_t ws_max = 0;                   // workspace serving every candidate tuning
-  // tables of the current tuning, staged in pinned host memory
-  void* host = nullptr;
-  uint64_t host_bytes = 0;
+  void* host = nullptr;                  // pinned staging of the descriptors
   void* uploaded_to = nullptr;           // workspace that holds them
   hipGraphExec_t graph = nullptr;
   void* graph_ws = nullptr;
@@ -956,18 +977,22 @@ namespace {
 constexpr uint32_t kBatchL[] = {1u << 16, 1u << 18, 1u << 20};
 constexpr uint32_t kBatchBT[] = {2048u, 4096u};
 constexpr uint32_t kBatchJCH[] = {16384u, 65536u};
+constexpr uint32_t BATCH_N_MAX = 1u << 20;        // joins per batch
+constexpr uint32_t BATCH_SORT_GRID = 1u << 16;    // workgroups of the batch's bucket sorts (they loop)
 
+// Sizes of a batch launch, from the number of joins and bounds on their
+// sizes only (the descriptors are in device memory): every launch grid and
+// every table is sized for the largest batch of this shape class.
 struct BatchPlan {
-  uint32_t n, L, BT, JCH;
-  uint32_t NBs, OSs, OSr, Qtot, Gs, Gr, nact;
-  uint64_t nS, nR;
+  uint32_t n, L, BT, JCH, W;
+  uint64_t maxR, maxS, maxNS;
+  uint32_t NBs, OSs, OSr, Qmax, Gs, Gr, nbRmax;
   uint32_t tilesS, tilesR, Pmax;
   uint64_t cntS, cntR, ocap, item_cap;
   // workspace offsets
-  uint64_t T, U, Rp, Rs, cS, cR, bsum, bsumR, segS, segR, srcS, srcR, splS, splR, bstS, bstR, bndS, bndR;
-  uint64_t bigS, midS, redoS, midR, redoR, redoR2, bigR, ctr, bkey, Pc, pstart, plen, pkey, pjoin, ridx, o, items, item_pre;
-  uint64_t J, tstart, ototal, span;
-  uint64_t tab_off, tab_bytes;           // host-written tables: one contiguous range
+  uint64_t status, descs, T, U, Rp, Rs, cS, cR, bsum, bsumR, segS, segR, srcS, srcR, J, wave, splS, splR, bstS, bstR;
+  uint64_t bndS, bndR, bigS, midS, redoS, midR, redoR, redoR2, bigR, ctr, bkey, Pc, pstart, plen, pkey, pjoin, ridx;
+  uint64_t o, items, item_pre, tstart, ototal, span;
   uint64_t total;
 };
 
@@ -976,71 +1001,88 @@ bool batch_tuning_valid(uint32_t L, uint32_t BT, uint32_t JCH) {
          JCH <= (uint32_t)JOIN_CHUNK_MAX;
 }
 
-uint32_t batch_nb(uint64_t len, uint32_t BT) {   // k_seg_plan's bucket count of one segment
-  uint64_t nb = cdiv(len, BT);
-  if (nb < 1) nb = 1;
-  if (nb > MAX_NB) nb = MAX_NB;
-  return (uint32_t)nb;
+bool batch_cfg_supported(const mpsm_config* cfg) {
+  return cfg->splitter == MPSM_SPLIT_SAMPLED && cfg->search != MPSM_SEARCH_LEARNED && !cfg->want_max &&
+         cfg->role != MPSM_ROLE_SWAP;
 }
 
-bool make_batch_plan(const mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH, BatchPlan* P) {
+// Waves: as configured, else 4 for 32 joins or more, 2 for 8 or more;
+// never more than the joins, and one when there are too many joins to rank.
+uint32_t batch_waves(uint32_t n, const mpsm_config& cfg) {
+  uint32_t W = cfg.waves ? cfg.waves : (n >= 32 ? 4u : (n >= 8 ? 2u : 1u));
+  if (W > n) W = n;
+  if (n > BATCH_RANK_MAX || W < 1) W = 1;
+  return W;
+}
+
+// Default run length: the shortest of 2^16 .. 2^22 that keeps every join
+// within the run limit.
+uint32_t batch_default_L(uint64_t maxNS) {
+  uint32_t L = 1u << 16;
+  while (L < (1u << 22) && cdiv(maxNS, L) > (uint64_t)JOIN_QMAX) L <<= 1;
+  return L;
+}
+
+bool make_batch_plan(uint32_t n, const mpsm_batch_shape& sh, const mpsm_config& cfg, uint32_t L, uint32_t BT,
+                     uint32_t JCH, BatchPlan* P) {
   memset(P, 0, sizeof(*P));
-  P->n = (uint32_t)b->d.size();
-  P->L = L; P->BT = BT; P->JCH = JCH;
-  if (!batch_tuning_valid(L, BT, JCH)) return false;
+  if (n == 0 || n > BATCH_N_MAX || !batch_tuning_valid(L, BT, JCH)) return false;
+  P->n = n; P->L = L; P->BT = BT; P->JCH = JCH;
+  P->maxR = sh.max_sum_nR; P->maxS = sh.max_sum_nS;
+  P->maxNS = sh.max_nS && sh.max_nS < sh.max_sum_nS ? sh.max_nS : sh.max_sum_nS;
+  if (P->maxR >= (1ull << 32) || P->maxS >= (1ull << 32)) return false;
+  if (cdiv(P->maxNS, L) > (uint64_t)JOIN_QMAX) return false;
+  P->W = batch_waves(n, cfg);
   const uint32_t BTs = BT < S_BUCKET_MEAN ? BT : S_BUCKET_MEAN;
   P->NBs = (uint32_t)cdiv(L, BTs);
   if (P->NBs > (uint32_t)MAX_NB) P->NBs = MAX_NB;
-  const uint32_t OSreq = b->cfg.oversample ? b->cfg.oversample : 32u;
+  const uint32_t OSreq = cfg.oversample ? cfg.oversample : 32u;
   auto os_for = [&](uint32_t NB) { return NB > 1 ? (SMP_CAP / NB < OSreq ? SMP_CAP / NB : OSreq) : 1u; };
   P->OSs = os_for(P->NBs);
   P->OSr = os_for(MAX_NB);
-  uint64_t tilesS = 0, tilesR = 0, cntR = 0, ocap = 0;
-  for (const mpsm_join_desc& j : b->d) {
-    if (!j.nR || !j.nS) continue;
-    const uint64_t Q = cdiv(j.nS, L);
-    if (Q > (uint64_t)JOIN_QMAX) return false;
-    const uint32_t nb = batch_nb(j.nR, BT);
-    P->nact++;
-    P->nS += j.nS; P->nR += j.nR; P->Qtot += (uint32_t)Q; P->Gr += nb;
-    for (uint64_t q = 0; q < Q; q++) tilesS += cdiv(q + 1 < Q ? L : j.nS - q * L, HIST_TILE);
-    const uint64_t tr = cdiv(j.nR, HIST_TILE);
-    tilesR += tr;
-    cntR += tr * nb;
-    ocap += (uint64_t)(nb + 1) * Q;
-  }
-  if (P->nS >= (1ull << 32) || P->nR >= (1ull << 32)) return false;
-  P->Gs = P->Qtot * P->NBs;
-  P->tilesS = (uint32_t)tilesS; P->tilesR = (uint32_t)tilesR;
-  P->cntS = tilesS * P->NBs; P->cntR = cntR ? cntR : 1;
+  // S: every join adds at most one partial run, every run one partial tile
+  uint64_t Q = P->maxS / L + n;
+  if (Q > P->maxS) Q = P->maxS;
+  if (Q < 1) Q = 1;
+  P->Qmax = (uint32_t)Q;
+  P->Gs = P->Qmax * P->NBs;
+  P->tilesS = (uint32_t)(P->maxS / HIST_TILE + P->Qmax);
+  P->cntS = (uint64_t)P->tilesS * P->NBs;
+  // R: one segment per join, ceil(nR / BT) buckets (1 for an empty segment)
+  uint64_t Gr = P->maxR / BT + n;
+  if (Gr > (uint64_t)n * MAX_NB) Gr = (uint64_t)n * MAX_NB;
+  P->Gr = (uint32_t)Gr;
+  P->nbRmax = (uint32_t)(P->maxR / BT + 1 < (uint64_t)MAX_NB ? P->maxR / BT + 1 : MAX_NB);
+  P->tilesR = (uint32_t)(P->maxR / HIST_TILE + n);
+  P->cntR = (uint64_t)P->nbRmax * P->tilesR;
+  if (P->cntR < 1) P->cntR = 1;
   P->Pmax = P->Gr;
-  P->ocap = ocap;
-  P->item_cap = P->nS / JCH + P->Pmax + 2;
+  P->ocap = ((uint64_t)P->nbRmax + 1) * P->Qmax;
+  P->item_cap = P->maxS / JCH + P->Pmax + 2;
   const uint32_t ipr = (uint32_t)cdiv(L, IDX_STRIDE);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) { uint64_t o = off; off += (bytes + 255) & ~255ull; return o; };
   const uint64_t ts = sizeof(tup_t);
-  P->T = take(P->nS * ts);
-  P->U = take(P->nS * ts);
-  P->Rp = take(P->nR * ts);
-  P->Rs = take(P->nR * ts);
+  P->status = take(8);   // offset 0: the batch status word
+  P->descs = take((uint64_t)n * sizeof(mpsm_join_desc));
+  P->T = take(P->maxS * ts);
+  P->U = take(P->maxS * ts);
+  P->Rp = take(P->maxR * ts);
+  P->Rs = take(P->maxR * ts);
   P->cS = take(P->cntS * 4 + 4);
   P->cR = take(P->cntR * 4);
   uint64_t maxscan = P->cntS > P->cntR ? P->cntS : P->cntR;
   if (P->item_cap > maxscan) maxscan = P->item_cap;
   P->bsum = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);
   P->bsumR = take((cdiv(P->cntR, SCAN_BLOCK) + 1) * 4);   // R's scan, beside S's phase
-  // host-written tables, contiguous: S and R segment start/len (inside the
-  // 6-array segment tables), source pointers, join table
-  P->tab_off = off;
-  P->segS = take(6ull * (P->Qtot + 1) * 4);
-  P->segR = take(6ull * (P->nact + 1) * 4);
-  P->srcS = take((uint64_t)P->Qtot * 8);
-  P->srcR = take((uint64_t)P->nact * 8);
-  P->J = take((uint64_t)P->n * sizeof(BatchJoin));
-  P->tab_bytes = off - P->tab_off;
-  P->splS = take((uint64_t)P->Qtot * P->NBs * 8);
-  P->splR = take((uint64_t)P->nact * MAX_NB * 8);
+  P->segS = take(6ull * (P->Qmax + 1) * 4);
+  P->segR = take(6ull * (n + 1) * 4);
+  P->srcS = take((uint64_t)P->Qmax * 8);
+  P->srcR = take((uint64_t)n * 8);
+  P->J = take((uint64_t)n * sizeof(BatchJoin));
+  P->wave = take((uint64_t)n * 4);
+  P->splS = take((uint64_t)P->Qmax * P->NBs * 8);
+  P->splR = take((uint64_t)n * MAX_NB * 8);
   P->bstS = take(((uint64_t)P->Gs + 1) * 4);
   P->bstR = take(((uint64_t)P->Gr + 1) * 4);
   P->bndS = take((uint64_t)P->Gs * 16);
@@ -1059,7 +1101,7 @@ bool make_batch_plan(const mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH,
   P->plen = take((uint64_t)P->Pmax * 4);
   P->pkey = take((uint64_t)P->Pmax * 8);
   P->pjoin = take((uint64_t)P->Pmax * 4);
-  P->ridx = take((uint64_t)P->Qtot * ipr * 8);
+  P->ridx = take((uint64_t)P->Qmax * ipr * 8);
   P->o = take(P->ocap * 4);
   P->items = take(((uint64_t)P->Pmax + 2) * 4);
   P->item_pre = take(((uint64_t)P->Pmax + 2) * 4);
@@ -1070,57 +1112,18 @@ bool make_batch_plan(const mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH,
   return true;
 }
 
-// Host image of the tables of plan P (written at workspace offset P.tab_off).
-void batch_tables(const mpsm_batch* b, const BatchPlan& P, char* img) {
-  memset(img, 0, P.tab_bytes);
-  uint32_t* sS = reinterpret_cast<uint32_t*>(img + (P.segS - P.tab_off));
-  uint32_t* sR = reinterpret_cast<uint32_t*>(img + (P.segR - P.tab_off));
-  const tup_t** pS = reinterpret_cast<const tup_t**>(img + (P.srcS - P.tab_off));
-  const tup_t** pR = reinterpret_cast<const tup_t**>(img + (P.srcR - P.tab_off));
-  BatchJoin* J = reinterpret_cast<BatchJoin*>(img + (P.J - P.tab_off));
-  uint32_t q = 0, a = 0, posS = 0, posR = 0, g0 = 0;
-  for (uint32_t i = 0; i < P.n; i++) {
-    const mpsm_join_desc& j = b->d[i];
-    BatchJoin& x = J[i];
-    memset(&x, 0, sizeof(x));
-    x.out_count = j.d_out_count;
-    x.out_checksum = j.d_out_checksum;
-    x.out_times = j.d_out_times;
-    x.r0 = q; x.g0 = g0;
-    if (!j.nR || !j.nS) continue;
-    const uint32_t Q = (uint32_t)cdiv(j.nS, P.L);
-    for (uint32_t r = 0; r < Q; r++) {
-      const uint64_t len = r + 1 < Q ? P.L : j.nS - (uint64_t)r * P.L;
-      sS[q + r] = posS + r * P.L;                         // start
-      sS[(P.Qtot + 1) + q + r] = (uint32_t)len;          // len
-      pS[q + r] = reinterpret_cast<const tup_t*>(j.d_S) + (uint64_t)r * P.L;
-    }
-    sR[a] = posR;
-    sR[(P.nact + 1) + a] = (uint32_t)j.nR;
-    pR[a] = reinterpret_cast<const tup_t*>(j.d_R);
-    x.Q = Q;
-    x.G = batch_nb(j.nR, P.BT);
-    q += Q; a++; g0 += x.G;
-    posS += (uint32_t)j.nS; posR += (uint32_t)j.nR;
-  }
+// The run-length, bucket and work-item tuning of a config (0: defaults).
+void batch_tuning_of(const mpsm_config& cfg, uint64_t maxNS, uint32_t* L, uint32_t* BT, uint32_t* JCH) {
+  *L = cfg.log2_run_len ? (1u << cfg.log2_run_len) : batch_default_L(maxNS);
+  *BT = cfg.bucket_target ? cfg.bucket_target : 4096u;
+  *JCH = cfg.join_chunk ? cfg.join_chunk : 65536u;
 }
 
-void batch_drop_graph(mpsm_batch* b) {
-  if (b->graph) (void)hipGraphExecDestroy(b->graph);
-  b->graph = nullptr;
-  b->graph_ws = nullptr;
-}
-
-mpsm_status batch_set(mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH) {
-  BatchPlan P;
-  if (!make_batch_plan(b, L, BT, JCH, &P)) return MPSM_EUNSUPPORTED;
-  b->L = L; b->BT = BT; b->JCH = JCH;
-  b->uploaded_to = nullptr;
-  batch_drop_graph(b);
-  return MPSM_OK;
-}
-
-mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hipStream_t st) {
+// The launch sequence of a batch whose descriptors are at d_descs (device):
+// the descriptor check and wave assignment, then per wave its tables and
+// every phase of the method for the wave's joins.
+mpsm_status batch_enqueue(const mpsm_join_desc* d_descs, const BatchPlan& P, uint64_t seed, int search, char* ws,
+                          hipStream_t st) {
   tup_t* T = reinterpret_cast<tup_t*>(ws + P.T);
   tup_t* U = reinterpret_cast<tup_t*>(ws + P.U);
   tup_t* Rp = reinterpret_cast<tup_t*>(ws + P.Rp);
@@ -1128,24 +1131,33 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
   uint32_t* bsum = reinterpret_cast<uint32_t*>(ws + P.bsum);
   unsigned long long* ctr = reinterpret_cast<unsigned long long*>(ws + P.ctr);
   BatchJoin* J = reinterpret_cast<BatchJoin*>(ws + P.J);
+  uint32_t* wave = reinterpret_cast<uint32_t*>(ws + P.wave);
   unsigned long long* tstart = reinterpret_cast<unsigned long long*>(ws + P.tstart);
   unsigned long long* ototal = reinterpret_cast<unsigned long long*>(ws + P.ototal);
-  const uint64_t seed = b->cfg.seed;
+  // R's phase runs on the side stream beside S's run sort, from the point
+  // where S's tuples are scattered (as for a single join); under capture
+  // the fork and join make them two branches of the graph
+  SideStream* side = nullptr;
+  mpsm_status rc = side_stream(&side);
+  if (rc != MPSM_OK) return rc;
   Marker mk{nullptr, 0, st};
-  k_batch_init<<<(uint32_t)cdiv(P.n, 256) + 1, 256, 0, st>>>(J, P.n, tstart, reinterpret_cast<uint32_t*>(ctr), 16);
+  k_batch_check<<<1, BPLAN_NT, 0, st>>>(d_descs, P.n, P.W, P.maxR, P.maxS, P.maxNS, wave,
+                                        reinterpret_cast<uint32_t*>(ws + P.status), tstart);
   LAUNCH_CHECK();
-  if (P.nact) {
-    // R's phase runs on the side stream beside S's run sort, from the
-    // point where S's tuples are scattered (as for a single join); under
-    // capture the fork and join make them two branches of the graph
-    SideStream* side = nullptr;
-    mpsm_status rc = side_stream(&side);
-    if (rc != MPSM_OK) return rc;
-    // phase 1: S runs of every join
-    Level LS = make_level(ws, P.segS, P.Qtot, P.NBs, 0, P.OSs, P.tilesS, seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
+  const Seg sgS = seg_at(ws, P.segS, P.Qmax);
+  const Seg sgR = seg_at(ws, P.segR, P.n);
+  const tup_t** srcS = reinterpret_cast<const tup_t**>(ws + P.srcS);
+  const tup_t** srcR = reinterpret_cast<const tup_t**>(ws + P.srcR);
+  const uint32_t sort_grid_s = P.Gs < BATCH_SORT_GRID ? P.Gs : BATCH_SORT_GRID;
+  const uint32_t sort_grid_r = P.Gr < BATCH_SORT_GRID ? P.Gr : BATCH_SORT_GRID;
+  for (uint32_t w = 0; w < P.W; w++) {
+    k_batch_plan<<<1, BPLAN_NT, 0, st>>>(d_descs, P.n, wave, w, P.L, P.BT, P.Qmax, J, sgS.start, sgS.len, srcS,
+                                         sgR.start, sgR.len, srcR, reinterpret_cast<uint32_t*>(ctr), 16);
+    LAUNCH_CHECK();
+    // phase 1: S runs of the wave's joins
+    Level LS = make_level(ws, P.segS, P.Qmax, P.NBs, 0, P.OSs, P.tilesS, seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
                           P.bndS, P.Gs);
-    rc = bucket_pass(nullptr, T, (uint32_t)P.nS, LS, bsum, st, mk, 0,
-                     reinterpret_cast<const tup_t* const*>(ws + P.srcS));
+    rc = bucket_pass(nullptr, T, 0, LS, bsum, st, mk, 0, srcS);
     if (rc != MPSM_OK) return rc;
     HIP_TRY(hipEventRecord(side->fork, st));
     HIP_TRY(hipStreamWaitEvent(side->st, side->fork, 0));
@@ -1160,24 +1172,22 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
     uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
     uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
-    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
-                                                                 nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<sort_grid_s, BS_NT, 0, st>>>(
+        T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(), nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
     LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
-                                                                      midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
-                                                                      soS);
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(
+        T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(), midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3, soS);
     LAUNCH_CHECK();
     k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, redoS, ctr + 3, bigS, ctr + 0, soS);
     LAUNCH_CHECK();
     k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, bigS, ctr + 0, soS);
     LAUNCH_CHECK();
     // phases 2 and 3: one R segment per join, bucket counts from its size
-    Level LR = make_level(ws, P.segR, P.nact, MAX_NB, P.BT, P.OSr, P.tilesR, seed ^ TAG_R1, P.splR, P.cR, P.cntR,
+    Level LR = make_level(ws, P.segR, P.n, MAX_NB, P.BT, P.OSr, P.tilesR, seed ^ TAG_R1, P.splR, P.cR, P.cntR,
                           P.bstR, P.bndR, P.Gr);
     const hipStream_t rst = side->st;
     Marker mkR{nullptr, 0, rst};
-    rc = bucket_pass(nullptr, Rp, (uint32_t)P.nR, LR, reinterpret_cast<uint32_t*>(ws + P.bsumR), rst, mkR, 0,
-                     reinterpret_cast<const tup_t* const*>(ws + P.srcR));
+    rc = bucket_pass(nullptr, Rp, 0, LR, reinterpret_cast<uint32_t*>(ws + P.bsumR), rst, mkR, 0, srcR);
     if (rc != MPSM_OK) return rc;
     SortOut soR;
     soR.run_idx = nullptr;
@@ -1191,16 +1201,14 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     uint32_t* redoR = reinterpret_cast<uint32_t*>(ws + P.redoR);
     uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
     uint32_t* bigR = reinterpret_cast<uint32_t*>(ws + P.bigR);
-    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gr, BS_NT, 0, rst>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi,
-                                                                 LR.Gcount(), nullptr, nullptr, midR, ctr + 6, redoR,
-                                                                 ctr + 4, soR);
+    k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<sort_grid_r, BS_NT, 0, rst>>>(
+        Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(), nullptr, nullptr, midR, ctr + 6, redoR, ctr + 4, soR);
     LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi,
-                                                                 LR.Gcount(), midR, ctr + 6, bigR, ctr + 1, redoR,
-                                                                 ctr + 4, soR);
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(
+        Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(), midR, ctr + 6, bigR, ctr + 1, redoR, ctr + 4, soR);
     LAUNCH_CHECK();
-    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(),
-                                                                 redoR, ctr + 4, bigR, ctr + 1, redoR2, ctr + 5, soR);
+    k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(
+        Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(), redoR, ctr + 4, bigR, ctr + 1, redoR2, ctr + 5, soR);
     LAUNCH_CHECK();
     k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rp, Rs, LR.bstart, redoR2, ctr + 5, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
@@ -1223,15 +1231,12 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     LAUNCH_CHECK();
     // phase 4
     uint32_t* o = reinterpret_cast<uint32_t*>(ws + P.o);
-    const int mode = b->cfg.search == MPSM_SEARCH_BINARY ? SEARCH_BINARY
-                   : b->cfg.search == MPSM_SEARCH_INTERP ? SEARCH_INTERP : SEARCH_INDEX;
-    if (P.ocap) {
-      k_search_batch<<<(uint32_t)cdiv(P.ocap, 256), 256, 0, st>>>(U, LS.seg.start, LS.seg.len,
-                                                                 reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
-                                                                 soS.idx_per_run, J, P.n, pkey, o, ototal, mode,
-                                                                 span);
-      LAUNCH_CHECK();
-    }
+    const int mode = search == MPSM_SEARCH_BINARY ? SEARCH_BINARY
+                   : search == MPSM_SEARCH_INTERP ? SEARCH_INTERP : SEARCH_INDEX;
+    k_search_batch<<<(uint32_t)cdiv(P.ocap, 256), 256, 0, st>>>(U, LS.seg.start, LS.seg.len,
+                                                               reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
+                                                               soS.idx_per_run, J, P.n, pkey, o, ototal, mode, span);
+    LAUNCH_CHECK();
     uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
     uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
     k_join_items_batch<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, pjoin, J, o, LS.seg.len, P.Pmax, P.JCH,
@@ -1259,48 +1264,68 @@ mpsm_status batch_enqueue(const mpsm_batch* b, const BatchPlan& P, char* ws, hip
     A.span = span;
     k_join<0, VAL_HR, true><<<g_num_cus, JOIN_NT, 0, st>>>(A);
     LAUNCH_CHECK();
+    k_finalize_batch<<<(uint32_t)cdiv(P.n, 256), 256, 0, st>>>(J, P.n, tstart);
+    LAUNCH_CHECK();
   }
-  k_finalize_batch<<<(uint32_t)cdiv(P.n, 256), 256, 0, st>>>(J, P.n, tstart);
-  LAUNCH_CHECK();
+  return MPSM_OK;
+}
+
+void ensure_num_cus() {
+  if (g_num_cus) return;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) ==
+                                              hipSuccess)
+    g_num_cus = ncu > 0 ? ncu : 256;
+  else
+    g_num_cus = 256;
+}
+
+bool batch_shape_valid(const mpsm_batch_shape* sh) {
+  return sh && sh->max_sum_nR < (1ull << 32) && sh->max_sum_nS < (1ull << 32);
+}
+
+void batch_drop_graph(mpsm_batch* b) {
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  b->graph_ws = nullptr;
+}
+
+mpsm_status batch_set(mpsm_batch* b, uint32_t L, uint32_t BT, uint32_t JCH) {
+  BatchPlan P;
+  if (!make_batch_plan((uint32_t)b->d.size(), b->shape, b->cfg, L, BT, JCH, &P)) return MPSM_EUNSUPPORTED;
+  b->L = L; b->BT = BT; b->JCH = JCH;
+  batch_drop_graph(b);
   return MPSM_OK;
 }
 
 mpsm_status batch_run(mpsm_batch* b, void* d_ws, uint64_t bytes, void* stream, int use_graph) {
   if (!b || !d_ws || ((uintptr_t)d_ws & 255)) return MPSM_EINVAL;
   BatchPlan P;
-  if (!make_batch_plan(b, b->L, b->BT, b->JCH, &P)) return MPSM_EUNSUPPORTED;
+  if (!make_batch_plan((uint32_t)b->d.size(), b->shape, b->cfg, b->L, b->BT, b->JCH, &P)) return MPSM_EUNSUPPORTED;
   if (bytes < P.total) return MPSM_ENOMEM;
-  if (!g_num_cus) {
-    int dev = 0, ncu = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    g_num_cus = ncu > 0 ? ncu : 256;
-  }
+  ensure_num_cus();
   hipStream_t st = (hipStream_t)stream;
   char* ws = static_cast<char*>(d_ws);
+  // the descriptors sit at the same workspace offset under every tuning
+  const uint64_t dbytes = b->d.size() * sizeof(mpsm_join_desc);
   if (b->uploaded_to != d_ws) {
-    if (P.tab_bytes > b->host_bytes) {   // pinned staging of the tables, kept with the batch
-      if (b->host) (void)hipHostFree(b->host);
-      b->host = nullptr;
-      b->host_bytes = 0;
-      HIP_TRY(hipHostMalloc(&b->host, P.tab_bytes, hipHostMallocDefault));
-      b->host_bytes = P.tab_bytes;
-    }
-    batch_tables(b, P, static_cast<char*>(b->host));
-    HIP_TRY(hipMemcpyAsync(ws + P.tab_off, b->host, P.tab_bytes, hipMemcpyHostToDevice, st));
+    if (!b->host) HIP_TRY(hipHostMalloc(&b->host, dbytes, hipHostMallocDefault));
+    memcpy(b->host, b->d.data(), dbytes);
+    HIP_TRY(hipMemcpyAsync(ws + P.descs, b->host, dbytes, hipMemcpyHostToDevice, st));
     b->uploaded_to = d_ws;
   }
-  if (!use_graph) return batch_enqueue(b, P, ws, st);
+  const mpsm_join_desc* d_descs = reinterpret_cast<const mpsm_join_desc*>(ws + P.descs);
+  if (!use_graph) return batch_enqueue(d_descs, P, b->cfg.seed, b->cfg.search, ws, st);
   if (!b->graph || b->graph_ws != d_ws) {
     // captured on a stream of the batch's own (the caller's may be the
     // legacy default stream, which cannot be captured), launched on the
-    // caller's; the tables reach the workspace first
+    // caller's; the descriptors reach the workspace first
     batch_drop_graph(b);
     if (!b->capture) HIP_TRY(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
     HIP_TRY(hipStreamSynchronize(st));
     hipGraph_t g = nullptr;
     HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-    const mpsm_status rc = batch_enqueue(b, P, ws, b->capture);
+    const mpsm_status rc = batch_enqueue(d_descs, P, b->cfg.seed, b->cfg.search, ws, b->capture);
     const hipError_t ec = hipStreamEndCapture(b->capture, &g);
     if (rc != MPSM_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (ec != hipSuccess || !g) return MPSM_EHIP;
@@ -1325,8 +1350,8 @@ std::string batch_signature(const mpsm_batch* b) {
   }
   auto lg = [](uint64_t x) { int k = 0; while (x > 1) { x >>= 1; k++; } return k; };
   char buf[160];
-  snprintf(buf, sizeof(buf), "gfx950:n%u:R%d:S%d:maxR%d:maxS%d:search%d", (unsigned)b->d.size(), lg(sR), lg(sS),
-           lg(mR), lg(mS), (int)b->cfg.search);
+  snprintf(buf, sizeof(buf), "gfx950:n%u:R%d:S%d:maxR%d:maxS%d:search%d:w%u", (unsigned)b->d.size(), lg(sR),
+           lg(sS), lg(mR), lg(mS), (int)b->cfg.search, batch_waves((uint32_t)b->d.size(), b->cfg));
   return buf;
 }
 
@@ -1355,16 +1380,43 @@ bool cache_lookup(const char* path, const std::string& sig, uint32_t* L, uint32_
 
 extern "C" {
 
+uint64_t mpsm_join_batch_workspace_bytes(uint32_t n, const mpsm_batch_shape* shape, const mpsm_config* cfg) {
+  mpsm_config def;
+  if (!cfg) { mpsm_config_default(&def); cfg = &def; }
+  if (!config_valid(cfg) || !batch_cfg_supported(cfg) || !batch_shape_valid(shape)) return 0;
+  uint32_t L, BT, JCH;
+  batch_tuning_of(*cfg, shape->max_nS ? shape->max_nS : shape->max_sum_nS, &L, &BT, &JCH);
+  BatchPlan P;
+  if (!make_batch_plan(n, *shape, *cfg, L, BT, JCH, &P)) return 0;
+  return P.total;
+}
+
+mpsm_status mpsm_join_batch(const mpsm_join_desc* d_descs, uint32_t n, const mpsm_batch_shape* shape,
+                            const mpsm_config* cfg, void* d_workspace, uint64_t workspace_bytes, void* stream) {
+  mpsm_config def;
+  if (!cfg) { mpsm_config_default(&def); cfg = &def; }
+  if (!config_valid(cfg) || !batch_shape_valid(shape)) return MPSM_EINVAL;
+  if (!batch_cfg_supported(cfg)) return MPSM_EUNSUPPORTED;
+  if (!d_descs || ((uintptr_t)d_descs & 7) || !d_workspace || ((uintptr_t)d_workspace & 255)) return MPSM_EINVAL;
+  uint32_t L, BT, JCH;
+  batch_tuning_of(*cfg, shape->max_nS ? shape->max_nS : shape->max_sum_nS, &L, &BT, &JCH);
+  BatchPlan P;
+  if (!make_batch_plan(n, *shape, *cfg, L, BT, JCH, &P)) return MPSM_EINVAL;
+  if (workspace_bytes < P.total) return MPSM_ENOMEM;
+  ensure_num_cus();
+  return batch_enqueue(d_descs, P, cfg->seed, cfg->search, static_cast<char*>(d_workspace), (hipStream_t)stream);
+}
+
 mpsm_status mpsm_batch_create(const mpsm_join_desc* descs, uint32_t n, const mpsm_config* cfg, mpsm_batch** out) {
   if (!out) return MPSM_EINVAL;
   *out = nullptr;
-  if (!descs || n == 0) return MPSM_EINVAL;
+  if (!descs || n == 0 || n > BATCH_N_MAX) return MPSM_EINVAL;
   mpsm_config def;
   if (!cfg) { mpsm_config_default(&def); cfg = &def; }
   if (!config_valid(cfg)) return MPSM_EINVAL;
-  if (cfg->splitter != MPSM_SPLIT_SAMPLED || cfg->search == MPSM_SEARCH_LEARNED || cfg->want_max ||
-      cfg->role == MPSM_ROLE_SWAP)
-    return MPSM_EUNSUPPORTED;
+  if (!batch_cfg_supported(cfg)) return MPSM_EUNSUPPORTED;
+  mpsm_batch_shape sh;
+  memset(&sh, 0, sizeof(sh));
   for (uint32_t i = 0; i < n; i++) {
     const mpsm_join_desc& j = descs[i];
     if ((j.nR && !j.d_R) || (j.nS && !j.d_S) || !j.d_out_count || !j.d_out_checksum) return MPSM_EINVAL;
@@ -1372,26 +1424,30 @@ mpsm_status mpsm_batch_create(const mpsm_join_desc* descs, uint32_t n, const mps
         ((uintptr_t)j.d_out_checksum & 7) || ((uintptr_t)j.d_out_times & 7))
       return MPSM_EINVAL;
     if (j.nR >= (1ull << 32) || j.nS >= (1ull << 32)) return MPSM_EINVAL;
+    if (j.nR && j.nS) {
+      sh.max_sum_nR += j.nR;
+      sh.max_sum_nS += j.nS;
+      if (j.nS > sh.max_nS) sh.max_nS = j.nS;
+    }
   }
+  if (!batch_shape_valid(&sh)) return MPSM_EINVAL;
   mpsm_batch* b = new mpsm_batch();
   b->d.assign(descs, descs + n);
   b->cfg = *cfg;
+  b->shape = sh;
   // initial tuning: the config's values, else a run length that keeps every
   // join within the run limit, 4096-tuple buckets and 64 K-tuple work items
-  uint64_t maxS = 0;
-  for (const mpsm_join_desc& j : b->d) maxS = j.nS > maxS ? j.nS : maxS;
-  uint32_t L = cfg->log2_run_len ? (1u << cfg->log2_run_len) : (1u << 18);
-  while (!cfg->log2_run_len && L < (1u << 22) && cdiv(maxS, L) > (uint64_t)JOIN_QMAX) L <<= 1;
-  const uint32_t BT = cfg->bucket_target ? cfg->bucket_target : 4096u;
-  const uint32_t JCH = cfg->join_chunk ? cfg->join_chunk : 65536u;
+  uint32_t L, BT, JCH;
+  batch_tuning_of(*cfg, sh.max_nS, &L, &BT, &JCH);
+  if (!cfg->log2_run_len && L < (1u << 18)) L = 1u << 18;
   // workspace for every candidate tuning (and the initial one)
   BatchPlan P;
   uint64_t ws = 0;
   for (uint32_t l : kBatchL)
     for (uint32_t bt : kBatchBT)
       for (uint32_t jc : kBatchJCH)
-        if (make_batch_plan(b, l, bt, jc, &P) && P.total > ws) ws = P.total;
-  if (!make_batch_plan(b, L, BT, JCH, &P)) { delete b; return MPSM_EUNSUPPORTED; }
+        if (make_batch_plan(n, sh, b->cfg, l, bt, jc, &P) && P.total > ws) ws = P.total;
+  if (!make_batch_plan(n, sh, b->cfg, L, BT, JCH, &P)) { delete b; return MPSM_EUNSUPPORTED; }
   b->ws_max = P.total > ws ? P.total : ws;
   const mpsm_status rc = batch_set(b, L, BT, JCH);
   if (rc != MPSM_OK) { mpsm_batch_destroy(b); return rc; }
@@ -1424,19 +1480,18 @@ mpsm_status mpsm_batch_get_tuning(const mpsm_batch* b, mpsm_batch_tuning* t) {
 
 mpsm_status mpsm_batch_set_tuning(mpsm_batch* b, const mpsm_batch_tuning* t) {
   if (!b || !t || t->log2_run_len > 31) return MPSM_EINVAL;
-  BatchPlan P;
-  if (!make_batch_plan(b, 1u << t->log2_run_len, t->bucket_target, t->join_chunk, &P)) return MPSM_EUNSUPPORTED;
   return batch_set(b, 1u << t->log2_run_len, t->bucket_target, t->join_chunk);
 }
 
 mpsm_status mpsm_batch_autotune(mpsm_batch* b, void* d_workspace, uint64_t workspace_bytes, void* stream,
                                 const char* cache_path, mpsm_batch_tuning* chosen) {
   if (!b) return MPSM_EINVAL;
+  const uint32_t n = (uint32_t)b->d.size();
   const std::string sig = batch_signature(b);
   uint32_t L = 0, BT = 0, JCH = 0;
   if (cache_lookup(cache_path, sig, &L, &BT, &JCH)) {
     BatchPlan P;
-    if (make_batch_plan(b, L, BT, JCH, &P) && (!d_workspace || P.total <= workspace_bytes)) {
+    if (make_batch_plan(n, b->shape, b->cfg, L, BT, JCH, &P) && (!d_workspace || P.total <= workspace_bytes)) {
       const mpsm_status rc = batch_set(b, L, BT, JCH);
       if (rc != MPSM_OK) return rc;
       if (chosen) { mpsm_batch_get_tuning(b, chosen); chosen->from_cache = 1; }
@@ -1455,7 +1510,7 @@ mpsm_status mpsm_batch_autotune(mpsm_batch* b, void* d_workspace, uint64_t works
     for (uint32_t bt : kBatchBT)
       for (uint32_t jc : kBatchJCH) {
         BatchPlan P;
-        if (!make_batch_plan(b, l, bt, jc, &P) || P.total > workspace_bytes) continue;
+        if (!make_batch_plan(n, b->shape, b->cfg, l, bt, jc, &P) || P.total > workspace_bytes) continue;
         if ((rc = batch_set(b, l, bt, jc)) != MPSM_OK) break;
         if ((rc = batch_run(b, d_workspace, workspace_bytes, stream, 0)) != MPSM_OK) break;   // warm-up
         float t[3];

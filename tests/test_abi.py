@@ -59,7 +59,7 @@ def test_unsupported_sizes():
     assert mpsm.workspace_bytes(10, 1 << 32) == 0
     assert mpsm.workspace_bytes(10, 10, mpsm.config(search=7)) == 0
     assert mpsm.workspace_bytes(10, 10, mpsm.config(log2_run_len=30)) == 0
-    assert mpsm.workspace_bytes(10, 10, mpsm.config(reserved=1)) == 0
+    assert mpsm.workspace_bytes(10, 10, mpsm.config(waves=65)) == 0
     assert mpsm.workspace_bytes(10, 10, mpsm.config(join_chunk=1 << 20)) == 0
     assert mpsm.workspace_bytes(10, 10, mpsm.config(join_chunk=261888)) > 0
     bad = mpsm.config()
@@ -151,7 +151,38 @@ def test_batch_rejects_bad_input():
     assert _create([(10, 10)], mpsm.config(splitter=mpsm.SPLIT_LEARNED))[0] == 5
     assert _create([(10, 10)], mpsm.config(search=mpsm.SEARCH_LEARNED))[0] == 5
     assert _create([(10, 10)], mpsm.config(want_max=1))[0] == 5
-    assert _create([(1 << 31, 10), (1 << 31, 10)])[0] == 5             # sum of nR beyond 2^32
+    assert _create([(1 << 31, 10), (1 << 31, 10)])[0] == 1             # sum of nR beyond 2^32
+
+
+def test_join_batch_host_checks():
+    """mpsm_join_batch: every host-side check returns before anything is
+    enqueued (no GPU needed: the fake pointers are never used)."""
+    L = mpsm.lib()
+    sh = mpsm.batch_shape(1 << 20, 1 << 22, 1 << 20)
+    need = mpsm.join_batch_workspace_bytes(256, sh)
+    assert need > 32 * ((1 << 20) + (1 << 22))
+    # bounds grow the workspace; more joins need larger tables
+    assert mpsm.join_batch_workspace_bytes(256, mpsm.batch_shape(1 << 21, 1 << 22, 1 << 20)) > need
+    assert mpsm.join_batch_workspace_bytes(512, sh) > need
+    assert mpsm.join_batch_workspace_bytes(0, sh) == 0
+    assert mpsm.join_batch_workspace_bytes(256, mpsm.batch_shape(1 << 32, 10)) == 0
+    assert mpsm.join_batch_workspace_bytes(256, sh, mpsm.config(splitter=mpsm.SPLIT_LEARNED)) == 0
+    # one join of 2^28 S tuples would need 4096 runs of 2^16 (at most 2048)
+    assert mpsm.join_batch_workspace_bytes(4, mpsm.batch_shape(1 << 20, 1 << 28, 1 << 28),
+                                           mpsm.config(log2_run_len=16)) == 0
+    assert mpsm.join_batch_workspace_bytes(4, mpsm.batch_shape(1 << 20, 1 << 28, 1 << 28)) > 0
+    d, ws = ctypes.c_void_p(1 << 24), ctypes.c_void_p(1 << 30)
+    call = lambda descs, n, shape, cfg, w, nb: L.mpsm_join_batch(descs, n, shape, cfg, w, nb, None)
+    assert call(None, 256, ctypes.byref(sh), None, ws, need) == 1                      # no descriptors
+    assert call(ctypes.c_void_p((1 << 24) + 4), 256, ctypes.byref(sh), None, ws, need) == 1   # misaligned
+    assert call(d, 256, None, None, ws, need) == 1                                     # no shape
+    assert call(d, 256, ctypes.byref(sh), None, ctypes.c_void_p((1 << 30) + 64), need) == 1   # workspace alignment
+    assert call(d, 256, ctypes.byref(sh), None, ws, need - 1) == 3                     # workspace too small
+    assert call(d, 0, ctypes.byref(sh), None, ws, need) == 1                           # no joins
+    cfg = mpsm.config(want_max=1)
+    assert call(d, 256, ctypes.byref(sh), ctypes.byref(cfg), ws, need) == 5
+    cfg = mpsm.config(waves=65)
+    assert call(d, 256, ctypes.byref(sh), ctypes.byref(cfg), ws, need) == 1
 
 
 def test_batch_autotune_cache_hit_and_malformed_entries(tmp_path):
@@ -167,7 +198,7 @@ def test_batch_autotune_cache_hit_and_malformed_entries(tmp_path):
         # no entry and no workspace: nothing to measure with
         assert L.mpsm_batch_autotune(h, None, 0, None, str(cache).encode(), ctypes.byref(t)) == 1
         # learn the signature from a measured entry format, then plant entries
-        sig = "gfx950:n2:R16:S18:maxR16:maxS18:search3"
+        sig = "gfx950:n2:R16:S18:maxR16:maxS18:search3:w1"
         cache.write_text("garbage line\n"
                          f"{sig} 40 4096 65536 1.0\n"          # log2 run length out of range
                          f"{sig} 18 999 65536 1.0\n"           # bucket target out of range

@@ -132,3 +132,97 @@ def test_batch_full_size_config():
         fk = oracle.fk_closed_form(w.R, w.S, w.partner)
         assert got[i] == (fk.count, fk.checksum), w.name
     b.close()
+
+
+# ------------------------------------------- device descriptors (mpsm_join_batch)
+
+def _device_batch(cases_list, waves=0):
+    """Descriptor array, outputs and workspace sized for every batch in
+    cases_list (same number of joins each)."""
+    n = len(cases_list[0])
+    sums = [(sum(len(R) for R, S in c if len(R) and len(S)), sum(len(S) for R, S in c if len(R) and len(S)),
+             max([len(S) for R, S in c if len(R) and len(S)] or [0])) for c in cases_list]
+    shape = mpsm.batch_shape(max(s[0] for s in sums), max(s[1] for s in sums), max(s[2] for s in sums))
+    cfg = mpsm.config(waves=waves)
+    ws = torch.empty(mpsm.join_batch_workspace_bytes(n, shape, cfg), dtype=torch.uint8, device="cuda")
+    descs = torch.zeros((n, 7), dtype=torch.int64, device="cuda")
+    out = torch.zeros((n, 2), dtype=torch.int64, device="cuda")
+    times = torch.zeros((n, 3), dtype=torch.int64, device="cuda")
+    return shape, cfg, ws, descs, out, times
+
+
+def _results(out):
+    return [(c & U64, s & U64) for c, s in out.cpu().tolist()]
+
+
+def test_join_batch_device_descriptors_graph_replayed_over_new_batches():
+    """One call over a device descriptor array; the call captured once into
+    a graph and replayed for other batches written into the same array
+    (same count, within the shape's bounds), with eager work and
+    synchronisation between replays; every replay against the oracle."""
+    n = 20
+    rng = np.random.default_rng(11)
+    batches = []
+    for k, (lo, hi) in enumerate([(8, 16), (10, 17), (6, 15)]):
+        c = _batch_cases(n - 7, 0x1207014500000401 + k, lo, hi)
+        order = rng.permutation(len(c))        # empty and edge joins at varying places
+        batches.append([c[i] for i in order])
+    shape, cfg, ws, descs, out, times = _device_batch(batches)
+    dev = [[(_dev(R), _dev(S)) for R, S in c] for c in batches]
+    # eager, first batch (also creates the library's second stream)
+    mpsm.write_descs(descs, dev[0], out, times)
+    _say(f"mpsm_join_batch eager: n={n} shape=({shape.max_sum_nR}, {shape.max_sum_nS}, {shape.max_nS})")
+    mpsm.join_batch(descs, n, shape, ws, cfg)
+    torch.cuda.synchronize()
+    assert int(ws[:4].view(torch.int32).item()) == 0
+    _check_results(batches[0], _results(out))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        mpsm.join_batch(descs, n, shape, ws, cfg, stream=torch.cuda.current_stream())
+    x = torch.randn(256, 256, device="cuda")
+    for rep, k in enumerate([1, 2, 0, 1]):
+        mpsm.write_descs(descs, dev[k], out, times)
+        out.fill_(-1)
+        _ = (x @ x).sum().item()
+        _say(f"graph replay {rep}: batch {k}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(ws[:4].view(torch.int32).item()) == 0
+        _check_results(batches[k], _results(out))
+
+
+def test_join_batch_waves_finish_small_joins_first():
+    """With four waves the smallest quarter of the joins (by nR + nS)
+    finishes before the largest quarter starts its join work."""
+    cases = _batch_cases(32, 0x1207014500000501, 6, 18)[:32]
+    shape, cfg, ws, descs, out, times = _device_batch([cases], waves=4)
+    dev = [(_dev(R), _dev(S)) for R, S in cases]
+    mpsm.write_descs(descs, dev, out, times)
+    mpsm.join_batch(descs, len(cases), shape, ws, cfg)
+    torch.cuda.synchronize()
+    _check_results(cases, _results(out))
+    t = times.cpu().numpy().view(np.uint64)
+    work = np.array([len(R) + len(S) if len(R) and len(S) else 0 for R, S in cases])
+    order = [i for i in np.argsort(work, kind="stable") if work[i]]
+    q = len(order) // 4
+    small, large = order[:q], order[-q:]
+    assert t[small, 2].max() < t[large, 1].min()
+    assert np.all(t[:, 0] == t[0, 0])
+
+
+def test_join_batch_device_check_rejects_out_of_bounds_batch():
+    """A batch whose join exceeds the shape's per-join bound: status word
+    MPSM_EINVAL, no output written."""
+    cases = _batch_cases(6, 0x1207014500000601, 8, 12)
+    shape, cfg, ws, descs, out, times = _device_batch([cases])
+    bad = list(cases)
+    rng = np.random.default_rng(5)
+    big = int(shape.max_nS) + 1
+    bad[0] = (bad[0][0] if len(bad[0][0]) else np.ones((3, 2), np.uint64),
+              np.stack([rng.integers(0, 10, big, dtype=np.uint64), np.zeros(big, np.uint64)], 1))
+    mpsm.write_descs(descs, [(_dev(R), _dev(S)) for R, S in bad], out, times)
+    out.fill_(-7)
+    mpsm.join_batch(descs, len(bad), shape, ws, cfg)
+    torch.cuda.synchronize()
+    assert int(ws[:4].view(torch.int32).item()) == 1
+    assert bool((out == -7).all())

@@ -152,6 +152,8 @@ CONFIGS = [
     dict(splitter=mpsm.SPLIT_LEARNED), dict(search=mpsm.SEARCH_LEARNED),
     dict(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED, bucket_target=1024),
     dict(splitter=mpsm.SPLIT_COST), dict(splitter=mpsm.SPLIT_COST, bucket_target=1024, search=mpsm.SEARCH_INTERP),
+    dict(splitter=mpsm.SPLIT_NONE), dict(splitter=mpsm.SPLIT_NONE, log2_run_len=14, search=mpsm.SEARCH_INTERP),
+    dict(splitter=mpsm.SPLIT_NONE, log2_run_len=13, role=mpsm.ROLE_SWAP, want_max=1),
 ]
 
 
@@ -374,6 +376,32 @@ def test_lognormal_reduced():
     got = gpu_join(w.R, w.S)
     assert got["count"] == w.expected_count == inv
     assert got["checksum"] == want.checksum
+
+
+# ------------------------------------------------- B-MPSM (no range partitioning)
+
+BMPSM = dict(splitter=mpsm.SPLIT_NONE)
+
+
+@pytest.mark.parametrize("nR,nS,domain", [(0, 10, 5), (10, 0, 5), (1, 1, 2), (3000, 9000, 500),
+                                          (70000, 5000, 0), (5000, 70001, 1 << 40)])
+def test_bmpsm_small_with_pairs(nR, nS, domain):
+    """B-MPSM: every R run against every S run; pair lists equal the oracle's."""
+    rng = np.random.default_rng(nR * 7 + nS)
+    check(rel(rng, nR, domain), rel(rng, nS, domain), cfg=mpsm.config(log2_run_len=12, **BMPSM), pairs=True)
+
+
+@pytest.mark.parametrize("name,shift", [("skewed", 8), ("lognormal", 10)])
+def test_bmpsm_skewed_and_duplicates(name, shift):
+    """B-MPSM on Zipf(1) foreign keys and on log-normal keys with duplicates
+    in R, with several R runs (run length 2^14)."""
+    w = workloads.make(name, scale_shift=shift)
+    want = oracle.join(w.R, w.S)
+    for kw in (dict(log2_run_len=14), dict(log2_run_len=14, search=mpsm.SEARCH_LEARNED)):
+        got = gpu_join(w.R, w.S, mpsm.config(**BMPSM, **kw), stats=True)
+        assert (got["count"], got["checksum"]) == (want.count, want.checksum), kw
+        lay = mpsm.layout(len(w.R), len(w.S), mpsm.config(**BMPSM, **kw))
+        assert lay["runs"] > 1
 
 
 def test_batch_members_reduced():

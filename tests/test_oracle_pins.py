@@ -464,3 +464,30 @@ def test_pmpsm_join_with_skewed_splitter_vector():
     a = oracle.pmpsm_join(R, S, T, B, 44, sp)
     b = oracle.join(R, S)
     assert (a.count, a.checksum) == (b.count, b.checksum)
+
+
+# ------------------------------------------------------ B-MPSM on the CPU
+
+@pytest.mark.parametrize("T,nR,nS,domain", [(1, 300, 900, 50), (4, 300, 900, 50), (9, 1000, 3000, 300),
+                                            (16, 5, 40, 3), (3, 0, 10, 5), (3, 10, 0, 5)])
+def test_bmpsm_join_equals_brute_force(T, nR, nS, domain):
+    """Every R run against every S run (Section 2.1): equal to the nested-loop
+    join on small inputs with heavy duplicates (more workers than tuples
+    leave runs empty); joining R_i with S_i only would miss pairs here."""
+    rng = np.random.default_rng(T * 1000 + nR)
+    R, S = _rand_rel(rng, nR, domain), _rand_rel(rng, nS, domain)
+    a = oracle.bmpsm_join(R, S, T)
+    b = oracle.join_nested(R, S)
+    assert (a.count, a.checksum, a.maxsum, a.nonempty) == (b.count, b.checksum, b.maxsum, b.nonempty)
+    kr, cr = np.unique(R[:, 0], return_counts=True)
+    ks, cs = np.unique(S[:, 0], return_counts=True)
+    _, ir, is_ = np.intersect1d(kr, ks, return_indices=True)
+    assert a.count == int((cr[ir].astype(np.int64) * cs[is_]).sum())
+
+
+def test_bmpsm_join_equals_definition_larger():
+    rng = np.random.default_rng(5)
+    R, S = _rand_rel(rng, 20000, 1 << 14), _rand_rel(rng, 60000, 1 << 14)
+    a = oracle.bmpsm_join(R, S, 12)
+    b = oracle.join(R, S)
+    assert (a.count, a.checksum) == (b.count, b.checksum)

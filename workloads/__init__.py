@@ -18,6 +18,11 @@ The five named workloads:
 * ``batch``      256 joins, |R_b| log-uniform in [2^12, 2^22],
   |S_b| = k_b |R_b|, k_b in {1..8}, half uniform, half Zipf(0.5..1.2).
 
+Workloads of the paper's other experiments: ``negcorr`` (negatively
+correlated 80:20 skew, Section 5.6), ``location_skew`` (S ordered small to
+large in clusters, Section 5.5) and foreign-key joins of multiplicity m for
+role reversal (Section 5.4, ``fk_uniform`` with |S| = m |R|).
+
 ``scale_shift`` shrinks every size by 2^scale_shift for tests.
 """
 from __future__ import annotations
@@ -152,6 +157,42 @@ def uniform_keys(n: int, domain: int, seed: int, tag: int = 0) -> np.ndarray:
 
 def splitmix_at(seed: int, i: int) -> int:
     return int(lib().wl_splitmix_at(seed, i))
+
+
+def negcorr(nR: int, nS: int, seed: int, domain: int | None = None, hot: float = 0.8, span: float = 0.2) -> Workload:
+    """Negatively correlated skew (the paper's Section 5.6 data set): 80% of
+    R's keys uniform in the top 20% of the key domain, the rest uniform
+    below it; 80% of S's keys uniform in the bottom 20%, the rest above it.
+    Keys are drawn independently (duplicates kept; no foreign-key relation).
+    The paper draws 1600 M keys from [0, 2^32), about 0.37 keys per domain
+    value; the default domain here is 4 x the power of two at or above |R|
+    (0.25 per value at |R| = 2^24)."""
+    D = domain or 4 * (1 << max(0, (nR - 1).bit_length()))
+    cut_r, cut_s = int(D * (1 - span)), int(D * span)
+    rng = np.random.default_rng(seed)
+    hr = rng.random(nR) < hot
+    rk = np.where(hr, rng.integers(cut_r, D, nR, dtype=np.uint64), rng.integers(0, cut_r, nR, dtype=np.uint64))
+    hs = rng.random(nS) < hot
+    sk = np.where(hs, rng.integers(0, cut_s, nS, dtype=np.uint64), rng.integers(cut_s, D, nS, dtype=np.uint64))
+    pr = rng.integers(0, (1 << 64) - 1, nR, dtype=np.uint64, endpoint=True)
+    ps = rng.integers(0, (1 << 64) - 1, nS, dtype=np.uint64, endpoint=True)
+    return Workload("negcorr", np.stack([rk, pr], 1), np.stack([sk, ps], 1), None, None,
+                    {"domain": D, "hot": hot, "span": span})
+
+
+def location_skew(w: Workload, clusters: int, seed: int) -> Workload:
+    """S arranged small to large in `clusters` consecutive clusters of equal
+    size, each in random order inside (the paper's Section 5.5: no total
+    order, so the clusters still need sorting); R unchanged."""
+    rng = np.random.default_rng(seed)
+    order = np.argsort(w.S[:, 0], kind="stable")
+    n = len(order)
+    bounds = [(c * n) // clusters for c in range(clusters + 1)]
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        rng.shuffle(order[a:b])
+    S = np.ascontiguousarray(w.S[order])
+    partner = None if w.partner is None else np.ascontiguousarray(w.partner[order])
+    return Workload(w.name + "+location_skew", w.R, S, partner, w.expected_count, {**w.meta, "clusters": clusters})
 
 
 def make(name: str, scale_shift: int = 0, seed: int | None = None):
