@@ -34,8 +34,10 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "join throughput (M tuples/s of |R|+|S|) + % HBM roofline; learned vs plain"
 
 # algorithmic HBM bytes of each launch step, per tuple of the relation it reads
+# S's histogram pass is folded into its scatter on large inputs (the step
+# then only redoes runs whose bucket regions overflowed): no bytes of its own
 STEP_BYTES = {
-    "s_histogram": ("S", 16), "s_scatter": ("S", 32), "s_bucket_sort": ("S", 32),
+    "s_histogram": ("S", 0), "s_scatter": ("S", 32), "s_bucket_sort": ("S", 32),
     "r1_histogram": ("R", 16), "r1_scatter": ("R", 32), "r2_histogram": ("R", 16), "r2_scatter": ("R", 32),
     "r_bucket_sort": ("R", 32), "join": ("RS", 16),
 }
@@ -77,9 +79,13 @@ WORKLOAD_KEYS = {
 
 # launch steps -> (kernel name prefix, occurrence of that kernel inside one join)
 STEP_DISPATCH = {
-    "s_histogram": ("k_bucket_hist", 0), "s_scatter": ("k_bucket_scatter", 0),
-    "r1_histogram": ("k_bucket_hist", 1), "r1_scatter": ("k_bucket_scatter", 1),
-    "r2_histogram": ("k_bucket_hist", 2), "r2_scatter": ("k_bucket_scatter", 2),
+    # S: the scatter into regions, then the exact path's histogram and
+    # scatter for runs whose regions overflowed (launched always, most often
+    # with nothing to do)
+    "s_histogram": ("k_bucket_hist", 0),
+    "s_scatter": [("void k_bucket_scatter<true>", 0), ("void k_bucket_scatter<false>", 0)],
+    "r1_histogram": ("k_bucket_hist", 1), "r1_scatter": ("void k_bucket_scatter<false>", 1),
+    "r2_histogram": ("k_bucket_hist", 2), "r2_scatter": ("void k_bucket_scatter<false>", 2),
     # the sorts: the two-per-CU kernel, then the one-per-CU kernel over the larger buckets
     "s_bucket_sort": [("void k_bucket_sort_cs<1024, 4", 0), ("void k_bucket_sort_cs<1024, 8", 0)],
     "r_bucket_sort": [("void k_bucket_sort_cs<1024, 4", 1), ("void k_bucket_sort_cs<1024, 8", 1)],
@@ -222,7 +228,52 @@ def profile_markdown(t, kt_csv, workload):
             out.append(f"| {(int(r['Start_Timestamp']) - t0) / 1e6:.3f} | "
                        f"{(int(r['End_Timestamp']) - int(r['Start_Timestamp'])) / 1e6:.3f} | "
                        f"{r.get('Queue_Id', '')} | `{r['Kernel_Name'].split('(')[0].replace('void ', '')}` |")
+    if t.get("sq"):
+        out += ["", "Wave-level instruction counts (SQ counters, one more run of the same command with "
+                "`--pmc " + " ".join(SQ_COUNTERS) + "`), per tuple of the step's relation "
+                "(S for S's steps, R for R's, both for the join):", "",
+                "| step | VALU | LDS | SALU | VMEM | SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES |", "|---|---|---|---|---|---|"]
+        for step, v in t["sq"].items():
+            pt = v["per_tuple"]
+            out.append(f"| {step} | {pt['valu']} | {pt['lds']} | {pt['salu']} | {pt['vmem']} | "
+                       f"{v['wait_inst_any_over_wave_cycles']} |")
     return "\n".join(out) + "\n"
+
+
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VMEM", "SQ_WAVE_CYCLES",
+               "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY")
+
+
+def summarize_sq(sq_csv, nR, nS):
+    """Per launch step of the first join in a counter run of SQ_COUNTERS:
+    every counter summed over the step's dispatches, and the wave-level
+    instruction counts per tuple of the step's relation."""
+    rows = _read_csv(sq_csv)
+    by_disp = {}
+    for r in rows:
+        d = by_disp.setdefault(r["Dispatch_Id"], {"Dispatch_Id": r["Dispatch_Id"], "Kernel_Name": r["Kernel_Name"],
+                                                  "Start_Timestamp": r.get("Start_Timestamp", "0")})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    joins = _per_join(list(by_disp.values()), "Kernel_Name", "Start_Timestamp")
+    if not joins:
+        return {}
+    out = {}
+    for step, spec in STEP_DISPATCH.items():
+        picks = spec if isinstance(spec, list) else [spec]
+        ds = [_nth(joins[0], prefix, k) for prefix, k in picks]
+        if any(d is None for d in ds):
+            continue
+        tot = {c: sum(d.get(c, 0.0) for d in ds) for c in SQ_COUNTERS}
+        rel = STEP_BYTES.get(step, ("RS", 0))[0]
+        n = {"S": nS, "R": nR, "RS": nR + nS}[rel]
+        out[step] = {"counters": {c: int(v) for c, v in tot.items()},
+                     "per_tuple": {"tuples": n, "valu": round(tot["SQ_INSTS_VALU"] / n, 2),
+                                   "lds": round(tot["SQ_INSTS_LDS"] / n, 2),
+                                   "salu": round(tot["SQ_INSTS_SALU"] / n, 2),
+                                   "vmem": round(tot["SQ_INSTS_VMEM"] / n, 3)},
+                     "wait_inst_any_over_wave_cycles": round(tot["SQ_WAIT_INST_ANY"] / tot["SQ_WAVE_CYCLES"], 3)
+                     if tot["SQ_WAVE_CYCLES"] else None}
+    return out
 
 
 def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=5):
@@ -644,12 +695,16 @@ def main():
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("KERNEL_TRACE_CSV", "FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic_<workload>.json from rocprofv3 output (no GPU needed)")
     ap.add_argument("--profile-command", default="", help="command line recorded in the summary")
+    ap.add_argument("--summarize-sq", default=None, metavar="SQ_CSV",
+                    help="with --summarize-profiles: also the SQ counter run's per-step instruction counts")
     args = ap.parse_args()
     if args.summarize_profiles:
         sizes = {"fk_uniform": (1 << 26, 1 << 28), "skewed": (1 << 26, 1 << 28), "fk_small": (1 << 20, 1 << 22),
                  "lognormal": (1 << 28, 1 << 30)}
         nR, nS = sizes[args.workload]
         t = summarize_profiles(*args.summarize_profiles, args.workload, nR, nS, args.profile_command)
+        if args.summarize_sq:
+            t["sq"] = summarize_sq(args.summarize_sq, nR, nS)
         out = os.path.join(ROOT, "profiles", f"traffic_{args.workload}.json")
         with open(out, "w") as f:
             json.dump(t, f, indent=1)

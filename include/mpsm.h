@@ -124,6 +124,8 @@ typedef struct mpsm_stats {
   uint64_t resorted_buckets;  /* buckets whose one-pass sort gave up, re-sorted by LSD radix passes */
   uint64_t retried_buckets;   /* R buckets the one-pass sort gave up on and sorted again over their own key range */
   uint64_t pairs_truncated;   /* 1 if pairs were requested and the join has more than pairs_capacity */
+  uint64_t redone_runs;       /* S runs whose bucket regions overflowed and were scattered again exactly
+                                 (large S only: smaller S takes the exact path directly) */
 } mpsm_stats;
 
 /* Fill *cfg with defaults (all automatic, role AUTO, sampled splitters,

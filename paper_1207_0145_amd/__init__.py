@@ -43,7 +43,7 @@ class MpsmStats(ctypes.Structure):
                 ("search_fallbacks", ctypes.c_uint64), ("max_partition", ctypes.c_uint64),
                 ("cdf_eps_r", ctypes.c_double), ("cdf_eps_s", ctypes.c_double),
                 ("resorted_buckets", ctypes.c_uint64), ("retried_buckets", ctypes.c_uint64),
-                ("pairs_truncated", ctypes.c_uint64)]
+                ("pairs_truncated", ctypes.c_uint64), ("redone_runs", ctypes.c_uint64)]
 
 
 class MpsmLayout(ctypes.Structure):

@@ -155,8 +155,11 @@ __global__ void __launch_bounds__(1024) k_seg_plan(uint32_t nseg, uint32_t NBmax
 
 // ------------------------------------------------------------------- scan
 
-__global__ void __launch_bounds__(SCAN_NT) k_scan_reduce(const uint32_t* in, uint32_t n, uint32_t* bsum) {
+// With enable set, a scan runs only if *enable is non-zero.
+__global__ void __launch_bounds__(SCAN_NT) k_scan_reduce(const uint32_t* in, uint32_t n, uint32_t* bsum,
+                                                         const uint32_t* enable) {
   __shared__ uint64_t red[SCAN_NT / 64 + 1];
+  if (enable && !*enable) return;
   const uint32_t base = blockIdx.x * SCAN_BLOCK;
   uint64_t s = 0;
 #pragma unroll
@@ -173,9 +176,10 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_reduce(const uint32_t* in, uin
 // every block adds up itself (a few thousand blocks at most, so this costs
 // less than a launch that scans the totals).
 __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const uint32_t* in, uint32_t* out, uint32_t n,
-                                                        const uint32_t* bsum) {
+                                                        const uint32_t* bsum, const uint32_t* enable) {
   __shared__ uint32_t wsum[SCAN_NT / 64 + 2];
   __shared__ uint64_t red[SCAN_NT / 64 + 1];
+  if (enable && !*enable) return;
   uint64_t pre = 0;
   for (uint32_t i = threadIdx.x; i < blockIdx.x; i += SCAN_NT) pre += bsum[i];
   pre = block_sum64<SCAN_NT>(pre, red);
@@ -209,19 +213,90 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const uint32_t* in, uint
 // before or after its rank gets a bucket of its own: the next splitter
 // becomes key + 1 when that is below it; along a run of such splitters
 // every other one moves (a moved splitter no longer carries its key).
+//
+// With regions (a bucket pass without a histogram, see k_bucket_scatter_padded)
+// the kernel also sizes every bucket's region of the segment's area
+// (reg.stride tuples from s * reg.stride): from the sample keys c that fall
+// in the bucket (by the final splitters and the bucket function), an upper
+// bound on its tuples, len/M (c + 4 sqrt(c) + 10) + 16 (the sample count is
+// about Poisson with mean len/M of the bucket's size; the bound holds except
+// for about one bucket in 10^4, and a bucket past it only sends its segment
+// through the exact path).  Regions are scaled down if they would not fit
+// the area.
+struct Regions {
+  uint32_t* cap;     // per global bucket: region size
+  uint32_t* start;   // per global bucket: region start (tuple index into the padded array)
+  uint32_t* fill;    // per global bucket: tuples claimed (zeroed here)
+  uint32_t* dirty;   // per segment: 1 if a bucket outgrew its region (zeroed here)
+  uint32_t* any;     // 1 if any segment is dirty (zeroed by the call's init)
+  uint32_t stride;   // area of a segment
+};
+
+template <int NT>
+__device__ void size_regions(const Regions& rg, uint32_t s, uint32_t g0, uint32_t nb, uint32_t len, uint32_t M,
+                             const uint32_t* bcnt, uint32_t* wsum, uint64_t* red) {
+  constexpr int PER = (MAX_NB + NT - 1) / NT;
+  const uint32_t tid = threadIdx.x;
+  const float scale = M ? (float)len / (float)M : 0.f;
+  uint32_t c[PER];
+  uint64_t tot = 0;
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const uint32_t b = tid * PER + q;
+    c[q] = 0;
+    if (b < nb) {
+      const float x = (float)bcnt[b];
+      const float bound = nb == 1 ? (float)len : scale * (x + 4.f * __builtin_sqrtf(x) + 10.f) + 16.f;
+      c[q] = bound >= (float)rg.stride ? rg.stride : (uint32_t)bound + 1u;
+      tot += c[q];
+    }
+  }
+  tot = block_sum64<NT>(tot, red);
+  // fit the area: scale every region down by the same factor
+  if (tot > rg.stride) {
+#pragma unroll
+    for (int q = 0; q < PER; q++) c[q] = (uint32_t)((uint64_t)c[q] * rg.stride / tot);
+  }
+  uint32_t run = 0, loc[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) { loc[q] = run; run += c[q]; }
+  uint32_t all;
+  const uint32_t ex = block_excl_scan<NT>(run, wsum, &all);
+  const uint64_t base = (uint64_t)s * rg.stride;
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const uint32_t b = tid * PER + q;
+    if (b < nb) {
+      rg.cap[g0 + b] = c[q];
+      rg.start[g0 + b] = (uint32_t)(base + loc[q] + ex);
+      rg.fill[g0 + b] = 0;
+    }
+  }
+  if (tid == 0) rg.dirty[s] = 0;
+}
+
 template <int NT, int IPT>
 __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict__ src, const uint32_t* seg_start,
                                                          const uint32_t* seg_len, const uint32_t* seg_nb,
                                                          uint32_t NBmax, uint32_t OS, uint64_t level_seed,
                                                          uint64_t* spl, const tup_t* const* seg_src,
-                                                         uint64_t* full) {
+                                                         uint64_t* full, Regions rg, const uint32_t* seg_b0) {
   using Sorter = BlockSort<NT, IPT, 4>;
   __shared__ uint64_t buf[Sorter::BUF_WORDS];
   __shared__ uint32_t wsum[Sorter::WSUM_WORDS];
   __shared__ uint64_t red[NT / 64 + 1];
+  __shared__ uint64_t lspl[MAX_NB];
+  __shared__ uint32_t bcnt[MAX_NB];
   const uint32_t s = blockIdx.x, tid = threadIdx.x;
   const uint32_t len = seg_len[s], start = seg_start[s], nb = seg_nb[s];
-  if (len == 0 || nb < 2) return;
+  if (len == 0 || nb < 2) {
+    if (rg.cap) {   // one bucket holds the segment (or nothing)
+      for (uint32_t b = tid; b < MAX_NB; b += NT) bcnt[b] = 0;
+      __syncthreads();
+      size_regions<NT>(rg, s, seg_b0[s], nb, len, 0, bcnt, wsum, red);
+    }
+    return;
+  }
   // a segment may be read in place from its own array
   const gtup_t* const gsrc = as_global(seg_src ? seg_src[s] - start : src);
   const uint32_t M = nb * OS;
@@ -264,8 +339,17 @@ __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict
     uint32_t t = 0;
     while (t < j && moves[j - 1 - t]) t++;
     const uint32_t pos = (j + 1) * OS;
-    out[j] = (t & 1) ? buf[pos - OS] + 1 : buf[pos];
+    const uint64_t v = (t & 1) ? buf[pos - OS] + 1 : buf[pos];
+    out[j] = v;
+    lspl[j] = v;
   }
+  if (!rg.cap) return;
+  // the sample keys per bucket, by the final splitters and the bucket function
+  for (uint32_t b = tid; b < nb; b += NT) bcnt[b] = 0;
+  __syncthreads();
+  for (uint32_t r = tid; r < M; r += NT) atomicAdd(&bcnt[bucket_of(lspl, nb - 1, buf[r])], 1u);
+  __syncthreads();
+  size_regions<NT>(rg, s, seg_b0[s], nb, len, M, bcnt, wsum, red);
 }
 
 // ------------------------------------------------- cost-balanced splitters
@@ -275,14 +359,16 @@ __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict
 // sorted sample key x of R, the S tuples below x: in run j about
 // lb * stride - stride / 2, lb = number of bounds below x.  s_below[i] for
 // sample key i; s_below[M] = all S tuples.
-__global__ void k_cost_s_cdf(const uint64_t* sample, uint32_t M, const uint64_t* run_idx, const uint32_t* run_len,
-                             uint32_t Q, uint32_t idx_per_run, uint32_t stride, uint64_t nS, uint64_t* s_below) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_cost_s_cdf(const uint64_t* sample, uint32_t M, const uint64_t* run_idx,
+                                                    const uint32_t* run_len, uint32_t Q, uint32_t idx_per_run,
+                                                    uint32_t stride, uint64_t nS, uint64_t* s_below) {
+  // one wave per sample key; its lanes take the runs in turn
+  const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (i > M) return;
-  if (i == M) { s_below[M] = nS; return; }
+  if (i == M) { if (lane == 0) s_below[M] = nS; return; }
   const uint64_t x = sample[i];
   uint64_t tot = 0;
-  for (uint32_t j = 0; j < Q; j++) {
+  for (uint32_t j = lane; j < Q; j += 64) {
     const uint64_t* idx = run_idx + (uint64_t)j * idx_per_run;
     const uint32_t n = run_len[j], nidx = (n + stride - 1) / stride;
     uint32_t lo = 0, hi = nidx;
@@ -290,13 +376,17 @@ __global__ void k_cost_s_cdf(const uint64_t* sample, uint32_t M, const uint64_t*
     const uint64_t est = lo ? (uint64_t)lo * stride - stride / 2 : 0;
     tot += est < n ? est : n;
   }
-  s_below[i] = tot;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, 64);
+  if (lane == 0) s_below[i] = tot;
 }
 
 // Cost of a partition of r R tuples and s S tuples (Section 4.3): sorting
 // it, r log2 r, plus joining it, T r + s (T = S runs).
+// The logarithm is the hardware's single-precision log2 (its relative
+// error, about 2^-22, only moves a group border where two costs tie).
 __device__ __forceinline__ double cost_of(double r, double s, double T) {
-  return (r > 1.0 ? r * log2(r) : 0.0) + T * r + s;
+  return (r > 1.0 ? r * (double)__builtin_amdgcn_logf((float)r) : 0.0) + T * r + s;
 }
 
 constexpr int COST_NT = 1024;
@@ -323,7 +413,13 @@ __global__ void __launch_bounds__(COST_NT) k_cost_splitters(const uint64_t* samp
   for (uint32_t i = tid; i <= M; i += COST_NT) sc[i] = i == 0 ? 0 : s_below[i];
   __syncthreads();
   const double dT = (double)T;
-  auto rc = [&](uint32_t i) -> double { return (double)((uint64_t)i * nR / M); };
+  // R tuples below cell i: floor(i nR / M); M = buckets x oversample is a
+  // power of two here (both are), so the division is a shift
+  const bool pow2 = (M & (M - 1)) == 0;
+  const uint32_t msh = pow2 ? (uint32_t)__builtin_ctz(M) : 0u;
+  auto rc = [&](uint32_t i) -> double {
+    return (double)(pow2 ? ((uint64_t)i * nR) >> msh : (uint64_t)i * nR / M);
+  };
   auto cost = [&](uint32_t a, uint32_t b) -> double {
     return cost_of(rc(b) - rc(a), (double)(sc[b] - sc[a]), dT);
   };
@@ -342,23 +438,42 @@ __global__ void __launch_bounds__(COST_NT) k_cost_splitters(const uint64_t* samp
     }
     return g;
   };
-  if (tid == 0) {
+  {
+    // the largest single cell: the lower end of the threshold search
     double mx = 0.0;
-    for (uint32_t i = 0; i < M; i++) { const double c = cost(i, i + 1); mx = c > mx ? c : mx; }
-    lohi[0] = mx > 0.0 ? mx : 1.0;
-    lohi[1] = cost(0, M) > lohi[0] ? cost(0, M) : lohi[0];
+    for (uint32_t i = tid; i < M; i += COST_NT) { const double c = cost(i, i + 1); mx = c > mx ? c : mx; }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) { const double o = __shfl_xor(mx, d, 64); mx = o > mx ? o : mx; }
+    if (tid == 0) { lohi[0] = 0.0; first_ok = 0; }
+    __syncthreads();
+    // doubles are non-negative here, so their bit patterns order like u64
+    if ((tid & 63) == 0) atomicMax(reinterpret_cast<unsigned long long*>(&lohi[0]), __double_as_longlong(mx));
+    __syncthreads();
+    if (tid == 0) {
+      lohi[0] = lohi[0] > 0.0 ? lohi[0] : 1.0;
+      lohi[1] = cost(0, M) > lohi[0] ? cost(0, M) : lohi[0];
+    }
   }
   __syncthreads();
+  // threshold t of a geometric grid of COST_NT over [lo, hi] (single-precision
+  // exponent: the grid only has to be monotone and reach both ends)
+  auto grid = [&](double lo, double hi, uint32_t t) -> double {
+    if (t == 0) return lo;
+    if (t == COST_NT - 1) return hi;
+    const float e = __builtin_amdgcn_logf((float)(hi / lo)) * ((float)t / (float)(COST_NT - 1));
+    const double c = lo * (double)__builtin_amdgcn_exp2f(e);
+    return c < lo ? lo : (c > hi ? hi : c);
+  };
   for (int round = 0; round < 2; round++) {
     const double lo = lohi[0], hi = lohi[1];
     if (tid == 0) first_ok = COST_NT;
     __syncthreads();
-    const double C = tid == COST_NT - 1 ? hi : lo * pow(hi / lo, (double)tid / (double)(COST_NT - 1));
+    const double C = grid(lo, hi, tid);
     if (groups(C) <= NB) atomicMin(&first_ok, tid);
     __syncthreads();
-    const uint32_t f = first_ok;
-    const double Cf = f == COST_NT - 1 ? hi : lo * pow(hi / lo, (double)f / (double)(COST_NT - 1));
-    const double Cp = f == 0 ? lo : lo * pow(hi / lo, (double)(f - 1) / (double)(COST_NT - 1));
+    const uint32_t f = first_ok < COST_NT ? first_ok : COST_NT - 1;
+    const double Cf = grid(lo, hi, f);
+    const double Cp = f == 0 ? lo : grid(lo, hi, f - 1);
     __syncthreads();
     if (tid == 0) { lohi[0] = Cp; lohi[1] = Cf; }
     __syncthreads();
@@ -400,13 +515,15 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
                                                          const uint32_t* seg_len, const uint32_t* seg_tile0,
                                                          const uint32_t* seg_cnt0, const uint32_t* seg_nb,
                                                          uint32_t nseg, const uint64_t* spl, uint32_t NBmax,
-                                                         uint32_t TILE, uint32_t* cnt, const tup_t* const* seg_src) {
+                                                         uint32_t TILE, uint32_t* cnt, const tup_t* const* seg_src,
+                                                         const uint32_t* only_dirty) {
   __shared__ uint64_t sp[MAX_NB];
   __shared__ uint32_t h[MAX_NB];
   __shared__ SplitDir<SPLIT_DIR, MAX_NB> dir;
   const uint32_t g = blockIdx.x;
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
+  if (only_dirty && !only_dirty[s]) return;   // redo of the segments a padded scatter could not place
   // a segment may be read in place from its own array
   const gtup_t* const gsrc = as_global(seg_src ? seg_src[s] - seg_start[s] : src);
   const uint32_t t = g - seg_tile0[s], ntiles = seg_tile0[s + 1] - seg_tile0[s];
@@ -438,12 +555,30 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
 
 // Scatter of every tile to its precomputed sub-ranges (pos = scanned cnt),
 // staged in LDS so that consecutive lanes write consecutive addresses.
+//
+// PAD (a bucket pass without a histogram): instead of the scanned counts,
+// every chunk claims room for its tuples of each bucket in that bucket's
+// region (Regions; one atomic per bucket and chunk) and writes them there;
+// a claim that outgrows the region writes nothing and marks the segment
+// dirty.  The tuples of a bucket then sit at the start of its region in
+// the order of the claims.
+// redo (not PAD, redo.dirty set): only dirty segments are scattered, each
+// compactly from the start of its own area (s * redo.stride), by the
+// scanned counts of its own tiles.
+struct Redo {
+  const uint32_t* dirty;   // per segment, or NULL: every segment, at the scanned positions
+  uint32_t stride;
+};
+constexpr uint32_t NO_ROOM = 0xFFFFFFFFu;
+
+template <bool PAD>
 __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
                                                             const uint32_t* seg_start, const uint32_t* seg_len,
                                                             const uint32_t* seg_tile0, const uint32_t* seg_cnt0,
                                                             const uint32_t* seg_nb, uint32_t nseg, const uint64_t* spl,
                                                             uint32_t NBmax, uint32_t TILE, const uint32_t* pos,
-                                                            const tup_t* const* seg_src) {
+                                                            const tup_t* const* seg_src, Regions rg,
+                                                            const uint32_t* seg_b0, Redo redo) {
   __shared__ uint64_t sp[MAX_NB];
   __shared__ uint32_t cursor[MAX_NB], lcnt[MAX_NB], lofs[MAX_NB];
   __shared__ tup_t stage[SCAT_CH];
@@ -452,6 +587,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   const uint32_t g = blockIdx.x, tid = threadIdx.x;
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
+  if (!PAD && redo.dirty && !redo.dirty[s]) return;
   // a segment may be read in place from its own array
   const gtup_t* const gsrc = as_global(seg_src ? seg_src[s] - seg_start[s] : src);
   const uint32_t t = g - seg_tile0[s], ntiles = seg_tile0[s + 1] - seg_tile0[s];
@@ -459,9 +595,17 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   const uint32_t a = seg_start[s] + t * TILE;
   const uint32_t b = min(a + TILE, segend);
   const uint32_t NB = seg_nb[s], nspl = NB - 1;
+  const uint32_t g0 = PAD ? seg_b0[s] : 0u;
   for (uint32_t i = tid; i < nspl; i += SCAT_NT) sp[i] = spl[(uint64_t)s * (NBmax - 1) + i];
-  const uint32_t* p = pos + seg_cnt0[s] + t;
-  for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] = p[(uint64_t)i * ntiles]; lcnt[i] = 0; }
+  if (PAD) {
+    for (uint32_t i = tid; i < NB; i += SCAT_NT) lcnt[i] = 0;
+  } else {
+    const uint32_t* p = pos + seg_cnt0[s] + t;
+    // redo: positions relative to the segment's first count, from its own area
+    const uint32_t rel = redo.dirty ? pos[seg_cnt0[s]] : 0u;
+    const uint32_t base = redo.dirty ? s * redo.stride : 0u;
+    for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] = base + (p[(uint64_t)i * ntiles] - rel); lcnt[i] = 0; }
+  }
   __syncthreads();
   if (nspl) dir.build<SCAT_NT>(sp, nspl);
   const SplitView sv = dir.view(nspl);
@@ -491,13 +635,25 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
       }
     }
     __syncthreads();
-    // exclusive scan of lcnt over NB buckets (PER consecutive buckets per thread)
+    // exclusive scan of lcnt over NB buckets (PER consecutive buckets per
+    // thread); with PAD each thread also claims its buckets' room
     uint32_t loc[PER], run = 0;
 #pragma unroll
     for (int q = 0; q < PER; q++) {
       const uint32_t i = tid * PER + q;
+      const uint32_t c = (i < NB) ? lcnt[i] : 0;
       loc[q] = run;
-      run += (i < NB) ? lcnt[i] : 0;
+      run += c;
+      if (PAD && c) {
+        const uint32_t at = atomicAdd(&rg.fill[g0 + i], c);
+        if (at + c <= rg.cap[g0 + i]) {
+          cursor[i] = rg.start[g0 + i] + at;
+        } else {
+          cursor[i] = NO_ROOM;
+          rg.dirty[s] = 1u;
+          *rg.any = 1u;
+        }
+      }
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan<SCAT_NT>(run, wsum, &tot);
@@ -522,10 +678,14 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
       // tuples per chunk, so that every bucket gets a run of several tuples
       const tup_t tq = stage[q];
       const uint32_t bb = dir.bucket(sv, sp, tq.key);
-      store_tup(dst + cursor[bb] + (q - lofs[bb]), tq);
+      const uint32_t cb = cursor[bb];
+      if (!PAD || cb != NO_ROOM) store_tup(dst + cb + (q - lofs[bb]), tq);
     }
     __syncthreads();
-    for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] += lcnt[i]; lcnt[i] = 0; }
+    for (uint32_t i = tid; i < NB; i += SCAT_NT) {
+      if (!PAD) cursor[i] += lcnt[i];
+      lcnt[i] = 0;
+    }
     __syncthreads();
   }
 }
@@ -557,6 +717,49 @@ __global__ void k_bucket_table(uint32_t nseg, uint32_t NBmax, const uint32_t* se
   const uint64_t* sp = spl + (uint64_t)s * (NBmax - 1);
   blo[g] = b > 0 ? sp[b - 1] : olo;
   bhi[g] = b + 1 < nb ? sp[b] : ohi;
+}
+
+// Bucket table of a padded pass (one workgroup per segment): bucket g of
+// segment s holds fill[g] tuples.  Its sorted output starts at the segment
+// start plus the tuples of the segment's earlier buckets (bstart; bstart[G]
+// = the end of the last segment), and its tuples are read from its region
+// (bsrc = region start), or, for a segment the exact path redid, from the
+// same compact offset inside the segment's area.  Key bounds as in
+// k_bucket_table.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_region_table(uint32_t nseg, uint32_t NBmax, const uint32_t* seg_start,
+                                                     const uint32_t* seg_len, const uint32_t* seg_nb,
+                                                     const uint32_t* seg_b0, Regions rg, const uint64_t* spl,
+                                                     uint32_t* bstart, uint32_t* bsrc, uint64_t* blo,
+                                                     uint64_t* bhi) {
+  constexpr int PER = (MAX_NB + NT - 1) / NT;
+  __shared__ uint32_t wsum[NT / 64 + 2];
+  const uint32_t s = blockIdx.x, tid = threadIdx.x;
+  const uint32_t nb = seg_nb[s], g0 = seg_b0[s];
+  const bool redone = rg.dirty[s] != 0;
+  uint32_t c[PER], loc[PER], run = 0;
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const uint32_t b = tid * PER + q;
+    c[q] = b < nb ? rg.fill[g0 + b] : 0;
+    loc[q] = run;
+    run += c[q];
+  }
+  uint32_t tot;
+  const uint32_t ex = block_excl_scan<NT>(run, wsum, &tot);
+  const uint64_t* sp = spl + (uint64_t)s * (NBmax - 1);
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const uint32_t b = tid * PER + q;
+    if (b < nb) {
+      const uint32_t g = g0 + b, pre = loc[q] + ex;
+      bstart[g] = seg_start[s] + pre;
+      bsrc[g] = redone ? s * rg.stride + pre : rg.start[g];
+      blo[g] = b > 0 ? sp[b - 1] : 0ull;
+      bhi[g] = b + 1 < nb ? sp[b] : ~0ull;
+    }
+  }
+  if (s == nseg - 1 && tid == 0) bstart[g0 + nb] = seg_start[s] + seg_len[s];
 }
 
 // ------------------------------------------------------------ bucket sort
@@ -638,9 +841,11 @@ __device__ __forceinline__ uint32_t cs_group_rank(const uint64_t* sk, uint32_t g
   return r;
 }
 
+// bsrc (or NULL): where a bucket's tuples are read, when not at its output
+// start in src (the regions of a padded pass).
 template <int NT, int IPT, int M, int MINB, bool STAGE, bool TIGHT>
 __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
-                                                       const uint32_t* bstart, const uint64_t* blo,
+                                                       const uint32_t* bstart, const uint32_t* bsrc, const uint64_t* blo,
                                                        const uint64_t* bhi, const uint32_t* Gcount,
                                                        const uint32_t* in_list, const unsigned long long* in_count,
                                                        uint32_t* over_list, unsigned long long* over_count,
@@ -696,6 +901,9 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
     const uint32_t g = in_list ? in_list[it] : it;
     const uint32_t a = bstart[g], n = bstart[g + 1] - a;
     if (n == 0) continue;
+    // the bucket's tuples (uniform: kept in scalar registers)
+    const uint32_t ain = __builtin_amdgcn_readfirstlane(bsrc ? bsrc[g] : a);
+    const tup_t* const in = src + ain;
     uint64_t lo = blo[g], span = bhi[g] - lo;
     if (span == 0) {   // one key: input order is sorted order
       // Lane indexes pass through an empty asm where the lane's addresses
@@ -707,7 +915,7 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
       for (; i + 3 * NT < n; i += 4 * NT) {   // four loads in flight
         tup_t t[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) t[u] = load_tup(src + a + i + u * NT);
+        for (int u = 0; u < 4; u++) t[u] = load_tup(in + i + u * NT);
 #pragma unroll
         for (int u = 0; u < 4; u++) {
           store_tup(dst + a + i + u * NT, t[u]);
@@ -715,7 +923,7 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
         }
       }
       for (; i < n; i += NT) {
-        store_tup(dst + a + i, load_tup(src + a + i));
+        store_tup(dst + a + i, load_tup(in + i));
         emit_sorted(so, g, a, i, lo);
       }
       continue;
@@ -729,7 +937,7 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
     for (int k = 0; k < IPT; k++) {
       const uint32_t i = k * NT + tid;
       if (i < n) {
-        const tup_t v = load_tup(src + a + i);
+        const tup_t v = load_tup(in + i);
         key[k] = v.key; val[k] = v.pay;
       } else {
         key[k] = ~0ull; val[k] = 0;
@@ -1096,7 +1304,8 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
 // LSD radix sort (BlockSort) of the buckets on a list, one workgroup per
 // bucket; buckets larger than the tile go to over_list.
 __global__ void __launch_bounds__(LSD_NT) k_bucket_sort_lsd(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
-                                                            const uint32_t* bstart, const uint32_t* in_list,
+                                                            const uint32_t* bstart, const uint32_t* bsrc,
+                                                            const uint32_t* in_list,
                                                             const unsigned long long* in_count, uint32_t* over_list,
                                                             unsigned long long* over_count, SortOut so) {
   using Sorter = BlockSort<LSD_NT, LSD_IPT, 4>;
@@ -1116,7 +1325,7 @@ __global__ void __launch_bounds__(LSD_NT) k_bucket_sort_lsd(const tup_t* __restr
 #pragma unroll
     for (int k = 0; k < LSD_IPT; k++) {
       const uint32_t i = k * LSD_NT + tid;
-      if (i < n) { const tup_t v = load_tup(src + a + i); key[k] = v.key; val[k] = v.pay; }
+      if (i < n) { const tup_t v = load_tup(src + (bsrc ? bsrc[g] : a) + i); key[k] = v.key; val[k] = v.pay; }
       else { key[k] = ~0ull; val[k] = 0; }
     }
     Sorter::sort<true>(key, val, (int)n, buf, wsum, red);
@@ -1141,7 +1350,8 @@ __global__ void __launch_bounds__(LSD_NT) k_bucket_sort_lsd(const tup_t* __restr
 // and writes every tuple to its digit's cursor.
 constexpr int BIG_NT = 1024, BIG_IPT = 8;
 __global__ void __launch_bounds__(BIG_NT) k_big_sort(tup_t* __restrict__ src, tup_t* __restrict__ dst,
-                                                     const uint32_t* bstart, const uint32_t* big_list,
+                                                     const uint32_t* bstart, const uint32_t* bsrc,
+                                                     const uint32_t* big_list,
                                                      const unsigned long long* big_count, SortOut so) {
   using RS = BlockSort<BIG_NT, BIG_IPT, 4>;
   constexpr uint32_t CH = BIG_NT * BIG_IPT;
@@ -1154,11 +1364,12 @@ __global__ void __launch_bounds__(BIG_NT) k_big_sort(tup_t* __restrict__ src, tu
   for (uint32_t e = blockIdx.x; e < nbig; e += gridDim.x) {
     const uint32_t g = big_list[e];
     const uint32_t a = bstart[g], n = bstart[g + 1] - a;
-    const uint64_t k0 = src[a].key;
+    tup_t* const in = src + (bsrc ? bsrc[g] : a);   // the bucket's tuples (room for n: its region)
+    const uint64_t k0 = in[0].key;
     uint64_t vary = 0;
-    for (uint32_t i = tid; i < n; i += BIG_NT) vary |= src[a + i].key ^ k0;
+    for (uint32_t i = tid; i < n; i += BIG_NT) vary |= in[i].key ^ k0;
     vary = RS::block_or(vary, red);
-    tup_t* from = src + a;
+    tup_t* from = in;
     tup_t* to = dst + a;
     for (int sh = 0; sh < 64; sh += 4) {
       if (((vary >> sh) & 15ull) == 0) continue;

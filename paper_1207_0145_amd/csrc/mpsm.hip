@@ -37,6 +37,8 @@ struct Plan {
   uint32_t L, Q, NBs, OSs;
   uint32_t levels, NB1, OS1, NB2, OS2;
   uint32_t QR;                 // B-MPSM (no range partitioning): sorted R runs of L tuples
+  int padS;                    // S's bucket pass without a histogram: runs in areas of Lpad tuples
+  uint32_t Lpad;
   uint32_t Gs, Gr, Pmax;
   uint32_t idx_per_run;
   uint32_t JCH, BT;
@@ -57,6 +59,7 @@ struct Plan {
   uint64_t ridx, o, items, item_pre, item_cnt, res, span, pterm;
   uint64_t cdf_chunks, cdf_sorted, modelR, modelS;  // learned CDF samples and models
   uint64_t cost_sample, cost_s_below, cost_best;   // cost-balanced splitters
+  uint64_t capS, rstS, fillS, bsrcS, dirtyS;        // S's regions (padS)
   uint64_t total;
 };
 
@@ -143,7 +146,9 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
     // level-2 buckets per level-1 bucket: ceil(len / BT), at most twice the
     // average need (level-1 buckets are sampled, so their sizes vary)
     P->NB2 = 2 * next_pow2(cdiv(F, P->NB1));
-    if (P->NB2 > (uint32_t)MAX_NB) P->NB2 = MAX_NB;
+    // cost-balanced first-level buckets differ in size by design (fewer R
+    // tuples where S is dense): room for the largest to be cut to the target
+    if (P->splitter == MPSM_SPLIT_COST || P->NB2 > (uint32_t)MAX_NB) P->NB2 = MAX_NB;
     // 16 samples per level-2 bucket (the larger sample sort when NB2 > 128):
     // with 4, bucket sizes spread so far that about 1% exceed the LDS tile
     P->OS2 = SMP_CAP / P->NB2 < 16u ? SMP_CAP / P->NB2 : 16u;
@@ -162,10 +167,16 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->cntR2 = P->levels == 2 ? (uint64_t)P->tilesR2 * P->NB2 : 1;
   P->item_cap = P->nS / P->JCH + P->Pmax + 2;
 
+  // S's runs are scattered into sample-sized bucket regions without a
+  // histogram pass when S is large enough for that pass to matter; each run
+  // gets an area of 2.75 L tuples (the regions' bound is about 2.5 times a
+  // bucket's mean size)
+  P->Lpad = (uint32_t)((((uint64_t)P->L * 11) / 4 + 63) & ~63ull);
+  P->padS = P->nS >= (1u << 22) && (uint64_t)P->Q * P->Lpad < (1ull << 32);
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) { uint64_t o = off; off += (bytes + 255) & ~255ull; return o; };
   const uint64_t ts = sizeof(tup_t);
-  P->T = take(P->nS * ts);
+  P->T = take((P->padS ? (uint64_t)P->Q * P->Lpad : P->nS) * ts);
   P->U = take(P->nS * ts);
   P->R1 = take(P->nR * ts);
   P->R2 = take(P->nR * ts);
@@ -217,6 +228,13 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->cost_sample = take((uint64_t)COST_MAX * 8);
   P->cost_s_below = take(((uint64_t)COST_MAX + 1) * 8);
   P->cost_best = take(8);
+  if (P->padS) {
+    P->capS = take((uint64_t)P->Gs * 4);
+    P->rstS = take((uint64_t)P->Gs * 4);
+    P->fillS = take((uint64_t)P->Gs * 4);
+    P->bsrcS = take(((uint64_t)P->Gs + 1) * 4);
+    P->dirtyS = take((uint64_t)P->Q * 4);
+  }
   P->res = take(sizeof(Result));
   P->total = off;
   return true;
@@ -240,12 +258,13 @@ Seg seg_at(char* ws, uint64_t off, uint32_t nseg) {
   } while (0)
 #define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
 
-mpsm_status scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* bsum, hipStream_t st) {
+mpsm_status scan_u32(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* bsum, hipStream_t st,
+                     const uint32_t* enable = nullptr) {
   if (n == 0) return MPSM_OK;
   const uint32_t nb = (uint32_t)cdiv(n, SCAN_BLOCK);
-  k_scan_reduce<<<nb, SCAN_NT, 0, st>>>(in, (uint32_t)n, bsum);
+  k_scan_reduce<<<nb, SCAN_NT, 0, st>>>(in, (uint32_t)n, bsum, enable);
   LAUNCH_CHECK();
-  k_scan_apply<<<nb, SCAN_NT, 0, st>>>(in, out, (uint32_t)n, bsum);
+  k_scan_apply<<<nb, SCAN_NT, 0, st>>>(in, out, (uint32_t)n, bsum, enable);
   LAUNCH_CHECK();
   return MPSM_OK;
 }
@@ -294,6 +313,10 @@ struct Level {
   // tuples, the buckets of a previous level, or filled in beforehand
   uint32_t run_len = 0;
   const uint32_t* src_bstart = nullptr;
+  // a pass without a histogram (rg.cap set): buckets in sample-sized regions
+  // of dst, read through bsrc (see k_bucket_scatter)
+  Regions rg{};
+  uint32_t* bsrc = nullptr;
   const uint32_t* Gcount() const { return seg.b0 + nseg; }
 };
 
@@ -343,13 +366,14 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
     const uint32_t M = L.NBmax * L.OS;
     if (M <= (uint32_t)(SMP_NT_S * SMP_IPT_S))
       k_sample_splitters<SMP_NT_S, SMP_IPT_S><<<1, SMP_NT_S, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax, L.OS,
-                                                                      L.level_seed, L.spl, seg_src, c.sample);
+                                                                      L.level_seed, L.spl, seg_src, c.sample, L.rg,
+                                                                      sg.b0);
     else
       k_sample_splitters<SMP_NT, SMP_IPT><<<1, SMP_NT, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax, L.OS,
-                                                                L.level_seed, L.spl, seg_src, c.sample);
+                                                                L.level_seed, L.spl, seg_src, c.sample, L.rg, sg.b0);
     LAUNCH_CHECK();
-    k_cost_s_cdf<<<(uint32_t)cdiv((uint64_t)M + 1, 256), 256, 0, st>>>(c.sample, M, c.run_idx, c.run_len, c.Q,
-                                                                      c.idx_per_run, c.stride, c.nS, c.s_below);
+    k_cost_s_cdf<<<(uint32_t)cdiv((uint64_t)M + 1, 4), 256, 0, st>>>(c.sample, M, c.run_idx, c.run_len, c.Q,
+                                                                    c.idx_per_run, c.stride, c.nS, c.s_below);
     LAUNCH_CHECK();
     k_cost_splitters<<<1, COST_NT, 0, st>>>(c.sample, c.s_below, M, c.nR, L.NBmax, c.Q, L.spl, c.best);
     LAUNCH_CHECK();
@@ -360,23 +384,49 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
     if (L.NBmax * L.OS <= (uint32_t)(SMP_NT_S * SMP_IPT_S))
       k_sample_splitters<SMP_NT_S, SMP_IPT_S><<<L.nseg, SMP_NT_S, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax,
                                                                            L.OS, L.level_seed, L.spl, seg_src,
-                                                                           nullptr);
+                                                                           nullptr, L.rg, sg.b0);
     else
       k_sample_splitters<SMP_NT, SMP_IPT><<<L.nseg, SMP_NT, 0, st>>>(src, sg.start, sg.len, sg.nb, L.NBmax, L.OS,
-                                                                     L.level_seed, L.spl, seg_src, nullptr);
+                                                                     L.level_seed, L.spl, seg_src, nullptr, L.rg, sg.b0);
     LAUNCH_CHECK();
   }
   mk.mark(mk0);
+  if (L.rg.cap) {
+    // no histogram: every chunk claims room in its buckets' regions; the
+    // segments where a bucket outgrew its region are redone by the exact
+    // path (histogram, scan, scatter), whose launches end at once when no
+    // segment needs it
+    mk.mark_range(mk0 + 1, mk0 + 2);
+    k_bucket_scatter<true><<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb,
+                                                            L.nseg, L.spl, L.NBmax, HIST_TILE, nullptr, seg_src, L.rg,
+                                                            sg.b0, Redo{nullptr, 0});
+    LAUNCH_CHECK();
+    k_bucket_hist<<<L.max_tiles, HIST_NT, 0, st>>>(src, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb, L.nseg, L.spl,
+                                                   L.NBmax, HIST_TILE, L.cnt, seg_src, L.rg.dirty);
+    LAUNCH_CHECK();
+    mpsm_status rc = scan_u32(L.cnt, L.cnt, L.ncnt, bsum, st, L.rg.any);
+    if (rc != MPSM_OK) return rc;
+    k_bucket_scatter<false><<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb,
+                                                             L.nseg, L.spl, L.NBmax, HIST_TILE, L.cnt, seg_src,
+                                                             Regions{}, nullptr, Redo{L.rg.dirty, L.rg.stride});
+    LAUNCH_CHECK();
+    k_region_table<1024><<<L.nseg, 1024, 0, st>>>(L.nseg, L.NBmax, sg.start, sg.len, sg.nb, sg.b0, L.rg, L.spl,
+                                                  L.bstart, L.bsrc, L.blo, L.bhi);
+    LAUNCH_CHECK();
+    mk.mark(mk0 + 3);
+    return MPSM_OK;
+  }
   if (L.max_tiles) {
     k_bucket_hist<<<L.max_tiles, HIST_NT, 0, st>>>(src, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb, L.nseg, L.spl,
-                                                   L.NBmax, HIST_TILE, L.cnt, seg_src);
+                                                   L.NBmax, HIST_TILE, L.cnt, seg_src, nullptr);
     LAUNCH_CHECK();
     mk.mark(mk0 + 1);
     mpsm_status rc = scan_u32(L.cnt, L.cnt, L.ncnt, bsum, st);
     if (rc != MPSM_OK) return rc;
     mk.mark(mk0 + 2);
-    k_bucket_scatter<<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb, L.nseg,
-                                                      L.spl, L.NBmax, HIST_TILE, L.cnt, seg_src);
+    k_bucket_scatter<false><<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb,
+                                                             L.nseg, L.spl, L.NBmax, HIST_TILE, L.cnt, seg_src,
+                                                             Regions{}, nullptr, Redo{nullptr, 0});
     LAUNCH_CHECK();
   } else {
     mk.mark_range(mk0 + 1, mk0 + 2);
@@ -615,6 +665,15 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       Level LS = make_level(ws, P.segS, P.Q, P.NBs, 0, P.OSs, P.tilesS, P.seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
                             P.bndS, P.Gs);
       LS.run_len = P.L;
+      if (P.padS) {
+        LS.rg.cap = reinterpret_cast<uint32_t*>(ws + P.capS);
+        LS.rg.start = reinterpret_cast<uint32_t*>(ws + P.rstS);
+        LS.rg.fill = reinterpret_cast<uint32_t*>(ws + P.fillS);
+        LS.rg.dirty = reinterpret_cast<uint32_t*>(ws + P.dirtyS);
+        LS.rg.any = reinterpret_cast<uint32_t*>(ctr + 7);   // zeroed by k_init_result
+        LS.rg.stride = P.Lpad;
+        LS.bsrc = reinterpret_cast<uint32_t*>(ws + P.bsrcS);
+      }
       rc = bucket_pass(Sin, T, (uint32_t)P.nS, LS, bsum, st, mk, MK_S_SPL);
       if (rc != MPSM_OK) return rc;
       if (r_side) HIP_TRY(hipEventRecord(side->gate, st));
@@ -631,17 +690,17 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
       uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
       uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
-      k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+      k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.bsrc, LS.blo, LS.bhi, LS.Gcount(),
                                                                    nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
       LAUNCH_CHECK();
-      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(),
+      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.bsrc, LS.blo, LS.bhi, LS.Gcount(),
                                                                         midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
                                                                         soS);
       LAUNCH_CHECK();
-      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, redoS, ctr + 3, bigS, ctr + 0, soS);
+      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, LS.bsrc, redoS, ctr + 3, bigS, ctr + 0, soS);
       LAUNCH_CHECK();
       mk.mark(MK_S_SORT);
-      k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, bigS, ctr + 0, soS);
+      k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, LS.bsrc, bigS, ctr + 0, soS);
       LAUNCH_CHECK();
       mk.mark(MK_S_BIG);
 
@@ -707,11 +766,11 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       // as for S runs: the 2-per-CU sort takes the buckets up to its tile, the
       // larger ones go to the 1-per-CU sort
       uint32_t* midR = reinterpret_cast<uint32_t*>(ws + P.midR);
-      k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<LRf->Gmax, BS_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
+      k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<LRf->Gmax, BS_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, nullptr, LRf->blo,
                                                                         LRf->bhi, LRf->Gcount(), nullptr, nullptr, midR,
                                                                         ctr + 6, redoR, ctr + 4, soR);
       LAUNCH_CHECK();
-      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo,
+      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, nullptr, LRf->blo,
                                                                         LRf->bhi, LRf->Gcount(), midR, ctr + 6, bigR,
                                                                         ctr + 1, redoR, ctr + 4, soR);
       LAUNCH_CHECK();
@@ -719,14 +778,14 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       // (splitter bounds can enclose a gap between key clusters); the rest go
       // to the LSD radix sort
       uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
-      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->blo, LRf->bhi,
+      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, nullptr, LRf->blo, LRf->bhi,
                                                                         LRf->Gcount(), redoR, ctr + 4, bigR, ctr + 1,
                                                                         redoR2, ctr + 5, soR);
       LAUNCH_CHECK();
-      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, redoR2, ctr + 5, bigR, ctr + 1, soR);
+      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, nullptr, redoR2, ctr + 5, bigR, ctr + 1, soR);
       LAUNCH_CHECK();
       mkR.mark(MK_R_SORT);
-      k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, bigR, ctr + 1, soR);
+      k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, nullptr, bigR, ctr + 1, soR);
       LAUNCH_CHECK();
       mkR.mark(MK_R_BIG);
       if (r_side) {   // the rest needs R's partitions
@@ -854,6 +913,11 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     stats->swapped = (uint64_t)P.swapped;
     stats->ms_total = ms;
     stats->pairs_truncated = r.truncated;
+    if (P.padS && P.nR && P.nS) {
+      std::vector<uint32_t> dirty(P.Q);
+      HIP_TRY(hipMemcpy(dirty.data(), ws + P.dirtyS, (size_t)P.Q * 4, hipMemcpyDeviceToHost));
+      for (uint32_t d : dirty) stats->redone_runs += d ? 1 : 0;
+    }
     if (r.truncated) return MPSM_ECAPACITY;
   }
   return MPSM_OK;
@@ -1173,14 +1237,14 @@ mpsm_status batch_enqueue(const mpsm_join_desc* d_descs, const BatchPlan& P, uin
     uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
     uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
     k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<sort_grid_s, BS_NT, 0, st>>>(
-        T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(), nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
+        T, U, LS.bstart, nullptr, LS.blo, LS.bhi, LS.Gcount(), nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
     LAUNCH_CHECK();
     k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(
-        T, U, LS.bstart, LS.blo, LS.bhi, LS.Gcount(), midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3, soS);
+        T, U, LS.bstart, nullptr, LS.blo, LS.bhi, LS.Gcount(), midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3, soS);
     LAUNCH_CHECK();
-    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, redoS, ctr + 3, bigS, ctr + 0, soS);
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, nullptr, redoS, ctr + 3, bigS, ctr + 0, soS);
     LAUNCH_CHECK();
-    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, bigS, ctr + 0, soS);
+    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, nullptr, bigS, ctr + 0, soS);
     LAUNCH_CHECK();
     // phases 2 and 3: one R segment per join, bucket counts from its size
     Level LR = make_level(ws, P.segR, P.n, MAX_NB, P.BT, P.OSr, P.tilesR, seed ^ TAG_R1, P.splR, P.cR, P.cntR,
@@ -1202,17 +1266,17 @@ mpsm_status batch_enqueue(const mpsm_join_desc* d_descs, const BatchPlan& P, uin
     uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
     uint32_t* bigR = reinterpret_cast<uint32_t*>(ws + P.bigR);
     k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<sort_grid_r, BS_NT, 0, rst>>>(
-        Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(), nullptr, nullptr, midR, ctr + 6, redoR, ctr + 4, soR);
+        Rp, Rs, LR.bstart, nullptr, LR.blo, LR.bhi, LR.Gcount(), nullptr, nullptr, midR, ctr + 6, redoR, ctr + 4, soR);
     LAUNCH_CHECK();
     k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(
-        Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(), midR, ctr + 6, bigR, ctr + 1, redoR, ctr + 4, soR);
+        Rp, Rs, LR.bstart, nullptr, LR.blo, LR.bhi, LR.Gcount(), midR, ctr + 6, bigR, ctr + 1, redoR, ctr + 4, soR);
     LAUNCH_CHECK();
     k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(
-        Rp, Rs, LR.bstart, LR.blo, LR.bhi, LR.Gcount(), redoR, ctr + 4, bigR, ctr + 1, redoR2, ctr + 5, soR);
+        Rp, Rs, LR.bstart, nullptr, LR.blo, LR.bhi, LR.Gcount(), redoR, ctr + 4, bigR, ctr + 1, redoR2, ctr + 5, soR);
     LAUNCH_CHECK();
-    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rp, Rs, LR.bstart, redoR2, ctr + 5, bigR, ctr + 1, soR);
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rp, Rs, LR.bstart, nullptr, redoR2, ctr + 5, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
-    k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rp, Rs, LR.bstart, bigR, ctr + 1, soR);
+    k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rp, Rs, LR.bstart, nullptr, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
     // the rest needs R's partitions
     HIP_TRY(hipEventRecord(side->done, rst));

@@ -25,7 +25,8 @@ HOT = {
     "s_sort": "_Z16k_bucket_sort_csILi1024ELi4ELi2048ELi8ELb0ELb0E",
     "r_sort": "_Z16k_bucket_sort_csILi1024ELi8ELi4096ELi1ELb1ELb0E",
     "r_retry": "_Z16k_bucket_sort_csILi1024ELi8ELi4096ELi1ELb1ELb1E",
-    "scatter": "_Z16k_bucket_scatter",
+    "scatter": "_Z16k_bucket_scatterILb0E",
+    "scatter_regions": "_Z16k_bucket_scatterILb1E",
     "hist": "_Z13k_bucket_hist",
     "join": "_Z6k_joinILi0ELi0ELb0E",
     "search": "_Z8k_search",
