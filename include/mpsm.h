@@ -102,7 +102,8 @@ typedef struct mpsm_config {
   uint32_t bucket_target;  /* mean tuples per sort bucket / R partition, 256..4096 */
   uint32_t join_chunk;     /* S tuples per join work item, 1024..261888 */
   uint32_t want_max;       /* 1: also compute max(R.payload + S.payload) (Section 5.1 query) */
-  uint32_t oversample;     /* sample keys drawn per bucket for the splitters, 1..64 */
+  uint32_t oversample;     /* sample keys drawn per bucket for the splitters of every level, 1..64
+                              (0: 32 for S's runs and R's first level, 16 for R's second) */
   uint32_t waves;          /* batches only: waves the joins are taken in, 1..64 (see mpsm_join_batch) */
   uint64_t seed;           /* seed of the splitter samples */
 } mpsm_config;
@@ -126,6 +127,8 @@ typedef struct mpsm_stats {
   uint64_t pairs_truncated;   /* 1 if pairs were requested and the join has more than pairs_capacity */
   uint64_t redone_runs;       /* S runs whose bucket regions overflowed and were scattered again exactly
                                  (large S only: smaller S takes the exact path directly) */
+  uint64_t redone_r_segments; /* the same for R: first-level buckets redone at the second level (large R with
+                                 two levels), or R runs (large R, MPSM_SPLIT_NONE) */
 } mpsm_stats;
 
 /* Fill *cfg with defaults (all automatic, role AUTO, sampled splitters,
@@ -220,7 +223,9 @@ typedef struct mpsm_layout {
   uint32_t idx_stride;       /* equi-height index: every idx_stride-th key of a run */
   uint64_t off_run_index;    /* runs * idx_per_run u64 */
   uint32_t idx_per_run;
-  uint32_t reserved;
+  uint32_t padded_passes;    /* bucket passes without a histogram (sample-sized regions, exact redo on
+                                overflow): bit 0 S's runs, bit 1 R's runs (MPSM_SPLIT_NONE), bit 2 R's
+                                second level */
   uint64_t off_join_span;    /* P u8: partitions joined together starting at p (2: p and p+1 share an LDS
                                 tile; 1: p alone; 0: p is the second of a pair) */
   /* splitter COST only: */

@@ -43,7 +43,8 @@ class MpsmStats(ctypes.Structure):
                 ("search_fallbacks", ctypes.c_uint64), ("max_partition", ctypes.c_uint64),
                 ("cdf_eps_r", ctypes.c_double), ("cdf_eps_s", ctypes.c_double),
                 ("resorted_buckets", ctypes.c_uint64), ("retried_buckets", ctypes.c_uint64),
-                ("pairs_truncated", ctypes.c_uint64), ("redone_runs", ctypes.c_uint64)]
+                ("pairs_truncated", ctypes.c_uint64), ("redone_runs", ctypes.c_uint64),
+                ("redone_r_segments", ctypes.c_uint64)]
 
 
 class MpsmLayout(ctypes.Structure):
@@ -60,7 +61,7 @@ class MpsmLayout(ctypes.Structure):
                 ("off_part_start", ctypes.c_uint64), ("off_part_len", ctypes.c_uint64),
                 ("off_part_key", ctypes.c_uint64), ("off_offsets", ctypes.c_uint64), ("p_max", ctypes.c_uint32),
                 ("idx_stride", ctypes.c_uint32), ("off_run_index", ctypes.c_uint64),
-                ("idx_per_run", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("idx_per_run", ctypes.c_uint32), ("padded_passes", ctypes.c_uint32),
                 ("off_join_span", ctypes.c_uint64), ("off_cost_sample", ctypes.c_uint64),
                 ("off_cost_s_below", ctypes.c_uint64), ("off_cost_best", ctypes.c_uint64),
                 ("cost_cells", ctypes.c_uint32), ("reserved2", ctypes.c_uint32)]

@@ -55,6 +55,21 @@ __device__ __forceinline__ void store_tup(tup_t* p, tup_t t) {
   *reinterpret_cast<ulonglong2*>(p) = v;
 }
 
+// The workgroups of a launch are handed to the 8 XCDs in turn (workgroup
+// b to XCD b mod 8), and each XCD has its own L2.  xcd_item gives workgroup b
+// the k-th item (k = b / 8) of its XCD's contiguous share of n items, so
+// that neighbouring items (the tiles of one segment, the buckets of one
+// run), whose outputs share cache lines at their ends, run on one XCD and
+// those lines are completed in its L2 before they are written back.  A
+// bijection of [0, n) for any grid of at least n workgroups; workgroups
+// without an item get n.
+constexpr uint32_t N_XCD = 8;
+__device__ __forceinline__ uint32_t xcd_item(uint32_t b, uint32_t n) {
+  const uint32_t x = b % N_XCD, k = b / N_XCD, per = n / N_XCD, rem = n % N_XCD;
+  const uint32_t cnt = per + (x < rem ? 1u : 0u);
+  return k < cnt ? x * per + (x < rem ? x : rem) + k : n;
+}
+
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 // Inclusive scan of a u32 across the 64 lanes of a wave, with DPP lane

@@ -214,9 +214,9 @@ __global__ void __launch_bounds__(SCAN_NT) k_scan_apply(const uint32_t* in, uint
 // becomes key + 1 when that is below it; along a run of such splitters
 // every other one moves (a moved splitter no longer carries its key).
 //
-// With regions (a bucket pass without a histogram, see k_bucket_scatter_padded)
+// With regions (a bucket pass without a histogram, see k_bucket_scatter)
 // the kernel also sizes every bucket's region of the segment's area
-// (reg.stride tuples from s * reg.stride): from the sample keys c that fall
+// (pad_area of its start up to pad_area of its end): from the sample keys c that fall
 // in the bucket (by the final splitters and the bucket function), an upper
 // bound on its tuples, len/M (c + 4 sqrt(c) + 10) + 16 (the sample count is
 // about Poisson with mean len/M of the bucket's size; the bound holds except
@@ -229,15 +229,22 @@ struct Regions {
   uint32_t* fill;    // per global bucket: tuples claimed (zeroed here)
   uint32_t* dirty;   // per segment: 1 if a bucket outgrew its region (zeroed here)
   uint32_t* any;     // 1 if any segment is dirty (zeroed by the call's init)
-  uint32_t stride;   // area of a segment
 };
 
+// Area of a padded pass: the segment that starts at (compact) position x
+// has its regions from pad_area(x) up to pad_area of its end, 2.75 times
+// its length rounded to 64 tuples, so the areas of consecutive segments
+// tile the padded array in order.
+__host__ __device__ inline uint64_t pad_area(uint64_t x) { return ((x * 11) / 4 + 63) & ~63ull; }
+
 template <int NT>
-__device__ void size_regions(const Regions& rg, uint32_t s, uint32_t g0, uint32_t nb, uint32_t len, uint32_t M,
-                             const uint32_t* bcnt, uint32_t* wsum, uint64_t* red) {
+__device__ void size_regions(const Regions& rg, uint32_t s, uint32_t g0, uint32_t nb, uint32_t start, uint32_t len,
+                             uint32_t M, const uint32_t* bcnt, uint32_t* wsum, uint64_t* red) {
   constexpr int PER = (MAX_NB + NT - 1) / NT;
   const uint32_t tid = threadIdx.x;
   const float scale = M ? (float)len / (float)M : 0.f;
+  const uint64_t base = pad_area(start);
+  const uint32_t area = (uint32_t)(pad_area((uint64_t)start + len) - base);
   uint32_t c[PER];
   uint64_t tot = 0;
 #pragma unroll
@@ -247,22 +254,21 @@ __device__ void size_regions(const Regions& rg, uint32_t s, uint32_t g0, uint32_
     if (b < nb) {
       const float x = (float)bcnt[b];
       const float bound = nb == 1 ? (float)len : scale * (x + 4.f * __builtin_sqrtf(x) + 10.f) + 16.f;
-      c[q] = bound >= (float)rg.stride ? rg.stride : (uint32_t)bound + 1u;
+      c[q] = bound >= (float)area ? area : (uint32_t)bound + 1u;
       tot += c[q];
     }
   }
   tot = block_sum64<NT>(tot, red);
   // fit the area: scale every region down by the same factor
-  if (tot > rg.stride) {
+  if (tot > area) {
 #pragma unroll
-    for (int q = 0; q < PER; q++) c[q] = (uint32_t)((uint64_t)c[q] * rg.stride / tot);
+    for (int q = 0; q < PER; q++) c[q] = (uint32_t)((uint64_t)c[q] * area / tot);
   }
   uint32_t run = 0, loc[PER];
 #pragma unroll
   for (int q = 0; q < PER; q++) { loc[q] = run; run += c[q]; }
   uint32_t all;
   const uint32_t ex = block_excl_scan<NT>(run, wsum, &all);
-  const uint64_t base = (uint64_t)s * rg.stride;
 #pragma unroll
   for (int q = 0; q < PER; q++) {
     const uint32_t b = tid * PER + q;
@@ -293,7 +299,7 @@ __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict
     if (rg.cap) {   // one bucket holds the segment (or nothing)
       for (uint32_t b = tid; b < MAX_NB; b += NT) bcnt[b] = 0;
       __syncthreads();
-      size_regions<NT>(rg, s, seg_b0[s], nb, len, 0, bcnt, wsum, red);
+      size_regions<NT>(rg, s, seg_b0[s], nb, start, len, 0, bcnt, wsum, red);
     }
     return;
   }
@@ -349,7 +355,7 @@ __global__ void __launch_bounds__(NT) k_sample_splitters(const tup_t* __restrict
   __syncthreads();
   for (uint32_t r = tid; r < M; r += NT) atomicAdd(&bcnt[bucket_of(lspl, nb - 1, buf[r])], 1u);
   __syncthreads();
-  size_regions<NT>(rg, s, seg_b0[s], nb, len, M, bcnt, wsum, red);
+  size_regions<NT>(rg, s, seg_b0[s], nb, start, len, M, bcnt, wsum, red);
 }
 
 // ------------------------------------------------- cost-balanced splitters
@@ -563,11 +569,10 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
 // dirty.  The tuples of a bucket then sit at the start of its region in
 // the order of the claims.
 // redo (not PAD, redo.dirty set): only dirty segments are scattered, each
-// compactly from the start of its own area (s * redo.stride), by the
+// compactly from the start of its own area (pad_area of its start), by the
 // scanned counts of its own tiles.
 struct Redo {
   const uint32_t* dirty;   // per segment, or NULL: every segment, at the scanned positions
-  uint32_t stride;
 };
 constexpr uint32_t NO_ROOM = 0xFFFFFFFFu;
 
@@ -584,7 +589,9 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   __shared__ tup_t stage[SCAT_CH];
   __shared__ uint32_t wsum[SCAT_NT / 64 + 2];
   __shared__ SplitDir<SPLIT_DIR, MAX_NB> dir;
-  const uint32_t g = blockIdx.x, tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x;
+  // the tiles of a segment write neighbouring pieces of its buckets: one XCD takes them
+  const uint32_t g = xcd_item(blockIdx.x, seg_tile0[nseg]);
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
   if (!PAD && redo.dirty && !redo.dirty[s]) return;
@@ -603,7 +610,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
     const uint32_t* p = pos + seg_cnt0[s] + t;
     // redo: positions relative to the segment's first count, from its own area
     const uint32_t rel = redo.dirty ? pos[seg_cnt0[s]] : 0u;
-    const uint32_t base = redo.dirty ? s * redo.stride : 0u;
+    const uint32_t base = redo.dirty ? (uint32_t)pad_area(seg_start[s]) : 0u;
     for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] = base + (p[(uint64_t)i * ntiles] - rel); lcnt[i] = 0; }
   }
   __syncthreads();
@@ -730,8 +737,8 @@ template <int NT>
 __global__ void __launch_bounds__(NT) k_region_table(uint32_t nseg, uint32_t NBmax, const uint32_t* seg_start,
                                                      const uint32_t* seg_len, const uint32_t* seg_nb,
                                                      const uint32_t* seg_b0, Regions rg, const uint64_t* spl,
-                                                     uint32_t* bstart, uint32_t* bsrc, uint64_t* blo,
-                                                     uint64_t* bhi) {
+                                                     const uint64_t* outer, uint32_t outer_nspl, uint32_t* bstart,
+                                                     uint32_t* bsrc, uint64_t* blo, uint64_t* bhi) {
   constexpr int PER = (MAX_NB + NT - 1) / NT;
   __shared__ uint32_t wsum[NT / 64 + 2];
   const uint32_t s = blockIdx.x, tid = threadIdx.x;
@@ -754,9 +761,9 @@ __global__ void __launch_bounds__(NT) k_region_table(uint32_t nseg, uint32_t NBm
     if (b < nb) {
       const uint32_t g = g0 + b, pre = loc[q] + ex;
       bstart[g] = seg_start[s] + pre;
-      bsrc[g] = redone ? s * rg.stride + pre : rg.start[g];
-      blo[g] = b > 0 ? sp[b - 1] : 0ull;
-      bhi[g] = b + 1 < nb ? sp[b] : ~0ull;
+      bsrc[g] = redone ? (uint32_t)pad_area(seg_start[s]) + pre : rg.start[g];
+      blo[g] = b > 0 ? sp[b - 1] : ((outer && s > 0) ? outer[s - 1] : 0ull);
+      bhi[g] = b + 1 < nb ? sp[b] : ((outer && s < outer_nspl) ? outer[s] : ~0ull);
     }
   }
   if (s == nseg - 1 && tid == 0) bstart[g0 + nb] = seg_start[s] + seg_len[s];
@@ -897,7 +904,11 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
   uint32_t* const anyf = lds.anyf;
   const uint32_t tid = threadIdx.x;
   const uint32_t nitems = in_list ? (uint32_t)*in_count : *Gcount;
-  for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+  // a grid of one workgroup per bucket takes the buckets XCD by XCD
+  // (neighbouring buckets share an output line); a smaller grid strides
+  const bool once = !in_list && gridDim.x >= nitems;
+  for (uint32_t it = once ? xcd_item(blockIdx.x, nitems) : blockIdx.x; it < nitems;
+       it += once ? nitems : gridDim.x) {
     const uint32_t g = in_list ? in_list[it] : it;
     const uint32_t a = bstart[g], n = bstart[g + 1] - a;
     if (n == 0) continue;

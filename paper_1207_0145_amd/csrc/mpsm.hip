@@ -37,8 +37,9 @@ struct Plan {
   uint32_t L, Q, NBs, OSs;
   uint32_t levels, NB1, OS1, NB2, OS2;
   uint32_t QR;                 // B-MPSM (no range partitioning): sorted R runs of L tuples
-  int padS;                    // S's bucket pass without a histogram: runs in areas of Lpad tuples
-  uint32_t Lpad;
+  // bucket passes without a histogram (sample-sized regions in areas of
+  // pad_area tuples): S's runs, R's runs (B-MPSM), R's second level
+  int padS, padR1, padR2;
   uint32_t Gs, Gr, Pmax;
   uint32_t idx_per_run;
   uint32_t JCH, BT;
@@ -60,6 +61,8 @@ struct Plan {
   uint64_t cdf_chunks, cdf_sorted, modelR, modelS;  // learned CDF samples and models
   uint64_t cost_sample, cost_s_below, cost_best;   // cost-balanced splitters
   uint64_t capS, rstS, fillS, bsrcS, dirtyS;        // S's regions (padS)
+  uint64_t capR1, rstR1, fillR1, bsrcR1, dirtyR1;   // R's level-1 regions (padR1)
+  uint64_t capR2, rstR2, fillR2, bsrcR2, dirtyR2;   // R's level-2 regions (padR2)
   uint64_t total;
 };
 
@@ -151,7 +154,8 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
     if (P->splitter == MPSM_SPLIT_COST || P->NB2 > (uint32_t)MAX_NB) P->NB2 = MAX_NB;
     // 16 samples per level-2 bucket (the larger sample sort when NB2 > 128):
     // with 4, bucket sizes spread so far that about 1% exceed the LDS tile
-    P->OS2 = SMP_CAP / P->NB2 < 16u ? SMP_CAP / P->NB2 : 16u;
+    const uint32_t OS2req = cfg->oversample ? cfg->oversample : 16u;
+    P->OS2 = SMP_CAP / P->NB2 < OS2req ? SMP_CAP / P->NB2 : OS2req;
   }
   P->Gs = P->Q * P->NBs;
   P->Gr = P->QR * P->NB1 * P->NB2;
@@ -167,19 +171,26 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->cntR2 = P->levels == 2 ? (uint64_t)P->tilesR2 * P->NB2 : 1;
   P->item_cap = P->nS / P->JCH + P->Pmax + 2;
 
-  // S's runs are scattered into sample-sized bucket regions without a
-  // histogram pass when S is large enough for that pass to matter; each run
-  // gets an area of 2.75 L tuples (the regions' bound is about 2.5 times a
-  // bucket's mean size)
-  P->Lpad = (uint32_t)((((uint64_t)P->L * 11) / 4 + 63) & ~63ull);
-  P->padS = P->nS >= (1u << 22) && (uint64_t)P->Q * P->Lpad < (1ull << 32);
+  // Bucket passes scatter into sample-sized bucket regions without a
+  // histogram pass when the relation is large enough for that pass to
+  // matter; every segment gets an area of 2.75 times its length (the
+  // regions' bound is about 2.5 times a bucket's mean size).  Every chunk
+  // claims its room by one atomic per bucket, so the pass needs many
+  // segments (S's runs, B-MPSM's R runs, R's level-1 buckets at the second
+  // level): R's first level is one segment, all of R, and there the claims
+  // of every chunk meet on the same 256 counters (measured: its scatter
+  // 3x slower than histogram and scatter together).
+  const bool big_r = P->nR >= (1u << 22) && pad_area(P->nR) < (1ull << 32);
+  P->padS = P->nS >= (1u << 22) && pad_area(P->nS) < (1ull << 32);
+  P->padR1 = big_r && P->splitter == MPSM_SPLIT_NONE;
+  P->padR2 = big_r && P->levels == 2;
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) { uint64_t o = off; off += (bytes + 255) & ~255ull; return o; };
   const uint64_t ts = sizeof(tup_t);
-  P->T = take((P->padS ? (uint64_t)P->Q * P->Lpad : P->nS) * ts);
+  P->T = take((P->padS ? pad_area(P->nS) : P->nS) * ts);
   P->U = take(P->nS * ts);
-  P->R1 = take(P->nR * ts);
-  P->R2 = take(P->nR * ts);
+  P->R1 = take((P->padR1 ? pad_area(P->nR) : P->nR) * ts);
+  P->R2 = take((P->padR2 ? pad_area(P->nR) : P->nR) * ts);
   P->cS = take(P->cntS * 4);
   P->cR1 = take(P->cntR1 * 4);
   P->cR2 = take(P->cntR2 * 4);
@@ -208,7 +219,7 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->redoR = take((uint64_t)P->Gr * 4);
   P->redoR2 = take((uint64_t)P->Gr * 4);
   P->bigR = take((uint64_t)P->Gr * 4);
-  P->ctr = take(8 * 8);
+  P->ctr = take(16 * 8);
   P->bkey = take((uint64_t)P->Gr * 8);
   P->Pc = take(4);
   P->pstart = take((uint64_t)P->Pmax * 4);
@@ -234,6 +245,21 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
     P->fillS = take((uint64_t)P->Gs * 4);
     P->bsrcS = take(((uint64_t)P->Gs + 1) * 4);
     P->dirtyS = take((uint64_t)P->Q * 4);
+  }
+  if (P->padR1) {
+    const uint64_t g1 = (uint64_t)P->QR * P->NB1;
+    P->capR1 = take(g1 * 4);
+    P->rstR1 = take(g1 * 4);
+    P->fillR1 = take(g1 * 4);
+    P->bsrcR1 = take((g1 + 1) * 4);
+    P->dirtyR1 = take((uint64_t)P->QR * 4);
+  }
+  if (P->padR2) {
+    P->capR2 = take((uint64_t)P->Gr * 4);
+    P->rstR2 = take((uint64_t)P->Gr * 4);
+    P->fillR2 = take((uint64_t)P->Gr * 4);
+    P->bsrcR2 = take(((uint64_t)P->Gr + 1) * 4);
+    P->dirtyR2 = take((uint64_t)P->NB1 * 4);
   }
   P->res = take(sizeof(Result));
   P->total = off;
@@ -399,7 +425,7 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
     mk.mark_range(mk0 + 1, mk0 + 2);
     k_bucket_scatter<true><<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb,
                                                             L.nseg, L.spl, L.NBmax, HIST_TILE, nullptr, seg_src, L.rg,
-                                                            sg.b0, Redo{nullptr, 0});
+                                                            sg.b0, Redo{nullptr});
     LAUNCH_CHECK();
     k_bucket_hist<<<L.max_tiles, HIST_NT, 0, st>>>(src, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb, L.nseg, L.spl,
                                                    L.NBmax, HIST_TILE, L.cnt, seg_src, L.rg.dirty);
@@ -408,10 +434,10 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
     if (rc != MPSM_OK) return rc;
     k_bucket_scatter<false><<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb,
                                                              L.nseg, L.spl, L.NBmax, HIST_TILE, L.cnt, seg_src,
-                                                             Regions{}, nullptr, Redo{L.rg.dirty, L.rg.stride});
+                                                             Regions{}, nullptr, Redo{L.rg.dirty});
     LAUNCH_CHECK();
     k_region_table<1024><<<L.nseg, 1024, 0, st>>>(L.nseg, L.NBmax, sg.start, sg.len, sg.nb, sg.b0, L.rg, L.spl,
-                                                  L.bstart, L.bsrc, L.blo, L.bhi);
+                                                  L.outer, L.outer_nspl, L.bstart, L.bsrc, L.blo, L.bhi);
     LAUNCH_CHECK();
     mk.mark(mk0 + 3);
     return MPSM_OK;
@@ -426,7 +452,7 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
     mk.mark(mk0 + 2);
     k_bucket_scatter<false><<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb,
                                                              L.nseg, L.spl, L.NBmax, HIST_TILE, L.cnt, seg_src,
-                                                             Regions{}, nullptr, Redo{nullptr, 0});
+                                                             Regions{}, nullptr, Redo{nullptr});
     LAUNCH_CHECK();
   } else {
     mk.mark_range(mk0 + 1, mk0 + 2);
@@ -553,6 +579,7 @@ mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* c
   out->idx_stride = IDX_STRIDE;
   out->off_run_index = P.ridx;
   out->idx_per_run = P.idx_per_run;
+  out->padded_passes = (P.padS ? 1u : 0u) | (P.padR1 ? 2u : 0u) | (P.padR2 ? 4u : 0u);
   out->off_join_span = P.span;
   out->off_cost_sample = P.cost_sample;
   out->off_cost_s_below = P.cost_s_below;
@@ -628,7 +655,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
   CdfModel* modelS = reinterpret_cast<CdfModel*>(ws + P.modelS);
   auto enqueue = [&]() -> mpsm_status {
     mk.mark(MK_START);
-    k_init_result<<<1, 64, 0, st>>>(res, reinterpret_cast<uint32_t*>(ctr), 16);
+    k_init_result<<<1, 64, 0, st>>>(res, reinterpret_cast<uint32_t*>(ctr), 32);
     LAUNCH_CHECK();
     mk.mark(MK_INIT);
     // The side stream may start from here (fork); its kernels are enqueued
@@ -665,15 +692,18 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       Level LS = make_level(ws, P.segS, P.Q, P.NBs, 0, P.OSs, P.tilesS, P.seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
                             P.bndS, P.Gs);
       LS.run_len = P.L;
-      if (P.padS) {
-        LS.rg.cap = reinterpret_cast<uint32_t*>(ws + P.capS);
-        LS.rg.start = reinterpret_cast<uint32_t*>(ws + P.rstS);
-        LS.rg.fill = reinterpret_cast<uint32_t*>(ws + P.fillS);
-        LS.rg.dirty = reinterpret_cast<uint32_t*>(ws + P.dirtyS);
-        LS.rg.any = reinterpret_cast<uint32_t*>(ctr + 7);   // zeroed by k_init_result
-        LS.rg.stride = P.Lpad;
-        LS.bsrc = reinterpret_cast<uint32_t*>(ws + P.bsrcS);
-      }
+      // regions of a pass without a histogram; `any` is a word of ctr,
+      // which k_init_result zeroes
+      auto regions = [&](Level& Lv, uint64_t cap, uint64_t rst, uint64_t fill, uint64_t dirty, uint64_t bsrc,
+                         uint32_t any_word) {
+        Lv.rg.cap = reinterpret_cast<uint32_t*>(ws + cap);
+        Lv.rg.start = reinterpret_cast<uint32_t*>(ws + rst);
+        Lv.rg.fill = reinterpret_cast<uint32_t*>(ws + fill);
+        Lv.rg.dirty = reinterpret_cast<uint32_t*>(ws + dirty);
+        Lv.rg.any = reinterpret_cast<uint32_t*>(ctr + any_word);
+        Lv.bsrc = reinterpret_cast<uint32_t*>(ws + bsrc);
+      };
+      if (P.padS) regions(LS, P.capS, P.rstS, P.fillS, P.dirtyS, P.bsrcS, 7);
       rc = bucket_pass(Sin, T, (uint32_t)P.nS, LS, bsum, st, mk, MK_S_SPL);
       if (rc != MPSM_OK) return rc;
       if (r_side) HIP_TRY(hipEventRecord(side->gate, st));
@@ -731,6 +761,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       uint32_t* const rbsum = r_side ? reinterpret_cast<uint32_t*>(ws + P.bsumR) : bsum;
       Marker mkR{events, n_events, rst};
       LR1.run_len = bmpsm ? P.L : (uint32_t)P.nR;   // B-MPSM: R runs; else one segment, all of R
+      if (P.padR1) regions(LR1, P.capR1, P.rstR1, P.fillR1, P.dirtyR1, P.bsrcR1, 8);
       rc = bucket_pass(Rin, R1, (uint32_t)P.nR, LR1, rbsum, rst, mkR, MK_R1_SPL);
       if (rc != MPSM_OK) return rc;
       SortOut soR;
@@ -755,6 +786,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
         LR2.outer_nspl = P.NB1 - 1;
         // the second level stays sampled: its buckets are finer than the model's knots
         LR2.src_bstart = LR1.bstart;   // segments: the level-1 buckets
+        if (P.padR2) regions(LR2, P.capR2, P.rstR2, P.fillR2, P.dirtyR2, P.bsrcR2, 9);
         rc = bucket_pass(R1, R2, (uint32_t)P.nR, LR2, rbsum, rst, mkR, MK_R2_SPL);
         if (rc != MPSM_OK) return rc;
         LRf = &LR2;
@@ -766,11 +798,11 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       // as for S runs: the 2-per-CU sort takes the buckets up to its tile, the
       // larger ones go to the 1-per-CU sort
       uint32_t* midR = reinterpret_cast<uint32_t*>(ws + P.midR);
-      k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<LRf->Gmax, BS_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, nullptr, LRf->blo,
+      k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<LRf->Gmax, BS_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->bsrc, LRf->blo,
                                                                         LRf->bhi, LRf->Gcount(), nullptr, nullptr, midR,
                                                                         ctr + 6, redoR, ctr + 4, soR);
       LAUNCH_CHECK();
-      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, nullptr, LRf->blo,
+      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->bsrc, LRf->blo,
                                                                         LRf->bhi, LRf->Gcount(), midR, ctr + 6, bigR,
                                                                         ctr + 1, redoR, ctr + 4, soR);
       LAUNCH_CHECK();
@@ -778,14 +810,14 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       // (splitter bounds can enclose a gap between key clusters); the rest go
       // to the LSD radix sort
       uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
-      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, nullptr, LRf->blo, LRf->bhi,
+      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->bsrc, LRf->blo, LRf->bhi,
                                                                         LRf->Gcount(), redoR, ctr + 4, bigR, ctr + 1,
                                                                         redoR2, ctr + 5, soR);
       LAUNCH_CHECK();
-      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, nullptr, redoR2, ctr + 5, bigR, ctr + 1, soR);
+      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->bsrc, redoR2, ctr + 5, bigR, ctr + 1, soR);
       LAUNCH_CHECK();
       mkR.mark(MK_R_SORT);
-      k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, nullptr, bigR, ctr + 1, soR);
+      k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->bsrc, bigR, ctr + 1, soR);
       LAUNCH_CHECK();
       mkR.mark(MK_R_BIG);
       if (r_side) {   // the rest needs R's partitions
@@ -913,11 +945,18 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     stats->swapped = (uint64_t)P.swapped;
     stats->ms_total = ms;
     stats->pairs_truncated = r.truncated;
-    if (P.padS && P.nR && P.nS) {
-      std::vector<uint32_t> dirty(P.Q);
-      HIP_TRY(hipMemcpy(dirty.data(), ws + P.dirtyS, (size_t)P.Q * 4, hipMemcpyDeviceToHost));
-      for (uint32_t d : dirty) stats->redone_runs += d ? 1 : 0;
-    }
+    // segments the exact path redid, from the dirty flags of each pass without a histogram
+    auto redone = [&](bool on, uint64_t off, uint32_t nseg, uint64_t* out) -> mpsm_status {
+      if (!on || !P.nR || !P.nS) return MPSM_OK;
+      std::vector<uint32_t> dirty(nseg);
+      HIP_TRY(hipMemcpy(dirty.data(), ws + off, (size_t)nseg * 4, hipMemcpyDeviceToHost));
+      for (uint32_t d : dirty) *out += d ? 1 : 0;
+      return MPSM_OK;
+    };
+    mpsm_status rr = redone(P.padS, P.dirtyS, P.Q, &stats->redone_runs);
+    if (rr == MPSM_OK) rr = redone(P.padR1, P.dirtyR1, P.QR, &stats->redone_r_segments);
+    if (rr == MPSM_OK) rr = redone(P.padR2, P.dirtyR2, P.NB1, &stats->redone_r_segments);
+    if (rr != MPSM_OK) return rr;
     if (r.truncated) return MPSM_ECAPACITY;
   }
   return MPSM_OK;

@@ -784,3 +784,68 @@ def test_padded_s_scatter_and_its_exact_redo(oversample, expect_redo):
         a, b = j * L, (j + 1) * L
         x, y = U[a:b], ref[a:b]
         assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], y[np.lexsort((y[:, 1], y[:, 0]))]), j
+
+
+@pytest.mark.parametrize("form,oversample", [("sampled", 0), ("sampled", 2), ("learned", 0), ("learned", 3)])
+def test_padded_r_levels_and_their_exact_redo(form, oversample):
+    """|R| = 2^23 takes two partitioning levels; the second (one segment
+    per first-level bucket) has no histogram.  Few sample keys per bucket
+    make regions overflow and segments go through the exact path.  R sorted
+    and its partitions must equal the oracle's, and the join the
+    foreign-key closed form."""
+    w = workloads.fk_uniform(1 << 23, 1 << 24, seed=0x1207014500000b01, spread=True)
+    fk = oracle.fk_closed_form(w.R, w.S, w.partner)
+    kw = dict(splitter=mpsm.SPLIT_LEARNED) if form == "learned" else {}
+    cfg = mpsm.config(oversample=oversample, **kw)
+    lay = mpsm.layout(len(w.R), len(w.S), cfg)
+    assert lay["levels"] == 2
+    assert lay["padded_passes"] == 5
+    ws = mpsm.alloc_workspace(len(w.R), len(w.S), cfg)
+    _say(f"padded R levels: form {form}, oversample {oversample}")
+    got = mpsm.join(_dev(w.R), _dev(w.S), cfg, workspace=ws, with_stats=True)
+    assert (got["count"], got["checksum"]) == (fk.count, fk.checksum)
+    _say(f"redone: S runs {got['stats']['redone_runs']}, R segments {got['stats']['redone_r_segments']}")
+    if oversample == 2:
+        assert got["stats"]["redone_r_segments"] > 0
+    torch.cuda.synchronize()
+    nR = len(w.R)
+    Rsorted = _ws_view(ws, lay["off_r_sorted"], 2 * nR, np.uint64).reshape(-1, 2)
+    ref_R = oracle.sort_by_key(w.R)
+    assert np.array_equal(Rsorted[:, 0], ref_R[:, 0])
+    assert np.array_equal(Rsorted[np.lexsort((Rsorted[:, 1], Rsorted[:, 0]))],
+                          ref_R[np.lexsort((ref_R[:, 1], ref_R[:, 0]))])
+    P = int(_ws_view(ws, lay["off_partitions"], 1, np.uint32)[0])
+    pstart = _ws_view(ws, lay["off_part_start"], P, np.uint32).astype(np.int64)
+    plen = _ws_view(ws, lay["off_part_len"], P, np.uint32).astype(np.int64)
+    assert pstart[0] == 0 and np.all(pstart[1:] == pstart[:-1] + plen[:-1]) and pstart[-1] + plen[-1] == nR
+    assert np.all(Rsorted[pstart[1:] - 1, 0] < Rsorted[pstart[1:], 0])
+    # level-1 bucket starts (compact positions, whether or not the pass had
+    # regions): the sorted R falls into the level-1 buckets in order, each
+    # bucket's keys within its splitters
+    NB1 = lay["r_buckets1"]
+    spl1 = _ws_view(ws, lay["off_r_splitters1"], NB1 - 1, np.uint64)
+    bst1 = _ws_view(ws, lay["off_r_bucket_start1"], NB1 + 1, np.uint32).astype(np.int64)
+    assert bst1[0] == 0 and bst1[-1] == nR and np.all(np.diff(bst1) >= 0)
+    for b in range(NB1):
+        keys = Rsorted[bst1[b]:bst1[b + 1], 0]
+        if len(keys):
+            assert b == 0 or keys[0] >= spl1[b - 1], b
+            assert b == NB1 - 1 or keys[-1] <= spl1[b], b
+
+
+@pytest.mark.parametrize("oversample", [0, 2])
+def test_padded_bmpsm_runs(oversample):
+    """B-MPSM with |R| = 2^22: R's runs, like S's, without a histogram; with
+    2 sample keys per bucket runs of both are redone by the exact path."""
+    w = workloads.fk_uniform(1 << 22, 1 << 22, seed=0x1207014500000c01, spread=True)
+    fk = oracle.fk_closed_form(w.R, w.S, w.partner)
+    cfg = mpsm.config(splitter=mpsm.SPLIT_NONE, role=mpsm.ROLE_AS_GIVEN, oversample=oversample, log2_run_len=20)
+    lay = mpsm.layout(len(w.R), len(w.S), cfg)
+    assert lay["padded_passes"] == 3
+    _say(f"padded B-MPSM runs: oversample {oversample}")
+    got = mpsm.join(_dev(w.R), _dev(w.S), cfg, with_stats=True)
+    assert (got["count"], got["checksum"]) == (fk.count, fk.checksum)
+    st = got["stats"]
+    _say(f"redone: S runs {st['redone_runs']}, R runs {st['redone_r_segments']}")
+    if oversample == 2:
+        assert st["redone_runs"] > 0 and st["redone_r_segments"] > 0
