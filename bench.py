@@ -37,8 +37,11 @@ METRIC = "join throughput (M tuples/s of |R|+|S|) + % HBM roofline; learned vs p
 # S's histogram pass is folded into its scatter on large inputs (the step
 # then only redoes runs whose bucket regions overflowed): no bytes of its own
 STEP_BYTES = {
+    # S's and R's second-level histograms are folded into their scatters
+    # (large inputs): the steps remain as the exact redo of overflowing
+    # segments, with nothing to do when every bucket fit its region
     "s_histogram": ("S", 0), "s_scatter": ("S", 32), "s_bucket_sort": ("S", 32),
-    "r1_histogram": ("R", 16), "r1_scatter": ("R", 32), "r2_histogram": ("R", 16), "r2_scatter": ("R", 32),
+    "r1_histogram": ("R", 16), "r1_scatter": ("R", 32), "r2_histogram": ("R", 0), "r2_scatter": ("R", 32),
     "r_bucket_sort": ("R", 32), "join": ("RS", 16),
 }
 KERNEL_OF_STEP = {
@@ -79,13 +82,15 @@ WORKLOAD_KEYS = {
 
 # launch steps -> (kernel name prefix, occurrence of that kernel inside one join)
 STEP_DISPATCH = {
-    # S: the scatter into regions, then the exact path's histogram and
-    # scatter for runs whose regions overflowed (launched always, most often
-    # with nothing to do)
+    # S and R's second level: the scatter into regions, then the exact
+    # path's histogram and scatter for segments whose regions overflowed
+    # (launched always, most often with nothing to do); R's first level: the
+    # exact path
     "s_histogram": ("k_bucket_hist", 0),
     "s_scatter": [("void k_bucket_scatter<true>", 0), ("void k_bucket_scatter<false>", 0)],
     "r1_histogram": ("k_bucket_hist", 1), "r1_scatter": ("void k_bucket_scatter<false>", 1),
-    "r2_histogram": ("k_bucket_hist", 2), "r2_scatter": ("void k_bucket_scatter<false>", 2),
+    "r2_histogram": ("k_bucket_hist", 2),
+    "r2_scatter": [("void k_bucket_scatter<true>", 1), ("void k_bucket_scatter<false>", 2)],
     # the sorts: the two-per-CU kernel, then the one-per-CU kernel over the larger buckets
     "s_bucket_sort": [("void k_bucket_sort_cs<1024, 4", 0), ("void k_bucket_sort_cs<1024, 8", 0)],
     "r_bucket_sort": [("void k_bucket_sort_cs<1024, 4", 1), ("void k_bucket_sort_cs<1024, 8", 1)],

@@ -229,10 +229,29 @@ struct CellMap {
   }
 };
 
+// Logarithmic cells for skewed key spans: x = key - lo (x <= the span,
+// whose top bit is at position top) falls in cell (31 - d) * 64 + m, where d
+// is how many bit positions x's top bit lies below the span's and m the six
+// bits that follow x's top bit; x = 0 and x below 2^(top - 31) fall in cell 0.
+// Monotone in x, cells [0, 2048).  Each binary order of magnitude of x gets
+// 64 cells, so splitters crowded at the low end of a heavy-tailed span
+// (log-normal keys) still spread over many cells.
+__device__ __forceinline__ uint32_t log_cell(uint64_t x, uint32_t top) {
+  if (x == 0) return 0;
+  const uint32_t lz = (uint32_t)__builtin_clzll(x);
+  const uint32_t d = top - (63u - lz);
+  if (d >= 32u) return 0;
+  const uint32_t m = ((uint32_t)((x << lz) >> 32) >> 25) & 63u;
+  return (31u - d) * 64u + m;
+}
+
 // Directory over sorted splitters for fast bucket_of: the span [spl[0],
-// spl[nspl-1]] is cut into D cells by a CellMap.  Cell c's entry packs the
-// first splitter whose cell is >= c (bits 0..15) and the number of
-// splitters in cell c (bits 16..31).  A key in cell c has every splitter
+// spl[nspl-1]] is cut into D cells, by a CellMap (linear) or by log_cell,
+// whichever puts fewer splitters into a cell that already holds one (the
+// choice is made per directory from its splitters).  Cell c's entry packs
+// the first splitter whose cell is >= c (bits 0..15), the number of
+// splitters in cell c (bits 16..30) and whether they are all one key (bit
+// 31: the copies of a frequent key, compared once).  A key in cell c has every splitter
 // below the first under it and every splitter after the cell's above it, so
 // only its cell's splitters (usually 0 or 1) are compared: one LDS read of
 // the entry, then at most one of a splitter in the common case.  A splitter
@@ -245,43 +264,73 @@ struct CellMap {
 struct SplitView {
   uint64_t lo, last;
   uint32_t sh, C, nspl;
+  uint32_t logm, top;   // logarithmic cells (uniform over the workgroup), top bit of the span
 };
 
 template <int D, int NSPL>
 struct SplitDir {
+  static_assert(D == 2048, "log_cell fills 2048 cells");
   uint32_t ent[D];
   uint8_t dup[NSPL];
   CellMap map;
   uint64_t last;
+  uint32_t top, logm;
+  uint32_t coll[2];
 
   // All threads of the block call; spl (LDS) holds nspl sorted splitters,
   // 1 <= nspl <= NSPL < 2^16.
   template <int NT>
   __device__ void build(const uint64_t* spl, uint32_t nspl) {
-    if (threadIdx.x == 0) { map.init(spl[0], spl[nspl - 1] - spl[0], D); last = spl[nspl - 1]; }
+    if (threadIdx.x == 0) {
+      const uint64_t w = spl[nspl - 1] - spl[0];
+      map.init(spl[0], w, D);
+      last = spl[nspl - 1];
+      top = w ? 63u - (uint32_t)__builtin_clzll(w) : 0u;
+      coll[0] = coll[1] = 0;
+    }
     __syncthreads();
     const CellMap mp = map;
+    const uint32_t tp = top;
+    // splitters that share a cell with a smaller predecessor, under either map
+    uint32_t c0 = 0, c1 = 0;
+    for (uint32_t m = threadIdx.x + 1; m < nspl; m += NT) {
+      const uint64_t x = spl[m], y = spl[m - 1];
+      if (x != y) {
+        c0 += mp(x) == mp(y);
+        c1 += log_cell(x - mp.lo, tp) == log_cell(y - mp.lo, tp);
+      }
+    }
+    if (c0) atomicAdd(&coll[0], c0);
+    if (c1) atomicAdd(&coll[1], c1);
+    __syncthreads();
+    // a logarithmic cell costs a few more instructions: taken when it halves the collisions
+    const bool lg = 2 * coll[1] < coll[0];
+    auto cell_of = [&](uint64_t k) -> uint32_t { return lg ? log_cell(k - mp.lo, tp) : mp(k); };
     auto first_at = [&](uint32_t cell) -> uint32_t {   // first m with cell(spl[m]) >= cell
       uint32_t a = 0, b = nspl;
       while (a < b) {
         const uint32_t m = (a + b) >> 1;
-        if (mp(spl[m]) < cell) a = m + 1; else b = m;
+        if (cell_of(spl[m]) < cell) a = m + 1; else b = m;
       }
       return a;
     };
     for (uint32_t cell = threadIdx.x; cell < (uint32_t)D; cell += NT) {
       const uint32_t f0 = first_at(cell), f1 = first_at(cell + 1);
-      ent[cell] = f0 | ((f1 - f0) << 16);
+      const bool one = f1 - f0 >= 2 && spl[f0] == spl[f1 - 1];
+      ent[cell] = f0 | ((f1 - f0) << 16) | (one ? 0x80000000u : 0u);
     }
     for (uint32_t m = threadIdx.x; m < nspl; m += NT) dup[m] = m > 0 && spl[m] == spl[m - 1];
+    if (threadIdx.x == 0) logm = lg ? 1u : 0u;
     __syncthreads();
   }
 
   __device__ __forceinline__ SplitView view(uint32_t nspl) const {
     SplitView v;
     v.nspl = nspl;
-    if (nspl) { v.lo = map.lo; v.last = last; v.sh = map.sh; v.C = map.C; }
-    else { v.lo = ~0ull; v.last = ~0ull; v.sh = 0; v.C = 0; }
+    if (nspl) { v.lo = map.lo; v.last = last; v.sh = map.sh; v.C = map.C; v.top = top; v.logm = logm; }
+    else { v.lo = ~0ull; v.last = ~0ull; v.sh = 0; v.C = 0; v.top = 0; v.logm = 0; }
+    v.logm = __builtin_amdgcn_readfirstlane(v.logm);
+    v.top = __builtin_amdgcn_readfirstlane(v.top);
     return v;
   }
 
@@ -293,16 +342,17 @@ struct SplitDir {
       b = v.nspl;
       eq = key == v.last;
     } else {
-      const uint32_t cell = __umulhi((uint32_t)((key - v.lo) >> v.sh), v.C);   // below D
+      // below D
+      const uint32_t cell = v.logm ? log_cell(key - v.lo, v.top) : __umulhi((uint32_t)((key - v.lo) >> v.sh), v.C);
       const uint32_t e = ent[cell];
       uint32_t a = e & 0xFFFFu;
-      const uint32_t n = e >> 16;
+      const uint32_t n = (e >> 16) & 0x7FFFu;
       if (n == 0) {
         b = a;
         eq = false;
-      } else if (n == 1) {
+      } else if (n == 1 || (e >> 31)) {   // one splitter, or n copies of one key
         const uint64_t s0 = spl[a];
-        b = a + (s0 <= key);
+        b = a + (s0 <= key ? n : 0u);
         eq = s0 == key;
       } else {
         uint32_t z = a + n;

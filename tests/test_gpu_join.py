@@ -447,12 +447,15 @@ def _ws_view(ws, off, n, dtype):
 
 
 @pytest.mark.parametrize("nR,nS,bt,skew", [(1 << 17, 1 << 19, 1024, False), (1 << 19, 1 << 20, 256, False),
-                                          (1 << 17, 1 << 19, 4096, True)])
+                                          (1 << 17, 1 << 19, 4096, True), (1 << 17, 1 << 19, 2048, "lognormal")])
 def test_intermediate_results(nR, nS, bt, skew):
     rng = np.random.default_rng(nR + bt)
     R = rel(rng, nR, 1 << 24)
     S = rel(rng, nS, 1 << 24)
-    if skew:   # S keys with a heavy head: frequent keys of one splitter get their own bucket
+    if skew == "lognormal":   # heavy-tailed keys: the splitter directories take logarithmic cells
+        R[:, 0] = np.floor(np.exp(2.0 * rng.standard_normal(nR)) * 2.0 ** 28).astype(np.uint64)
+        S[:, 0] = R[rng.integers(0, nR, nS), 0]
+    elif skew:   # S keys with a heavy head: frequent keys of one splitter get their own bucket
         base = np.unique(R[:, 0])
         S[:, 0] = base[(len(base) * rng.random(nS) ** 4).astype(np.int64)]
     cfg = mpsm.config(bucket_target=bt, log2_run_len=17)
@@ -480,7 +483,7 @@ def test_intermediate_results(nR, nS, bt, skew):
         seed = oracle.splitmix_at(lay["s_level_seed"], j)
         a, b = j * L, min((j + 1) * L, nS)
         _check_splitters(spl[j], oracle.sample_splitters(S[a:b], NB, lay["s_oversample"], seed))
-    if skew:   # the frequent-key rule has fired: some splitter is its predecessor + 1
+    if skew is True:   # the frequent-key rule has fired: some splitter is its predecessor + 1
         assert np.count_nonzero(spl[:, 1:] == spl[:, :-1] + np.uint64(1)) > 0
     # S bucket boundaries: the oracle's stable partition of each run under the
     # GPU's own splitters, with the kernel's rule for keys equal to two or more
