@@ -82,15 +82,15 @@ WORKLOAD_KEYS = {
 
 # launch steps -> (kernel name prefix, occurrence of that kernel inside one join)
 STEP_DISPATCH = {
-    # S and R's second level: the scatter into regions, then the exact
-    # path's histogram and scatter for segments whose regions overflowed
-    # (launched always, most often with nothing to do); R's first level: the
-    # exact path
+    # S and R's second level: the scatter into regions, then the histogram
+    # and the redo scatter for segments whose regions overflowed (launched
+    # always, most often with nothing to do); R's first level: histogram and
+    # staged scatter
     "s_histogram": ("k_bucket_hist", 0),
-    "s_scatter": [("void k_bucket_scatter<true>", 0), ("void k_bucket_scatter<false>", 0)],
-    "r1_histogram": ("k_bucket_hist", 1), "r1_scatter": ("void k_bucket_scatter<false>", 1),
+    "s_scatter": [("void k_bucket_scatter<true>", 0), ("k_redo_scatter", 0)],
+    "r1_histogram": ("k_bucket_hist", 1), "r1_scatter": ("void k_bucket_scatter<false>", 0),
     "r2_histogram": ("k_bucket_hist", 2),
-    "r2_scatter": [("void k_bucket_scatter<true>", 1), ("void k_bucket_scatter<false>", 2)],
+    "r2_scatter": [("void k_bucket_scatter<true>", 1), ("k_redo_scatter", 1)],
     # the sorts: the two-per-CU kernel, then the one-per-CU kernel over the larger buckets
     "s_bucket_sort": [("void k_bucket_sort_cs<1024, 4", 0), ("void k_bucket_sort_cs<1024, 8", 0)],
     "r_bucket_sort": [("void k_bucket_sort_cs<1024, 4", 1), ("void k_bucket_sort_cs<1024, 8", 1)],

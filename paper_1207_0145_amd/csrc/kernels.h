@@ -568,12 +568,7 @@ __global__ void __launch_bounds__(HIST_NT) k_bucket_hist(const tup_t* __restrict
 // a claim that outgrows the region writes nothing and marks the segment
 // dirty.  The tuples of a bucket then sit at the start of its region in
 // the order of the claims.
-// redo (not PAD, redo.dirty set): only dirty segments are scattered, each
-// compactly from the start of its own area (pad_area of its start), by the
-// scanned counts of its own tiles.
-struct Redo {
-  const uint32_t* dirty;   // per segment, or NULL: every segment, at the scanned positions
-};
+// The segments it marks dirty are redone by k_redo_scatter.
 constexpr uint32_t NO_ROOM = 0xFFFFFFFFu;
 
 template <bool PAD>
@@ -583,7 +578,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
                                                             const uint32_t* seg_nb, uint32_t nseg, const uint64_t* spl,
                                                             uint32_t NBmax, uint32_t TILE, const uint32_t* pos,
                                                             const tup_t* const* seg_src, Regions rg,
-                                                            const uint32_t* seg_b0, Redo redo) {
+                                                            const uint32_t* seg_b0) {
   __shared__ uint64_t sp[MAX_NB];
   __shared__ uint32_t cursor[MAX_NB], lcnt[MAX_NB], lofs[MAX_NB];
   __shared__ tup_t stage[SCAT_CH];
@@ -594,7 +589,6 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   const uint32_t g = xcd_item(blockIdx.x, seg_tile0[nseg]);
   if (g >= seg_tile0[nseg]) return;
   const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
-  if (!PAD && redo.dirty && !redo.dirty[s]) return;
   // a segment may be read in place from its own array
   const gtup_t* const gsrc = as_global(seg_src ? seg_src[s] - seg_start[s] : src);
   const uint32_t t = g - seg_tile0[s], ntiles = seg_tile0[s + 1] - seg_tile0[s];
@@ -608,10 +602,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
     for (uint32_t i = tid; i < NB; i += SCAT_NT) lcnt[i] = 0;
   } else {
     const uint32_t* p = pos + seg_cnt0[s] + t;
-    // redo: positions relative to the segment's first count, from its own area
-    const uint32_t rel = redo.dirty ? pos[seg_cnt0[s]] : 0u;
-    const uint32_t base = redo.dirty ? (uint32_t)pad_area(seg_start[s]) : 0u;
-    for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] = base + (p[(uint64_t)i * ntiles] - rel); lcnt[i] = 0; }
+    for (uint32_t i = tid; i < NB; i += SCAT_NT) { cursor[i] = p[(uint64_t)i * ntiles]; lcnt[i] = 0; }
   }
   __syncthreads();
   if (nspl) dir.build<SCAT_NT>(sp, nspl);
@@ -694,6 +685,52 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
       lcnt[i] = 0;
     }
     __syncthreads();
+  }
+}
+
+// Redo of the segments that a scatter into regions marked dirty (a bucket
+// outgrew its region; rare): every tile of a dirty segment writes its
+// tuples straight to their places, compactly from the start of the
+// segment's area (pad_area of its start), by the scanned counts of the
+// segment's tiles (k_bucket_hist with only_dirty), each tuple taking its
+// place within its tile's share of its bucket by one LDS atomic.  Unstaged,
+// so slower than k_bucket_scatter, but with the LDS of the histogram: the
+// launch, which most often has nothing to do, needs no whole CU (the staged
+// scatter's workgroups, even those that exit at once, each wait for a CU
+// with all its LDS free, which the bucket sort running beside R's passes
+// rarely leaves).
+__global__ void __launch_bounds__(HIST_NT) k_redo_scatter(const tup_t* __restrict__ src, tup_t* __restrict__ dst,
+                                                          const uint32_t* seg_start, const uint32_t* seg_len,
+                                                          const uint32_t* seg_tile0, const uint32_t* seg_cnt0,
+                                                          const uint32_t* seg_nb, uint32_t nseg, const uint64_t* spl,
+                                                          uint32_t NBmax, uint32_t TILE, const uint32_t* pos,
+                                                          const tup_t* const* seg_src, const uint32_t* dirty) {
+  __shared__ uint64_t sp[MAX_NB];
+  __shared__ uint32_t cur[MAX_NB];
+  __shared__ SplitDir<SPLIT_DIR, MAX_NB> dir;
+  const uint32_t g = blockIdx.x;
+  if (g >= seg_tile0[nseg]) return;
+  const uint32_t s = seg_of_tile(seg_tile0, nseg, g);
+  if (!dirty[s]) return;
+  const gtup_t* const gsrc = as_global(seg_src ? seg_src[s] - seg_start[s] : src);
+  const uint32_t t = g - seg_tile0[s], ntiles = seg_tile0[s + 1] - seg_tile0[s];
+  const uint32_t segend = seg_start[s] + seg_len[s];
+  const uint32_t a = seg_start[s] + t * TILE;
+  const uint32_t b = min(a + TILE, segend);
+  const uint32_t NB = seg_nb[s], nspl = NB - 1;
+  // the segment's counts were scanned with every other segment's: positions
+  // relative to its first count, from the start of its own area
+  const uint32_t rel = pos[seg_cnt0[s]];
+  const uint32_t base = (uint32_t)pad_area(seg_start[s]);
+  const uint32_t* p = pos + seg_cnt0[s] + t;
+  for (uint32_t i = threadIdx.x; i < nspl; i += HIST_NT) sp[i] = spl[(uint64_t)s * (NBmax - 1) + i];
+  for (uint32_t i = threadIdx.x; i < NB; i += HIST_NT) cur[i] = base + (p[(uint64_t)i * ntiles] - rel);
+  __syncthreads();
+  if (nspl) dir.build<HIST_NT>(sp, nspl);
+  const SplitView sv = dir.view(nspl);
+  for (uint32_t i = a + threadIdx.x; i < b; i += HIST_NT) {
+    const tup_t v = load_tup(gsrc + i);
+    store_tup(dst + atomicAdd(&cur[dir.bucket(sv, sp, v.key)], 1u), v);
   }
 }
 

@@ -419,22 +419,21 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
   mk.mark(mk0);
   if (L.rg.cap) {
     // no histogram: every chunk claims room in its buckets' regions; the
-    // segments where a bucket outgrew its region are redone by the exact
-    // path (histogram, scan, scatter), whose launches end at once when no
-    // segment needs it
+    // segments where a bucket outgrew its region are redone (histogram,
+    // scan, unstaged scatter), whose launches end at once when no segment
+    // needs it
     mk.mark_range(mk0 + 1, mk0 + 2);
     k_bucket_scatter<true><<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb,
                                                             L.nseg, L.spl, L.NBmax, HIST_TILE, nullptr, seg_src, L.rg,
-                                                            sg.b0, Redo{nullptr});
+                                                            sg.b0);
     LAUNCH_CHECK();
     k_bucket_hist<<<L.max_tiles, HIST_NT, 0, st>>>(src, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb, L.nseg, L.spl,
                                                    L.NBmax, HIST_TILE, L.cnt, seg_src, L.rg.dirty);
     LAUNCH_CHECK();
     mpsm_status rc = scan_u32(L.cnt, L.cnt, L.ncnt, bsum, st, L.rg.any);
     if (rc != MPSM_OK) return rc;
-    k_bucket_scatter<false><<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb,
-                                                             L.nseg, L.spl, L.NBmax, HIST_TILE, L.cnt, seg_src,
-                                                             Regions{}, nullptr, Redo{L.rg.dirty});
+    k_redo_scatter<<<L.max_tiles, HIST_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb, L.nseg,
+                                                    L.spl, L.NBmax, HIST_TILE, L.cnt, seg_src, L.rg.dirty);
     LAUNCH_CHECK();
     k_region_table<1024><<<L.nseg, 1024, 0, st>>>(L.nseg, L.NBmax, sg.start, sg.len, sg.nb, sg.b0, L.rg, L.spl,
                                                   L.outer, L.outer_nspl, L.bstart, L.bsrc, L.blo, L.bhi);
@@ -452,7 +451,7 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
     mk.mark(mk0 + 2);
     k_bucket_scatter<false><<<L.max_tiles, SCAT_NT, 0, st>>>(src, dst, sg.start, sg.len, sg.tile0, sg.cnt0, sg.nb,
                                                              L.nseg, L.spl, L.NBmax, HIST_TILE, L.cnt, seg_src,
-                                                             Regions{}, nullptr, Redo{nullptr});
+                                                             Regions{}, nullptr);
     LAUNCH_CHECK();
   } else {
     mk.mark_range(mk0 + 1, mk0 + 2);
