@@ -39,8 +39,8 @@ using SampleSorterS = BlockSort<SMP_NT_S, SMP_IPT_S, 4>;
 
 constexpr int HIST_NT = 256;
 constexpr int SCAT_NT = 1024;
-constexpr int SCAT_IPT = 8;
-constexpr int SCAT_CH = SCAT_NT * SCAT_IPT;  // tuples staged in LDS per chunk
+constexpr int SCAT_IPT = 7;
+constexpr int SCAT_CH = SCAT_NT * SCAT_IPT;  // tuples staged in LDS per chunk (with their buckets)
 constexpr int MAX_NB = 1024;                 // buckets per segment
 constexpr uint32_t S_BUCKET_MEAN = 2400;   // mean tuples per S-run bucket
 constexpr int SPLIT_DIR = 2048;              // cells of the splitter directory
@@ -582,6 +582,7 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
   __shared__ uint64_t sp[MAX_NB];
   __shared__ uint32_t cursor[MAX_NB], lcnt[MAX_NB], lofs[MAX_NB];
   __shared__ tup_t stage[SCAT_CH];
+  __shared__ uint16_t sbk[SCAT_CH];   // bucket of every staged tuple
   __shared__ uint32_t wsum[SCAT_NT / 64 + 2];
   __shared__ SplitDir<SPLIT_DIR, MAX_NB> dir;
   const uint32_t tid = threadIdx.x;
@@ -667,15 +668,17 @@ __global__ void __launch_bounds__(SCAT_NT) k_bucket_scatter(const tup_t* __restr
       if (i < b) {
         const uint32_t q = lofs[bk[k]] + lr[k];
         stage[q] = v[k];
+        sbk[q] = (uint16_t)bk[k];
       }
     }
     __syncthreads();
     const uint32_t m = min((uint32_t)SCAT_CH, b - c0);
     for (uint32_t q = tid; q < m; q += SCAT_NT) {
-      // the bucket is looked up again rather than staged: LDS holds 8 K
-      // tuples per chunk, so that every bucket gets a run of several tuples
+      // the bucket is staged with the tuple rather than looked up again
+      // (two or more splitter compares on skewed keys): 7 K tuples per
+      // chunk, so that every bucket still gets a run of several tuples
       const tup_t tq = stage[q];
-      const uint32_t bb = dir.bucket(sv, sp, tq.key);
+      const uint32_t bb = sbk[q];
       const uint32_t cb = cursor[bb];
       if (!PAD || cb != NO_ROOM) store_tup(dst + cb + (q - lofs[bb]), tq);
     }

@@ -18,7 +18,7 @@
 
 namespace {
 
-constexpr uint32_t HIST_TILE = 1u << 16;      // tuples per histogram / scatter tile
+constexpr uint32_t HIST_TILE = 9 * SCAT_CH;   // tuples per histogram / scatter tile (9 chunks of the scatter)
 constexpr uint32_t IDX_STRIDE = 256;          // equi-height index stride of S runs
 constexpr uint64_t DEFAULT_SEED = 0x1207014500000000ull;
 constexpr uint64_t TAG_S = 0x5300000000000001ull, TAG_R1 = 0x5200000000000001ull, TAG_R2 = 0x5200000000000002ull;
