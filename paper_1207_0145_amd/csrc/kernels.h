@@ -49,7 +49,7 @@ constexpr int JOIN_NT = 1024;
 constexpr int JOIN_CAP = 8192;               // R partition held in LDS
 constexpr int JOIN_QMAX = 2048;              // S runs
 constexpr int JOIN_DIR = 4096;               // cells of the R-partition directory
-constexpr int JOIN_RDIR = 1024;              // run directory of a work item (one entry per 256 positions)
+constexpr int JOIN_RDIR = 1024;              // run directory of a work item (one entry per 64 or 256 positions)
 constexpr int JOIN_CHUNK_MAX = 256 * (JOIN_RDIR - 1);
 
 constexpr int SCAN_NT = 256;
@@ -1902,11 +1902,14 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
     const uint32_t lo_item = k * A.JCH;
     const uint32_t hi_item = min(lo_item + A.JCH, cum[Q]);
     const tup_t* Rg = A.Rs + rs;
-    // run directory of the item: rdir[d] = run of position lo_item + 256 d,
+    // run directory of the item: rdir[d] = run of position lo_item + 2^rsh d
+    // (64 positions per entry where the item allows: a slice is often
+    // shorter than 256 positions when there are many runs),
     // so that a position's run is found between two neighbouring entries
-    const uint32_t nd = (hi_item - lo_item + 255) >> 8;
+    const uint32_t rsh = A.JCH <= 64u * (JOIN_RDIR - 1) ? 6u : 8u;
+    const uint32_t nd = (hi_item - lo_item + (1u << rsh) - 1) >> rsh;
     for (uint32_t d = tid; d < nd; d += JOIN_NT) {
-      const uint32_t x = lo_item + (d << 8);
+      const uint32_t x = lo_item + (d << rsh);
       uint32_t a0 = 0, b0 = Q;
       while (b0 - a0 > 1) { const uint32_t m = (a0 + b0) >> 1; if (cum[m] <= x) a0 = m; else b0 = m; }
       rdir[d] = (uint16_t)a0;
@@ -1919,7 +1922,7 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
       for (int u = 0; u < JOIN_U; u++) {
         const uint32_t x = base + u * JOIN_NT + tid;
         if (x < hi_item) {
-          const uint32_t d = (x - lo_item) >> 8;   // run j: cum[j] <= x < cum[j+1]
+          const uint32_t d = (x - lo_item) >> rsh;   // run j: cum[j] <= x < cum[j+1]
           uint32_t a0 = rdir[d], b0 = d + 1 < nd ? rdir[d + 1] + 1u : Q;
           while (b0 - a0 > 1) { const uint32_t m = (a0 + b0) >> 1; if (cum[m] <= x) a0 = m; else b0 = m; }
           sv[u] = load_tup(A.U + sbase[a0] + x);
