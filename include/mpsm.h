@@ -391,6 +391,17 @@ uint64_t mpsm_clock_hz(void);
 mpsm_status mpsm_join_slices_host(const uint32_t* oa, const uint32_t* ob, const uint32_t* run_start,
                                   const uint32_t* run_len, uint32_t Q, uint32_t* cum, uint32_t* sbase);
 
+/* The last step of the start search (Section 3.2.2: where a private
+ * partition starts in a public run), run on the CPU with the device code, for
+ * tests (no GPU needed): the lower bound of key in keys[a, b) (sorted), given
+ * that every key before a is smaller and keys[b], if inside the run, is not;
+ * klo and khi (the index keys around the window) only choose the first
+ * 8-key line it probes.  keys: host array of at least b keys.  *out: the
+ * lower bound; *probes (may be NULL): lines probed.  MPSM_EINVAL on NULL
+ * out, or NULL keys with a < b. */
+mpsm_status mpsm_lower_bound_window_host(const uint64_t* keys, uint32_t a, uint32_t b, uint64_t klo, uint64_t khi,
+                                         uint64_t key, uint32_t* out, uint32_t* probes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,8 @@ EXPORTS = ("mpsm_config_default", "mpsm_workspace_bytes", "mpsm_join", "mpsm_sta
            "mpsm_events_create", "mpsm_events_destroy", "mpsm_events_elapsed", "mpsm_batch_create",
            "mpsm_batch_destroy", "mpsm_batch_workspace_bytes", "mpsm_batch_run", "mpsm_batch_autotune",
            "mpsm_batch_get_tuning", "mpsm_batch_set_tuning", "mpsm_clock_hz", "mpsm_join_slices_host",
-           "mpsm_join_noalloc", "mpsm_join_batch", "mpsm_join_batch_workspace_bytes")
+           "mpsm_join_noalloc", "mpsm_join_batch", "mpsm_join_batch_workspace_bytes",
+           "mpsm_lower_bound_window_host")
 
 
 class MpsmConfig(ctypes.Structure):
@@ -143,6 +144,9 @@ def lib():
         L.mpsm_clock_hz.restype = u64
         L.mpsm_join_slices_host.argtypes = [p, p, p, p, ctypes.c_uint32, p, p]
         L.mpsm_join_slices_host.restype = ctypes.c_int
+        L.mpsm_lower_bound_window_host.argtypes = [p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                                   ctypes.c_uint64, ctypes.c_uint64, p, p]
+        L.mpsm_lower_bound_window_host.restype = ctypes.c_int
         L.mpsm_join_noalloc.argtypes = [p, u64, p, u64, p, p, p, u64, ctypes.POINTER(MpsmConfig), p]
         L.mpsm_join_noalloc.restype = ctypes.c_int
         L.mpsm_join_batch_workspace_bytes.argtypes = [ctypes.c_uint32, ctypes.POINTER(MpsmBatchShape),
@@ -452,3 +456,16 @@ def join_slices_host(oa, ob, run_start, run_len):
     if rc != 0:
         raise MpsmError(rc, "mpsm_join_slices_host")
     return cum, sbase[:Q]
+
+
+def lower_bound_window_host(keys, a, b, klo, khi, key):
+    """The start search's last step, run on the host (no GPU): (lower bound
+    of key in keys[a, b), lines probed)."""
+    import numpy as np
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    out, pr = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    rc = lib().mpsm_lower_bound_window_host(ctypes.c_void_p(k.ctypes.data if len(k) else 0), a, b, klo, khi, key,
+                                            ctypes.byref(out), ctypes.byref(pr))
+    if rc != 0:
+        raise MpsmError(rc, "mpsm_lower_bound_window_host")
+    return out.value, pr.value

@@ -11,7 +11,7 @@ SO = os.path.join(HERE, "libmpsm.so")
 # library last built (read by the tests that keep hot kernels spill-free)
 RESOURCES = os.path.join(HERE, "libmpsm.resources.json")
 SOURCES = [os.path.join(HERE, "csrc", "mpsm.hip")]
-HEADERS = ["common.h", "block_sort.h", "join_slices.h", "kernels.h", "learned.h", "batch.h"]
+HEADERS = ["common.h", "block_sort.h", "join_slices.h", "search_window.h", "kernels.h", "learned.h", "batch.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -18,6 +18,7 @@
 #pragma once
 #include "block_sort.h"
 #include "join_slices.h"
+#include "search_window.h"
 
 // ------------------------------------------------------------------ config
 // bucket sort instances: small tiles for S buckets, large tiles (= the join's
@@ -1557,6 +1558,11 @@ __device__ __forceinline__ uint32_t lb_keys(const tup_t* run, uint32_t lo, uint3
   return lo;
 }
 
+__device__ __forceinline__ uint32_t lb_window(const tup_t* run, uint32_t a, uint32_t b, uint64_t klo, uint64_t khi,
+                                              uint64_t key, uint32_t* probes) {
+  return lb_window_at([run](uint32_t i) { return run[i].key; }, a, b, klo, khi, key, probes);
+}
+
 // Interpolation search (Section 3.2.2, Fig. 7) with the invariant
 // run[lo] < key <= run[hi]; bisection once a probe fails to halve the range
 // twice or the range is at most 16.  Same answer as lower_bound.
@@ -1612,7 +1618,7 @@ __device__ __forceinline__ uint32_t run_lower_bound(int mode, const tup_t* run, 
   }
   const uint32_t a = lo ? (lo - 1) * idx_stride + 1 : 0;
   const uint32_t b = lo < nidx ? lo * idx_stride : n;
-  return lb_keys(run, a, b, key, probes);
+  return lb_window(run, a, b, lo ? idx[lo - 1] : 0ull, lo < nidx ? idx[lo] : ~0ull, key, probes);
 }
 
 // Launch shape: a wave takes 64 consecutive partitions of one run, so the
@@ -1675,7 +1681,7 @@ __global__ void __launch_bounds__(SEARCH_NT) k_search(const tup_t* __restrict__ 
         }
         const uint32_t a = lo ? (lo - 1) * idx_stride + 1 : 0;
         const uint32_t b = lo < nidx ? lo * idx_stride : n;
-        r = lb_keys(run, a, b, key, &probes);
+        r = lb_window(run, a, b, lo ? idx[lo - 1] : 0ull, lo < nidx ? idx[lo] : ~0ull, key, &probes);
       }
     }
     o[(uint64_t)p * Q + j] = r;

@@ -1661,4 +1661,13 @@ mpsm_status mpsm_join_slices_host(const uint32_t* oa, const uint32_t* ob, const 
   return MPSM_OK;
 }
 
+mpsm_status mpsm_lower_bound_window_host(const uint64_t* keys, uint32_t a, uint32_t b, uint64_t klo, uint64_t khi,
+                                         uint64_t key, uint32_t* out, uint32_t* probes) {
+  if (!out || (a < b && !keys)) return MPSM_EINVAL;
+  uint32_t pr = 0;
+  *out = lb_window_at([keys](uint32_t i) { return keys[i]; }, a, b, klo, khi, key, &pr);
+  if (probes) *probes = pr;
+  return MPSM_OK;
+}
+
 }  // extern "C"
