@@ -1621,6 +1621,18 @@ __device__ __forceinline__ uint32_t run_lower_bound(int mode, const tup_t* run, 
   return lb_window(run, a, b, lo ? idx[lo - 1] : 0ull, lo < nidx ? idx[lo] : ~0ull, key, probes);
 }
 
+// The learned search's prediction for every partition's first key and the
+// model's error near it (one evaluation per partition, not per partition
+// and run: the key is the same in every run).
+__global__ void k_search_model(const CdfModel* model, const uint64_t* pkey, const uint32_t* Pcount, uint32_t Pmax,
+                               float2* qe) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  const CdfModel& m = *model;
+  if (p >= *Pcount || p >= Pmax || !m.valid) return;
+  const float q = cdf_eval(m, pkey[p]);
+  qe[p] = make_float2(q, cdf_local_eps(m, q));
+}
+
 // Launch shape: a wave takes 64 consecutive partitions of one run, so the
 // first levels of its lanes' bisections read the same index entries and the
 // last ones neighbouring lines; a workgroup takes 16 runs, so that each row
@@ -1633,8 +1645,8 @@ __global__ void __launch_bounds__(SEARCH_NT) k_search(const tup_t* __restrict__ 
                                                 const uint32_t* run_len, uint32_t Q, const uint64_t* run_idx,
                                                 uint32_t idx_stride, uint32_t idx_per_run, const uint32_t* Pcount,
                                                 const uint64_t* pkey, uint32_t Pmax, uint32_t* o, int mode,
-                                                const CdfModel* model, Result* res, const uint8_t* span,
-                                                const uint8_t* pterm) {
+                                                const CdfModel* model, const float2* qe, Result* res,
+                                                const uint8_t* span, const uint8_t* pterm) {
   const bool learned = mode == SEARCH_LEARNED;
   const CdfModel& m = *model;   // read through the caches: its knots are shared by all threads
   const uint32_t njt = (Q + SEARCH_RUNS - 1) / SEARCH_RUNS;
@@ -1662,9 +1674,10 @@ __global__ void __launch_bounds__(SEARCH_NT) k_search(const tup_t* __restrict__ 
         if (learned && m.valid) {
           // window: the model's error on its sample near the prediction, plus the sampling error of
           // a 2^16-key sample and of this run (two standard deviations each)
-          const float q = cdf_eval(m, key);
+          const float2 pq = qe[p];   // the prediction for the key and the model's error near it
+          const float q = pq.x;
           const float sd = sqrtf(q * (1.f - q) + 1e-4f);
-          const float err = cdf_local_eps(m, q) + 2.f * sd * (1.f / 256.f + rsqrtf((float)n + 1.f));
+          const float err = pq.y + 2.f * sd * (1.f / 256.f + rsqrtf((float)n + 1.f));
           const int64_t t = (int64_t)(q * (float)nidx);
           const int64_t w = (int64_t)(err * (float)nidx) + 2;
           const uint32_t a = (uint32_t)(t - w < 0 ? 0 : (t - w > (int64_t)nidx ? (int64_t)nidx : t - w));

@@ -57,7 +57,7 @@ struct Plan {
   uint64_t bndS, bndR1, bndR2;             // per-bucket key bounds (lo array, then hi array)
   uint64_t bigS, midS, redoS, midR, redoR, redoR2, bigR, ctr;
   uint64_t bkey, Pc, pstart, plen, pkey;
-  uint64_t ridx, o, items, item_pre, item_cnt, res, span, pterm;
+  uint64_t ridx, o, items, item_pre, item_cnt, res, span, pterm, qe;
   uint64_t cdf_chunks, cdf_sorted, modelR, modelS;  // learned CDF samples and models
   uint64_t cost_sample, cost_s_below, cost_best;   // cost-balanced splitters
   uint64_t capS, rstS, fillS, bsrcS, dirtyS;        // S's regions (padS)
@@ -231,6 +231,7 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->item_pre = take(((uint64_t)P->Pmax + 2) * 4);
   P->item_cnt = take((P->item_cap + 1) * 4);
   P->span = take((uint64_t)P->Pmax + 2);
+  P->qe = take(((uint64_t)P->Pmax + 1) * 8);
   P->pterm = take((uint64_t)P->Pmax + 2);
   P->cdf_chunks = take(2ull * CDF_M * 8);
   P->cdf_sorted = take(2ull * CDF_M * 8);
@@ -842,6 +843,11 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
 
       // ---- phase 4: merge starts of every partition in every run, then the join
       uint32_t* o = reinterpret_cast<uint32_t*>(ws + P.o);
+      float2* qe = reinterpret_cast<float2*>(ws + P.qe);
+      if (learn_s) {
+        k_search_model<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, st>>>(modelS, pkey, Pc, P.Pmax, qe);
+        LAUNCH_CHECK();
+      }
       const uint64_t nsearch = cdiv((uint64_t)P.Pmax + 1, 64) * cdiv(P.Q, SEARCH_RUNS);
       k_search<<<(uint32_t)nsearch, SEARCH_NT, 0, st>>>(U, LS.seg.start, LS.seg.len, P.Q,
                                                             reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
@@ -849,7 +855,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
                                                             learn_s ? MPSM_SEARCH_LEARNED
                                                                     : (P.search == MPSM_SEARCH_LEARNED ? MPSM_SEARCH_INDEX
                                                                                                        : P.search),
-                                                            modelS, stats ? res : nullptr, span, pterm);
+                                                            modelS, qe, stats ? res : nullptr, span, pterm);
       LAUNCH_CHECK();
       mk.mark(MK_SEARCH);
       uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
