@@ -852,3 +852,29 @@ def test_padded_bmpsm_runs(oversample):
     _say(f"redone: S runs {st['redone_runs']}, R runs {st['redone_r_segments']}")
     if oversample == 2:
         assert st["redone_runs"] > 0 and st["redone_r_segments"] > 0
+
+
+@pytest.mark.parametrize("nR,nS", [((1 << 22) + 777, (1 << 22) + 12345), ((1 << 22) - 1, 1 << 22)])
+def test_padded_passes_at_ragged_sizes(nR, nS):
+    """Sizes at and around the threshold of the passes without a histogram
+    (2^22), with a ragged last run and ragged level-1 buckets: the join
+    equals the oracle's, S's runs and R's order equal the oracle's sorts."""
+    rng = np.random.default_rng(nR ^ nS)
+    R = rel(rng, nR, 1 << 40)
+    S = rel(rng, nS, 1 << 40)
+    S[: nS // 2, 0] = R[rng.integers(0, nR, nS // 2), 0]
+    cfg = mpsm.config()
+    lay = mpsm.layout(nR, nS, cfg)
+    _say(f"ragged padded sizes nR={nR} nS={nS}: passes {lay['padded_passes']}, levels {lay['levels']}")
+    assert lay["padded_passes"] & 1 == (1 if nS >= (1 << 22) else 0)
+    assert (lay["padded_passes"] >> 2) & 1 == (1 if nR >= (1 << 22) and lay["levels"] == 2 else 0)
+    ws = mpsm.alloc_workspace(nR, nS, cfg)
+    got = gpu_join(R, S, cfg, workspace=ws)
+    want = oracle.join(R, S)
+    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+    torch.cuda.synchronize()
+    L = lay["run_len"]
+    Ssorted = _ws_view(ws, lay["off_s_sorted"], 2 * nS, np.uint64).reshape(-1, 2)
+    assert np.array_equal(Ssorted[:, 0], oracle.sort_runs(S, L)[:, 0])
+    Rsorted = _ws_view(ws, lay["off_r_sorted"], 2 * nR, np.uint64).reshape(-1, 2)
+    assert np.array_equal(Rsorted[:, 0], np.sort(R[:, 0]))
