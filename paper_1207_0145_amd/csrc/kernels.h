@@ -1485,28 +1485,34 @@ __global__ void __launch_bounds__(BIG_NT) k_big_sort(tup_t* __restrict__ src, tu
 
 // ------------------------------------------------------------ partitions
 
-// Compact the non-empty R buckets into partitions p = 0..P-1 (start, length,
-// first key).  Single workgroup.
-__global__ void __launch_bounds__(1024) k_partitions(const uint32_t* bstart, const uint64_t* bkey,
-                                                     const uint32_t* Gcount, uint32_t* Pcount, uint32_t* pstart,
-                                                     uint32_t* plen, uint64_t* pkey, Result* res) {
-  __shared__ uint32_t wsum[1024 / 64 + 2];
-  const uint32_t G = *Gcount;
-  uint32_t carry = 0;
-  for (uint32_t b = 0; b < G; b += 1024) {
-    const uint32_t g = b + threadIdx.x;
-    const uint32_t len = g < G ? bstart[g + 1] - bstart[g] : 0;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<1024>(len ? 1u : 0u, wsum, &tot);
-    if (len) {
-      const uint32_t p = carry + ex;
-      pstart[p] = bstart[g]; plen[p] = len; pkey[p] = bkey[g];
-      if (res) atomicMax(&res->spare, (unsigned long long)len);
-    }
-    carry += tot;
-    __syncthreads();
+// Compact the non-empty R buckets into partitions p = 0..P-1 (start,
+// length, first key) over the whole grid of buckets at once: flags of the
+// non-empty buckets (k_partition_flags), their exclusive scan (pre), then
+// every non-empty bucket writes its partition (k_partition_write).  Gmax:
+// buckets the grid covers (>= *Gcount).
+__global__ void k_partition_flags(const uint32_t* bstart, const uint32_t* Gcount, uint32_t Gmax, uint32_t* flags) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= Gmax) return;
+  flags[g] = (g < *Gcount && bstart[g + 1] > bstart[g]) ? 1u : 0u;
+}
+
+__global__ void k_partition_write(const uint32_t* bstart, const uint64_t* bkey, uint32_t Gmax, const uint32_t* flags,
+                                  const uint32_t* pre, uint32_t* Pcount, uint32_t* pstart, uint32_t* plen,
+                                  uint64_t* pkey, Result* res) {
+  const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t len = 0;
+  if (g < Gmax && flags[g]) {
+    const uint32_t p = pre[g];
+    len = bstart[g + 1] - bstart[g];
+    pstart[p] = bstart[g]; plen[p] = len; pkey[p] = bkey[g];
   }
-  if (threadIdx.x == 0) *Pcount = carry;
+  if (g + 1 == Gmax) *Pcount = pre[g] + flags[g];
+  if (res) {   // statistics only: the largest partition, one atomic per wave
+    unsigned long long m = len;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) { const unsigned long long x = __shfl_xor(m, d, 64); m = x > m ? x : m; }
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(&res->spare, m);
+  }
 }
 
 // B-MPSM (Section 2.1, Fig. 3: no range partitioning; every sorted R run
@@ -1737,23 +1743,24 @@ __global__ void k_join_units(const uint32_t* Pcount, const uint32_t* plen, uint3
 
 // Work items: join unit u contributes ceil(n_u / JCH) items, n_u = S tuples
 // in its slices (0 when nothing can match).  items has Pmax + 2 entries.
+// One wave per partition: its lanes read the unit's two rows of offsets
+// across the runs side by side (each row is Q consecutive words), then add.
 __global__ void k_join_items(const uint32_t* Pcount, const uint32_t* o, uint32_t Q, const uint32_t* run_len,
                              uint32_t Pmax, uint32_t JCH, const uint8_t* span, uint32_t* items) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t p = (uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const uint32_t lane = threadIdx.x & 63;
   if (p > Pmax + 1) return;
   const uint32_t P = *Pcount;
-  uint32_t it = 0;
-  if (p < P) {
-    const uint32_t sp = span[p];
-    if (sp) {
-      uint64_t np = 0;
-      const uint32_t* a = o + (uint64_t)p * Q;
-      const uint32_t* b = a + (uint64_t)sp * Q;
-      for (uint32_t j = 0; j < Q; j++) np += slice_len(a[j], b[j], run_len[j]);   // as in k_join
-      it = (uint32_t)((np + JCH - 1) / JCH);
-    }
+  const uint32_t sp = p < P ? span[p] : 0u;
+  uint64_t np = 0;
+  if (sp) {
+    const uint32_t* a = o + (uint64_t)p * Q;
+    const uint32_t* b = a + (uint64_t)sp * Q;
+    for (uint32_t j = lane; j < Q; j += 64) np += slice_len(a[j], b[j], run_len[j]);   // as in k_join
   }
-  items[p] = it;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) np += __shfl_xor(np, d, 64);
+  if (lane == 0) items[p] = (uint32_t)((np + JCH - 1) / JCH);
 }
 
 enum { VAL_HR = 0, VAL_RAW = 1 };

@@ -829,13 +829,23 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       uint32_t* plen = reinterpret_cast<uint32_t*>(ws + P.plen);
       uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + P.pkey);
       uint8_t* const pterm = bmpsm ? reinterpret_cast<uint8_t*>(ws + P.pterm) : nullptr;
-      if (bmpsm)
+      if (bmpsm) {
         k_partitions_runs<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), P.NB1, Pc, pstart, plen, pkey,
                                               pterm, stats ? res : nullptr);
-      else
-        k_partitions<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), Pc, pstart, plen, pkey,
-                                         stats ? res : nullptr);
-      LAUNCH_CHECK();
+        LAUNCH_CHECK();
+      } else {
+        // flags in items, their scan in item_pre (both free until the join's items are counted)
+        uint32_t* flags = reinterpret_cast<uint32_t*>(ws + P.items);
+        uint32_t* pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
+        const uint32_t nb = (uint32_t)cdiv(LRf->Gmax, 256);
+        k_partition_flags<<<nb, 256, 0, st>>>(LRf->bstart, LRf->Gcount(), LRf->Gmax, flags);
+        LAUNCH_CHECK();
+        rc = scan_u32(flags, pre, LRf->Gmax, bsum, st);
+        if (rc != MPSM_OK) return rc;
+        k_partition_write<<<nb, 256, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gmax, flags, pre, Pc, pstart, plen, pkey,
+                                              stats ? res : nullptr);
+        LAUNCH_CHECK();
+      }
       uint8_t* span = reinterpret_cast<uint8_t*>(ws + P.span);
       k_join_units<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, st>>>(Pc, plen, P.Pmax, span, pterm);
       LAUNCH_CHECK();
@@ -860,8 +870,8 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       mk.mark(MK_SEARCH);
       uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
       uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
-      k_join_items<<<(uint32_t)cdiv(P.Pmax + 2, 256), 256, 0, st>>>(Pc, o, P.Q, LS.seg.len, P.Pmax, P.JCH, span,
-                                                                    items);
+      k_join_items<<<(uint32_t)cdiv(((uint64_t)P.Pmax + 2) * 64, 256), 256, 0, st>>>(Pc, o, P.Q, LS.seg.len, P.Pmax,
+                                                                                     P.JCH, span, items);
       LAUNCH_CHECK();
       rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
       if (rc != MPSM_OK) return rc;
