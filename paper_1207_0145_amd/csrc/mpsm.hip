@@ -1111,6 +1111,9 @@ struct BatchPlan {
   uint64_t status, descs, T, U, Rp, Rs, cS, cR, bsum, bsumR, segS, segR, srcS, srcR, J, wave, splS, splR, bstS, bstR;
   uint64_t bndS, bndR, bigS, midS, redoS, midR, redoR, redoR2, bigR, ctr, bkey, Pc, pstart, plen, pkey, pjoin, ridx;
   uint64_t o, items, item_pre, tstart, ototal, span;
+  // passes without a histogram (as for one join): S's runs, R's segments
+  int padS, padR;
+  uint64_t capS, rstS, fillS, bsrcS, dirtyS, capR, rstR, fillR, bsrcR, dirtyR;
   uint64_t total;
 };
 
@@ -1181,11 +1184,15 @@ bool make_batch_plan(uint32_t n, const mpsm_batch_shape& sh, const mpsm_config& 
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) { uint64_t o = off; off += (bytes + 255) & ~255ull; return o; };
   const uint64_t ts = sizeof(tup_t);
+  // every join's runs and R segment are segments of the batch's passes, so
+  // the claims spread over many counters
+  P->padS = P->maxS >= (1u << 22) && pad_area(P->maxS) < (1ull << 32);
+  P->padR = P->maxR >= (1u << 22) && pad_area(P->maxR) < (1ull << 32);
   P->status = take(8);   // offset 0: the batch status word
   P->descs = take((uint64_t)n * sizeof(mpsm_join_desc));
-  P->T = take(P->maxS * ts);
+  P->T = take((P->padS ? pad_area(P->maxS) : P->maxS) * ts);
   P->U = take(P->maxS * ts);
-  P->Rp = take(P->maxR * ts);
+  P->Rp = take((P->padR ? pad_area(P->maxR) : P->maxR) * ts);
   P->Rs = take(P->maxR * ts);
   P->cS = take(P->cntS * 4 + 4);
   P->cR = take(P->cntR * 4);
@@ -1212,7 +1219,7 @@ bool make_batch_plan(uint32_t n, const mpsm_batch_shape& sh, const mpsm_config& 
   P->redoR = take((uint64_t)P->Gr * 4);
   P->redoR2 = take((uint64_t)P->Gr * 4);
   P->bigR = take((uint64_t)P->Gr * 4);
-  P->ctr = take(8 * 8);
+  P->ctr = take(16 * 8);
   P->bkey = take((uint64_t)P->Gr * 8);
   P->Pc = take(4);
   P->pstart = take((uint64_t)P->Pmax * 4);
@@ -1226,6 +1233,20 @@ bool make_batch_plan(uint32_t n, const mpsm_batch_shape& sh, const mpsm_config& 
   P->tstart = take(8);
   P->ototal = take(8);
   P->span = take((uint64_t)P->Pmax + 2);
+  if (P->padS) {
+    P->capS = take((uint64_t)P->Gs * 4);
+    P->rstS = take((uint64_t)P->Gs * 4);
+    P->fillS = take((uint64_t)P->Gs * 4);
+    P->bsrcS = take(((uint64_t)P->Gs + 1) * 4);
+    P->dirtyS = take((uint64_t)P->Qmax * 4);
+  }
+  if (P->padR) {
+    P->capR = take((uint64_t)P->Gr * 4);
+    P->rstR = take((uint64_t)P->Gr * 4);
+    P->fillR = take((uint64_t)P->Gr * 4);
+    P->bsrcR = take(((uint64_t)P->Gr + 1) * 4);
+    P->dirtyR = take((uint64_t)n * 4);
+  }
   P->total = off;
   return true;
 }
@@ -1270,11 +1291,23 @@ mpsm_status batch_enqueue(const mpsm_join_desc* d_descs, const BatchPlan& P, uin
   const uint32_t sort_grid_r = P.Gr < BATCH_SORT_GRID ? P.Gr : BATCH_SORT_GRID;
   for (uint32_t w = 0; w < P.W; w++) {
     k_batch_plan<<<1, BPLAN_NT, 0, st>>>(d_descs, P.n, wave, w, P.L, P.BT, P.Qmax, J, sgS.start, sgS.len, srcS,
-                                         sgR.start, sgR.len, srcR, reinterpret_cast<uint32_t*>(ctr), 16);
+                                         sgR.start, sgR.len, srcR, reinterpret_cast<uint32_t*>(ctr), 32);
     LAUNCH_CHECK();
     // phase 1: S runs of the wave's joins
     Level LS = make_level(ws, P.segS, P.Qmax, P.NBs, 0, P.OSs, P.tilesS, seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
                           P.bndS, P.Gs);
+    // regions of a pass without a histogram; `any` is a word of ctr, which
+    // k_batch_plan zeroes for every wave
+    auto regions = [&](Level& Lv, uint64_t cap, uint64_t rst, uint64_t fill, uint64_t dirty, uint64_t bsrc,
+                       uint32_t any_word) {
+      Lv.rg.cap = reinterpret_cast<uint32_t*>(ws + cap);
+      Lv.rg.start = reinterpret_cast<uint32_t*>(ws + rst);
+      Lv.rg.fill = reinterpret_cast<uint32_t*>(ws + fill);
+      Lv.rg.dirty = reinterpret_cast<uint32_t*>(ws + dirty);
+      Lv.rg.any = reinterpret_cast<uint32_t*>(ctr + any_word);
+      Lv.bsrc = reinterpret_cast<uint32_t*>(ws + bsrc);
+    };
+    if (P.padS) regions(LS, P.capS, P.rstS, P.fillS, P.dirtyS, P.bsrcS, 7);
     rc = bucket_pass(nullptr, T, 0, LS, bsum, st, mk, 0, srcS);
     if (rc != MPSM_OK) return rc;
     HIP_TRY(hipEventRecord(side->fork, st));
@@ -1291,20 +1324,21 @@ mpsm_status batch_enqueue(const mpsm_join_desc* d_descs, const BatchPlan& P, uin
     uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
     uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
     k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<sort_grid_s, BS_NT, 0, st>>>(
-        T, U, LS.bstart, nullptr, LS.blo, LS.bhi, LS.Gcount(), nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
+        T, U, LS.bstart, LS.bsrc, LS.blo, LS.bhi, LS.Gcount(), nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
     LAUNCH_CHECK();
     k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(
-        T, U, LS.bstart, nullptr, LS.blo, LS.bhi, LS.Gcount(), midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3, soS);
+        T, U, LS.bstart, LS.bsrc, LS.blo, LS.bhi, LS.Gcount(), midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3, soS);
     LAUNCH_CHECK();
-    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, nullptr, redoS, ctr + 3, bigS, ctr + 0, soS);
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, LS.bsrc, redoS, ctr + 3, bigS, ctr + 0, soS);
     LAUNCH_CHECK();
-    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, nullptr, bigS, ctr + 0, soS);
+    k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, LS.bsrc, bigS, ctr + 0, soS);
     LAUNCH_CHECK();
     // phases 2 and 3: one R segment per join, bucket counts from its size
     Level LR = make_level(ws, P.segR, P.n, MAX_NB, P.BT, P.OSr, P.tilesR, seed ^ TAG_R1, P.splR, P.cR, P.cntR,
                           P.bstR, P.bndR, P.Gr);
     const hipStream_t rst = side->st;
     Marker mkR{nullptr, 0, rst};
+    if (P.padR) regions(LR, P.capR, P.rstR, P.fillR, P.dirtyR, P.bsrcR, 8);
     rc = bucket_pass(nullptr, Rp, 0, LR, reinterpret_cast<uint32_t*>(ws + P.bsumR), rst, mkR, 0, srcR);
     if (rc != MPSM_OK) return rc;
     SortOut soR;
@@ -1320,17 +1354,17 @@ mpsm_status batch_enqueue(const mpsm_join_desc* d_descs, const BatchPlan& P, uin
     uint32_t* redoR2 = reinterpret_cast<uint32_t*>(ws + P.redoR2);
     uint32_t* bigR = reinterpret_cast<uint32_t*>(ws + P.bigR);
     k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<sort_grid_r, BS_NT, 0, rst>>>(
-        Rp, Rs, LR.bstart, nullptr, LR.blo, LR.bhi, LR.Gcount(), nullptr, nullptr, midR, ctr + 6, redoR, ctr + 4, soR);
+        Rp, Rs, LR.bstart, LR.bsrc, LR.blo, LR.bhi, LR.Gcount(), nullptr, nullptr, midR, ctr + 6, redoR, ctr + 4, soR);
     LAUNCH_CHECK();
     k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, rst>>>(
-        Rp, Rs, LR.bstart, nullptr, LR.blo, LR.bhi, LR.Gcount(), midR, ctr + 6, bigR, ctr + 1, redoR, ctr + 4, soR);
+        Rp, Rs, LR.bstart, LR.bsrc, LR.blo, LR.bhi, LR.Gcount(), midR, ctr + 6, bigR, ctr + 1, redoR, ctr + 4, soR);
     LAUNCH_CHECK();
     k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, true><<<g_num_cus, BL_NT, 0, rst>>>(
-        Rp, Rs, LR.bstart, nullptr, LR.blo, LR.bhi, LR.Gcount(), redoR, ctr + 4, bigR, ctr + 1, redoR2, ctr + 5, soR);
+        Rp, Rs, LR.bstart, LR.bsrc, LR.blo, LR.bhi, LR.Gcount(), redoR, ctr + 4, bigR, ctr + 1, redoR2, ctr + 5, soR);
     LAUNCH_CHECK();
-    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rp, Rs, LR.bstart, nullptr, redoR2, ctr + 5, bigR, ctr + 1, soR);
+    k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, rst>>>(Rp, Rs, LR.bstart, LR.bsrc, redoR2, ctr + 5, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
-    k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rp, Rs, LR.bstart, nullptr, bigR, ctr + 1, soR);
+    k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rp, Rs, LR.bstart, LR.bsrc, bigR, ctr + 1, soR);
     LAUNCH_CHECK();
     // the rest needs R's partitions
     HIP_TRY(hipEventRecord(side->done, rst));

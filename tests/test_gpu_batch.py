@@ -226,3 +226,27 @@ def test_join_batch_device_check_rejects_out_of_bounds_batch():
     torch.cuda.synchronize()
     assert int(ws[:4].view(torch.int32).item()) == 1
     assert bool((out == -7).all())
+
+
+@pytest.mark.parametrize("oversample", [0, 2])
+def test_batch_passes_without_histogram(oversample):
+    """A batch whose S and R sums pass 2^22 takes the passes without a
+    histogram over every join's runs and R segment; with 2 sample keys per
+    bucket regions overflow and segments are redone by the exact path.  Every
+    join against the foreign-key closed form, eager and graph-replayed."""
+    ws_ = workloads.batch(24, 0x1207014500000d01 + oversample, 17, 20)
+    nS = sum(len(w.S) for w in ws_)
+    nR = sum(len(w.R) for w in ws_)
+    assert nS >= (1 << 22) and nR >= (1 << 22)
+    _say(f"batch without histograms: {len(ws_)} joins, sum |R| {nR}, sum |S| {nS}, oversample {oversample}")
+    joins = [(_dev(w.R), _dev(w.S)) for w in ws_]
+    b = mpsm.Batch(joins, mpsm.config(oversample=oversample))
+    for use_graph in (False, True, True):
+        b.out.zero_()
+        b.run(use_graph=use_graph)
+        torch.cuda.synchronize()
+        got = b.results()
+        for i, w in enumerate(ws_):
+            fk = oracle.fk_closed_form(w.R, w.S, w.partner)
+            assert got[i] == (fk.count, fk.checksum), (w.name, use_graph)
+    b.close()
