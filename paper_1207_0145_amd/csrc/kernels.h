@@ -1834,7 +1834,13 @@ __global__ void __launch_bounds__(JOIN_NT) k_join(JoinArgs A) {
   constexpr int JPF = JOIN_CAP / JOIN_NT;   // R tuples per thread
   tup_t pre[JPF];                          // next item's R partition, loaded during this item
   bool have_pre = false;
-  for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+  // Workgroup b runs on XCD b mod 8.  Items are taken in rounds of
+  // gridDim.x consecutive items; within a round the workgroups of one XCD
+  // take neighbouring items (neighbouring join units, whose slices of a run
+  // share their end lines), so those lines meet in one L2.
+  const uint32_t item0 = gridDim.x % N_XCD == 0 ? (blockIdx.x % N_XCD) * (gridDim.x / N_XCD) + blockIdx.x / N_XCD
+                                                : blockIdx.x;
+  for (uint32_t item = item0; item < total; item += gridDim.x) {
     const uint32_t p = item_partition(A.item_pre, np2, item);
     const uint32_t k = item - A.item_pre[p];
     const uint32_t pe = p + A.span[p];   // the item's join unit: partitions [p, pe)
