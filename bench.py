@@ -25,6 +25,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -407,7 +408,8 @@ def batch_bench(args):
     nR = sum(len(w.R) for w in ws)
     nS = sum(len(w.S) for w in ws)
     del ws
-    cache = os.path.join(ROOT, "gpurun_out", "batch_autotune.txt") if args.autotune_cache is None else args.autotune_cache
+    cache = os.path.join(tempfile.gettempdir(), "mpsm_batch_autotune.txt") if args.autotune_cache is None \
+        else args.autotune_cache
     os.makedirs(os.path.dirname(cache), exist_ok=True)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -718,7 +720,7 @@ def main():
         print(json.dumps(t, indent=1))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 
