@@ -995,7 +995,8 @@ __global__ void __launch_bounds__(NT, MINB) k_bucket_sort_cs(const tup_t* __rest
         key[k] = ~0ull; val[k] = 0;
       }
     }
-    __syncthreads();   // LDS of the previous bucket is free
+    // LDS of the previous bucket is free (a workgroup that takes one bucket has none)
+    if (!once) __syncthreads();
     for (uint32_t b = tid; b <= (uint32_t)M; b += NT) cnt[b] = 0;
     for (uint32_t b = tid; b < (uint32_t)(CAP / 4); b += NT) gcnt[b] = 0;
     if (tid < 2) nslot[tid] = 0;
