@@ -524,7 +524,12 @@ def experiment_bench(args):
                m = 1, 4, 8, 16; R private (as given) against S private;
       locskew  (Section 5.5) |R| = 2^24, |S| = 2^26 uniform foreign keys, S
                unordered against S ordered small to large in one cluster per
-               S run."""
+               S run;
+      hostruns (Section 3.1) |R| = 2^26, |S| = 2^28 uniform foreign keys with
+               S and its sorted runs in pinned host memory, for several
+               chunk sizes (the share of S on the device at a time), against
+               the join with S in device memory and the host link's copy
+               rates."""
     import numpy as np
     import torch
     import paper_1207_0145_amd as mpsm
@@ -574,6 +579,58 @@ def experiment_bench(args):
                 "ms_per_step": res["m4"]["R_private"]["ms_per_step"],
                 "config": {"workload": "roles: |R|=2^24 uniform foreign keys, |S| = m |R|; value at m = 4, R private"},
                 "multiplicities": res}
+    elif args.workload == "hostruns":
+        w = workloads.make("fk_uniform")
+        nR, nS = len(w.R), len(w.S)
+        R = to_dev(w.R)
+        Sh = torch.empty((nS, 2), dtype=torch.int64, pin_memory=True)
+        Sh.copy_(torch.from_numpy(w.S.view(np.int64)))
+        del w
+        runs = torch.empty((nS, 2), dtype=torch.int64, pin_memory=True)
+        out = torch.zeros(2, dtype=torch.int64, device=dev)
+        # copy rates of the host link (pinned memory, one copy of S each way)
+        Sd = Sh.to(dev)
+        rates = {}
+        for name, dst, src in (("h2d", Sd, Sh), ("d2h", runs, Sd)):
+            dst.copy_(src, non_blocking=True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                dst.copy_(src, non_blocking=True)
+            torch.cuda.synchronize()
+            rates[name + "_GBps"] = round(3 * nS * 16 / (time.perf_counter() - t) / 1e9, 1)
+        log(f"host link: {rates}")
+        ms_dev, r_dev, ws = time_join(mpsm, torch, R, Sd, mpsm.config(), args, steps)
+        del ws, Sd
+        torch.cuda.empty_cache()
+        log(f"hostruns device-resident S: {ms_dev:.3f} ms")
+        res = {"device_resident": {"ms_per_step": round(ms_dev, 4), "result": r_dev}}
+        for lg in (28, 26, 24):
+            nbytes = mpsm.join_host_runs_workspace_bytes(nR, nS, 1 << lg)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            for _ in range(args.warmup):
+                mpsm.join_host_runs_into(R, Sh, runs, out, ws, 1 << lg)
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0.record()
+            for _ in range(steps):
+                mpsm.join_host_runs_into(R, Sh, runs, out, ws, 1 << lg)
+            t1.record()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / steps
+            c, k = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
+            res[f"chunk_2^{lg}"] = {"ms_per_step": round(ms, 4), "value": round((nR + nS) / (ms * 1e-3) / 1e6, 2),
+                                    "result": (c, f"{k:#018x}"), "workspace_GiB": round(nbytes / 2**30, 3)}
+            log(f"hostruns chunk 2^{lg}: {ms:.3f} ms, workspace {nbytes / 2**30:.2f} GiB")
+            del ws
+            torch.cuda.empty_cache()
+        # the least the host link allows: S in, the runs out, the runs read back
+        floor_ms = nS * 16 * (2 / rates["h2d_GBps"] + 1 / rates["d2h_GBps"]) / 1e6
+        line = {**base, "value": res["chunk_2^26"]["value"], "ms_per_step": res["chunk_2^26"]["ms_per_step"],
+                "config": {"workload": "hostruns: |R|=2^26, |S|=2^28 uniform foreign keys; S and its sorted runs "
+                                       "in pinned host memory, value at a chunk of 2^26 tuples"},
+                "chunks": res, "host_link": rates, "host_link_floor_ms": round(floor_ms, 2)}
     else:   # locskew
         w = workloads.fk_uniform(1 << 24, 1 << 26, seed=0x1207014500000901, spread=True)
         runs = mpsm.layout(len(w.R), len(w.S))["runs"]
@@ -688,7 +745,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal",
                     choices=["fk_uniform", "fk_small", "skewed", "lognormal", "batch", "negcorr", "roles",
-                             "locskew"])
+                             "locskew", "hostruns"])
     ap.add_argument("--extra", default="fk_uniform,skewed",
                     help="comma-separated single-join workloads reported beside the headline ('' for none)")
     ap.add_argument("--autotune-cache", default=None, help="batch workload: autotuner cache file")
@@ -727,7 +784,7 @@ def main():
     if args.workload == "batch":
         batch_bench(args)
         return
-    if args.workload in ("negcorr", "roles", "locskew"):
+    if args.workload in ("negcorr", "roles", "locskew", "hostruns"):
         experiment_bench(args)
         return
     import torch

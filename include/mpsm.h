@@ -255,6 +255,34 @@ mpsm_status mpsm_join_events(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tupl
                              uint64_t pairs_capacity, const mpsm_config* cfg, void* d_workspace,
                              uint64_t workspace_bytes, void* stream, void** events, uint32_t n_events);
 
+/* The equi-join with S outside device memory (the memory-constrained
+ * variant of Section 3.1 and its Figure 4, which writes the sorted runs to
+ * disk and reads them back in key order during the join; here the runs live
+ * in host memory and the join reads them over the host link):
+ *   h_S       pinned host array (hipHostMalloc, or a pinned torch tensor) of
+ *             nS tuples, 16-byte aligned; read only.
+ *   h_runs    pinned host array of nS tuples, 16-byte aligned, written: on
+ *             completion it holds S's Q = ceil(nS / L) runs in place (run q
+ *             is S[q*L, min((q+1)*L, nS)) sorted by key, L = 2^log2_run_len),
+ *             which the search and the join read where they are.
+ *   chunk_tuples  tuples copied in and sorted at a time (rounded down to a
+ *             multiple of L, at least L): the device holds one chunk of S,
+ *             so the workspace grows with it, not with nS.
+ * d_R, nR, d_out_count, d_out_checksum, d_workspace (at least
+ * mpsm_join_host_runs_workspace_bytes() bytes) and stream as for mpsm_join;
+ * R stays the private input and S the public one (cfg->role SWAP, and the
+ * splitter kinds that need S's runs before R's partitioning, COST and NONE,
+ * return MPSM_EINVAL), no pairs are written and no statistics kept.  A host
+ * buffer that the device cannot address returns MPSM_EINVAL before anything
+ * is enqueued.  The call returns once the work is enqueued on `stream`;
+ * h_S must stay unchanged and h_runs unread until the stream completes. */
+uint64_t mpsm_join_host_runs_workspace_bytes(uint64_t nR, uint64_t nS, const mpsm_config* cfg,
+                                             uint64_t chunk_tuples);
+mpsm_status mpsm_join_host_runs(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* h_S, uint64_t nS,
+                                mpsm_tuple* h_runs, uint64_t* d_out_count, uint64_t* d_out_checksum,
+                                const mpsm_config* cfg, uint64_t chunk_tuples, void* d_workspace,
+                                uint64_t workspace_bytes, void* stream);
+
 /* Number of markers and the name of the step that ends at marker i
  * (static string; NULL for i out of range). */
 uint32_t mpsm_marker_count(void);

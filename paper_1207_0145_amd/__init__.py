@@ -27,7 +27,7 @@ EXPORTS = ("mpsm_config_default", "mpsm_workspace_bytes", "mpsm_join", "mpsm_sta
            "mpsm_batch_destroy", "mpsm_batch_workspace_bytes", "mpsm_batch_run", "mpsm_batch_autotune",
            "mpsm_batch_get_tuning", "mpsm_batch_set_tuning", "mpsm_clock_hz", "mpsm_join_slices_host",
            "mpsm_join_noalloc", "mpsm_join_batch", "mpsm_join_batch_workspace_bytes",
-           "mpsm_lower_bound_window_host")
+           "mpsm_lower_bound_window_host", "mpsm_join_host_runs", "mpsm_join_host_runs_workspace_bytes")
 
 
 class MpsmConfig(ctypes.Structure):
@@ -149,6 +149,10 @@ def lib():
         L.mpsm_lower_bound_window_host.restype = ctypes.c_int
         L.mpsm_join_noalloc.argtypes = [p, u64, p, u64, p, p, p, u64, ctypes.POINTER(MpsmConfig), p]
         L.mpsm_join_noalloc.restype = ctypes.c_int
+        L.mpsm_join_host_runs_workspace_bytes.argtypes = [u64, u64, ctypes.POINTER(MpsmConfig), u64]
+        L.mpsm_join_host_runs_workspace_bytes.restype = u64
+        L.mpsm_join_host_runs.argtypes = [p, u64, p, u64, p, p, p, ctypes.POINTER(MpsmConfig), u64, p, u64, p]
+        L.mpsm_join_host_runs.restype = ctypes.c_int
         L.mpsm_join_batch_workspace_bytes.argtypes = [ctypes.c_uint32, ctypes.POINTER(MpsmBatchShape),
                                                       ctypes.POINTER(MpsmConfig)]
         L.mpsm_join_batch_workspace_bytes.restype = u64
@@ -249,6 +253,38 @@ def join_noalloc_into(R, S, out, cfg: MpsmConfig | None = None, stream=None, pai
                                  pp, cap, _cfg_ptr(cfg), _stream_handle(stream))
     if rc != 0:
         raise MpsmError(rc, "mpsm_join_noalloc")
+    return rc
+
+
+def join_host_runs_workspace_bytes(nR: int, nS: int, chunk_tuples: int, cfg: MpsmConfig | None = None) -> int:
+    return int(lib().mpsm_join_host_runs_workspace_bytes(nR, nS, _cfg_ptr(cfg), chunk_tuples))
+
+
+def _check_host_tuples(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.is_cuda or (t.numel() and not t.is_pinned()):
+        raise TypeError(f"{name} must be a pinned host tensor")
+    if t.dim() != 2 or t.shape[1] != 2 or t.dtype not in (torch.int64, torch.uint64) or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous [n, 2] int64/uint64 tensor")
+
+
+def join_host_runs_into(R, S_host, runs_host, out, workspace, chunk_tuples: int, cfg: MpsmConfig | None = None,
+                        stream=None) -> int:
+    """mpsm_join_host_runs: the join with S (and its sorted runs, written to
+    runs_host) in pinned host memory; R, out and workspace on the GPU as in
+    join_into.  Enqueues the work; runs_host is complete once the stream is."""
+    _check_tuples(R, "R")
+    _check_host_tuples(S_host, "S_host")
+    _check_host_tuples(runs_host, "runs_host")
+    if runs_host.shape[0] != S_host.shape[0]:
+        raise ValueError("runs_host must hold as many tuples as S_host")
+    rc = lib().mpsm_join_host_runs(ctypes.c_void_p(R.data_ptr()), R.shape[0], ctypes.c_void_p(S_host.data_ptr()),
+                                   S_host.shape[0], ctypes.c_void_p(runs_host.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(out.data_ptr() + 8),
+                                   _cfg_ptr(cfg), chunk_tuples, ctypes.c_void_p(workspace.data_ptr()),
+                                   workspace.numel(), _stream_handle(stream))
+    if rc != 0:
+        raise MpsmError(rc, "mpsm_join_host_runs")
     return rc
 
 

@@ -40,6 +40,13 @@ struct Plan {
   // bucket passes without a histogram (sample-sized regions in areas of
   // pad_area tuples): S's runs, R's runs (B-MPSM), R's second level
   int padS, padR1, padR2;
+  // S in host memory (the disk-resident variant): phase 1 runs over chunks of
+  // nSc tuples (Qc runs each) and the sorted runs go back to host memory,
+  // where the search and the join read them; run start/length of all Q runs
+  // in runtab.  Otherwise nSc = nS and Qc = Q.
+  int hostS;
+  uint64_t nSc;
+  uint32_t Qc;
   uint32_t Gs, Gr, Pmax;
   uint32_t idx_per_run;
   uint32_t JCH, BT;
@@ -63,6 +70,7 @@ struct Plan {
   uint64_t capS, rstS, fillS, bsrcS, dirtyS;        // S's regions (padS)
   uint64_t capR1, rstR1, fillR1, bsrcR1, dirtyR1;   // R's level-1 regions (padR1)
   uint64_t capR2, rstR2, fillR2, bsrcR2, dirtyR2;   // R's level-2 regions (padR2)
+  uint64_t runtab;                                  // hostS: run start (Q + 1), then length (Q + 1)
   uint64_t total;
 };
 
@@ -84,10 +92,12 @@ bool config_valid(const mpsm_config* c) {
   return true;
 }
 
-bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
+bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P, uint64_t chunk = 0) {
   memset(P, 0, sizeof(*P));
   if (nR_c >= (1ull << 32) || nS_c >= (1ull << 32)) return false;
-  P->swapped = cfg->role == MPSM_ROLE_SWAP || (cfg->role == MPSM_ROLE_AUTO && nS_c < nR_c);
+  P->hostS = chunk != 0;
+  // with S in host memory the roles stay as given (S is the public input)
+  P->swapped = !P->hostS && (cfg->role == MPSM_ROLE_SWAP || (cfg->role == MPSM_ROLE_AUTO && nS_c < nR_c));
   P->nR = P->swapped ? nS_c : nR_c;
   P->nS = P->swapped ? nR_c : nS_c;
   P->search = cfg->search;
@@ -116,6 +126,13 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   P->L = (uint32_t)L;
   P->Q = P->nS ? (uint32_t)cdiv(P->nS, L) : 1;
   if (P->Q > (uint32_t)JOIN_QMAX) return false;
+  P->nSc = P->nS;
+  if (P->hostS) {   // whole runs per chunk
+    uint64_t c = chunk / L * L;
+    if (c < L) c = L;
+    if (c < P->nSc) P->nSc = c;
+  }
+  P->Qc = P->nSc ? (uint32_t)cdiv(P->nSc, L) : 1;
   P->NBs = (uint32_t)cdiv(L, BTs);
   if (P->NBs > (uint32_t)MAX_NB) P->NBs = MAX_NB;
   const uint32_t OSreq = cfg->oversample ? cfg->oversample : 32u;
@@ -161,13 +178,13 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
     const uint32_t OS2req = cfg->oversample ? cfg->oversample : OS2def;
     P->OS2 = SMP_CAP / P->NB2 < OS2req ? SMP_CAP / P->NB2 : OS2req;
   }
-  P->Gs = P->Q * P->NBs;
+  P->Gs = P->Qc * P->NBs;
   P->Gr = P->QR * P->NB1 * P->NB2;
   P->Pmax = P->Gr + (P->splitter == MPSM_SPLIT_NONE ? P->QR : 0u);   // B-MPSM: one terminator per R run
   P->idx_per_run = (uint32_t)cdiv(L, IDX_STRIDE);
   P->JCH = cfg->join_chunk ? cfg->join_chunk : 32768u;
   P->BT = BT;
-  P->tilesS = (uint32_t)(P->nS / HIST_TILE + P->Q);
+  P->tilesS = (uint32_t)(P->nSc / HIST_TILE + P->Qc);
   P->tilesR1 = (uint32_t)(P->nR / HIST_TILE + P->QR);
   P->tilesR2 = (uint32_t)(P->nR / HIST_TILE + P->NB1);
   P->cntS = (uint64_t)P->tilesS * P->NBs;
@@ -185,14 +202,14 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   // of every chunk meet on the same 256 counters (measured: its scatter
   // 3x slower than histogram and scatter together).
   const bool big_r = P->nR >= (1u << 22) && pad_area(P->nR) < (1ull << 32);
-  P->padS = P->nS >= (1u << 22) && pad_area(P->nS) < (1ull << 32);
+  P->padS = P->nSc >= (1u << 22) && pad_area(P->nSc) < (1ull << 32);
   P->padR1 = big_r && P->splitter == MPSM_SPLIT_NONE;
   P->padR2 = big_r && P->levels == 2;
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) { uint64_t o = off; off += (bytes + 255) & ~255ull; return o; };
   const uint64_t ts = sizeof(tup_t);
-  P->T = take((P->padS ? pad_area(P->nS) : P->nS) * ts);
-  P->U = take(P->nS * ts);
+  P->T = take((P->padS ? pad_area(P->nSc) : P->nSc) * ts);
+  P->U = take(P->nSc * ts);   // hostS: one chunk's runs on their way to host memory
   P->R1 = take((P->padR1 ? pad_area(P->nR) : P->nR) * ts);
   P->R2 = take((P->padR2 ? pad_area(P->nR) : P->nR) * ts);
   P->cS = take(P->cntS * 4);
@@ -204,10 +221,10 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
   if (P->item_cap > maxscan) maxscan = P->item_cap;
   P->bsum = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);
   P->bsumR = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);   // R's scans, which may run beside S's
-  P->segS = take(6ull * (P->Q + 1) * 4);
+  P->segS = take(6ull * (P->Qc + 1) * 4);
   P->segR1 = take(6ull * (P->QR + 1) * 4);
   P->segR2 = take(6ull * (P->NB1 + 1) * 4);
-  P->splS = take((uint64_t)P->Q * P->NBs * 8);
+  P->splS = take((uint64_t)P->Qc * P->NBs * 8);
   P->splR1 = take((uint64_t)P->QR * P->NB1 * 8);
   P->splR2 = take((uint64_t)P->NB1 * P->NB2 * 8);
   P->bstS = take(((uint64_t)P->Gs + 1) * 4);
@@ -249,8 +266,9 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P) {
     P->rstS = take((uint64_t)P->Gs * 4);
     P->fillS = take((uint64_t)P->Gs * 4);
     P->bsrcS = take(((uint64_t)P->Gs + 1) * 4);
-    P->dirtyS = take((uint64_t)P->Q * 4);
+    P->dirtyS = take((uint64_t)P->Qc * 4);
   }
+  if (P->hostS) P->runtab = take(2ull * (P->Q + 1) * 4);
   if (P->padR1) {
     const uint64_t g1 = (uint64_t)P->QR * P->NB1;
     P->capR1 = take(g1 * 4);
@@ -281,6 +299,23 @@ Seg seg_at(char* ws, uint64_t off, uint32_t nseg) {
   s.nb = b + 4 * (nseg + 1);
   s.b0 = b + 5 * (nseg + 1);
   return s;
+}
+
+// Zeroes the 64-bit words w[i] whose bit i is set in mask.
+__global__ void k_clear_words(unsigned long long* w, uint32_t mask) {
+  const uint32_t i = threadIdx.x;
+  if (i < 32 && ((mask >> i) & 1u)) w[i] = 0;
+}
+
+// Start and length of each of the Q runs of L tuples over [0, n) (entry Q:
+// start n, length 0), for runs that are not the segments of a bucket pass.
+__global__ void k_run_table(uint32_t* start, uint32_t* len, uint32_t Q, uint32_t L, uint32_t n) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q > Q) return;
+  const uint64_t a = (uint64_t)q * L;
+  const uint32_t s = (uint32_t)(a < n ? a : n);
+  start[q] = s;
+  len[q] = q < Q ? (n - s < L ? n - s : L) : 0u;
 }
 
 #define HIP_TRY(x)                        \
@@ -596,10 +631,22 @@ mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* c
 
 namespace {
 
+// S in pinned host memory (the runs of S kept outside device memory, as the
+// memory-constrained variant of Section 3.1 keeps them on disk): its tuples, its
+// sorted runs, each by its host address (copies) and its device address
+// (kernels), and the tuples of whole runs copied in and sorted at a time.
+struct HostS {
+  const tup_t* S_host;
+  const tup_t* S_dev;
+  tup_t* runs_host;
+  const tup_t* runs_dev;
+  uint64_t chunk;
+};
+
 mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS, uint64_t* d_out_count,
                       uint64_t* d_out_checksum, mpsm_pair* d_pairs, uint64_t pairs_capacity, const mpsm_config* cfg,
                       void* d_workspace, uint64_t workspace_bytes, void* stream, mpsm_stats* stats, void** events,
-                      uint32_t n_events, bool single_stream = false) {
+                      uint32_t n_events, bool single_stream = false, const HostS* hs = nullptr) {
   mpsm_config def;
   if (!cfg) { mpsm_config_default(&def); cfg = &def; }
   if (!config_valid(cfg)) return MPSM_EINVAL;
@@ -609,7 +656,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     return MPSM_EINVAL;
   if (d_pairs && pairs_capacity == 0) d_pairs = nullptr;
   Plan P;
-  if (!make_plan(nR, nS, cfg, &P)) return MPSM_EINVAL;
+  if (!make_plan(nR, nS, cfg, &P, hs ? hs->chunk : 0)) return MPSM_EINVAL;
   if (workspace_bytes < P.total) return MPSM_ENOMEM;
   hipStream_t st = (hipStream_t)stream;
   if (!g_num_cus) {
@@ -677,7 +724,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       memset(&job, 0, sizeof(job));
       uint32_t nm = 0;
       if (learn_r) { job.src[nm] = Rin; job.n[nm] = (uint32_t)P.nR; job.seed[nm] = P.seed ^ TAG_CR; job.model[nm] = modelR; nm++; }
-      if (learn_s) { job.src[nm] = Sin; job.n[nm] = (uint32_t)P.nS; job.seed[nm] = P.seed ^ TAG_CS; job.model[nm] = modelS; nm++; }
+      if (learn_s) { job.src[nm] = hs ? hs->S_dev : Sin; job.n[nm] = (uint32_t)P.nS; job.seed[nm] = P.seed ^ TAG_CS; job.model[nm] = modelS; nm++; }
       mpsm_status rc = train_cdf(job, nm, reinterpret_cast<uint64_t*>(ws + P.cdf_chunks),
                                  reinterpret_cast<uint64_t*>(ws + P.cdf_sorted), side ? side->st : st);
       if (rc != MPSM_OK) return rc;
@@ -693,7 +740,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     } else {
       mpsm_status rc;
       // ---- phase 1: sort S into Q runs of L tuples
-      Level LS = make_level(ws, P.segS, P.Q, P.NBs, 0, P.OSs, P.tilesS, P.seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
+      Level LS = make_level(ws, P.segS, P.Qc, P.NBs, 0, P.OSs, P.tilesS, P.seed ^ TAG_S, P.splS, P.cS, P.cntS, P.bstS,
                             P.bndS, P.Gs);
       LS.run_len = P.L;
       // regions of a pass without a histogram; `any` is a word of ctr,
@@ -707,36 +754,85 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
         Lv.rg.any = reinterpret_cast<uint32_t*>(ctr + any_word);
         Lv.bsrc = reinterpret_cast<uint32_t*>(ws + bsrc);
       };
-      if (P.padS) regions(LS, P.capS, P.rstS, P.fillS, P.dirtyS, P.bsrcS, 7);
-      rc = bucket_pass(Sin, T, (uint32_t)P.nS, LS, bsum, st, mk, MK_S_SPL);
-      if (rc != MPSM_OK) return rc;
-      if (r_side) HIP_TRY(hipEventRecord(side->gate, st));
-      rc = start_models();
-      if (rc != MPSM_OK) return rc;
-      SortOut soS;
-      soS.run_idx = reinterpret_cast<uint64_t*>(ws + P.ridx);
-      soS.run_start = LS.seg.start;
-      soS.idx_stride = IDX_STRIDE;
-      soS.idx_shift = __builtin_ctz(IDX_STRIDE);
-      soS.idx_per_run = P.idx_per_run;
-      soS.NB = P.NBs;
-      soS.bkey = nullptr;
+      uint64_t* const ridx = reinterpret_cast<uint64_t*>(ws + P.ridx);
       uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
       uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
       uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
-      k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gs, BS_NT, 0, st>>>(T, U, LS.bstart, LS.bsrc, LS.blo, LS.bhi, LS.Gcount(),
-                                                                   nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, soS);
-      LAUNCH_CHECK();
-      k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(T, U, LS.bstart, LS.bsrc, LS.blo, LS.bhi, LS.Gcount(),
-                                                                        midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
-                                                                        soS);
-      LAUNCH_CHECK();
-      k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, LS.bstart, LS.bsrc, redoS, ctr + 3, bigS, ctr + 0, soS);
-      LAUNCH_CHECK();
-      mk.mark(MK_S_SORT);
-      k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, LS.bstart, LS.bsrc, bigS, ctr + 0, soS);
-      LAUNCH_CHECK();
-      mk.mark(MK_S_BIG);
+      // the bucket sorts of a pass over S's runs (T to U); run_idx: the index
+      // entries of the pass's first run
+      auto sort_runs = [&](const Level& Lv, uint64_t* run_idx) -> mpsm_status {
+        SortOut so;
+        so.run_idx = run_idx;
+        so.run_start = Lv.seg.start;
+        so.idx_stride = IDX_STRIDE;
+        so.idx_shift = __builtin_ctz(IDX_STRIDE);
+        so.idx_per_run = P.idx_per_run;
+        so.NB = P.NBs;
+        so.bkey = nullptr;
+        k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gs, BS_NT, 0, st>>>(T, U, Lv.bstart, Lv.bsrc, Lv.blo, Lv.bhi, Lv.Gcount(),
+                                                                     nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, so);
+        LAUNCH_CHECK();
+        k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(T, U, Lv.bstart, Lv.bsrc, Lv.blo, Lv.bhi, Lv.Gcount(),
+                                                                          midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
+                                                                          so);
+        LAUNCH_CHECK();
+        k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, Lv.bstart, Lv.bsrc, redoS, ctr + 3, bigS, ctr + 0, so);
+        LAUNCH_CHECK();
+        mk.mark(MK_S_SORT);
+        k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, Lv.bstart, Lv.bsrc, bigS, ctr + 0, so);
+        LAUNCH_CHECK();
+        mk.mark(MK_S_BIG);
+        return MPSM_OK;
+      };
+      // where the search and the join find S's runs
+      const tup_t* Uj = U;
+      const uint32_t* run_start = LS.seg.start;
+      const uint32_t* run_len = LS.seg.len;
+      if (!P.hostS) {
+        if (P.padS) regions(LS, P.capS, P.rstS, P.fillS, P.dirtyS, P.bsrcS, 7);
+        rc = bucket_pass(Sin, T, (uint32_t)P.nS, LS, bsum, st, mk, MK_S_SPL);
+        if (rc != MPSM_OK) return rc;
+        if (r_side) HIP_TRY(hipEventRecord(side->gate, st));
+        rc = start_models();
+        if (rc != MPSM_OK) return rc;
+        rc = sort_runs(LS, ridx);
+        if (rc != MPSM_OK) return rc;
+      } else {
+        // S in host memory: the tuples of whole runs at a time are copied
+        // into U, bucketed into T, sorted back into U and copied out to the
+        // host runs; the search and the join read the runs there.  The
+        // counters of S's passes (words 0, 2, 3 and 7 of ctr) start at zero
+        // in every chunk; R's passes, beside them, use the others.
+        for (uint64_t c = 0; c < P.nS; c += P.nSc) {
+          const uint64_t n = P.nS - c < P.nSc ? P.nS - c : P.nSc;
+          const uint32_t q0 = (uint32_t)(c / P.L), qn = (uint32_t)cdiv(n, P.L);
+          if (c) {
+            k_clear_words<<<1, 64, 0, st>>>(ctr, (1u << 0) | (1u << 2) | (1u << 3) | (1u << 7));
+            LAUNCH_CHECK();
+          }
+          HIP_TRY(hipMemcpyAsync(U, hs->S_host + c, n * sizeof(tup_t), hipMemcpyHostToDevice, st));
+          Level LC = make_level(ws, P.segS, qn, P.NBs, 0, P.OSs, P.tilesS, P.seed ^ TAG_S, P.splS, P.cS, P.cntS,
+                                P.bstS, P.bndS, qn * P.NBs);
+          LC.run_len = P.L;
+          if (P.padS) regions(LC, P.capS, P.rstS, P.fillS, P.dirtyS, P.bsrcS, 7);
+          rc = bucket_pass(U, T, (uint32_t)n, LC, bsum, st, mk, MK_S_SPL);
+          if (rc != MPSM_OK) return rc;
+          if (c == 0) {
+            if (r_side) HIP_TRY(hipEventRecord(side->gate, st));
+            rc = start_models();
+            if (rc != MPSM_OK) return rc;
+          }
+          rc = sort_runs(LC, ridx + (uint64_t)q0 * P.idx_per_run);
+          if (rc != MPSM_OK) return rc;
+          HIP_TRY(hipMemcpyAsync(hs->runs_host + c, U, n * sizeof(tup_t), hipMemcpyDeviceToHost, st));
+        }
+        uint32_t* rt = reinterpret_cast<uint32_t*>(ws + P.runtab);
+        k_run_table<<<(uint32_t)cdiv((uint64_t)P.Q + 1, 256), 256, 0, st>>>(rt, rt + P.Q + 1, P.Q, P.L, (uint32_t)P.nS);
+        LAUNCH_CHECK();
+        Uj = hs->runs_dev;
+        run_start = rt;
+        run_len = rt + P.Q + 1;
+      }
 
       // ---- phase 2: range-partition R (one or two levels); phase 3: sort partitions
       const bool bmpsm = P.splitter == MPSM_SPLIT_NONE;
@@ -748,7 +844,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
         cost_args.sample = reinterpret_cast<uint64_t*>(ws + P.cost_sample);
         cost_args.s_below = reinterpret_cast<uint64_t*>(ws + P.cost_s_below);
         cost_args.best = reinterpret_cast<double*>(ws + P.cost_best);
-        cost_args.run_idx = soS.run_idx;
+        cost_args.run_idx = ridx;
         cost_args.run_len = LS.seg.len;
         cost_args.Q = P.Q;
         cost_args.idx_per_run = P.idx_per_run;
@@ -863,7 +959,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
         LAUNCH_CHECK();
       }
       const uint64_t nsearch = cdiv((uint64_t)P.Pmax + 1, 64) * cdiv(P.Q, SEARCH_RUNS);
-      k_search<<<(uint32_t)nsearch, SEARCH_NT, 0, st>>>(U, LS.seg.start, LS.seg.len, P.Q,
+      k_search<<<(uint32_t)nsearch, SEARCH_NT, 0, st>>>(Uj, run_start, run_len, P.Q,
                                                             reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
                                                             P.idx_per_run, Pc, pkey, P.Pmax, o,
                                                             learn_s ? MPSM_SEARCH_LEARNED
@@ -874,7 +970,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       mk.mark(MK_SEARCH);
       uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
       uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
-      k_join_items<<<(uint32_t)cdiv(((uint64_t)P.Pmax + 2) * 64, 256), 256, 0, st>>>(Pc, o, P.Q, LS.seg.len, P.Pmax,
+      k_join_items<<<(uint32_t)cdiv(((uint64_t)P.Pmax + 2) * 64, 256), 256, 0, st>>>(Pc, o, P.Q, run_len, P.Pmax,
                                                                                      P.JCH, span, items);
       LAUNCH_CHECK();
       rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
@@ -883,9 +979,9 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
 
       JoinArgs A;
       A.Rs = Rsorted;
-      A.U = U;
-      A.run_start = LS.seg.start;
-      A.run_len = LS.seg.len;
+      A.U = Uj;
+      A.run_start = run_start;
+      A.run_len = run_len;
       A.Q = P.Q;
       A.Pcount = Pc;
       A.pstart = pstart;
@@ -972,7 +1068,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       for (uint32_t d : dirty) *out += d ? 1 : 0;
       return MPSM_OK;
     };
-    mpsm_status rr = redone(P.padS, P.dirtyS, P.Q, &stats->redone_runs);
+    mpsm_status rr = redone(P.padS, P.dirtyS, P.Qc, &stats->redone_runs);
     if (rr == MPSM_OK) rr = redone(P.padR1, P.dirtyR1, P.QR, &stats->redone_r_segments);
     if (rr == MPSM_OK) rr = redone(P.padR2, P.dirtyR2, P.NB1, &stats->redone_r_segments);
     if (rr != MPSM_OK) return rr;
@@ -999,6 +1095,61 @@ mpsm_status mpsm_join_events(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tupl
   if (n_events && !events) return MPSM_EINVAL;
   return join_impl(d_R, nR, d_S, nS, d_out_count, d_out_checksum, d_pairs, pairs_capacity, cfg, d_workspace,
                    workspace_bytes, stream, nullptr, events, n_events);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Options the join with S in host memory supports: S keeps its role (it is
+// the relation outside device memory) and R's splitters need no S runs.
+bool host_runs_config_ok(const mpsm_config* cfg) {
+  return config_valid(cfg) && cfg->role != MPSM_ROLE_SWAP &&
+         (cfg->splitter == MPSM_SPLIT_SAMPLED || cfg->splitter == MPSM_SPLIT_LEARNED);
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t mpsm_join_host_runs_workspace_bytes(uint64_t nR, uint64_t nS, const mpsm_config* cfg, uint64_t chunk_tuples) {
+  mpsm_config def;
+  if (!cfg) { mpsm_config_default(&def); cfg = &def; }
+  if (!host_runs_config_ok(cfg) || chunk_tuples == 0) return 0;
+  Plan P;
+  if (!make_plan(nR, nS, cfg, &P, chunk_tuples)) return 0;
+  return P.total;
+}
+
+mpsm_status mpsm_join_host_runs(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* h_S, uint64_t nS,
+                                mpsm_tuple* h_runs, uint64_t* d_out_count, uint64_t* d_out_checksum,
+                                const mpsm_config* cfg, uint64_t chunk_tuples, void* d_workspace,
+                                uint64_t workspace_bytes, void* stream) {
+  mpsm_config def;
+  if (!cfg) { mpsm_config_default(&def); cfg = &def; }
+  if (!host_runs_config_ok(cfg) || chunk_tuples == 0) return MPSM_EINVAL;
+  if (nS && (!h_S || !h_runs)) return MPSM_EINVAL;
+  if (((uintptr_t)h_S & 15) || ((uintptr_t)h_runs & 15)) return MPSM_EINVAL;
+  HostS hs;
+  hs.S_host = reinterpret_cast<const tup_t*>(h_S);
+  hs.runs_host = reinterpret_cast<tup_t*>(h_runs);
+  hs.S_dev = nullptr;
+  hs.runs_dev = nullptr;
+  hs.chunk = chunk_tuples;
+  if (nS) {
+    // both buffers must be pinned host memory the device can address
+    void* p = nullptr;
+    void* q = nullptr;
+    if (hipHostGetDevicePointer(&p, const_cast<mpsm_tuple*>(h_S), 0) != hipSuccess || !p ||
+        hipHostGetDevicePointer(&q, h_runs, 0) != hipSuccess || !q) {
+      (void)hipGetLastError();   // the failed lookup is the caller's error, not a later call's
+      return MPSM_EINVAL;
+    }
+    hs.S_dev = static_cast<const tup_t*>(p);
+    hs.runs_dev = static_cast<const tup_t*>(q);
+  }
+  return join_impl(d_R, nR, h_S, nS, d_out_count, d_out_checksum, nullptr, 0, cfg, d_workspace, workspace_bytes,
+                   stream, nullptr, nullptr, 0, false, &hs);
 }
 
 }  // extern "C"

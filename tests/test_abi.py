@@ -67,6 +67,41 @@ def test_unsupported_sizes():
     assert mpsm.workspace_bytes(10, 10, bad) == 0
 
 
+def test_host_runs_workspace():
+    """The join with S in host memory holds one chunk of S on the device: its
+    workspace shrinks by both copies of the rest of S (the bucketed and the
+    sorted one); options it does not take and chunk 0 size to 0."""
+    nR, nS, chunk = 1 << 20, 1 << 30, 1 << 24
+    full = mpsm.workspace_bytes(nR, nS)
+    host = mpsm.join_host_runs_workspace_bytes(nR, nS, chunk)
+    assert 0 < host and host + 2 * 16 * (nS - chunk) <= full
+    assert mpsm.join_host_runs_workspace_bytes(nR, nS, nS) >= full - 1024
+    assert mpsm.join_host_runs_workspace_bytes(nR, nS, 1) == mpsm.join_host_runs_workspace_bytes(nR, nS, 1 << 16)
+    assert mpsm.join_host_runs_workspace_bytes(nR, nS, 0) == 0
+    assert mpsm.join_host_runs_workspace_bytes(nR, 1 << 32, chunk) == 0
+    for kw in (dict(splitter=mpsm.SPLIT_COST), dict(splitter=mpsm.SPLIT_NONE), dict(role=mpsm.ROLE_SWAP)):
+        assert mpsm.join_host_runs_workspace_bytes(nR, nS, chunk, mpsm.config(**kw)) == 0, kw
+    assert mpsm.join_host_runs_workspace_bytes(nR, nS, chunk, mpsm.config(splitter=mpsm.SPLIT_LEARNED)) > 0
+
+
+def test_host_runs_bad_arguments_rejected_on_host():
+    # rejected before any HIP call: the pointers are never dereferenced
+    L = mpsm.lib()
+    good = ctypes.c_void_p(0x100000)
+
+    def call(S, runs, chunk, cfg=None):
+        return L.mpsm_join_host_runs(good, 5, S, 5, runs, good, good, None if cfg is None else ctypes.byref(cfg),
+                                     chunk, good, 1 << 40, None)
+
+    assert call(good, good, 0) == 1
+    assert call(None, good, 4096) == 1
+    assert call(good, None, 4096) == 1
+    assert call(ctypes.c_void_p(0x100008), good, 4096) == 1
+    assert call(good, ctypes.c_void_p(0x100004), 4096) == 1
+    assert call(good, good, 4096, mpsm.config(splitter=mpsm.SPLIT_COST)) == 1
+    assert call(good, good, 4096, mpsm.config(role=mpsm.ROLE_SWAP)) == 1
+
+
 def _call(R, nR, S, nS, out_c, out_s, ws, wsb, cfg=None):
     L = mpsm.lib()
     return L.mpsm_join(R, nR, S, nS, out_c, out_s, None, 0, None if cfg is None else ctypes.byref(cfg), ws, wsb,

@@ -1,0 +1,155 @@
+"""GPU parity of the join with S in host memory (the memory-constrained
+variant of Section 3.1, its runs kept in pinned host memory instead of on
+disk): count and checksum against the oracle's join, and the runs it leaves
+in host memory against the oracle's sorted runs (keys position by position,
+tuples as a multiset per run, since equal keys may come in any order)."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1207_0145_amd as mpsm
+import workloads
+
+pytestmark = pytest.mark.gpu
+U64 = (1 << 64) - 1
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _dev(a):
+    a = np.ascontiguousarray(a, dtype=np.uint64).reshape(-1, 2)
+    return torch.from_numpy(a.view(np.int64)).to("cuda")
+
+
+def _pinned(a):
+    a = np.ascontiguousarray(a, dtype=np.uint64).reshape(-1, 2)
+    t = torch.empty((len(a), 2), dtype=torch.int64, pin_memory=True)
+    t.copy_(torch.from_numpy(a.view(np.int64)))
+    return t
+
+
+def rel(rng, n, domain):
+    k = (rng.integers(0, domain, size=n, dtype=np.uint64) if domain
+         else rng.integers(0, U64, size=n, dtype=np.uint64, endpoint=True))
+    p = rng.integers(0, U64, size=n, dtype=np.uint64, endpoint=True)
+    return np.stack([k, p], axis=1)
+
+
+def host_join(R, S, chunk, cfg=None):
+    cfg = cfg if cfg is not None else mpsm.config()
+    nR, nS = len(R), len(S)
+    _say(f"mpsm_join_host_runs nR={nR} nS={nS} chunk={chunk} L=2^{cfg.log2_run_len or 'default'} "
+         f"splitter={cfg.splitter} search={cfg.search}")
+    nbytes = mpsm.join_host_runs_workspace_bytes(nR, nS, chunk, cfg)
+    assert nbytes > 0
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(2, dtype=torch.int64, device="cuda")
+    Sh = _pinned(S)
+    runs = torch.empty((nS, 2), dtype=torch.int64, pin_memory=True)
+    mpsm.join_host_runs_into(_dev(R), Sh, runs, out, ws, chunk, cfg)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().view(np.uint64)
+    return int(o[0]), int(o[1]), runs.numpy().view(np.uint64)
+
+
+def check_runs(S, runs, L):
+    want = oracle.sort_runs(S, L)
+    assert np.array_equal(runs[:, 0], want[:, 0])
+    for q in range(0, len(S), L):
+        a, b = runs[q:q + L], want[q:q + L]
+        assert np.array_equal(a[np.lexsort((a[:, 1], a[:, 0]))], b[np.lexsort((b[:, 1], b[:, 0]))]), q
+
+
+@pytest.mark.parametrize("nR,nS,domain,chunk", [
+    (5000, 100000, 3000, 3 * 4096),    # 9 chunks, the last one ragged, runs of 2^12
+    (5000, 100000, 0, 1 << 30),        # one chunk holds all of S
+    (3000, 50001, 500, 1000),          # chunk below a run: one run at a time
+    (20000, 4095, 100, 4096),          # S shorter than one run
+])
+def test_host_runs_small(nR, nS, domain, chunk):
+    rng = np.random.default_rng(nR + nS + domain)
+    R, S = rel(rng, nR, domain), rel(rng, nS, domain)
+    cfg = mpsm.config(log2_run_len=12)
+    cnt, chk, runs = host_join(R, S, chunk, cfg)
+    want = oracle.join(R, S)
+    assert (cnt, chk) == (want.count, want.checksum)
+    check_runs(S, runs, 1 << 12)
+
+
+@pytest.mark.parametrize("kw", [dict(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED),
+                                dict(search=mpsm.SEARCH_BINARY), dict(search=mpsm.SEARCH_INTERP)])
+def test_host_runs_options(kw):
+    rng = np.random.default_rng(77)
+    R, S = rel(rng, 30000, 20000), rel(rng, 200000, 20000)
+    cfg = mpsm.config(log2_run_len=13, **kw)
+    cnt, chk, runs = host_join(R, S, 5 * 8192, cfg)
+    want = oracle.join(R, S)
+    assert (cnt, chk) == (want.count, want.checksum)
+    check_runs(S, runs, 1 << 13)
+
+
+@pytest.mark.parametrize("nR,nS", [(0, 1000), (1000, 0), (0, 0)])
+def test_host_runs_empty(nR, nS):
+    rng = np.random.default_rng(nR + 3 * nS)
+    R, S = rel(rng, nR, 10), rel(rng, nS, 10)
+    cnt, chk, _ = host_join(R, S, 4096, mpsm.config(log2_run_len=12))
+    assert (cnt, chk) == (0, 0)
+
+
+@pytest.mark.parametrize("chunk", [1 << 22, 1 << 21])
+def test_host_runs_lognormal_reduced(chunk):
+    """|R| = 2^20, |S| = 2^22 log-normal keys with duplicates, default runs
+    (2^16 tuples): a chunk of all 64 runs (2^22 tuples) takes the pass
+    without a histogram, a chunk of 32 the counted one."""
+    w = workloads.make("lognormal", scale_shift=8)
+    want, inv = oracle.join_hash(w.R, w.S)
+    cnt, chk, runs = host_join(w.R, w.S, chunk)
+    assert cnt == w.expected_count == inv and chk == want.checksum
+    L = 1 << 16
+    assert np.array_equal(runs[:, 0], oracle.sort_runs(w.S, L)[:, 0])
+
+
+def test_host_runs_matches_device_join():
+    """fk_uniform at |R| = 2^20, |S| = 2^22 (every S tuple has one partner):
+    the same count and checksum as the join with S in device memory and as
+    the closed form."""
+    w = workloads.make("fk_small")
+    fk = oracle.fk_closed_form(w.R, w.S, w.partner)
+    dev = mpsm.join(_dev(w.R), _dev(w.S))
+    cnt, chk, _ = host_join(w.R, w.S, 3 << 20)
+    assert (cnt, chk) == (dev["count"], dev["checksum"]) == (len(w.S), fk.checksum)
+
+
+def test_host_runs_rejects():
+    """Options that need S's runs before R's partitioning, a swapped role,
+    chunk 0 and a host buffer that is not pinned: MPSM_EINVAL before anything
+    is enqueued; a join afterwards still runs."""
+    L = mpsm.lib()
+    rng = np.random.default_rng(5)
+    R, S = rel(rng, 1000, 50), rel(rng, 5000, 50)
+    Rd, Sh = _dev(R), _pinned(S)
+    runs = torch.empty_like(Sh).pin_memory()
+    out = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ws = torch.empty(mpsm.join_host_runs_workspace_bytes(1000, 5000, 4096), dtype=torch.uint8, device="cuda")
+
+    def call(cfg, chunk, s_ptr, runs_ptr):
+        return L.mpsm_join_host_runs(ctypes.c_void_p(Rd.data_ptr()), 1000, ctypes.c_void_p(s_ptr), 5000,
+                                     ctypes.c_void_p(runs_ptr), ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr() + 8), ctypes.byref(cfg), chunk,
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), None)
+
+    for kw in (dict(splitter=mpsm.SPLIT_COST), dict(splitter=mpsm.SPLIT_NONE), dict(role=mpsm.ROLE_SWAP)):
+        assert call(mpsm.config(**kw), 4096, Sh.data_ptr(), runs.data_ptr()) == 1, kw
+    assert call(mpsm.config(), 0, Sh.data_ptr(), runs.data_ptr()) == 1
+    plain = np.ascontiguousarray(S.copy())
+    assert call(mpsm.config(), 4096, plain.ctypes.data, runs.data_ptr()) == 1
+    with pytest.raises(TypeError):
+        mpsm.join_host_runs_into(Rd, torch.from_numpy(S.view(np.int64)), runs, out, ws, 4096)
+    cnt, chk, _ = host_join(R, S, 4096, mpsm.config(log2_run_len=12))
+    want = oracle.join(R, S)
+    assert (cnt, chk) == (want.count, want.checksum)
