@@ -528,8 +528,8 @@ def experiment_bench(args):
       hostruns (Section 3.1) |R| = 2^26, |S| = 2^28 uniform foreign keys with
                S and its sorted runs in pinned host memory, for several
                chunk sizes (the share of S on the device at a time), against
-               the join with S in device memory and the host link's copy
-               rates."""
+               the join with S in device memory and the time S takes over
+               the host link in and out."""
     import numpy as np
     import torch
     import paper_1207_0145_amd as mpsm
@@ -625,8 +625,8 @@ def experiment_bench(args):
             log(f"hostruns chunk 2^{lg}: {ms:.3f} ms, workspace {nbytes / 2**30:.2f} GiB")
             del ws
             torch.cuda.empty_cache()
-        # the least the host link allows: S in, the runs out, the runs read back
-        floor_ms = nS * 16 * (2 / rates["h2d_GBps"] + 1 / rates["d2h_GBps"]) / 1e6
+        # the least the host link allows, one way after the other: S in and its runs out
+        floor_ms = nS * 16 * (1 / rates["h2d_GBps"] + 1 / rates["d2h_GBps"]) / 1e6
         line = {**base, "value": res["chunk_2^26"]["value"], "ms_per_step": res["chunk_2^26"]["ms_per_step"],
                 "config": {"workload": "hostruns: |R|=2^26, |S|=2^28 uniform foreign keys; S and its sorted runs "
                                        "in pinned host memory, value at a chunk of 2^26 tuples"},

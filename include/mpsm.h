@@ -256,18 +256,22 @@ mpsm_status mpsm_join_events(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tupl
                              uint64_t workspace_bytes, void* stream, void** events, uint32_t n_events);
 
 /* The equi-join with S outside device memory (the memory-constrained
- * variant of Section 3.1 and its Figure 4, which writes the sorted runs to
- * disk and reads them back in key order during the join; here the runs live
- * in host memory and the join reads them over the host link):
+ * variant of Section 3.1 and its Figure 4, which spills the sorted runs to
+ * disk and reads them back in key order during the join).  Here S and its
+ * runs live in host memory; R, the private input, is partitioned and sorted
+ * on the device first, and S then passes through the device once, in
+ * chunks of whole runs: each chunk is sorted into runs, joined with every R
+ * partition while it is on the device (the join is a sum over runs), and
+ * its runs are written back to host memory.
  *   h_S       pinned host array (hipHostMalloc, or a pinned torch tensor) of
  *             nS tuples, 16-byte aligned; read only.
  *   h_runs    pinned host array of nS tuples, 16-byte aligned, written: on
  *             completion it holds S's Q = ceil(nS / L) runs in place (run q
- *             is S[q*L, min((q+1)*L, nS)) sorted by key, L = 2^log2_run_len),
- *             which the search and the join read where they are.
- *   chunk_tuples  tuples copied in and sorted at a time (rounded down to a
- *             multiple of L, at least L): the device holds one chunk of S,
- *             so the workspace grows with it, not with nS.
+ *             is S[q*L, min((q+1)*L, nS)) sorted by key, L = 2^log2_run_len).
+ *   chunk_tuples  tuples copied in, sorted and joined at a time (rounded
+ *             down to a multiple of L, at least L): the device holds two
+ *             chunks of S (one is copied while the other is sorted), so the
+ *             workspace grows with the chunk, not with nS.
  * d_R, nR, d_out_count, d_out_checksum, d_workspace (at least
  * mpsm_join_host_runs_workspace_bytes() bytes) and stream as for mpsm_join;
  * R stays the private input and S the public one (cfg->role SWAP, and the

@@ -40,10 +40,9 @@ struct Plan {
   // bucket passes without a histogram (sample-sized regions in areas of
   // pad_area tuples): S's runs, R's runs (B-MPSM), R's second level
   int padS, padR1, padR2;
-  // S in host memory (the disk-resident variant): phase 1 runs over chunks of
-  // nSc tuples (Qc runs each) and the sorted runs go back to host memory,
-  // where the search and the join read them; run start/length of all Q runs
-  // in runtab.  Otherwise nSc = nS and Qc = Q.
+  // S in host memory (the memory-constrained variant): S is sorted and
+  // joined in chunks of nSc tuples (Qc runs each), whose sorted runs then go
+  // back to host memory.  Otherwise nSc = nS and Qc = Q.
   int hostS;
   uint64_t nSc;
   uint32_t Qc;
@@ -70,7 +69,6 @@ struct Plan {
   uint64_t capS, rstS, fillS, bsrcS, dirtyS;        // S's regions (padS)
   uint64_t capR1, rstR1, fillR1, bsrcR1, dirtyR1;   // R's level-1 regions (padR1)
   uint64_t capR2, rstR2, fillR2, bsrcR2, dirtyR2;   // R's level-2 regions (padR2)
-  uint64_t runtab;                                  // hostS: run start (Q + 1), then length (Q + 1)
   uint64_t total;
 };
 
@@ -209,7 +207,8 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P, ui
   auto take = [&](uint64_t bytes) { uint64_t o = off; off += (bytes + 255) & ~255ull; return o; };
   const uint64_t ts = sizeof(tup_t);
   P->T = take((P->padS ? pad_area(P->nSc) : P->nSc) * ts);
-  P->U = take(P->nSc * ts);   // hostS: one chunk's runs on their way to host memory
+  // hostS: two chunks' runs (one copied in or out while the other is sorted)
+  P->U = take(P->nSc * ts * (P->nSc < P->nS ? 2u : 1u));
   P->R1 = take((P->padR1 ? pad_area(P->nR) : P->nR) * ts);
   P->R2 = take((P->padR2 ? pad_area(P->nR) : P->nR) * ts);
   P->cS = take(P->cntS * 4);
@@ -268,7 +267,6 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P, ui
     P->bsrcS = take(((uint64_t)P->Gs + 1) * 4);
     P->dirtyS = take((uint64_t)P->Qc * 4);
   }
-  if (P->hostS) P->runtab = take(2ull * (P->Q + 1) * 4);
   if (P->padR1) {
     const uint64_t g1 = (uint64_t)P->QR * P->NB1;
     P->capR1 = take(g1 * 4);
@@ -305,17 +303,6 @@ Seg seg_at(char* ws, uint64_t off, uint32_t nseg) {
 __global__ void k_clear_words(unsigned long long* w, uint32_t mask) {
   const uint32_t i = threadIdx.x;
   if (i < 32 && ((mask >> i) & 1u)) w[i] = 0;
-}
-
-// Start and length of each of the Q runs of L tuples over [0, n) (entry Q:
-// start n, length 0), for runs that are not the segments of a bucket pass.
-__global__ void k_run_table(uint32_t* start, uint32_t* len, uint32_t Q, uint32_t L, uint32_t n) {
-  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q > Q) return;
-  const uint64_t a = (uint64_t)q * L;
-  const uint32_t s = (uint32_t)(a < n ? a : n);
-  start[q] = s;
-  len[q] = q < Q ? (n - s < L ? n - s : L) : 0u;
 }
 
 #define HIP_TRY(x)                        \
@@ -511,6 +498,10 @@ mpsm_status bucket_pass(const tup_t* src, tup_t* dst, uint32_t n, const Level& L
 struct SideStream {
   hipStream_t st = nullptr;
   hipEvent_t fork = nullptr, gate = nullptr, done = nullptr;
+  // copies of S's chunks in and of their runs out (S in host memory), one
+  // stream per direction, and the events that order them
+  hipStream_t cin = nullptr, cout = nullptr;
+  hipEvent_t c_start = nullptr, c_in = nullptr, c_sorted = nullptr, c_out = nullptr, c_joined = nullptr;
 };
 constexpr int SIDE_MAX_DEVICES = 64;
 thread_local SideStream t_side[SIDE_MAX_DEVICES];
@@ -527,6 +518,20 @@ mpsm_status side_stream(SideStream** out) {
     HIP_TRY(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
   }
   *out = &s;
+  return MPSM_OK;
+}
+
+// The side stream's copy streams and their events (created on first use).
+mpsm_status copy_streams(SideStream* s) {
+  if (!s->cin) {
+    HIP_TRY(hipStreamCreateWithFlags(&s->cin, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&s->cout, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&s->c_start, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&s->c_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&s->c_sorted, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&s->c_out, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&s->c_joined, hipEventDisableTiming));
+  }
   return MPSM_OK;
 }
 
@@ -632,14 +637,14 @@ mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* c
 namespace {
 
 // S in pinned host memory (the runs of S kept outside device memory, as the
-// memory-constrained variant of Section 3.1 keeps them on disk): its tuples, its
-// sorted runs, each by its host address (copies) and its device address
-// (kernels), and the tuples of whole runs copied in and sorted at a time.
+// memory-constrained variant of Section 3.1 keeps them on disk): its tuples
+// by host address (copies) and device address (the learned model's
+// sample), where its sorted runs go, and the tuples of whole runs copied in,
+// sorted and joined at a time.
 struct HostS {
   const tup_t* S_host;
   const tup_t* S_dev;
   tup_t* runs_host;
-  const tup_t* runs_dev;
   uint64_t chunk;
 };
 
@@ -678,10 +683,12 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
   const bool r_side = P.splitter != MPSM_SPLIT_COST && P.nR && P.nS && !single_stream;
   // the side stream and its events exist before anything is enqueued
   SideStream* side = nullptr;
-  if ((learn_r || learn_s || r_side) && !single_stream) {
+  if ((learn_r || learn_s || r_side || P.hostS) && !single_stream) {
     mpsm_status rs = side_stream(&side);
+    if (rs == MPSM_OK && P.hostS) rs = copy_streams(side);
     if (rs != MPSM_OK) return rs;
   }
+  if (P.hostS && !side) return MPSM_EINVAL;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (stats) {
     HIP_TRY(hipEventCreate(&ev0));
@@ -690,7 +697,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
   }
   // the launch sequence; on a failure after the side stream was forked, the
   // caller's stream is made to wait for it before returning
-  bool forked = false;
+  bool forked = false, copies_forked = false;
   Marker mk{events, n_events, st};
   char* ws = static_cast<char*>(d_workspace);
   const tup_t* Rin = reinterpret_cast<const tup_t*>(P.swapped ? d_S : d_R);
@@ -758,9 +765,9 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       uint32_t* midS = reinterpret_cast<uint32_t*>(ws + P.midS);
       uint32_t* bigS = reinterpret_cast<uint32_t*>(ws + P.bigS);
       uint32_t* redoS = reinterpret_cast<uint32_t*>(ws + P.redoS);
-      // the bucket sorts of a pass over S's runs (T to U); run_idx: the index
-      // entries of the pass's first run
-      auto sort_runs = [&](const Level& Lv, uint64_t* run_idx) -> mpsm_status {
+      // the bucket sorts of a pass over S's runs (T to dst); run_idx: the
+      // index entries of the pass's first run
+      auto sort_runs = [&](const Level& Lv, tup_t* dst, uint64_t* run_idx) -> mpsm_status {
         SortOut so;
         so.run_idx = run_idx;
         so.run_start = Lv.seg.start;
@@ -769,25 +776,21 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
         so.idx_per_run = P.idx_per_run;
         so.NB = P.NBs;
         so.bkey = nullptr;
-        k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gs, BS_NT, 0, st>>>(T, U, Lv.bstart, Lv.bsrc, Lv.blo, Lv.bhi, Lv.Gcount(),
+        k_bucket_sort_cs<BS_NT, BS_IPT, BS_M, 8, false, false><<<P.Gs, BS_NT, 0, st>>>(T, dst, Lv.bstart, Lv.bsrc, Lv.blo, Lv.bhi, Lv.Gcount(),
                                                                      nullptr, nullptr, midS, ctr + 2, redoS, ctr + 3, so);
         LAUNCH_CHECK();
-        k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(T, U, Lv.bstart, Lv.bsrc, Lv.blo, Lv.bhi, Lv.Gcount(),
+        k_bucket_sort_cs<BL_NT, BL_IPT, BL_M, 1, true, false><<<g_num_cus, BL_NT, 0, st>>>(T, dst, Lv.bstart, Lv.bsrc, Lv.blo, Lv.bhi, Lv.Gcount(),
                                                                           midS, ctr + 2, bigS, ctr + 0, redoS, ctr + 3,
                                                                           so);
         LAUNCH_CHECK();
-        k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, U, Lv.bstart, Lv.bsrc, redoS, ctr + 3, bigS, ctr + 0, so);
+        k_bucket_sort_lsd<<<g_num_cus, LSD_NT, 0, st>>>(T, dst, Lv.bstart, Lv.bsrc, redoS, ctr + 3, bigS, ctr + 0, so);
         LAUNCH_CHECK();
         mk.mark(MK_S_SORT);
-        k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, U, Lv.bstart, Lv.bsrc, bigS, ctr + 0, so);
+        k_big_sort<<<g_num_cus, BIG_NT, 0, st>>>(T, dst, Lv.bstart, Lv.bsrc, bigS, ctr + 0, so);
         LAUNCH_CHECK();
         mk.mark(MK_S_BIG);
         return MPSM_OK;
       };
-      // where the search and the join find S's runs
-      const tup_t* Uj = U;
-      const uint32_t* run_start = LS.seg.start;
-      const uint32_t* run_len = LS.seg.len;
       if (!P.hostS) {
         if (P.padS) regions(LS, P.capS, P.rstS, P.fillS, P.dirtyS, P.bsrcS, 7);
         rc = bucket_pass(Sin, T, (uint32_t)P.nS, LS, bsum, st, mk, MK_S_SPL);
@@ -795,43 +798,13 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
         if (r_side) HIP_TRY(hipEventRecord(side->gate, st));
         rc = start_models();
         if (rc != MPSM_OK) return rc;
-        rc = sort_runs(LS, ridx);
+        rc = sort_runs(LS, U, ridx);
         if (rc != MPSM_OK) return rc;
       } else {
-        // S in host memory: the tuples of whole runs at a time are copied
-        // into U, bucketed into T, sorted back into U and copied out to the
-        // host runs; the search and the join read the runs there.  The
-        // counters of S's passes (words 0, 2, 3 and 7 of ctr) start at zero
-        // in every chunk; R's passes, beside them, use the others.
-        for (uint64_t c = 0; c < P.nS; c += P.nSc) {
-          const uint64_t n = P.nS - c < P.nSc ? P.nS - c : P.nSc;
-          const uint32_t q0 = (uint32_t)(c / P.L), qn = (uint32_t)cdiv(n, P.L);
-          if (c) {
-            k_clear_words<<<1, 64, 0, st>>>(ctr, (1u << 0) | (1u << 2) | (1u << 3) | (1u << 7));
-            LAUNCH_CHECK();
-          }
-          HIP_TRY(hipMemcpyAsync(U, hs->S_host + c, n * sizeof(tup_t), hipMemcpyHostToDevice, st));
-          Level LC = make_level(ws, P.segS, qn, P.NBs, 0, P.OSs, P.tilesS, P.seed ^ TAG_S, P.splS, P.cS, P.cntS,
-                                P.bstS, P.bndS, qn * P.NBs);
-          LC.run_len = P.L;
-          if (P.padS) regions(LC, P.capS, P.rstS, P.fillS, P.dirtyS, P.bsrcS, 7);
-          rc = bucket_pass(U, T, (uint32_t)n, LC, bsum, st, mk, MK_S_SPL);
-          if (rc != MPSM_OK) return rc;
-          if (c == 0) {
-            if (r_side) HIP_TRY(hipEventRecord(side->gate, st));
-            rc = start_models();
-            if (rc != MPSM_OK) return rc;
-          }
-          rc = sort_runs(LC, ridx + (uint64_t)q0 * P.idx_per_run);
-          if (rc != MPSM_OK) return rc;
-          HIP_TRY(hipMemcpyAsync(hs->runs_host + c, U, n * sizeof(tup_t), hipMemcpyDeviceToHost, st));
-        }
-        uint32_t* rt = reinterpret_cast<uint32_t*>(ws + P.runtab);
-        k_run_table<<<(uint32_t)cdiv((uint64_t)P.Q + 1, 256), 256, 0, st>>>(rt, rt + P.Q + 1, P.Q, P.L, (uint32_t)P.nS);
-        LAUNCH_CHECK();
-        Uj = hs->runs_dev;
-        run_start = rt;
-        run_len = rt + P.Q + 1;
+        // S in host memory: R's phases and partitions come first, on the
+        // side stream, and S's chunks are sorted and joined after them
+        rc = start_models();
+        if (rc != MPSM_OK) return rc;
       }
 
       // ---- phase 2: range-partition R (one or two levels); phase 3: sort partitions
@@ -857,7 +830,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       // after them, or on this stream after S's
       if (side && !r_side) HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
       const hipStream_t rst = r_side ? side->st : st;
-      if (r_side) HIP_TRY(hipStreamWaitEvent(rst, side->gate, 0));
+      if (r_side && !P.hostS) HIP_TRY(hipStreamWaitEvent(rst, side->gate, 0));
       uint32_t* const rbsum = r_side ? reinterpret_cast<uint32_t*>(ws + P.bsumR) : bsum;
       Marker mkR{events, n_events, rst};
       LR1.run_len = bmpsm ? P.L : (uint32_t)P.nR;   // B-MPSM: R runs; else one segment, all of R
@@ -920,17 +893,21 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       k_big_sort<<<g_num_cus, BIG_NT, 0, rst>>>(Rsrc, Rsorted, LRf->bstart, LRf->bsrc, bigR, ctr + 1, soR);
       LAUNCH_CHECK();
       mkR.mark(MK_R_BIG);
-      if (r_side) {   // the rest needs R's partitions
+      if (r_side && !P.hostS) {   // the rest needs R's partitions
         HIP_TRY(hipEventRecord(side->done, rst));
         HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
       }
+      // the partition table: on this stream after R's sort, or with S in
+      // host memory on R's stream, which S's chunks wait for
+      const hipStream_t pst = P.hostS ? rst : st;
+      uint32_t* const pbsum = P.hostS ? rbsum : bsum;
       uint32_t* Pc = reinterpret_cast<uint32_t*>(ws + P.Pc);
       uint32_t* pstart = reinterpret_cast<uint32_t*>(ws + P.pstart);
       uint32_t* plen = reinterpret_cast<uint32_t*>(ws + P.plen);
       uint64_t* pkey = reinterpret_cast<uint64_t*>(ws + P.pkey);
       uint8_t* const pterm = bmpsm ? reinterpret_cast<uint8_t*>(ws + P.pterm) : nullptr;
       if (bmpsm) {
-        k_partitions_runs<<<1, 1024, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gcount(), P.NB1, Pc, pstart, plen, pkey,
+        k_partitions_runs<<<1, 1024, 0, pst>>>(LRf->bstart, soR.bkey, LRf->Gcount(), P.NB1, Pc, pstart, plen, pkey,
                                               pterm, stats ? res : nullptr);
         LAUNCH_CHECK();
       } else {
@@ -938,16 +915,16 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
         uint32_t* flags = reinterpret_cast<uint32_t*>(ws + P.items);
         uint32_t* pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
         const uint32_t nb = (uint32_t)cdiv(LRf->Gmax, 256);
-        k_partition_flags<<<nb, 256, 0, st>>>(LRf->bstart, LRf->Gcount(), LRf->Gmax, flags);
+        k_partition_flags<<<nb, 256, 0, pst>>>(LRf->bstart, LRf->Gcount(), LRf->Gmax, flags);
         LAUNCH_CHECK();
-        rc = scan_u32(flags, pre, LRf->Gmax, bsum, st);
+        rc = scan_u32(flags, pre, LRf->Gmax, pbsum, pst);
         if (rc != MPSM_OK) return rc;
-        k_partition_write<<<nb, 256, 0, st>>>(LRf->bstart, soR.bkey, LRf->Gmax, flags, pre, Pc, pstart, plen, pkey,
+        k_partition_write<<<nb, 256, 0, pst>>>(LRf->bstart, soR.bkey, LRf->Gmax, flags, pre, Pc, pstart, plen, pkey,
                                               stats ? res : nullptr);
         LAUNCH_CHECK();
       }
       uint8_t* span = reinterpret_cast<uint8_t*>(ws + P.span);
-      k_join_units<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, st>>>(Pc, plen, P.Pmax, span, pterm);
+      k_join_units<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, pst>>>(Pc, plen, P.Pmax, span, pterm);
       LAUNCH_CHECK();
       mk.mark(MK_PART);
 
@@ -955,61 +932,127 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       uint32_t* o = reinterpret_cast<uint32_t*>(ws + P.o);
       float2* qe = reinterpret_cast<float2*>(ws + P.qe);
       if (learn_s) {
-        k_search_model<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, st>>>(modelS, pkey, Pc, P.Pmax, qe);
+        k_search_model<<<(uint32_t)cdiv(P.Pmax, 256), 256, 0, pst>>>(modelS, pkey, Pc, P.Pmax, qe);
         LAUNCH_CHECK();
       }
-      const uint64_t nsearch = cdiv((uint64_t)P.Pmax + 1, 64) * cdiv(P.Q, SEARCH_RUNS);
-      k_search<<<(uint32_t)nsearch, SEARCH_NT, 0, st>>>(Uj, run_start, run_len, P.Q,
-                                                            reinterpret_cast<uint64_t*>(ws + P.ridx), IDX_STRIDE,
-                                                            P.idx_per_run, Pc, pkey, P.Pmax, o,
-                                                            learn_s ? MPSM_SEARCH_LEARNED
-                                                                    : (P.search == MPSM_SEARCH_LEARNED ? MPSM_SEARCH_INDEX
-                                                                                                       : P.search),
-                                                            modelS, qe, stats ? res : nullptr, span, pterm);
-      LAUNCH_CHECK();
-      mk.mark(MK_SEARCH);
-      uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
-      uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
-      k_join_items<<<(uint32_t)cdiv(((uint64_t)P.Pmax + 2) * 64, 256), 256, 0, st>>>(Pc, o, P.Q, run_len, P.Pmax,
-                                                                                     P.JCH, span, items);
-      LAUNCH_CHECK();
-      rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
-      if (rc != MPSM_OK) return rc;
-      mk.mark(MK_ITEMS);
-
-      JoinArgs A;
-      A.Rs = Rsorted;
-      A.U = Uj;
-      A.run_start = run_start;
-      A.run_len = run_len;
-      A.Q = P.Q;
-      A.Pcount = Pc;
-      A.pstart = pstart;
-      A.plen = plen;
-      A.o = o;
-      A.item_pre = item_pre;
-      A.Pmax = P.Pmax;
-      A.JCH = P.JCH;
-      A.res = res;
-      A.J = nullptr;
-      A.pjoin = nullptr;
-      A.span = span;
-      A.pairs = reinterpret_cast<uint64_t*>(d_pairs);
-      A.pairs_cap = d_pairs ? pairs_capacity : 0;
-      A.item_cnt = reinterpret_cast<uint32_t*>(ws + P.item_cnt);
-      A.item_cap = (uint32_t)P.item_cap;
-      A.swapped = P.swapped;
-      const bool raw = P.swapped || P.want_max || d_pairs;
-      if (raw) k_join<0, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
-      else k_join<0, VAL_HR><<<g_num_cus, JOIN_NT, 0, st>>>(A);
-      LAUNCH_CHECK();
-      if (d_pairs) {
-        k_join<1, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+      // the search and the join over Qn runs of S in Ub (run_start / run_len
+      // relative to Ub; run_idx: their index entries)
+      auto search_join = [&](const tup_t* Ub, const uint32_t* run_start, const uint32_t* run_len, uint32_t Qn,
+                             const uint64_t* run_idx) -> mpsm_status {
+        const uint64_t nsearch = cdiv((uint64_t)P.Pmax + 1, 64) * cdiv(Qn, SEARCH_RUNS);
+        k_search<<<(uint32_t)nsearch, SEARCH_NT, 0, st>>>(Ub, run_start, run_len, Qn, run_idx, IDX_STRIDE,
+                                                              P.idx_per_run, Pc, pkey, P.Pmax, o,
+                                                              learn_s ? MPSM_SEARCH_LEARNED
+                                                                      : (P.search == MPSM_SEARCH_LEARNED ? MPSM_SEARCH_INDEX
+                                                                                                         : P.search),
+                                                              modelS, qe, stats ? res : nullptr, span, pterm);
         LAUNCH_CHECK();
-        rc = scan_u32(A.item_cnt, A.item_cnt, P.item_cap, bsum, st);
+        mk.mark(MK_SEARCH);
+        uint32_t* items = reinterpret_cast<uint32_t*>(ws + P.items);
+        uint32_t* item_pre = reinterpret_cast<uint32_t*>(ws + P.item_pre);
+        k_join_items<<<(uint32_t)cdiv(((uint64_t)P.Pmax + 2) * 64, 256), 256, 0, st>>>(Pc, o, Qn, run_len, P.Pmax,
+                                                                                       P.JCH, span, items);
+        LAUNCH_CHECK();
+        rc = scan_u32(items, item_pre, (uint64_t)P.Pmax + 2, bsum, st);
         if (rc != MPSM_OK) return rc;
-        k_join<2, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+        mk.mark(MK_ITEMS);
+
+        JoinArgs A;
+        A.Rs = Rsorted;
+        A.U = Ub;
+        A.run_start = run_start;
+        A.run_len = run_len;
+        A.Q = Qn;
+        A.Pcount = Pc;
+        A.pstart = pstart;
+        A.plen = plen;
+        A.o = o;
+        A.item_pre = item_pre;
+        A.Pmax = P.Pmax;
+        A.JCH = P.JCH;
+        A.res = res;
+        A.J = nullptr;
+        A.pjoin = nullptr;
+        A.span = span;
+        A.pairs = reinterpret_cast<uint64_t*>(d_pairs);
+        A.pairs_cap = d_pairs ? pairs_capacity : 0;
+        A.item_cnt = reinterpret_cast<uint32_t*>(ws + P.item_cnt);
+        A.item_cap = (uint32_t)P.item_cap;
+        A.swapped = P.swapped;
+        const bool raw = P.swapped || P.want_max || d_pairs;
+        if (raw) k_join<0, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+        else k_join<0, VAL_HR><<<g_num_cus, JOIN_NT, 0, st>>>(A);
         LAUNCH_CHECK();
+        if (d_pairs) {
+          k_join<1, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+          LAUNCH_CHECK();
+          rc = scan_u32(A.item_cnt, A.item_cnt, P.item_cap, bsum, st);
+          if (rc != MPSM_OK) return rc;
+          k_join<2, VAL_RAW><<<g_num_cus, JOIN_NT, 0, st>>>(A);
+          LAUNCH_CHECK();
+        }
+        return MPSM_OK;
+      };
+      if (!P.hostS) {
+        rc = search_join(U, LS.seg.start, LS.seg.len, P.Q, ridx);
+        if (rc != MPSM_OK) return rc;
+      } else {
+        HIP_TRY(hipEventRecord(side->done, rst));   // R's partitions are ready
+        // S in host memory: the tuples of whole runs at a time are copied
+        // into a buffer of U, bucketed into T, sorted back into the buffer,
+        // joined there with every R partition (the join is a sum over runs)
+        // and copied out to the host runs.  Two buffers, so that the next
+        // chunk comes in and the previous chunk's runs go out (one copy
+        // stream per direction) while a chunk is sorted and joined.  The
+        // counters of S's passes (words 0, 2, 3 and 7 of ctr) start at zero
+        // in every chunk.
+        SideStream& cs = *side;
+        const uint32_t nbuf = P.nSc < P.nS ? 2u : 1u;
+        const uint64_t nk = cdiv(P.nS, P.nSc);
+        auto ubuf = [&](uint64_t k) { return U + (k % nbuf) * P.nSc; };
+        auto clen = [&](uint64_t k) { return P.nS - k * P.nSc < P.nSc ? P.nS - k * P.nSc : P.nSc; };
+        HIP_TRY(hipEventRecord(cs.c_start, st));
+        HIP_TRY(hipStreamWaitEvent(cs.cin, cs.c_start, 0));
+        HIP_TRY(hipStreamWaitEvent(cs.cout, cs.c_start, 0));
+        copies_forked = true;
+        HIP_TRY(hipMemcpyAsync(ubuf(0), hs->S_host, clen(0) * sizeof(tup_t), hipMemcpyHostToDevice, cs.cin));
+        HIP_TRY(hipEventRecord(cs.c_in, cs.cin));
+        for (uint64_t k = 0; k < nk; k++) {
+          const uint64_t c = k * P.nSc, n = clen(k);
+          const uint32_t q0 = (uint32_t)(c / P.L), qn = (uint32_t)cdiv(n, P.L);
+          HIP_TRY(hipStreamWaitEvent(st, cs.c_in, 0));   // chunk k is in
+          if (k + 1 < nk) {
+            // chunk k + 1's buffer held chunk k - 1, which must be joined and out
+            if (k >= 1) {
+              HIP_TRY(hipStreamWaitEvent(cs.cin, cs.c_joined, 0));
+              HIP_TRY(hipStreamWaitEvent(cs.cin, cs.c_out, 0));
+            }
+            HIP_TRY(hipMemcpyAsync(ubuf(k + 1), hs->S_host + c + P.nSc, clen(k + 1) * sizeof(tup_t),
+                                   hipMemcpyHostToDevice, cs.cin));
+            HIP_TRY(hipEventRecord(cs.c_in, cs.cin));
+          }
+          if (k) {
+            k_clear_words<<<1, 64, 0, st>>>(ctr, (1u << 0) | (1u << 2) | (1u << 3) | (1u << 7));
+            LAUNCH_CHECK();
+          }
+          Level LC = make_level(ws, P.segS, qn, P.NBs, 0, P.OSs, P.tilesS, P.seed ^ TAG_S, P.splS, P.cS, P.cntS,
+                                P.bstS, P.bndS, qn * P.NBs);
+          LC.run_len = P.L;
+          if (P.padS) regions(LC, P.capS, P.rstS, P.fillS, P.dirtyS, P.bsrcS, 7);
+          rc = bucket_pass(ubuf(k), T, (uint32_t)n, LC, bsum, st, mk, MK_S_SPL);
+          if (rc != MPSM_OK) return rc;
+          rc = sort_runs(LC, ubuf(k), ridx + (uint64_t)q0 * P.idx_per_run);
+          if (rc != MPSM_OK) return rc;
+          HIP_TRY(hipEventRecord(cs.c_sorted, st));
+          HIP_TRY(hipStreamWaitEvent(cs.cout, cs.c_sorted, 0));
+          HIP_TRY(hipMemcpyAsync(hs->runs_host + c, ubuf(k), n * sizeof(tup_t), hipMemcpyDeviceToHost, cs.cout));
+          HIP_TRY(hipEventRecord(cs.c_out, cs.cout));
+          if (k == 0) HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
+          rc = search_join(ubuf(k), LC.seg.start, LC.seg.len, qn, ridx + (uint64_t)q0 * P.idx_per_run);
+          if (rc != MPSM_OK) return rc;
+          HIP_TRY(hipEventRecord(cs.c_joined, st));
+        }
+        HIP_TRY(hipStreamWaitEvent(st, cs.c_out, 0));   // every run is in host memory
       }
       mk.mark(MK_JOIN);
       k_finalize<<<1, 64, 0, st>>>(res, d_out_count, d_out_checksum, d_pairs ? pairs_capacity : 0);
@@ -1023,6 +1066,12 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
     if (forked) {
       (void)hipEventRecord(side->done, side->st);
       (void)hipStreamWaitEvent(st, side->done, 0);
+    }
+    if (copies_forked) {
+      (void)hipEventRecord(side->c_in, side->cin);
+      (void)hipStreamWaitEvent(st, side->c_in, 0);
+      (void)hipEventRecord(side->c_out, side->cout);
+      (void)hipStreamWaitEvent(st, side->c_out, 0);
     }
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
@@ -1134,7 +1183,6 @@ mpsm_status mpsm_join_host_runs(const mpsm_tuple* d_R, uint64_t nR, const mpsm_t
   hs.S_host = reinterpret_cast<const tup_t*>(h_S);
   hs.runs_host = reinterpret_cast<tup_t*>(h_runs);
   hs.S_dev = nullptr;
-  hs.runs_dev = nullptr;
   hs.chunk = chunk_tuples;
   if (nS) {
     // both buffers must be pinned host memory the device can address
@@ -1146,7 +1194,6 @@ mpsm_status mpsm_join_host_runs(const mpsm_tuple* d_R, uint64_t nR, const mpsm_t
       return MPSM_EINVAL;
     }
     hs.S_dev = static_cast<const tup_t*>(p);
-    hs.runs_dev = static_cast<const tup_t*>(q);
   }
   return join_impl(d_R, nR, h_S, nS, d_out_count, d_out_checksum, nullptr, 0, cfg, d_workspace, workspace_bytes,
                    stream, nullptr, nullptr, 0, false, &hs);

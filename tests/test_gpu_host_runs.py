@@ -153,3 +153,31 @@ def test_host_runs_rejects():
     cnt, chk, _ = host_join(R, S, 4096, mpsm.config(log2_run_len=12))
     want = oracle.join(R, S)
     assert (cnt, chk) == (want.count, want.checksum)
+
+
+def test_host_runs_back_to_back():
+    """Two calls on one stream and one workspace with no synchronisation
+    between them (the second with fewer tuples and other chunks): both
+    results and both sets of runs are the oracle's."""
+    rng = np.random.default_rng(99)
+    cases = [(rel(rng, 7000, 4000), rel(rng, 120000, 4000), 2 * 4096),
+             (rel(rng, 3000, 900), rel(rng, 70001, 900), 5 * 4096)]
+    cfg = mpsm.config(log2_run_len=12)
+    nbytes = max(mpsm.join_host_runs_workspace_bytes(len(R), len(S), ch, cfg) for R, S, ch in cases)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    outs, runs, keep = [], [], []
+    for R, S, ch in cases:
+        _say(f"back to back: nR={len(R)} nS={len(S)} chunk={ch}")
+        Rd, Sh = _dev(R), _pinned(S)
+        rh = torch.empty((len(S), 2), dtype=torch.int64, pin_memory=True)
+        out = torch.zeros(2, dtype=torch.int64, device="cuda")
+        mpsm.join_host_runs_into(Rd, Sh, rh, out, ws, ch, cfg)
+        outs.append(out)
+        runs.append(rh)
+        keep.append((Rd, Sh))
+    torch.cuda.synchronize()
+    for (R, S, _), out, rh in zip(cases, outs, runs):
+        o = out.cpu().numpy().view(np.uint64)
+        want = oracle.join(R, S)
+        assert (int(o[0]), int(o[1])) == (want.count, want.checksum)
+        check_runs(S, rh.numpy().view(np.uint64), 1 << 12)
