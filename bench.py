@@ -625,6 +625,26 @@ def experiment_bench(args):
             log(f"hostruns chunk 2^{lg}: {ms:.3f} ms, workspace {nbytes / 2**30:.2f} GiB")
             del ws
             torch.cuda.empty_cache()
+        # runs not kept: S crosses the link once
+        nbytes = mpsm.join_host_runs_workspace_bytes(nR, nS, 1 << 24)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        for _ in range(args.warmup):
+            mpsm.join_host_runs_into(R, Sh, None, out, ws, 1 << 24)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(steps):
+            mpsm.join_host_runs_into(R, Sh, None, out, ws, 1 << 24)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        c, k = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
+        res["chunk_2^24_runs_not_kept"] = {"ms_per_step": round(ms, 4), "value": round((nR + nS) / (ms * 1e-3) / 1e6, 2),
+                                           "result": (c, f"{k:#018x}"),
+                                           "link_floor_ms": round(nS * 16 / rates["h2d_GBps"] / 1e6, 2)}
+        log(f"hostruns chunk 2^24, runs not kept: {ms:.3f} ms")
+        del ws
         # the least the host link allows, one way after the other: S in and its runs out
         floor_ms = nS * 16 * (1 / rates["h2d_GBps"] + 1 / rates["d2h_GBps"]) / 1e6
         line = {**base, "value": res["chunk_2^26"]["value"], "ms_per_step": res["chunk_2^26"]["ms_per_step"],

@@ -271,15 +271,17 @@ def _check_host_tuples(t, name):
 def join_host_runs_into(R, S_host, runs_host, out, workspace, chunk_tuples: int, cfg: MpsmConfig | None = None,
                         stream=None) -> int:
     """mpsm_join_host_runs: the join with S (and its sorted runs, written to
-    runs_host) in pinned host memory; R, out and workspace on the GPU as in
-    join_into.  Enqueues the work; runs_host is complete once the stream is."""
+    runs_host unless it is None) in pinned host memory; R, out and workspace
+    on the GPU as in join_into.  Enqueues the work; runs_host is complete once
+    the stream is."""
     _check_tuples(R, "R")
     _check_host_tuples(S_host, "S_host")
-    _check_host_tuples(runs_host, "runs_host")
-    if runs_host.shape[0] != S_host.shape[0]:
-        raise ValueError("runs_host must hold as many tuples as S_host")
+    if runs_host is not None:
+        _check_host_tuples(runs_host, "runs_host")
+        if runs_host.shape[0] != S_host.shape[0]:
+            raise ValueError("runs_host must hold as many tuples as S_host")
     rc = lib().mpsm_join_host_runs(ctypes.c_void_p(R.data_ptr()), R.shape[0], ctypes.c_void_p(S_host.data_ptr()),
-                                   S_host.shape[0], ctypes.c_void_p(runs_host.data_ptr()),
+                                   S_host.shape[0], None if runs_host is None else ctypes.c_void_p(runs_host.data_ptr()),
                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(out.data_ptr() + 8),
                                    _cfg_ptr(cfg), chunk_tuples, ctypes.c_void_p(workspace.data_ptr()),
                                    workspace.numel(), _stream_handle(stream))

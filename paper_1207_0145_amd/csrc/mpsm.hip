@@ -1001,7 +1001,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
         // S in host memory: the tuples of whole runs at a time are copied
         // into a buffer of U, bucketed into T, sorted back into the buffer,
         // joined there with every R partition (the join is a sum over runs)
-        // and copied out to the host runs.  Two buffers, so that the next
+        // and copied out to the host runs, if the caller keeps them.  Two buffers, so that the next
         // chunk comes in and the previous chunk's runs go out (one copy
         // stream per direction) while a chunk is sorted and joined.  The
         // counters of S's passes (words 0, 2, 3 and 7 of ctr) start at zero
@@ -1025,7 +1025,7 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
             // chunk k + 1's buffer held chunk k - 1, which must be joined and out
             if (k >= 1) {
               HIP_TRY(hipStreamWaitEvent(cs.cin, cs.c_joined, 0));
-              HIP_TRY(hipStreamWaitEvent(cs.cin, cs.c_out, 0));
+              if (hs->runs_host) HIP_TRY(hipStreamWaitEvent(cs.cin, cs.c_out, 0));
             }
             HIP_TRY(hipMemcpyAsync(ubuf(k + 1), hs->S_host + c + P.nSc, clen(k + 1) * sizeof(tup_t),
                                    hipMemcpyHostToDevice, cs.cin));
@@ -1043,16 +1043,18 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
           if (rc != MPSM_OK) return rc;
           rc = sort_runs(LC, ubuf(k), ridx + (uint64_t)q0 * P.idx_per_run);
           if (rc != MPSM_OK) return rc;
-          HIP_TRY(hipEventRecord(cs.c_sorted, st));
-          HIP_TRY(hipStreamWaitEvent(cs.cout, cs.c_sorted, 0));
-          HIP_TRY(hipMemcpyAsync(hs->runs_host + c, ubuf(k), n * sizeof(tup_t), hipMemcpyDeviceToHost, cs.cout));
-          HIP_TRY(hipEventRecord(cs.c_out, cs.cout));
+          if (hs->runs_host) {
+            HIP_TRY(hipEventRecord(cs.c_sorted, st));
+            HIP_TRY(hipStreamWaitEvent(cs.cout, cs.c_sorted, 0));
+            HIP_TRY(hipMemcpyAsync(hs->runs_host + c, ubuf(k), n * sizeof(tup_t), hipMemcpyDeviceToHost, cs.cout));
+            HIP_TRY(hipEventRecord(cs.c_out, cs.cout));
+          }
           if (k == 0) HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
           rc = search_join(ubuf(k), LC.seg.start, LC.seg.len, qn, ridx + (uint64_t)q0 * P.idx_per_run);
           if (rc != MPSM_OK) return rc;
           HIP_TRY(hipEventRecord(cs.c_joined, st));
         }
-        HIP_TRY(hipStreamWaitEvent(st, cs.c_out, 0));   // every run is in host memory
+        if (hs->runs_host) HIP_TRY(hipStreamWaitEvent(st, cs.c_out, 0));   // every run is in host memory
       }
       mk.mark(MK_JOIN);
       k_finalize<<<1, 64, 0, st>>>(res, d_out_count, d_out_checksum, d_pairs ? pairs_capacity : 0);
@@ -1177,7 +1179,7 @@ mpsm_status mpsm_join_host_runs(const mpsm_tuple* d_R, uint64_t nR, const mpsm_t
   mpsm_config def;
   if (!cfg) { mpsm_config_default(&def); cfg = &def; }
   if (!host_runs_config_ok(cfg) || chunk_tuples == 0) return MPSM_EINVAL;
-  if (nS && (!h_S || !h_runs)) return MPSM_EINVAL;
+  if (nS && !h_S) return MPSM_EINVAL;
   if (((uintptr_t)h_S & 15) || ((uintptr_t)h_runs & 15)) return MPSM_EINVAL;
   HostS hs;
   hs.S_host = reinterpret_cast<const tup_t*>(h_S);
@@ -1189,7 +1191,7 @@ mpsm_status mpsm_join_host_runs(const mpsm_tuple* d_R, uint64_t nR, const mpsm_t
     void* p = nullptr;
     void* q = nullptr;
     if (hipHostGetDevicePointer(&p, const_cast<mpsm_tuple*>(h_S), 0) != hipSuccess || !p ||
-        hipHostGetDevicePointer(&q, h_runs, 0) != hipSuccess || !q) {
+        (h_runs && (hipHostGetDevicePointer(&q, h_runs, 0) != hipSuccess || !q))) {
       (void)hipGetLastError();   // the failed lookup is the caller's error, not a later call's
       return MPSM_EINVAL;
     }

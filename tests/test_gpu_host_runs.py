@@ -40,7 +40,7 @@ def rel(rng, n, domain):
     return np.stack([k, p], axis=1)
 
 
-def host_join(R, S, chunk, cfg=None):
+def host_join(R, S, chunk, cfg=None, keep_runs=True):
     cfg = cfg if cfg is not None else mpsm.config()
     nR, nS = len(R), len(S)
     _say(f"mpsm_join_host_runs nR={nR} nS={nS} chunk={chunk} L=2^{cfg.log2_run_len or 'default'} "
@@ -50,11 +50,11 @@ def host_join(R, S, chunk, cfg=None):
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     out = torch.zeros(2, dtype=torch.int64, device="cuda")
     Sh = _pinned(S)
-    runs = torch.empty((nS, 2), dtype=torch.int64, pin_memory=True)
+    runs = torch.empty((nS, 2), dtype=torch.int64, pin_memory=True) if keep_runs else None
     mpsm.join_host_runs_into(_dev(R), Sh, runs, out, ws, chunk, cfg)
     torch.cuda.synchronize()
     o = out.cpu().numpy().view(np.uint64)
-    return int(o[0]), int(o[1]), runs.numpy().view(np.uint64)
+    return int(o[0]), int(o[1]), runs.numpy().view(np.uint64) if keep_runs else None
 
 
 def check_runs(S, runs, L):
@@ -79,6 +79,16 @@ def test_host_runs_small(nR, nS, domain, chunk):
     want = oracle.join(R, S)
     assert (cnt, chk) == (want.count, want.checksum)
     check_runs(S, runs, 1 << 12)
+
+
+def test_host_runs_not_kept():
+    """No buffer for the runs: the same result, over 9 chunks and one."""
+    rng = np.random.default_rng(123)
+    R, S = rel(rng, 6000, 2500), rel(rng, 90000, 2500)
+    want = oracle.join(R, S)
+    for chunk in (10000, 1 << 20):
+        cnt, chk, runs = host_join(R, S, chunk, mpsm.config(log2_run_len=12), keep_runs=False)
+        assert (cnt, chk) == (want.count, want.checksum) and runs is None
 
 
 @pytest.mark.parametrize("kw", [dict(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED),
