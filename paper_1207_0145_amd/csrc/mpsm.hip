@@ -8,6 +8,7 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <initializer_list>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -521,17 +522,13 @@ mpsm_status side_stream(SideStream** out) {
   return MPSM_OK;
 }
 
-// The side stream's copy streams and their events (created on first use).
+// The side stream's copy streams and their events (each created on first
+// use, so that a call after a failed creation makes the missing ones).
 mpsm_status copy_streams(SideStream* s) {
-  if (!s->cin) {
-    HIP_TRY(hipStreamCreateWithFlags(&s->cin, hipStreamNonBlocking));
-    HIP_TRY(hipStreamCreateWithFlags(&s->cout, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&s->c_start, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&s->c_in, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&s->c_sorted, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&s->c_out, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&s->c_joined, hipEventDisableTiming));
-  }
+  for (hipStream_t* q : {&s->cin, &s->cout})
+    if (!*q) HIP_TRY(hipStreamCreateWithFlags(q, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&s->c_start, &s->c_in, &s->c_sorted, &s->c_out, &s->c_joined})
+    if (!*e) HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   return MPSM_OK;
 }
 
