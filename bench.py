@@ -250,6 +250,58 @@ SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ
                "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY")
 
 
+# calls of `--workload hostruns --steps 1 --warmup 1`, in order: each form is
+# run twice (the warm-up, then the timed call)
+HOSTRUNS_CALLS = ["device-resident S", "chunk 2^28", "chunk 2^26", "chunk 2^24", "chunk 2^24, runs not kept"]
+
+
+def summarize_host_trace(kt_csv, mc_csv, command):
+    """Markdown summary of a rocprofv3 kernel and memory-copy trace of the
+    hostruns experiment: per timed call its span, its copies in and out of
+    device memory (by the copy engines, or by the runtime's copy kernels)
+    and its own kernels."""
+    ev = []
+    for r in _read_csv(kt_csv):
+        ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), "kernel", r["Kernel_Name"].split("(")[0]))
+    for r in _read_csv(mc_csv):
+        ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), "copy", r["Direction"]))
+    ev.sort()
+    starts = [i for i, e in enumerate(ev) if e[2] == "kernel" and e[3].startswith("k_init_result")]
+    if len(starts) != 2 * len(HOSTRUNS_CALLS):
+        raise SystemExit(f"expected {2 * len(HOSTRUNS_CALLS)} joins in the trace, found {len(starts)}")
+    out = ["# Join with S in pinned host memory (hostruns: |R| = 2^26, |S| = 2^28 uniform foreign keys), MI355X", "",
+           "Kernel and memory-copy trace of the timed call of each form (the second of its two calls).  Copies in "
+           "and out are the host link's; the runtime moves some of them with copy kernels (`copyBuffer`), listed "
+           "with the copies.  Copies under 0.05 ms (the read-back of the result) are left out; the device-resident "
+           "form copies nothing else.  Kernel durations are summed over both streams, and a kernel's duration "
+           "includes the time it waits for compute units that copy kernels hold.", "",
+           "Command (run from /tmp, TMPDIR=/tmp):", "", "```", command, "```", "",
+           "| form | call span ms | copies in: n, total ms, each min-max ms | copies out: n, total ms, each min-max ms "
+           "| join kernels ms (sum of durations) | three longest kernels, ms |", "|---|---|---|---|---|---|"]
+    for c, name in enumerate(HOSTRUNS_CALLS):
+        a = starts[2 * c + 1]
+        b = starts[2 * c + 2] if 2 * c + 2 < len(starts) else len(ev)
+        call = ev[a:b]
+        t0 = call[0][0]
+        t1 = max(e[1] for e in call)
+        ins, outs, kern = [], [], {}
+        for t, u, kind, nm in call:
+            ms = (u - t) / 1e6
+            if kind == "copy" or "copyBuffer" in nm:
+                if ms >= 0.05:
+                    (ins if "HOST_TO_DEVICE" in nm else outs).append(ms)
+            else:
+                kern[nm] = kern.get(nm, 0.0) + ms
+
+        def cell(x):
+            return f"{len(x)}, {sum(x):.1f}, {min(x):.2f}-{max(x):.2f}" if x else "0"
+
+        top = sorted(kern.items(), key=lambda kv: -kv[1])[:3]
+        out.append(f"| {name} | {(t1 - t0) / 1e6:.2f} | {cell(ins)} | {cell(outs)} | {sum(kern.values()):.2f} | "
+                   + "; ".join(f"`{k.replace('void ', '')[:40]}` {v:.2f}" for k, v in top) + " |")
+    return "\n".join(out) + "\n"
+
+
 def summarize_sq(sq_csv, nR, nS):
     """Per launch step of the first join in a counter run of SQ_COUNTERS:
     every counter summed over the step's dispatches, and the wave-level
@@ -781,7 +833,15 @@ def main():
     ap.add_argument("--profile-command", default="", help="command line recorded in the summary")
     ap.add_argument("--summarize-sq", default=None, metavar="SQ_CSV",
                     help="with --summarize-profiles: also the SQ counter run's per-step instruction counts")
+    ap.add_argument("--summarize-host-trace", nargs=2, metavar=("KERNEL_TRACE_CSV", "MEMORY_COPY_TRACE_CSV"),
+                    help="write profiles/hostruns_fk_uniform.md from a trace of --workload hostruns")
     args = ap.parse_args()
+    if args.summarize_host_trace:
+        md = summarize_host_trace(*args.summarize_host_trace, args.profile_command)
+        with open(os.path.join(ROOT, "profiles", "hostruns_fk_uniform.md"), "w") as f:
+            f.write(md)
+        print(md)
+        return
     if args.summarize_profiles:
         sizes = {"fk_uniform": (1 << 26, 1 << 28), "skewed": (1 << 26, 1 << 28), "fk_small": (1 << 20, 1 << 22),
                  "lognormal": (1 << 28, 1 << 30)}
