@@ -501,6 +501,28 @@ def test_intermediate_results(nR, nS, bt, skew):
     spl1 = _ws_view(ws, lay["off_r_splitters1"], NB1 - 1, np.uint64)
     _check_splitters(spl1, oracle.sample_splitters(R, NB1, lay["r_oversample1"],
                                                    oracle.splitmix_at(lay["r_level_seed1"], 0)))
+    # R level-2 splitters (two levels): each level-1 bucket's first nb - 1
+    # (nb: its length over 3/4 of the bucket target, rounded up, within
+    # [1, r_buckets2]) are non-decreasing, inside the bucket's key range, and
+    # each an R key or one above an R key (a splitter moved past a frequent
+    # key).  They come from a sample of the bucket in the order the first
+    # level's scatter left it, a buffer the join reuses, so they are judged by
+    # these properties, not against the oracle's quantiles.
+    NB2 = lay["r_buckets2"]
+    if NB2 > 1:
+        bst1 = _ws_view(ws, lay["off_r_bucket_start1"], NB1 + 1, np.uint32).astype(np.int64)
+        spl2 = _ws_view(ws, lay["off_r_splitters2"], NB1 * (NB2 - 1), np.uint64).reshape(NB1, NB2 - 1)
+        rkeys = np.unique(R[:, 0])
+        bt2 = bt * 3 // 4
+        for s1 in range(NB1):
+            ln = int(bst1[s1 + 1] - bst1[s1])
+            nb = min(max(-(-ln // bt2), 1), NB2)
+            sp = spl2[s1, :nb - 1]
+            lo = spl1[s1 - 1] if s1 > 0 else np.uint64(0)
+            hi = spl1[s1] if s1 < NB1 - 1 else np.uint64(U64)
+            assert np.all(sp[1:] >= sp[:-1]), s1
+            assert np.all((sp >= lo) & (sp <= hi)), s1
+            assert np.all(np.isin(sp, rkeys) | np.isin(sp - np.uint64(1), rkeys)), s1
     # phase 2+3: R sorted, partitions contiguous, first keys
     Rsorted = _ws_view(ws, lay["off_r_sorted"], 2 * nR, np.uint64).reshape(-1, 2)
     ref_R = oracle.sort_by_key(R)
