@@ -92,6 +92,26 @@ def test_all_equal_keys():
     check(R, S)                        # 6e8 pairs, count and checksum
 
 
+def test_partitions_beyond_the_lds_tile_at_scale():
+    """|R| = 2^21 with 64 keys of 12000 copies each (join units larger than
+    the 8192-tuple LDS tile, joined from global memory) among distinct keys,
+    |S| = 2^23 drawn from R's distinct keys: count and checksum against the
+    oracle, which also counts the heavy keys' pairs one by one."""
+    rng = np.random.default_rng(2112)
+    n = 1 << 21
+    heavy = rng.integers(0, U64, 64, dtype=np.uint64)
+    k = rng.integers(0, U64, n, dtype=np.uint64)
+    k[: 64 * 12000] = np.repeat(heavy, 12000)
+    R = np.stack([k[rng.permutation(n)], rng.integers(0, U64, n, dtype=np.uint64, endpoint=True)], 1)
+    u = np.unique(R[:, 0])
+    S = np.stack([u[rng.integers(0, len(u), 1 << 23)], rng.integers(0, U64, 1 << 23, dtype=np.uint64, endpoint=True)], 1)
+    want = oracle.join(R, S)
+    assert np.isin(S[:, 0], heavy).sum() >= 64   # the heavy keys meet S
+    got = gpu_join(R, S, stats=True)
+    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+    assert got["stats"]["max_partition"] >= 12000
+
+
 def test_disjoint_ranges():
     rng = np.random.default_rng(10)
     R = rel(rng, 5000, 1000)
