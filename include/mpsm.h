@@ -269,7 +269,8 @@ mpsm_status mpsm_join_events(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tupl
  *             completion it holds S's Q = ceil(nS / L) runs in place (run q
  *             is S[q*L, min((q+1)*L, nS)) sorted by key, L = 2^log2_run_len).
  *             May be NULL: the runs are then not kept, and S crosses the
- *             host link once, inwards.
+ *             host link once, inwards.  With nR = 0 nothing is joined and
+ *             no runs are written.
  *   chunk_tuples  tuples copied in, sorted and joined at a time (rounded
  *             down to a multiple of L, at least L): the device holds two
  *             chunks of S (one is copied while the other is sorted), so the
