@@ -252,7 +252,8 @@ SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ
 
 # calls of `--workload hostruns --steps 1 --warmup 1`, in order: each form is
 # run twice (the warm-up, then the timed call)
-HOSTRUNS_CALLS = ["device-resident S", "chunk 2^28", "chunk 2^26", "chunk 2^24", "chunk 2^24, runs not kept"]
+HOSTRUNS_CALLS = ["device-resident S", "chunk 2^28", "chunk 2^26", "chunk 2^24", "spilled runs rejoined",
+                  "chunk 2^24, runs not kept"]
 
 
 def summarize_host_trace(kt_csv, mc_csv, command):
@@ -581,7 +582,8 @@ def experiment_bench(args):
                S and its sorted runs in pinned host memory, for several
                chunk sizes (the share of S on the device at a time), against
                the join with S in device memory and the time S takes over
-               the host link in and out."""
+               the host link in and out; and the join phase alone, a new R
+               joined with the runs left in host memory."""
     import numpy as np
     import torch
     import paper_1207_0145_amd as mpsm
@@ -677,6 +679,27 @@ def experiment_bench(args):
             log(f"hostruns chunk 2^{lg}: {ms:.3f} ms, workspace {nbytes / 2**30:.2f} GiB")
             del ws
             torch.cuda.empty_cache()
+        # the join phase alone over the runs the last call left in host memory:
+        # S's runs read back over the link, in key order
+        nbytes = mpsm.join_spilled_runs_workspace_bytes(nR, nS)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        for _ in range(args.warmup):
+            mpsm.join_spilled_runs_into(R, runs, out, ws)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(steps):
+            mpsm.join_spilled_runs_into(R, runs, out, ws)
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        c, k = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
+        res["spilled_runs_rejoined"] = {"ms_per_step": round(ms, 4), "value": round((nR + nS) / (ms * 1e-3) / 1e6, 2),
+                                        "result": (c, f"{k:#018x}"), "workspace_GiB": round(nbytes / 2**30, 3),
+                                        "link_floor_ms": round(nS * 16 / rates["h2d_GBps"] / 1e6, 2)}
+        log(f"hostruns spilled runs rejoined: {ms:.3f} ms, workspace {nbytes / 2**30:.2f} GiB")
+        del ws
         # runs not kept: S crosses the link once
         nbytes = mpsm.join_host_runs_workspace_bytes(nR, nS, 1 << 24)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)

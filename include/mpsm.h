@@ -290,6 +290,27 @@ mpsm_status mpsm_join_host_runs(const mpsm_tuple* d_R, uint64_t nR, const mpsm_t
                                 const mpsm_config* cfg, uint64_t chunk_tuples, void* d_workspace,
                                 uint64_t workspace_bytes, void* stream);
 
+/* The join phase of the memory-constrained variant on its own (Section 3.1,
+ * Fig. 4): S's sorted runs are already in host memory, as
+ * mpsm_join_host_runs leaves them in h_runs, and a private input R is
+ * joined with them without sorting S again.  R is partitioned and sorted on
+ * the device; the run index (every 256th key of each run, the page index of
+ * Fig. 4) is read from the runs; the start search and the join then move
+ * through the key domain partition by partition and read each run's slice
+ * of it over the host link, each slice once.
+ *   h_runs  pinned host array of nS tuples, 16-byte aligned, read only:
+ *           Q = ceil(nS / L) runs in place, run q = positions [q*L,
+ *           min((q+1)*L, nS)) sorted by key, where L is the run length
+ *           mpsm_join_host_runs chooses for the same nS and cfg (it depends
+ *           on nS and cfg->log2_run_len only).  Runs that are not sorted
+ *           give undefined results, never an access outside h_runs.
+ * The other arguments, the workspace (mpsm_join_spilled_runs_workspace_bytes)
+ * and the errors are those of mpsm_join_host_runs. */
+uint64_t mpsm_join_spilled_runs_workspace_bytes(uint64_t nR, uint64_t nS, const mpsm_config* cfg);
+mpsm_status mpsm_join_spilled_runs(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* h_runs, uint64_t nS,
+                                   uint64_t* d_out_count, uint64_t* d_out_checksum, const mpsm_config* cfg,
+                                   void* d_workspace, uint64_t workspace_bytes, void* stream);
+
 /* Number of markers and the name of the step that ends at marker i
  * (static string; NULL for i out of range). */
 uint32_t mpsm_marker_count(void);

@@ -27,7 +27,8 @@ EXPORTS = ("mpsm_config_default", "mpsm_workspace_bytes", "mpsm_join", "mpsm_sta
            "mpsm_batch_destroy", "mpsm_batch_workspace_bytes", "mpsm_batch_run", "mpsm_batch_autotune",
            "mpsm_batch_get_tuning", "mpsm_batch_set_tuning", "mpsm_clock_hz", "mpsm_join_slices_host",
            "mpsm_join_noalloc", "mpsm_join_batch", "mpsm_join_batch_workspace_bytes",
-           "mpsm_lower_bound_window_host", "mpsm_join_host_runs", "mpsm_join_host_runs_workspace_bytes")
+           "mpsm_lower_bound_window_host", "mpsm_join_host_runs", "mpsm_join_host_runs_workspace_bytes",
+           "mpsm_join_spilled_runs", "mpsm_join_spilled_runs_workspace_bytes")
 
 
 class MpsmConfig(ctypes.Structure):
@@ -153,6 +154,10 @@ def lib():
         L.mpsm_join_host_runs_workspace_bytes.restype = u64
         L.mpsm_join_host_runs.argtypes = [p, u64, p, u64, p, p, p, ctypes.POINTER(MpsmConfig), u64, p, u64, p]
         L.mpsm_join_host_runs.restype = ctypes.c_int
+        L.mpsm_join_spilled_runs_workspace_bytes.argtypes = [u64, u64, ctypes.POINTER(MpsmConfig)]
+        L.mpsm_join_spilled_runs_workspace_bytes.restype = u64
+        L.mpsm_join_spilled_runs.argtypes = [p, u64, p, u64, p, p, ctypes.POINTER(MpsmConfig), p, u64, p]
+        L.mpsm_join_spilled_runs.restype = ctypes.c_int
         L.mpsm_join_batch_workspace_bytes.argtypes = [ctypes.c_uint32, ctypes.POINTER(MpsmBatchShape),
                                                       ctypes.POINTER(MpsmConfig)]
         L.mpsm_join_batch_workspace_bytes.restype = u64
@@ -287,6 +292,26 @@ def join_host_runs_into(R, S_host, runs_host, out, workspace, chunk_tuples: int,
                                    workspace.numel(), _stream_handle(stream))
     if rc != 0:
         raise MpsmError(rc, "mpsm_join_host_runs")
+    return rc
+
+
+def join_spilled_runs_workspace_bytes(nR: int, nS: int, cfg: MpsmConfig | None = None) -> int:
+    return int(lib().mpsm_join_spilled_runs_workspace_bytes(nR, nS, _cfg_ptr(cfg)))
+
+
+def join_spilled_runs_into(R, runs_host, out, workspace, cfg: MpsmConfig | None = None, stream=None) -> int:
+    """mpsm_join_spilled_runs: R (on the GPU) joined with S's sorted runs
+    already in pinned host memory (as join_host_runs_into leaves them);
+    out and workspace as in join_into.  Enqueues the work."""
+    _check_tuples(R, "R")
+    _check_host_tuples(runs_host, "runs_host")
+    rc = lib().mpsm_join_spilled_runs(ctypes.c_void_p(R.data_ptr()), R.shape[0],
+                                      ctypes.c_void_p(runs_host.data_ptr()), runs_host.shape[0],
+                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(out.data_ptr() + 8),
+                                      _cfg_ptr(cfg), ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                      _stream_handle(stream))
+    if rc != 0:
+        raise MpsmError(rc, "mpsm_join_spilled_runs")
     return rc
 
 

@@ -47,6 +47,7 @@ struct Plan {
   int hostS;
   uint64_t nSc;
   uint32_t Qc;
+  uint64_t runtab;   // hostS: start and length of every run (Q + 1 entries each)
   uint32_t Gs, Gr, Pmax;
   uint32_t idx_per_run;
   uint32_t JCH, BT;
@@ -222,6 +223,7 @@ bool make_plan(uint64_t nR_c, uint64_t nS_c, const mpsm_config* cfg, Plan* P, ui
   P->bsum = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);
   P->bsumR = take((cdiv(maxscan, SCAN_BLOCK) + 1) * 4);   // R's scans, which may run beside S's
   P->segS = take(6ull * (P->Qc + 1) * 4);
+  if (P->hostS) P->runtab = take(2ull * (P->Q + 1) * 4);
   P->segR1 = take(6ull * (P->QR + 1) * 4);
   P->segR2 = take(6ull * (P->NB1 + 1) * 4);
   P->splS = take((uint64_t)P->Qc * P->NBs * 8);
@@ -298,6 +300,28 @@ Seg seg_at(char* ws, uint64_t off, uint32_t nseg) {
   s.nb = b + 4 * (nseg + 1);
   s.b0 = b + 5 * (nseg + 1);
   return s;
+}
+
+// Start and length of each of the Q runs of L tuples over [0, n) (entry Q:
+// start n, length 0).
+__global__ void k_run_table(uint32_t* start, uint32_t* len, uint32_t Q, uint32_t L, uint32_t n) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q > Q) return;
+  const uint64_t a = (uint64_t)q * L;
+  const uint32_t s = (uint32_t)(a < n ? a : n);
+  start[q] = s;
+  len[q] = q < Q ? (n - s < L ? n - s : L) : 0u;
+}
+
+// Run index of sorted runs that are already in place: entry i of run q is
+// the key at the run's position i * stride (the entries the bucket sorts
+// emit when they write the runs).
+__global__ void k_run_index(const tup_t* runs, const uint32_t* start, const uint32_t* len, uint32_t Q,
+                            uint32_t idx_per_run, uint32_t stride, uint64_t* run_idx) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (uint64_t)Q * idx_per_run) return;
+  const uint32_t q = (uint32_t)(t / idx_per_run), i = (uint32_t)(t % idx_per_run);
+  if ((uint64_t)i * stride < len[q]) run_idx[t] = runs[start[q] + i * stride].key;
 }
 
 // Zeroes the 64-bit words w[i] whose bit i is set in mask.
@@ -643,6 +667,10 @@ struct HostS {
   const tup_t* S_dev;
   tup_t* runs_host;
   uint64_t chunk;
+  // S's sorted runs are already in host memory (runs_dev, their device
+  // address): no run generation, only the join, which reads them there
+  bool spilled;
+  const tup_t* runs_dev;
 };
 
 mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S, uint64_t nS, uint64_t* d_out_count,
@@ -993,6 +1021,21 @@ mpsm_status join_impl(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* d_S,
       if (!P.hostS) {
         rc = search_join(U, LS.seg.start, LS.seg.len, P.Q, ridx);
         if (rc != MPSM_OK) return rc;
+      } else if (hs->spilled) {
+        // S's runs in host memory from an earlier call: their run table and
+        // run index (every stride-th key, read from the runs), then the
+        // search and the join, which move through the key domain partition
+        // by partition and read every run's slice of it over the host link
+        uint32_t* rt = reinterpret_cast<uint32_t*>(ws + P.runtab);
+        k_run_table<<<(uint32_t)cdiv((uint64_t)P.Q + 1, 256), 256, 0, st>>>(rt, rt + P.Q + 1, P.Q, P.L, (uint32_t)P.nS);
+        LAUNCH_CHECK();
+        k_run_index<<<(uint32_t)cdiv((uint64_t)P.Q * P.idx_per_run, 256), 256, 0, st>>>(
+            hs->runs_dev, rt, rt + P.Q + 1, P.Q, P.idx_per_run, IDX_STRIDE, ridx);
+        LAUNCH_CHECK();
+        HIP_TRY(hipEventRecord(side->done, rst));   // R's partitions are ready
+        HIP_TRY(hipStreamWaitEvent(st, side->done, 0));
+        rc = search_join(hs->runs_dev, rt, rt + P.Q + 1, P.Q, ridx);
+        if (rc != MPSM_OK) return rc;
       } else {
         HIP_TRY(hipEventRecord(side->done, rst));   // R's partitions are ready
         // S in host memory: the tuples of whole runs at a time are copied
@@ -1183,6 +1226,8 @@ mpsm_status mpsm_join_host_runs(const mpsm_tuple* d_R, uint64_t nR, const mpsm_t
   hs.runs_host = reinterpret_cast<tup_t*>(h_runs);
   hs.S_dev = nullptr;
   hs.chunk = chunk_tuples;
+  hs.spilled = false;
+  hs.runs_dev = nullptr;
   if (nS) {
     // both buffers must be pinned host memory the device can address
     void* p = nullptr;
@@ -1195,6 +1240,38 @@ mpsm_status mpsm_join_host_runs(const mpsm_tuple* d_R, uint64_t nR, const mpsm_t
     hs.S_dev = static_cast<const tup_t*>(p);
   }
   return join_impl(d_R, nR, h_S, nS, d_out_count, d_out_checksum, nullptr, 0, cfg, d_workspace, workspace_bytes,
+                   stream, nullptr, nullptr, 0, false, &hs);
+}
+
+uint64_t mpsm_join_spilled_runs_workspace_bytes(uint64_t nR, uint64_t nS, const mpsm_config* cfg) {
+  // the plan of the host-memory join with the smallest chunk (one run)
+  return mpsm_join_host_runs_workspace_bytes(nR, nS, cfg, 1);
+}
+
+mpsm_status mpsm_join_spilled_runs(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tuple* h_runs, uint64_t nS,
+                                   uint64_t* d_out_count, uint64_t* d_out_checksum, const mpsm_config* cfg,
+                                   void* d_workspace, uint64_t workspace_bytes, void* stream) {
+  mpsm_config def;
+  if (!cfg) { mpsm_config_default(&def); cfg = &def; }
+  if (!host_runs_config_ok(cfg)) return MPSM_EINVAL;
+  if ((nS && !h_runs) || ((uintptr_t)h_runs & 15)) return MPSM_EINVAL;
+  HostS hs;
+  hs.S_host = nullptr;
+  hs.runs_host = nullptr;
+  hs.chunk = 1;
+  hs.spilled = true;
+  hs.S_dev = nullptr;
+  hs.runs_dev = nullptr;
+  if (nS) {
+    void* p = nullptr;
+    if (hipHostGetDevicePointer(&p, const_cast<mpsm_tuple*>(h_runs), 0) != hipSuccess || !p) {
+      (void)hipGetLastError();   // the failed lookup is the caller's error, not a later call's
+      return MPSM_EINVAL;
+    }
+    hs.runs_dev = static_cast<const tup_t*>(p);
+    hs.S_dev = hs.runs_dev;   // the learned search's sample: any positions of S's tuples
+  }
+  return join_impl(d_R, nR, h_runs, nS, d_out_count, d_out_checksum, nullptr, 0, cfg, d_workspace, workspace_bytes,
                    stream, nullptr, nullptr, 0, false, &hs);
 }
 

@@ -84,6 +84,24 @@ def test_host_runs_workspace():
     assert mpsm.join_host_runs_workspace_bytes(nR, nS, chunk, mpsm.config(splitter=mpsm.SPLIT_LEARNED)) > 0
 
 
+def test_spilled_runs_workspace_and_host_checks():
+    """The join over runs already in host memory holds no copy of S: its
+    workspace is far below the device-resident join's; refused options size
+    to 0; a NULL or misaligned run array is refused before any HIP call."""
+    nR, nS = 1 << 20, 1 << 30
+    ws = mpsm.join_spilled_runs_workspace_bytes(nR, nS)
+    assert 0 < ws and ws + 2 * 16 * (nS - (1 << 24)) <= mpsm.workspace_bytes(nR, nS)
+    for kw in (dict(splitter=mpsm.SPLIT_COST), dict(splitter=mpsm.SPLIT_NONE), dict(role=mpsm.ROLE_SWAP)):
+        assert mpsm.join_spilled_runs_workspace_bytes(nR, nS, mpsm.config(**kw)) == 0, kw
+    L = mpsm.lib()
+    good = ctypes.c_void_p(0x100000)
+    assert L.mpsm_join_spilled_runs(good, 5, None, 5, good, good, None, good, 1 << 40, None) == 1
+    assert L.mpsm_join_spilled_runs(good, 5, ctypes.c_void_p(0x100008), 5, good, good, None, good, 1 << 40,
+                                    None) == 1
+    assert L.mpsm_join_spilled_runs(good, 5, good, 5, good, good,
+                                    ctypes.byref(mpsm.config(splitter=mpsm.SPLIT_COST)), good, 1 << 40, None) == 1
+
+
 def test_host_runs_bad_arguments_rejected_on_host():
     # rejected before any HIP call: the pointers are never dereferenced
     L = mpsm.lib()

@@ -191,3 +191,52 @@ def test_host_runs_back_to_back():
         want = oracle.join(R, S)
         assert (int(o[0]), int(o[1])) == (want.count, want.checksum)
         check_runs(S, rh.numpy().view(np.uint64), 1 << 12)
+
+
+def spilled_join(R, runs_host, cfg=None):
+    cfg = cfg if cfg is not None else mpsm.config()
+    _say(f"mpsm_join_spilled_runs nR={len(R)} nS={runs_host.shape[0]} L=2^{cfg.log2_run_len or 'default'} "
+         f"splitter={cfg.splitter} search={cfg.search}")
+    ws = torch.empty(mpsm.join_spilled_runs_workspace_bytes(len(R), runs_host.shape[0], cfg), dtype=torch.uint8,
+                     device="cuda")
+    out = torch.zeros(2, dtype=torch.int64, device="cuda")
+    mpsm.join_spilled_runs_into(_dev(R), runs_host, out, ws, cfg)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().view(np.uint64)
+    return int(o[0]), int(o[1])
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(search=mpsm.SEARCH_BINARY), dict(search=mpsm.SEARCH_INTERP),
+                                dict(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED)])
+def test_spilled_runs_from_the_oracle(kw):
+    """Runs sorted by the oracle (ragged last run) in pinned host memory,
+    joined with an R the GPU partitions: the oracle's count and checksum."""
+    rng = np.random.default_rng(404)
+    R, S = rel(rng, 20000, 9000), rel(rng, 150001, 9000)
+    cfg = mpsm.config(log2_run_len=12, **kw)
+    runs = _pinned(oracle.sort_runs(S, 1 << 12))
+    want = oracle.join(R, S)
+    assert spilled_join(R, runs, cfg) == (want.count, want.checksum)
+
+
+def test_spilled_runs_rejoined():
+    """The runs one host-memory join leaves behind, joined again with two
+    other R: each the oracle's result against S, with S never sorted again."""
+    rng = np.random.default_rng(405)
+    S = rel(rng, 300000, 50000)
+    R0, R1, R2 = rel(rng, 40000, 50000), rel(rng, 7000, 50000), rel(rng, 90000, 60000)
+    cnt, chk, runs = host_join(R0, S, 3 << 16)
+    want = oracle.join(R0, S)
+    assert (cnt, chk) == (want.count, want.checksum)
+    runs_pinned = _pinned(runs)
+    for R in (R1, R2):
+        want = oracle.join(R, S)
+        assert spilled_join(R, runs_pinned) == (want.count, want.checksum)
+
+
+@pytest.mark.parametrize("nR,nS", [(0, 5000), (5000, 0)])
+def test_spilled_runs_empty(nR, nS):
+    rng = np.random.default_rng(406)
+    R, S = rel(rng, nR, 100), rel(rng, nS, 100)
+    runs = _pinned(oracle.sort_runs(S, 1 << 12)) if nS else torch.empty((0, 2), dtype=torch.int64)
+    assert spilled_join(R, runs, mpsm.config(log2_run_len=12)) == (0, 0)
