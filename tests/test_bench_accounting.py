@@ -104,3 +104,52 @@ def test_two_stream_steps():
         assert out["partitions"] == pytest.approx(dur["partitions"])
         for n in tail:
             assert out[n] == pytest.approx(dur[n]), n
+
+
+def _write_csv(path, header, rows):
+    import csv
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_host_trace_summary(tmp_path):
+    """The hostruns trace summary from a synthetic kernel and memory-copy
+    trace: one row per form (the second of its two joins), its span, its
+    copies in and out (copy kernels counted as copies out, copies under
+    0.05 ms left out) and the sum of its other kernels."""
+    b = _bench()
+    kt, mc = [], []
+    t = 0
+    ms = 1_000_000   # ns
+    for form in range(len(b.HOSTRUNS_CALLS)):
+        for call in range(2):
+            kt.append(("k_init_result(Result*)", t, t + 1000))
+            kt.append(("void k_join<0, 0, false>(JoinArgs)", t + ms, t + 3 * ms))        # 2 ms
+            mc.append(("MEMORY_COPY_HOST_TO_DEVICE", t + ms, t + 5 * ms))               # 4 ms in
+            kt.append(("__amd_rocclr_copyBuffer(...)", t + 5 * ms, t + 6 * ms))         # 1 ms out
+            mc.append(("MEMORY_COPY_DEVICE_TO_HOST", t + 6 * ms, t + 6 * ms + 10_000))  # 0.01 ms: left out
+            t += 10 * ms
+    _write_csv(tmp_path / "kt.csv", ["Kernel_Name", "Start_Timestamp", "End_Timestamp"], kt)
+    _write_csv(tmp_path / "mc.csv", ["Direction", "Start_Timestamp", "End_Timestamp"], mc)
+    md = b.summarize_host_trace(str(tmp_path / "kt.csv"), str(tmp_path / "mc.csv"), "cmd")
+    rows = [r for r in md.splitlines() if r.startswith("| ") and not r.startswith("| form")]
+    assert len(rows) == len(b.HOSTRUNS_CALLS)
+    for name, r in zip(b.HOSTRUNS_CALLS, rows):
+        cells = [c.strip() for c in r.strip("|").split("|")]
+        assert cells[0] == name
+        assert cells[1] == "6.01"                    # first kernel start to last end
+        assert cells[2] == "1, 4.0, 4.00-4.00"
+        assert cells[3] == "1, 1.0, 1.00-1.00"
+        assert cells[4] == "2.00"                    # k_init_result (0.001 ms) + k_join
+    assert "cmd" in md
+
+
+def test_host_trace_summary_needs_every_call(tmp_path):
+    b = _bench()
+    _write_csv(tmp_path / "kt.csv", ["Kernel_Name", "Start_Timestamp", "End_Timestamp"],
+               [("k_init_result(Result*)", 0, 1000)])
+    _write_csv(tmp_path / "mc.csv", ["Direction", "Start_Timestamp", "End_Timestamp"], [])
+    with pytest.raises(SystemExit):
+        b.summarize_host_trace(str(tmp_path / "kt.csv"), str(tmp_path / "mc.csv"), "cmd")
