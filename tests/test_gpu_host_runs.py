@@ -2,7 +2,9 @@
 variant of Section 3.1, its runs kept in pinned host memory instead of on
 disk): count and checksum against the oracle's join, and the runs it leaves
 in host memory against the oracle's sorted runs (keys position by position,
-tuples as a multiset per run, since equal keys may come in any order)."""
+tuples as a multiset per run, since equal keys may come in any order).  Its
+join phase on its own, over runs already in host memory (sorted by the
+oracle, or left by an earlier call), against the oracle's join too."""
 import ctypes
 
 import numpy as np
