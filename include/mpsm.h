@@ -234,6 +234,14 @@ typedef struct mpsm_layout {
   uint64_t off_cost_best;    /* f64: the largest group cost of the chosen split */
   uint32_t cost_cells;
   uint32_t reserved2;
+  /* learned CDF models (R's with splitter LEARNED, S's with search LEARNED):
+     each starts with cdf_knots u64 knot keys, the sorted keys of ranks
+     floor(i (cdf_sample - 1) / (cdf_knots - 1)) of a sample of cdf_sample
+     keys of the relation drawn at positions floor(x_t n / 2^64), x_t the
+     SplitMix64 stream cdf_seed_r / cdf_seed_s (t = 0 .. cdf_sample - 1) */
+  uint64_t off_cdf_model_r, off_cdf_model_s;
+  uint64_t cdf_seed_r, cdf_seed_s;
+  uint32_t cdf_sample, cdf_knots;
 } mpsm_layout;
 
 mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* cfg, mpsm_layout* out);

@@ -53,6 +53,7 @@ def lib():
             "orc_sort_runs": ([p, u64, u64, p], i32),
             "orc_radix_partition": ([p, u64, u64, i32, i32, p, u32, p, p, p, p], i32),
             "orc_sample_splitters": ([p, u64, u32, u32, u64, p], i32),
+            "orc_cdf_knots": ([p, u64, u32, u32, u64, p], i32),
             "orc_bucket_of": ([p, u32, u64], u32),
             "orc_bucket_partition": ([p, u64, p, u32, p, p], i32),
             "orc_lower_bound": ([p, u64, u64], u64),
@@ -211,6 +212,13 @@ def sample_splitters(T, nbucket: int, oversample: int, seed: int) -> np.ndarray:
     spl = np.zeros(max(nbucket - 1, 1), np.uint64)
     _check(lib().orc_sample_splitters(_p(T), len(T), nbucket, oversample, seed, _p(spl)), "sample_splitters")
     return spl[: max(nbucket - 1, 0)]
+
+
+def cdf_knots(T, m: int, k: int, seed: int) -> np.ndarray:
+    T = _tuples(T)
+    out = np.zeros(k, np.uint64)
+    _check(lib().orc_cdf_knots(_p(T), len(T), m, k, seed, _p(out)), "cdf_knots")
+    return out
 
 
 def bucket_of(spl, nbucket: int, key: int) -> int:

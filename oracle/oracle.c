@@ -322,6 +322,28 @@ int orc_sample_splitters(const uint64_t* T, uint64_t len, uint32_t nbucket, uint
   return 0;
 }
 
+/* Knots of a piecewise-linear CDF of T's keys, the shape of Section 4.1's S
+ * distribution (sample quantiles taken as equally high steps, linear between
+ * them) that the learned CDF's first part has (the learned model itself is an
+ * addition to the paper, so the sample is a reading): m keys drawn as in
+ * orc_sample_splitters (positions floor(x_t * len / 2^64), x_t the SplitMix64
+ * stream `seed`, t = 0 .. m-1), sorted; knot i (i = 0 .. k-1, k >= 2) is the
+ * sample key of rank floor(i (m-1) / (k-1)), so the first knot is the
+ * sample's smallest key and the last its largest.  Writes k knots. */
+int orc_cdf_knots(const uint64_t* T, uint64_t len, uint32_t m, uint32_t k, uint64_t seed, uint64_t* knots) {
+  if (len == 0 || m == 0 || k < 2) return -1;
+  uint64_t* smp = (uint64_t*)malloc(2 * (uint64_t)m * sizeof(uint64_t));
+  if (!smp) return -1;
+  for (uint64_t t = 0; t < m; t++) {
+    uint64_t pos = (uint64_t)(((unsigned __int128)orc_splitmix_at(seed, t) * len) >> 64);
+    smp[2 * t] = T[2 * pos]; smp[2 * t + 1] = 0;
+  }
+  orc_sort_by_key(smp, m);
+  for (uint32_t i = 0; i < k; i++) knots[i] = smp[2 * ((uint64_t)i * (m - 1) / (k - 1))];
+  free(smp);
+  return 0;
+}
+
 /* Bucket of a key under nbucket-1 sorted splitters: the number of splitters
  * <= key, so bucket b holds the keys in [spl[b-1], spl[b]) (the partition
  * [low, high) of Section 4.3).  Non-decreasing in the key, which is all the

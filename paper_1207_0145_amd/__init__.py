@@ -66,7 +66,10 @@ class MpsmLayout(ctypes.Structure):
                 ("idx_per_run", ctypes.c_uint32), ("padded_passes", ctypes.c_uint32),
                 ("off_join_span", ctypes.c_uint64), ("off_cost_sample", ctypes.c_uint64),
                 ("off_cost_s_below", ctypes.c_uint64), ("off_cost_best", ctypes.c_uint64),
-                ("cost_cells", ctypes.c_uint32), ("reserved2", ctypes.c_uint32)]
+                ("cost_cells", ctypes.c_uint32), ("reserved2", ctypes.c_uint32),
+                ("off_cdf_model_r", ctypes.c_uint64), ("off_cdf_model_s", ctypes.c_uint64),
+                ("cdf_seed_r", ctypes.c_uint64), ("cdf_seed_s", ctypes.c_uint64),
+                ("cdf_sample", ctypes.c_uint32), ("cdf_knots", ctypes.c_uint32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

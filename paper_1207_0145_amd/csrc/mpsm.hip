@@ -650,6 +650,12 @@ mpsm_status mpsm_workspace_layout(uint64_t nR, uint64_t nS, const mpsm_config* c
   out->off_cost_s_below = P.cost_s_below;
   out->off_cost_best = P.cost_best;
   out->cost_cells = P.NB1 * P.OS1;
+  out->off_cdf_model_r = P.modelR;
+  out->off_cdf_model_s = P.modelS;
+  out->cdf_seed_r = P.seed ^ TAG_CR;
+  out->cdf_seed_s = P.seed ^ TAG_CS;
+  out->cdf_sample = CDF_M;
+  out->cdf_knots = CDF_K;
   return MPSM_OK;
 }
 

@@ -215,6 +215,27 @@ def test_learned_modes_exact_and_model_sane(workload, shift):
             assert st["cdf_eps_r"] == -1.0 and st["search_fallbacks"] == 0
 
 
+@pytest.mark.parametrize("name,shift", [("skewed", 6), ("lognormal", 8)])
+def test_learned_cdf_knots_against_the_oracle(name, shift):
+    """The learned models' piecewise-linear part: every knot of R's model
+    (learned splitters) and of S's model (learned search) equals the
+    oracle's knot of the same seeded sample of the same relation; the join
+    stays exact."""
+    w = workloads.make(name, scale_shift=shift)
+    cfg = mpsm.config(splitter=mpsm.SPLIT_LEARNED, search=mpsm.SEARCH_LEARNED)
+    lay = mpsm.layout(len(w.R), len(w.S), cfg)
+    assert lay["swapped"] == 0
+    ws = mpsm.alloc_workspace(len(w.R), len(w.S), cfg)
+    got = gpu_join(w.R, w.S, cfg, workspace=ws)
+    want, _ = oracle.join_hash(w.R, w.S)
+    assert (got["count"], got["checksum"]) == (want.count, want.checksum)
+    torch.cuda.synchronize()
+    m, k = lay["cdf_sample"], lay["cdf_knots"]
+    for T, off, seed in ((w.R, lay["off_cdf_model_r"], lay["cdf_seed_r"]),
+                         (w.S, lay["off_cdf_model_s"], lay["cdf_seed_s"])):
+        assert np.array_equal(_ws_view(ws, off, k, np.uint64), oracle.cdf_knots(T, m, k, seed))
+
+
 def test_learned_search_with_bad_window_falls_back():
     # tiny R with a handful of distinct keys: the model sees a step function;
     # whatever it predicts, the bracket check keeps the offsets exact

@@ -491,3 +491,46 @@ def test_bmpsm_join_equals_definition_larger():
     a = oracle.bmpsm_join(R, S, 12)
     b = oracle.join(R, S)
     assert (a.count, a.checksum) == (b.count, b.checksum)
+
+
+# ------------------------------------------------------- learned CDF knots
+
+def test_cdf_knots_are_sample_quantiles():
+    """Knots of the piecewise-linear CDF (Section 4.1's shape: sample
+    quantiles as equally high steps): on keys 0 .. n-1 in random order the
+    fraction of keys at or below knot i is the knot's rank over the sample
+    size within the Dvoretzky-Kiefer-Wolfowitz bound of a 2^16-key sample
+    (sqrt(ln(2/1e-6) / 2^17) < 0.0106); the first and last knots bound the
+    keys; a wrong rank formula, an unsorted sample or a biased draw fails."""
+    n, m, k = 1 << 20, 1 << 16, 4096
+    rng = np.random.default_rng(61)
+    T = np.stack([rng.permutation(n).astype(np.uint64), np.zeros(n, np.uint64)], 1)
+    knots = oracle.cdf_knots(T, m, k, seed=0x1207)
+    assert np.all(knots[1:] >= knots[:-1])
+    eps = np.sqrt(np.log(2 / 1e-6) / (2 * m)) + 1.0 / m
+    ranks = (np.arange(k, dtype=np.int64) * (m - 1)) // (k - 1)
+    frac = (knots.astype(np.float64) + 1) / n          # keys <= knot, over all keys
+    assert np.max(np.abs(frac - (ranks + 0.5) / m)) <= eps
+    assert knots[0] < n // 100 and knots[-1] > n - n // 100
+
+
+def test_cdf_knots_special_cases_and_the_splitters_stream():
+    """All keys equal: every knot is that key.  Two keys half and half: the
+    knots switch from the low to the high key once, near the middle.  The
+    draw is the sampled splitters' stream: with m = (k-1) o + 1 keys, knot i
+    (rank i o) lies between splitters i-2 and i-1 of the (k-1) o-key sample
+    (one more key moves a rank by at most one place)."""
+    T = np.stack([np.full(5000, 77, np.uint64), np.arange(5000, dtype=np.uint64)], 1)
+    assert np.all(oracle.cdf_knots(T, 1 << 12, 64, seed=5) == 77)
+    T2 = np.stack([np.repeat(np.array([10, 1 << 60], np.uint64), 50000), np.zeros(100000, np.uint64)], 1)
+    kn = oracle.cdf_knots(T2, 1 << 14, 257, seed=9)
+    switch = int(np.argmax(kn == np.uint64(1 << 60)))
+    assert np.all(kn[:switch] == 10) and np.all(kn[switch:] == np.uint64(1 << 60))
+    assert abs(switch - 128) <= 8
+    rng = np.random.default_rng(62)
+    T3 = np.stack([rng.integers(0, 1 << 40, 200000, dtype=np.uint64), np.zeros(200000, np.uint64)], 1)
+    k, o = 129, 16
+    kn = oracle.cdf_knots(T3, (k - 1) * o + 1, k, seed=33)
+    spl = oracle.sample_splitters(T3, k - 1, o, seed=33)
+    for i in range(2, k - 1):
+        assert spl[i - 2] <= kn[i] <= spl[i - 1], i
