@@ -28,11 +28,13 @@
  *     (Section 3.2.2, Fig. 7), the global S distribution from merged
  *     equi-height bounds (Section 4.1, Fig. 8), the split-relevant cost and
  *     its min-max split (Section 4.3), the basic B-MPSM join (Section 2.1,
- *     Fig. 3) and the full P-MPSM join (Fig. 5).
+ *     Fig. 3), the full P-MPSM join (Fig. 5), and the knots of a
+ *     piecewise-linear CDF over a seeded sample (Section 4.1's shape).
  *
- * Pins: see tests/test_oracle_pins.py.  The learned-CDF quality is not
- * computed here (parity unpinned: the paper has no learned model; only
- * exactness of the join result is pinned).
+ * Pins: see tests/test_oracle_pins.py.  The learned CDF's residual network
+ * and its quality are not computed here (parity unpinned: the paper has no
+ * learned model; its knots and the exactness of the join result are
+ * pinned).
  */
 #include <stdint.h>
 #include <stdlib.h>
