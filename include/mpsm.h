@@ -275,7 +275,9 @@ mpsm_status mpsm_join_events(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tupl
  *             nS tuples, 16-byte aligned; read only.
  *   h_runs    pinned host array of nS tuples, 16-byte aligned, written: on
  *             completion it holds S's Q = ceil(nS / L) runs in place (run q
- *             is S[q*L, min((q+1)*L, nS)) sorted by key, L = 2^log2_run_len).
+ *             is S[q*L, min((q+1)*L, nS)) sorted by key; L is the run
+ *             length of the plan: 2^cfg->log2_run_len, or chosen from nS
+ *             when that is 0, as mpsm_workspace_layout's run_len reports).
  *             May be NULL: the runs are then not kept, and S crosses the
  *             host link once, inwards.  With nR = 0 nothing is joined and
  *             no runs are written.
