@@ -277,7 +277,8 @@ mpsm_status mpsm_join_events(const mpsm_tuple* d_R, uint64_t nR, const mpsm_tupl
  *             completion it holds S's Q = ceil(nS / L) runs in place (run q
  *             is S[q*L, min((q+1)*L, nS)) sorted by key; L is the run
  *             length of the plan: 2^cfg->log2_run_len, or chosen from nS
- *             when that is 0, as mpsm_workspace_layout's run_len reports).
+ *             when that is 0, as the run_len of mpsm_workspace_layout for
+ *             the same sizes and cfg->role = MPSM_ROLE_AS_GIVEN reports).
  *             May be NULL: the runs are then not kept, and S crosses the
  *             host link once, inwards.  With nR = 0 nothing is joined and
  *             no runs are written.
