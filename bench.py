@@ -725,6 +725,7 @@ def experiment_bench(args):
         line = {**base, "value": res["chunk_2^26"]["value"], "ms_per_step": res["chunk_2^26"]["ms_per_step"],
                 "config": {"workload": "hostruns: |R|=2^26, |S|=2^28 uniform foreign keys; S and its sorted runs "
                                        "in pinned host memory, value at a chunk of 2^26 tuples"},
+                "host_link_inclusive": True,   # these rates include S's copies over the host link
                 "chunks": res, "host_link": rates, "host_link_floor_ms": round(floor_ms, 2)}
     else:   # locskew
         w = workloads.fk_uniform(1 << 24, 1 << 26, seed=0x1207014500000901, spread=True)
