@@ -84,6 +84,20 @@ def test_host_runs_workspace():
     assert mpsm.join_host_runs_workspace_bytes(nR, nS, chunk, mpsm.config(splitter=mpsm.SPLIT_LEARNED)) > 0
 
 
+def test_host_runs_chunks_are_whole_runs():
+    """The chunk is rounded down to whole runs (at least one): the workspace
+    is the same for every chunk between k and k+1 runs, and grows with k."""
+    nR, nS = 1 << 20, 1 << 26
+    L = mpsm.layout(nR, nS, mpsm.config(role=mpsm.ROLE_AS_GIVEN))["run_len"]
+    sizes = []
+    for k in (1, 2, 3, 8):
+        w = {mpsm.join_host_runs_workspace_bytes(nR, nS, c) for c in (k * L, k * L + 1, (k + 1) * L - 1)}
+        assert len(w) == 1, k
+        sizes.append(w.pop())
+    assert sizes == sorted(sizes) and sizes[0] < sizes[-1]
+    assert mpsm.join_host_runs_workspace_bytes(nR, nS, L - 1) == sizes[0]
+
+
 def test_spilled_runs_workspace_and_host_checks():
     """The join over runs already in host memory holds no copy of S: its
     workspace is far below the device-resident join's; refused options size
