@@ -583,7 +583,9 @@ def experiment_bench(args):
                chunk sizes (the share of S on the device at a time), against
                the join with S in device memory and the time S takes over
                the host link in and out; and the join phase alone, a new R
-               joined with the runs left in host memory."""
+               joined with the runs left in host memory;
+      hostruns_large  the same forms with |S| = 2^31 (32 GiB of S in host
+               memory) and a device workspace of a few GiB."""
     import numpy as np
     import torch
     import paper_1207_0145_amd as mpsm
@@ -727,6 +729,50 @@ def experiment_bench(args):
                                        "in pinned host memory, value at a chunk of 2^26 tuples"},
                 "host_link_inclusive": True,   # these rates include S's copies over the host link
                 "chunks": res, "host_link": rates, "host_link_floor_ms": round(floor_ms, 2)}
+    elif args.workload == "hostruns_large":
+        # S of 2^31 tuples (32 GiB) in pinned host memory against a device
+        # workspace of a few GiB: the join's device footprint follows the chunk
+        nR, nS, chunk = 1 << 26, 1 << 31, 1 << 24
+        log("generating |R| = 2^26, |S| = 2^31 uniform foreign keys")
+        w = workloads.fk_uniform(nR, nS, seed=0x1207014500000b01, spread=True)
+        R = to_dev(w.R)
+        Sh = torch.empty((nS, 2), dtype=torch.int64, pin_memory=True)
+        Sh.copy_(torch.from_numpy(w.S.view(np.int64)))
+        del w
+        runs = torch.empty((nS, 2), dtype=torch.int64, pin_memory=True)
+        out = torch.zeros(2, dtype=torch.int64, device=dev)
+        res = {}
+
+        def timed(name, nbytes, call):
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            for _ in range(args.warmup):
+                call(ws)
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0.record()
+            for _ in range(steps):
+                call(ws)
+            t1.record()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / steps
+            c, k = [v & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
+            res[name] = {"ms_per_step": round(ms, 3), "value": round((nR + nS) / (ms * 1e-3) / 1e6, 2),
+                         "count": c, "count_is_nS": c == nS, "checksum": f"{k:#018x}",
+                         "workspace_GiB": round(nbytes / 2**30, 3)}
+            log(f"hostruns_large {name}: {ms:.1f} ms, workspace {nbytes / 2**30:.2f} GiB, count {c}")
+            del ws
+
+        hb = mpsm.join_host_runs_workspace_bytes(nR, nS, chunk)
+        timed("runs_kept", hb, lambda ws: mpsm.join_host_runs_into(R, Sh, runs, out, ws, chunk))
+        timed("spilled_runs_rejoined", mpsm.join_spilled_runs_workspace_bytes(nR, nS),
+              lambda ws: mpsm.join_spilled_runs_into(R, runs, out, ws))
+        timed("runs_not_kept", hb, lambda ws: mpsm.join_host_runs_into(R, Sh, None, out, ws, chunk))
+        line = {**base, "value": res["runs_kept"]["value"], "ms_per_step": res["runs_kept"]["ms_per_step"],
+                "config": {"workload": "hostruns_large: |R|=2^26, |S|=2^31 uniform foreign keys; S (32 GiB) and "
+                                       "its sorted runs in pinned host memory, chunks of 2^24 tuples"},
+                "host_link_inclusive": True, "forms": res,
+                "device_resident_workspace_GiB": round(mpsm.workspace_bytes(nR, nS) / 2**30, 1)}
     else:   # locskew
         w = workloads.fk_uniform(1 << 24, 1 << 26, seed=0x1207014500000901, spread=True)
         runs = mpsm.layout(len(w.R), len(w.S))["runs"]
@@ -841,7 +887,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal",
                     choices=["fk_uniform", "fk_small", "skewed", "lognormal", "batch", "negcorr", "roles",
-                             "locskew", "hostruns"])
+                             "locskew", "hostruns", "hostruns_large"])
     ap.add_argument("--extra", default="fk_uniform,skewed",
                     help="comma-separated single-join workloads reported beside the headline ('' for none)")
     ap.add_argument("--autotune-cache", default=None, help="batch workload: autotuner cache file")
@@ -888,7 +934,7 @@ def main():
     if args.workload == "batch":
         batch_bench(args)
         return
-    if args.workload in ("negcorr", "roles", "locskew", "hostruns"):
+    if args.workload in ("negcorr", "roles", "locskew", "hostruns", "hostruns_large"):
         experiment_bench(args)
         return
     import torch
