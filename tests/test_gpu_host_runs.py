@@ -242,3 +242,42 @@ def test_spilled_runs_empty(nR, nS):
     R, S = rel(rng, nR, 100), rel(rng, nS, 100)
     runs = _pinned(oracle.sort_runs(S, 1 << 12)) if nS else torch.empty((0, 2), dtype=torch.int64)
     assert spilled_join(R, runs, mpsm.config(log2_run_len=12)) == (0, 0)
+
+
+def test_host_runs_fk_uniform_full_size():
+    """The benchmark's fk_uniform workload (|R| = 2^26, |S| = 2^28) with S in
+    pinned host memory, in 2^24-tuple chunks as the bench times it: count and
+    checksum from the foreign-key closed form, four of the runs it leaves in
+    host memory against the oracle's sort, and the join phase over those runs
+    with the same result."""
+    w = workloads.make("fk_uniform")
+    nR, nS = len(w.R), len(w.S)
+    fk = oracle.fk_closed_form(w.R, w.S, w.partner)
+    cfg = mpsm.config()
+    L = mpsm.layout(nR, nS, mpsm.config(role=mpsm.ROLE_AS_GIVEN))["run_len"]
+    _say(f"host runs full size: nR={nR} nS={nS} L={L} chunk=2^24")
+    Rd = _dev(w.R)
+    Sh = _pinned(w.S)
+    runs = torch.empty((nS, 2), dtype=torch.int64, pin_memory=True)
+    out = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ws = torch.empty(mpsm.join_host_runs_workspace_bytes(nR, nS, 1 << 24, cfg), dtype=torch.uint8, device="cuda")
+    mpsm.join_host_runs_into(Rd, Sh, runs, out, ws, 1 << 24, cfg)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().view(np.uint64)
+    assert (int(o[0]), int(o[1])) == (nS, fk.checksum) == (fk.count, fk.checksum)
+    rv = runs.numpy().view(np.uint64)
+    Q = (nS + L - 1) // L
+    for j in sorted({0, 17, Q // 2, Q - 1}):
+        a, b = j * L, min((j + 1) * L, nS)
+        ref = oracle.sort_by_key(w.S[a:b])
+        x = rv[a:b]
+        assert np.array_equal(x[:, 0], ref[:, 0])
+        assert np.array_equal(x[np.lexsort((x[:, 1], x[:, 0]))], ref[np.lexsort((ref[:, 1], ref[:, 0]))])
+    del ws
+    _say("host runs full size: the join phase over the spilled runs")
+    ws = torch.empty(mpsm.join_spilled_runs_workspace_bytes(nR, nS, cfg), dtype=torch.uint8, device="cuda")
+    out.zero_()
+    mpsm.join_spilled_runs_into(Rd, runs, out, ws, cfg)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy().view(np.uint64)
+    assert (int(o[0]), int(o[1])) == (fk.count, fk.checksum)
